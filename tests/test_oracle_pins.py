@@ -576,3 +576,32 @@ def test_fp32_factors(oracle_mod):
     x, it, rr, st = oracle_mod.solve(s.nb, s.bs, s.Ap, s.Aj, s.Ax, O.Pp, O.Pj, None, None, rhs,
                                      F32=F32, Dinv32=D32)
     assert st == 0 and rr <= 1e-8
+
+
+@pytest.mark.parametrize("seed", [1, 7, 13])
+@pytest.mark.parametrize("method", [0, 1])
+def test_krylov_iteration_counts_match_scipy(oracle_mod, seed, method):
+    """Same preconditioner, same operator: the oracle's right-preconditioned
+    BiCGSTAB / GMRES(m) must take the same number of steps (within one, for
+    the exit-test difference) as scipy's implementations of the same
+    methods.  A wrong coefficient or sign in a recurrence changes the
+    trajectory and, on these mildly conditioned systems, the count."""
+    s = synth.reservoir(9, 8, 7, 3, seed=seed, sigma=2.0)
+    O = oracle_mod.OracleILU(s.nb, s.bs, s.Ap, s.Aj, 0).factor(s.Ax)
+    A = sp.csr_matrix(dense_blocks(s.nb, s.bs, s.Ap, s.Aj, s.Ax))
+    rhs = A @ s.xstar
+    x, it, rr, st = O.solve(s.Ax, rhs, method=method, restart=5, rtol=1e-10)
+    assert st == 0
+    Mop = spla.LinearOperator(A.shape, matvec=lambda r: O.apply(r))
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+
+    if method == 0:
+        xs, info = spla.bicgstab(A, rhs, M=Mop, rtol=1e-10, maxiter=500, callback=cb)
+    else:
+        xs, info = spla.gmres(A, rhs, M=Mop, rtol=1e-10, restart=5, maxiter=500,
+                              callback=cb, callback_type="pr_norm")
+    assert info == 0
+    assert abs(it - count[0]) <= 1, (it, count[0])
