@@ -1,0 +1,226 @@
+/*
+ * bilu.h -- C ABI of the MI355X (gfx950) decoupled block-wise ILU(k)
+ * preconditioner and the Krylov solves it is applied in.
+ *
+ * Method: Yang, Liu, Zhong, Chen, "Decoupled Block-Wise ILU(k)
+ * Preconditioner on GPU" (arXiv:1703.01325).  The calls follow the paper's
+ * statement of the problem (Algorithm 5, Eq 5, Algorithm 7):
+ *
+ *   bilu_analyze          symbolic ILU(k) on the point-wise view of the block
+ *                         pattern (Algorithm 3, Eq 1-2) and level sets for
+ *                         the sweeps (Eq 4, Algorithm 6)              [host]
+ *   bilu_factor_numeric   backfill A into the ILU(k) pattern and block ILU(0)
+ *                         on it (Algorithm 5 steps 3-5, Algorithm 4)  [GPU]
+ *   bilu_factor_diag      U = D U' (Eq 5), factors laid out for the sweeps
+ *   bilu_apply            z = (L D U')^{-1} r (Eq 6, Algorithm 7)     [GPU]
+ *   bilu_spmv             y = A x (or A^T x), block CSR               [GPU]
+ *   bilu_solve            right-preconditioned BiCGSTAB / GMRES(m)    [GPU]
+ *   bilu_grad_A           dL/dA = -lambda x^T on A's block pattern    [GPU]
+ *
+ * Common conventions
+ * ------------------
+ * - Indices are int32, 0-based.  A block pattern is block-CSR: Ap[nb+1] row
+ *   starts, Aj[nnzb] block columns, strictly ascending within a block row,
+ *   the diagonal block present in every row (Section 2.1).  A stored block
+ *   is an entry of the pattern whatever its values.
+ * - Block values: nnzb * bs * bs doubles, each bs x bs block stored column
+ *   by column (Section 2.1), blocks in Aj order: element (r, c) of block e
+ *   is Ax[e*bs*bs + c*bs + r].
+ * - Vectors: device doubles, nb*bs rows by nrhs columns, row-major
+ *   (element (i, j) at v[i*nrhs + j]).
+ * - Pointers named *_dev or documented as device pointers are device memory
+ *   owned by the caller; the library reads/writes them only during the call
+ *   (stream-ordered).  Host arrays passed in are borrowed for the call and
+ *   copied.  Host views returned by bilu_get_* are owned by the context and
+ *   stay valid until bilu_destroy.
+ * - Every GPU call is enqueued on `stream` and returns without waiting,
+ *   except bilu_factor_numeric (reads back the singular-pivot flag) and
+ *   bilu_solve (returns host-side convergence information); both
+ *   synchronise `stream`.
+ * - Errors are returned, never thrown; a negative status means the call did
+ *   nothing useful, a positive one is a numerical outcome.  One context is
+ *   used by one host thread / stream at a time.
+ */
+#ifndef BILU_H
+#define BILU_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BILU_OK = 0,
+    BILU_ERR_ARG = -1,          /* bad argument (null pointer, size, block size)   */
+    BILU_ERR_ALLOC = -2,        /* host or device allocation failed                */
+    BILU_ERR_HIP = -3,          /* a HIP runtime call failed                       */
+    BILU_ERR_MISSING_DIAG = -4, /* a block row does not store its diagonal block   */
+    BILU_ERR_PATTERN = -5,      /* unsorted / duplicate / out-of-range columns     */
+    BILU_ERR_TIMEOUT = -6,      /* a sweep's bounded wait expired (results invalid)*/
+    BILU_ERR_STATE = -7,        /* call order violated (e.g. apply before factor)  */
+    BILU_SINGULAR_PIVOT = 1,    /* a pivot block is singular or not finite         */
+    BILU_NOT_CONVERGED = 2,     /* maxit reached above the tolerance               */
+    BILU_BREAKDOWN = 3,         /* BiCGSTAB rho, <r^,v> or omega became zero       */
+    BILU_NONFINITE = 4          /* NaN / Inf met in the iteration                  */
+} bilu_status;
+
+/* Sweeps of the preconditioner and of its transpose (Eq 4 levels each). */
+typedef enum {
+    BILU_SWEEP_L = 0,   /* L y = r, forward                                 */
+    BILU_SWEEP_U = 1,   /* U' x = D^{-1} y, backward                        */
+    BILU_SWEEP_UT = 2,  /* U'^T w = r, forward   (transposed application)   */
+    BILU_SWEEP_LT = 3   /* L^T s = D^{-T} w, backward                       */
+} bilu_sweep;
+
+typedef enum { BILU_FACTORS_FP64 = 0, BILU_FACTORS_FP32 = 1 } bilu_precision;
+typedef enum { BILU_BICGSTAB = 0, BILU_GMRES = 1 } bilu_method;
+
+/* bilu_analyze flags */
+#define BILU_WANT_TRANSPOSE 1   /* also build U'^T / L^T sweeps and A^T SpMV */
+
+typedef struct bilu_ctx bilu_ctx;
+
+/* Sizes of an analysed pattern (filled by bilu_get_info). */
+typedef struct {
+    int nb, bs, k;
+    int64_t nnzb_A;       /* stored blocks of A                    */
+    int64_t nnzb_P;       /* blocks of the ILU(k) pattern P        */
+    int64_t nnzb_L;       /* strictly lower blocks of P            */
+    int64_t nnzb_U;       /* strictly upper blocks of P            */
+    int nlev[4];          /* levels per sweep (0 if not built)     */
+    int rows_per_chunk;   /* block rows per wavefront in the sweeps */
+    int64_t sweep_slots[4]; /* padded block slots of each sweep layout */
+} bilu_info;
+
+typedef struct {
+    int method;      /* bilu_method                                         */
+    int restart;     /* GMRES(m) restart length (ignored by BiCGSTAB)       */
+    double rtol;     /* stop when ||b - A x||_2 <= rtol ||b||_2 (true res.) */
+    int maxit;       /* BiCGSTAB steps / total GMRES Arnoldi steps           */
+} bilu_solve_opts;
+
+typedef struct {
+    int status;      /* bilu_status of this right-hand side              */
+    int iters;       /* BiCGSTAB steps or GMRES Arnoldi steps taken        */
+    double relres;   /* true relative residual ||b - A x|| / ||b|| at exit */
+} bilu_rhs_info;
+
+/*
+ * Symbolic phase (Algorithm 5 steps 1-2: Algorithm 3 with Eq 1-2) and the
+ * level sets of Eq 4.  Host-only: needs no GPU.
+ *   nb, bs   block rows (>= 1) and block size (1..8)
+ *   Ap, Aj   host block-CSR pattern of A (borrowed, copied)
+ *   k        fill level (>= 0); entries with level <= k are kept
+ *   flags    BILU_WANT_TRANSPOSE or 0
+ *   out      receives a new context (free with bilu_destroy)
+ * Errors: BILU_ERR_ARG, BILU_ERR_PATTERN, BILU_ERR_MISSING_DIAG,
+ * BILU_ERR_ALLOC.  Device memory is allocated on first factorisation.
+ */
+bilu_status bilu_analyze(int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k,
+                         int flags, bilu_ctx** out);
+
+/* Host views of the ILU(k) pattern P (block-CSR, ascending columns) and the
+ * level of fill of each kept entry (Eq 1-2).  Owned by the context. */
+bilu_status bilu_get_pattern(const bilu_ctx* ctx, int64_t* nnzb, const int32_t** Pp,
+                             const int32_t** Pj, const int32_t** lev);
+
+/* Host views of the level sets of one sweep (Eq 4, Algorithm 6): 0-based
+ * levels, level_ptr[nlev+1], level_rows[nb] with rows ascending inside a
+ * level.  BILU_ERR_STATE if the sweep was not built. */
+bilu_status bilu_get_levels(const bilu_ctx* ctx, int sweep, int* nlev,
+                            const int32_t** level_ptr, const int32_t** level_rows);
+
+bilu_status bilu_get_info(const bilu_ctx* ctx, bilu_info* info);
+
+/* Host-only self-check of the sweep layouts: every row appears once per
+ * sweep, every index is in range, every dependency sits in a strictly
+ * earlier chunk of the schedule (the persistent sweeps rely on this to
+ * drain) and matches the pattern.  BILU_OK or BILU_ERR_STATE. */
+bilu_status bilu_validate(const bilu_ctx* ctx);
+
+/*
+ * Factorisation phase (Algorithm 5 steps 3-5, Algorithm 4) on the GPU:
+ * copies A's blocks into P (zero blocks at fill positions) and runs block
+ * ILU(0) on P, block rows scheduled by the L level sets, each pivot block
+ * inverted explicitly in FP64 (Gauss-Jordan, partial pivoting inside the
+ * block).  Ax_dev: device values of A (layout above).  Synchronises
+ * `stream`.  Returns BILU_SINGULAR_PIVOT with *bad_row (may be NULL) set to
+ * the smallest block row whose pivot block is singular or not finite.
+ */
+bilu_status bilu_factor_numeric(bilu_ctx* ctx, const double* Ax_dev, hipStream_t stream,
+                                int* bad_row);
+
+/*
+ * Diagonal factorisation U = D U' (Eq 5): D^{-1} is the block diagonal of
+ * pivot inverses, U'_ij = D_i^{-1} U_ij.  Lays L, D^{-1} and U' out for the
+ * level-scheduled sweeps, stored as FP64 or rounded (nearest-even) to FP32
+ * (precision = bilu_precision).  Must follow bilu_factor_numeric.
+ */
+bilu_status bilu_factor_diag(bilu_ctx* ctx, int precision, hipStream_t stream);
+
+/*
+ * Copies the FP64 factors in pattern order to caller device buffers:
+ * F_dev[nnzb_P*bs*bs] holds L at strictly lower positions, U' at strictly
+ * upper positions and the identity at diagonal positions; Dinv_dev[nb*bs*bs]
+ * holds D^{-1}.  Either pointer may be NULL.
+ */
+bilu_status bilu_get_factors(const bilu_ctx* ctx, double* F_dev, double* Dinv_dev,
+                             hipStream_t stream);
+
+/* Same, for the FP32 factors the sweeps read when precision was FP32. */
+bilu_status bilu_get_factors_f32(const bilu_ctx* ctx, float* F_dev, float* Dinv_dev,
+                                 hipStream_t stream);
+
+/*
+ * z = M^{-1} r with M = L D U' (Eq 6, Algorithm 7): forward L sweep, D^{-1}
+ * fused into the backward U' sweep.  r, z: device vectors (nb*bs x nrhs,
+ * nrhs >= 1); z may not alias r.  Accumulation is FP64 whatever the factor
+ * precision.  BILU_ERR_TIMEOUT if a sweep's bounded wait expired.
+ */
+bilu_status bilu_apply(bilu_ctx* ctx, const double* r, double* z, int nrhs,
+                       hipStream_t stream);
+
+/* z = M^{-T} r = L^{-T} D^{-T} U'^{-T} r (needs BILU_WANT_TRANSPOSE). */
+bilu_status bilu_apply_transpose(bilu_ctx* ctx, const double* r, double* z, int nrhs,
+                                 hipStream_t stream);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1, needs
+ * BILU_WANT_TRANSPOSE); Ax_dev as in bilu_factor_numeric; y may not alias x. */
+bilu_status bilu_spmv(bilu_ctx* ctx, const double* Ax_dev, const double* x, double* y,
+                      int nrhs, int transpose, hipStream_t stream);
+
+/*
+ * Solves A x = b (transpose = 0) or A^T x = b (transpose = 1) for nrhs
+ * independent right-hand sides with right-preconditioned BiCGSTAB or
+ * GMRES(m), x0 = 0, FP64 vectors and reductions on the GPU.  Exit test on
+ * the true residual ||b - A x||_2 <= rtol ||b||_2.  info[nrhs] (host)
+ * receives per-RHS results; the return value is the worst of them.
+ * Synchronises `stream`.
+ */
+bilu_status bilu_solve(bilu_ctx* ctx, const double* Ax_dev, const double* b, double* x,
+                       int nrhs, const bilu_solve_opts* opts, bilu_rhs_info* info,
+                       int transpose, hipStream_t stream);
+
+/* dAx_dev[e*bs*bs + c*bs + r] = -lambda[i*bs + r] * x[j*bs + c] for every
+ * stored block e = (i, j) of A: the gradient of a loss with respect to A for
+ * x = A^{-1} b, given the adjoint lambda = A^{-T} dL/dx (single RHS). */
+bilu_status bilu_grad_A(bilu_ctx* ctx, const double* lambda, const double* x, double* dAx_dev,
+                        hipStream_t stream);
+
+/* Sweep scheduling: 0 = one kernel launch per level, 1 = one persistent
+ * launch per sweep with per-row ready flags (default). */
+bilu_status bilu_set_sweep_mode(bilu_ctx* ctx, int mode);
+
+/* Synchronises `stream` and reports (then clears) a timeout recorded by any
+ * sweep since the last check: BILU_ERR_TIMEOUT, else BILU_OK. */
+bilu_status bilu_check(bilu_ctx* ctx, hipStream_t stream);
+
+void bilu_destroy(bilu_ctx* ctx);
+const char* bilu_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BILU_H */

@@ -1,0 +1,215 @@
+"""ctypes binding of libbilu.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does
+nothing but convert arguments: numpy arrays for host structure, raw device
+pointers (ints) and HIP stream handles (ints) for device data.  All
+computation happens in the library.  Importing fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libbilu.so")
+
+OK = 0
+ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_MISSING_DIAG, ERR_PATTERN, ERR_TIMEOUT, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
+SINGULAR_PIVOT, NOT_CONVERGED, BREAKDOWN, NONFINITE = 1, 2, 3, 4
+SWEEP_L, SWEEP_U, SWEEP_UT, SWEEP_LT = 0, 1, 2, 3
+FACTORS_FP64, FACTORS_FP32 = 0, 1
+BICGSTAB, GMRES = 0, 1
+WANT_TRANSPOSE = 1
+
+# every symbol declared in include/bilu.h
+EXPORTS = (
+    "bilu_analyze", "bilu_get_pattern", "bilu_get_levels", "bilu_get_info", "bilu_validate",
+    "bilu_factor_numeric", "bilu_factor_diag", "bilu_get_factors", "bilu_get_factors_f32",
+    "bilu_apply", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
+    "bilu_set_sweep_mode", "bilu_check", "bilu_destroy", "bilu_status_string",
+)
+
+
+class BiluInfo(ct.Structure):
+    _fields_ = [("nb", ct.c_int), ("bs", ct.c_int), ("k", ct.c_int),
+                ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
+                ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
+                ("sweep_slots", ct.c_int64 * 4)]
+
+
+class SolveOpts(ct.Structure):
+    _fields_ = [("method", ct.c_int), ("restart", ct.c_int), ("rtol", ct.c_double),
+                ("maxit", ct.c_int)]
+
+
+class RhsInfo(ct.Structure):
+    _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("relres", ct.c_double)]
+
+
+class BiluError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950) first")
+    L = ct.CDLL(LIB_PATH)
+    P, I, VP = ct.c_void_p, ct.c_int, ct.c_void_p
+    L.bilu_analyze.argtypes = [I, I, P, P, I, I, ct.POINTER(VP)]
+    L.bilu_get_pattern.argtypes = [VP, ct.POINTER(ct.c_int64), ct.POINTER(P), ct.POINTER(P), ct.POINTER(P)]
+    L.bilu_get_levels.argtypes = [VP, I, ct.POINTER(I), ct.POINTER(P), ct.POINTER(P)]
+    L.bilu_get_info.argtypes = [VP, ct.POINTER(BiluInfo)]
+    L.bilu_validate.argtypes = [VP]
+    L.bilu_factor_numeric.argtypes = [VP, P, P, ct.POINTER(I)]
+    L.bilu_factor_diag.argtypes = [VP, I, P]
+    L.bilu_get_factors.argtypes = [VP, P, P, P]
+    L.bilu_get_factors_f32.argtypes = [VP, P, P, P]
+    L.bilu_apply.argtypes = [VP, P, P, I, P]
+    L.bilu_apply_transpose.argtypes = [VP, P, P, I, P]
+    L.bilu_spmv.argtypes = [VP, P, P, P, I, I, P]
+    L.bilu_solve.argtypes = [VP, P, P, P, I, ct.POINTER(SolveOpts), ct.POINTER(RhsInfo), I, P]
+    L.bilu_grad_A.argtypes = [VP, P, P, P, P]
+    L.bilu_set_sweep_mode.argtypes = [VP, I]
+    L.bilu_check.argtypes = [VP, P]
+    L.bilu_destroy.argtypes = [VP]
+    L.bilu_destroy.restype = None
+    L.bilu_status_string.argtypes = [I]
+    L.bilu_status_string.restype = ct.c_char_p
+    for name in EXPORTS:
+        if name not in ("bilu_destroy", "bilu_status_string"):
+            getattr(L, name).restype = I
+    return L
+
+
+lib = _load()
+
+
+def status_string(code: int) -> str:
+    return lib.bilu_status_string(int(code)).decode()
+
+
+def _check(code, where, allow_positive=False):
+    if code < 0 or (code > 0 and not allow_positive):
+        raise BiluError(code, where)
+    return code
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def bilu_analyze(nb, bs, Ap, Aj, k, flags=0):
+    Ap, Aj = _i32(Ap), _i32(Aj)
+    h = ct.c_void_p()
+    _check(lib.bilu_analyze(int(nb), int(bs), _ptr(Ap), _ptr(Aj), int(k), int(flags), ct.byref(h)),
+           "bilu_analyze")
+    return h
+
+
+def bilu_get_pattern(ctx):
+    n = ct.c_int64()
+    Pp, Pj, lev = ct.c_void_p(), ct.c_void_p(), ct.c_void_p()
+    _check(lib.bilu_get_pattern(ctx, ct.byref(n), ct.byref(Pp), ct.byref(Pj), ct.byref(lev)),
+           "bilu_get_pattern")
+    info = bilu_get_info(ctx)
+    nb = info.nb
+
+    def view(p, count):
+        if count == 0:
+            return np.zeros(0, np.int32)
+        return np.ctypeslib.as_array(ct.cast(p, ct.POINTER(ct.c_int32)), shape=(count,)).copy()
+
+    return view(Pp, nb + 1), view(Pj, n.value), view(lev, n.value)
+
+
+def bilu_get_levels(ctx, sweep):
+    nlev = ct.c_int()
+    ptr, rows = ct.c_void_p(), ct.c_void_p()
+    _check(lib.bilu_get_levels(ctx, int(sweep), ct.byref(nlev), ct.byref(ptr), ct.byref(rows)),
+           "bilu_get_levels")
+    nb = bilu_get_info(ctx).nb
+    lp = np.ctypeslib.as_array(ct.cast(ptr, ct.POINTER(ct.c_int32)), shape=(nlev.value + 1,)).copy()
+    lr = np.ctypeslib.as_array(ct.cast(rows, ct.POINTER(ct.c_int32)), shape=(nb,)).copy()
+    return lp, lr
+
+
+def bilu_get_info(ctx):
+    info = BiluInfo()
+    _check(lib.bilu_get_info(ctx, ct.byref(info)), "bilu_get_info")
+    return info
+
+
+def bilu_validate(ctx):
+    _check(lib.bilu_validate(ctx), "bilu_validate")
+
+
+def bilu_factor_numeric(ctx, Ax_ptr, stream):
+    bad = ct.c_int(-1)
+    st = _check(lib.bilu_factor_numeric(ctx, ct.c_void_p(Ax_ptr), ct.c_void_p(stream), ct.byref(bad)),
+                "bilu_factor_numeric", allow_positive=True)
+    return st, bad.value
+
+
+def bilu_factor_diag(ctx, precision, stream):
+    _check(lib.bilu_factor_diag(ctx, int(precision), ct.c_void_p(stream)), "bilu_factor_diag")
+
+
+def bilu_get_factors(ctx, F_ptr, Dinv_ptr, stream):
+    _check(lib.bilu_get_factors(ctx, ct.c_void_p(F_ptr), ct.c_void_p(Dinv_ptr), ct.c_void_p(stream)),
+           "bilu_get_factors")
+
+
+def bilu_get_factors_f32(ctx, F_ptr, Dinv_ptr, stream):
+    _check(lib.bilu_get_factors_f32(ctx, ct.c_void_p(F_ptr), ct.c_void_p(Dinv_ptr), ct.c_void_p(stream)),
+           "bilu_get_factors_f32")
+
+
+def bilu_apply(ctx, r_ptr, z_ptr, nrhs, stream):
+    _check(lib.bilu_apply(ctx, ct.c_void_p(r_ptr), ct.c_void_p(z_ptr), int(nrhs), ct.c_void_p(stream)),
+           "bilu_apply")
+
+
+def bilu_apply_transpose(ctx, r_ptr, z_ptr, nrhs, stream):
+    _check(lib.bilu_apply_transpose(ctx, ct.c_void_p(r_ptr), ct.c_void_p(z_ptr), int(nrhs),
+                                    ct.c_void_p(stream)), "bilu_apply_transpose")
+
+
+def bilu_spmv(ctx, Ax_ptr, x_ptr, y_ptr, nrhs, transpose, stream):
+    _check(lib.bilu_spmv(ctx, ct.c_void_p(Ax_ptr), ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), int(nrhs),
+                         int(transpose), ct.c_void_p(stream)), "bilu_spmv")
+
+
+def bilu_solve(ctx, Ax_ptr, b_ptr, x_ptr, nrhs, method, restart, rtol, maxit, transpose, stream):
+    opts = SolveOpts(int(method), int(restart), float(rtol), int(maxit))
+    info = (RhsInfo * int(nrhs))()
+    st = _check(lib.bilu_solve(ctx, ct.c_void_p(Ax_ptr), ct.c_void_p(b_ptr), ct.c_void_p(x_ptr), int(nrhs),
+                               ct.byref(opts), info, int(transpose), ct.c_void_p(stream)),
+                "bilu_solve", allow_positive=True)
+    return st, [(i.status, i.iters, i.relres) for i in info]
+
+
+def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
+    _check(lib.bilu_grad_A(ctx, ct.c_void_p(lam_ptr), ct.c_void_p(x_ptr), ct.c_void_p(dA_ptr),
+                           ct.c_void_p(stream)), "bilu_grad_A")
+
+
+def bilu_set_sweep_mode(ctx, mode):
+    _check(lib.bilu_set_sweep_mode(ctx, int(mode)), "bilu_set_sweep_mode")
+
+
+def bilu_check(ctx, stream):
+    _check(lib.bilu_check(ctx, ct.c_void_p(stream)), "bilu_check")
+
+
+def bilu_destroy(ctx):
+    lib.bilu_destroy(ctx)

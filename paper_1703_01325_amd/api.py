@@ -1,0 +1,136 @@
+"""Torch-facing wrapper over the C ABI: torch tensors in, pointers out.
+
+torch provides device memory and the current HIP stream; every step of
+the preconditioner and the solvers runs in libbilu.so's kernels.  There is
+no CPU fallback: the native library must be built and a GPU present.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_f64(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t
+
+
+class BlockILU:
+    """Decoupled block ILU(k) of one block pattern (Algorithm 5, Eq 5).
+
+    ``BlockILU(nb, bs, Ap, Aj, k)`` runs the symbolic phase and the level
+    sets on the host; ``factor(Ax)`` runs the numeric phase and the diagonal
+    split on the GPU; ``apply``/``spmv``/``solve`` run the hot path.
+    """
+
+    def __init__(self, nb, bs, Ap, Aj, k, transpose=False):
+        self.nb, self.bs, self.k = int(nb), int(bs), int(k)
+        self.n = self.nb * self.bs
+        self.Ap = np.ascontiguousarray(Ap, np.int32)
+        self.Aj = np.ascontiguousarray(Aj, np.int32)
+        self._ctx = N.bilu_analyze(nb, bs, self.Ap, self.Aj, k, N.WANT_TRANSPOSE if transpose else 0)
+        self.transpose = bool(transpose)
+        self.precision = None
+
+    # ---- host views -------------------------------------------------------
+    def info(self):
+        return N.bilu_get_info(self._ctx)
+
+    def pattern(self):
+        return N.bilu_get_pattern(self._ctx)
+
+    def levels(self, sweep):
+        return N.bilu_get_levels(self._ctx, sweep)
+
+    def set_sweep_mode(self, mode):
+        N.bilu_set_sweep_mode(self._ctx, mode)
+
+    # ---- GPU --------------------------------------------------------------
+    def factor(self, Ax: torch.Tensor, precision: str = "fp64"):
+        """Numeric factorisation + U = D U'.  Returns the block row of a
+        singular pivot, or -1."""
+        _dev_f64(Ax, "Ax")
+        st, bad = N.bilu_factor_numeric(self._ctx, Ax.data_ptr(), _stream())
+        if st == N.SINGULAR_PIVOT:
+            return bad
+        prec = N.FACTORS_FP32 if precision == "fp32" else N.FACTORS_FP64
+        N.bilu_factor_diag(self._ctx, prec, _stream())
+        self.precision = precision
+        return -1
+
+    def _vec_shape(self, v):
+        if v.dim() == 1:
+            return 1
+        return v.shape[1]
+
+    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None, transpose=False):
+        _dev_f64(r, "r")
+        z = torch.empty_like(r) if out is None else out
+        fn = N.bilu_apply_transpose if transpose else N.bilu_apply
+        fn(self._ctx, r.data_ptr(), z.data_ptr(), self._vec_shape(r), _stream())
+        return z
+
+    def spmv(self, Ax: torch.Tensor, x: torch.Tensor, out=None, transpose=False):
+        _dev_f64(Ax, "Ax")
+        _dev_f64(x, "x")
+        y = torch.empty_like(x) if out is None else out
+        N.bilu_spmv(self._ctx, Ax.data_ptr(), x.data_ptr(), y.data_ptr(), self._vec_shape(x),
+                    int(transpose), _stream())
+        return y
+
+    def solve(self, Ax, b, method="bicgstab", restart=30, rtol=1e-8, maxit=2000, transpose=False,
+              out=None):
+        """x = A^{-1} b (or A^{-T} b); returns (x, status, [(status, iters, relres)] per RHS)."""
+        _dev_f64(Ax, "Ax")
+        _dev_f64(b, "b")
+        x = torch.empty_like(b) if out is None else out
+        m = N.GMRES if method == "gmres" else N.BICGSTAB
+        st, info = N.bilu_solve(self._ctx, Ax.data_ptr(), b.data_ptr(), x.data_ptr(), self._vec_shape(b),
+                                m, restart, rtol, maxit, int(transpose), _stream())
+        return x, st, info
+
+    def grad_A(self, lam, x):
+        _dev_f64(lam, "lambda")
+        _dev_f64(x, "x")
+        info = self.info()
+        dA = torch.empty(int(info.nnzb_A) * self.bs * self.bs, dtype=torch.float64, device=x.device)
+        N.bilu_grad_A(self._ctx, lam.data_ptr(), x.data_ptr(), dA.data_ptr(), _stream())
+        return dA
+
+    def factors(self):
+        """FP64 factors in pattern order (L below, U' above, I on the diagonal) and D^{-1}."""
+        info = self.info()
+        bb = self.bs * self.bs
+        F = torch.empty(int(info.nnzb_P) * bb, dtype=torch.float64, device="cuda")
+        D = torch.empty(self.nb * bb, dtype=torch.float64, device="cuda")
+        N.bilu_get_factors(self._ctx, F.data_ptr(), D.data_ptr(), _stream())
+        return F, D
+
+    def factors_f32(self):
+        info = self.info()
+        bb = self.bs * self.bs
+        F = torch.empty(int(info.nnzb_P) * bb, dtype=torch.float32, device="cuda")
+        D = torch.empty(self.nb * bb, dtype=torch.float32, device="cuda")
+        N.bilu_get_factors_f32(self._ctx, F.data_ptr(), D.data_ptr(), _stream())
+        return F, D
+
+    def check(self):
+        N.bilu_check(self._ctx, _stream())
+
+    def close(self):
+        if self._ctx is not None:
+            N.bilu_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

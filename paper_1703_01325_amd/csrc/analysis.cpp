@@ -1,0 +1,363 @@
+// Host analysis: pattern validation, symbolic ILU(k), level sets and the
+// chunked sweep layouts the GPU kernels stream.  Integer work only.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "bilu_internal.h"
+
+namespace bilu {
+
+int validate_pattern(int nb, const int32_t* Ap, const int32_t* Aj)
+{
+    if (Ap[0] != 0) return BILU_ERR_PATTERN;
+    for (int i = 0; i < nb; ++i) {
+        if (Ap[i + 1] < Ap[i]) return BILU_ERR_PATTERN;
+        bool diag = false;
+        for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+            int32_t j = Aj[e];
+            if (j < 0 || j >= nb) return BILU_ERR_PATTERN;
+            if (e > Ap[i] && j <= Aj[e - 1]) return BILU_ERR_PATTERN;
+            diag |= (j == i);
+        }
+        if (!diag) return BILU_ERR_MISSING_DIAG;
+    }
+    return BILU_OK;
+}
+
+// Symbolic ILU(k) (Algorithm 3 with the level rule of Eq 1-2) on the
+// point-wise view of the block pattern: Ap/Aj serve directly as the
+// structure of the abstract point matrix (Section 2.3).
+//
+// Row i is held as a sorted singly linked list threaded through next[]
+// (node nb is the head), with the current level of each listed column in
+// lev[].  The list is walked in column order; at every column p < i whose
+// level is <= k the strictly upper part of the finished row p (columns
+// j > p, each with its own level) is merged into the list with level
+// lev(i,p) + lev(p,j) + 1, keeping the minimum for columns already listed.
+// Candidates above k are never inserted: they could not be used as pivots
+// and, by the min rule, a later candidate <= k gives the same final level.
+int symbolic_iluk(int nb, const int32_t* Ap, const int32_t* Aj, int k, std::vector<int32_t>& Pp,
+                  std::vector<int32_t>& Pj, std::vector<int32_t>& Plev)
+{
+    constexpr int32_t kEnd = -1;
+    const int32_t head = nb;
+    std::vector<int32_t> next(static_cast<size_t>(nb) + 1, kEnd);
+    std::vector<int32_t> lev(static_cast<size_t>(nb), 0);
+    std::vector<int32_t> diag(static_cast<size_t>(nb), 0);
+    Pp.assign(1, 0);
+    Pj.clear();
+    Plev.clear();
+    Pj.reserve(static_cast<size_t>(Ap[nb]) * (k > 0 ? 2 : 1));
+    Plev.reserve(Pj.capacity());
+    for (int32_t i = 0; i < nb; ++i) {
+        int32_t tail = head;
+        for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+            next[tail] = Aj[e];
+            tail = Aj[e];
+            lev[tail] = 0;
+        }
+        next[tail] = kEnd;
+        for (int32_t p = next[head]; p != kEnd && p < i; p = next[p]) {
+            const int32_t lip = lev[p];
+            if (lip > k) continue;
+            int32_t at = p;  // list node after which the next column goes
+            for (int32_t g = diag[p] + 1; g < Pp[p + 1]; ++g) {
+                const int32_t j = Pj[g];
+                const int32_t cand = lip + Plev[g] + 1;
+                if (cand > k) continue;
+                while (next[at] != kEnd && next[at] < j) at = next[at];
+                if (next[at] == j) {
+                    if (cand < lev[j]) lev[j] = cand;
+                } else {
+                    next[j] = next[at];
+                    next[at] = j;
+                    lev[j] = cand;
+                }
+                at = j;
+            }
+        }
+        for (int32_t j = next[head]; j != kEnd; j = next[j]) {
+            if (j == i) diag[i] = static_cast<int32_t>(Pj.size());
+            Pj.push_back(j);
+            Plev.push_back(lev[j]);
+        }
+        Pp.push_back(static_cast<int32_t>(Pj.size()));
+        if (Pj.size() > static_cast<size_t>(INT32_MAX) - static_cast<size_t>(nb)) return BILU_ERR_ALLOC;
+    }
+    return BILU_OK;
+}
+
+// 0-based level of every row for one sweep (Eq 4: one more than the deepest
+// row it reads, 0 for a row that reads none).  Returns the level count.
+int sweep_levels(int nb, const std::vector<int32_t>& Pp, const std::vector<int32_t>& Pj, int which,
+                 std::vector<int32_t>& lvl)
+{
+    lvl.assign(static_cast<size_t>(nb), 0);
+    switch (which) {
+    case BILU_SWEEP_L:   // row i reads y_j, j < i
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = Pp[i]; e < Pp[i + 1] && Pj[e] < i; ++e)
+                lvl[i] = std::max(lvl[i], lvl[Pj[e]] + 1);
+        break;
+    case BILU_SWEEP_U:   // row i reads x_j, j > i
+        for (int32_t i = nb - 1; i >= 0; --i)
+            for (int32_t e = Pp[i + 1] - 1; e >= Pp[i] && Pj[e] > i; --e)
+                lvl[i] = std::max(lvl[i], lvl[Pj[e]] + 1);
+        break;
+    case BILU_SWEEP_UT:  // row j of U'^T reads w_i for (i, j) in P, i < j
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = Pp[i + 1] - 1; e >= Pp[i] && Pj[e] > i; --e)
+                lvl[Pj[e]] = std::max(lvl[Pj[e]], lvl[i] + 1);
+        break;
+    case BILU_SWEEP_LT:  // row p of L^T reads s_i for (i, p) in P, i > p
+        for (int32_t i = nb - 1; i >= 0; --i)
+            for (int32_t e = Pp[i]; e < Pp[i + 1] && Pj[e] < i; ++e)
+                lvl[Pj[e]] = std::max(lvl[Pj[e]], lvl[i] + 1);
+        break;
+    default:
+        return -1;
+    }
+    int nlev = 0;
+    for (int32_t v : lvl) nlev = std::max(nlev, v + 1);
+    return nlev;
+}
+
+namespace {
+
+struct Dep {
+    int32_t col;
+    int64_t src;
+};
+
+// Dependencies of every row of a sweep, in ascending column order.
+void sweep_deps(const Host& h, int which, std::vector<int32_t>& ptr, std::vector<Dep>& deps)
+{
+    const int nb = h.nb;
+    ptr.assign(static_cast<size_t>(nb) + 1, 0);
+    auto lower = [&](int32_t i, int32_t e) { return h.Pj[e] < i; };
+    auto upper = [&](int32_t i, int32_t e) { return h.Pj[e] > i; };
+    if (which == BILU_SWEEP_L || which == BILU_SWEEP_U) {
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e)
+                if (which == BILU_SWEEP_L ? lower(i, e) : upper(i, e)) ptr[i + 1]++;
+        for (int i = 0; i < nb; ++i) ptr[i + 1] += ptr[i];
+        deps.resize(static_cast<size_t>(ptr[nb]));
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e)
+                if (which == BILU_SWEEP_L ? lower(i, e) : upper(i, e))
+                    deps[fill[i]++] = Dep{h.Pj[e], e};
+    } else {
+        // transposed sweeps: entry (i, j) of P feeds row j, reading row i
+        const bool ut = (which == BILU_SWEEP_UT);
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e)
+                if (ut ? upper(i, e) : lower(i, e)) ptr[h.Pj[e] + 1]++;
+        for (int i = 0; i < nb; ++i) ptr[i + 1] += ptr[i];
+        deps.resize(static_cast<size_t>(ptr[nb]));
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t i = 0; i < nb; ++i)        // ascending i => ascending columns
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e)
+                if (ut ? upper(i, e) : lower(i, e)) deps[fill[h.Pj[e]]++] = Dep{i, e};
+    }
+}
+
+}  // namespace
+
+// Level sets plus the chunked layout of one sweep.  Inside a level the rows
+// are independent, so the chunks may order them freely: rows are sorted by
+// decreasing dependency count (ties by row id) to keep the per-chunk
+// padding small; the canonical level_rows stay in ascending order.
+void build_sweep(const Host& h, int which, int rpc, HostSweep& s)
+{
+    const int nb = h.nb;
+    std::vector<int32_t> lvl;
+    s.which = which;
+    s.rpc = rpc;
+    s.transposed_blocks = (which == BILU_SWEEP_UT || which == BILU_SWEEP_LT);
+    s.nlev = sweep_levels(nb, h.Pp, h.Pj, which, lvl);
+    s.level_ptr.assign(static_cast<size_t>(s.nlev) + 1, 0);
+    for (int32_t i = 0; i < nb; ++i) s.level_ptr[lvl[i] + 1]++;
+    for (int l = 0; l < s.nlev; ++l) s.level_ptr[l + 1] += s.level_ptr[l];
+    s.level_rows.resize(static_cast<size_t>(nb));
+    {
+        std::vector<int32_t> fill(s.level_ptr.begin(), s.level_ptr.end() - 1);
+        for (int32_t i = 0; i < nb; ++i) s.level_rows[fill[lvl[i]]++] = i;
+    }
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, which, dptr, deps);
+
+    s.level_chunk_ptr.assign(static_cast<size_t>(s.nlev) + 1, 0);
+    s.chunk_off.assign(1, 0);
+    s.rows.clear();
+    s.cols.clear();
+    s.src.clear();
+    std::vector<int32_t> order;
+    for (int l = 0; l < s.nlev; ++l) {
+        order.assign(s.level_rows.begin() + s.level_ptr[l], s.level_rows.begin() + s.level_ptr[l + 1]);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return (dptr[a + 1] - dptr[a]) > (dptr[b + 1] - dptr[b]);
+        });
+        s.level_chunk_ptr[l] = static_cast<int32_t>(s.chunk_off.size() - 1);
+        for (size_t c0 = 0; c0 < order.size(); c0 += rpc) {
+            const size_t cn = std::min(order.size() - c0, static_cast<size_t>(rpc));
+            const int32_t w = dptr[order[c0] + 1] - dptr[order[c0]];
+            const int64_t base = s.chunk_off.back();
+            s.chunk_off.push_back(base + static_cast<int64_t>(w) * rpc);
+            s.cols.resize(static_cast<size_t>(base) + static_cast<size_t>(w) * rpc, -1);
+            s.src.resize(s.cols.size(), -1);
+            for (int q = 0; q < rpc; ++q) {
+                if (static_cast<size_t>(q) >= cn) {
+                    s.rows.push_back(-1);
+                    continue;
+                }
+                const int32_t r = order[c0 + q];
+                s.rows.push_back(r);
+                for (int32_t d = dptr[r]; d < dptr[r + 1]; ++d) {
+                    const size_t slot = static_cast<size_t>(base) + static_cast<size_t>(d - dptr[r]) * rpc + q;
+                    s.cols[slot] = deps[d].col;
+                    s.src[slot] = deps[d].src;
+                }
+            }
+        }
+    }
+    s.nchunks = static_cast<int>(s.chunk_off.size() - 1);
+    s.level_chunk_ptr[s.nlev] = s.nchunks;
+    s.nslots = s.chunk_off.back();
+    s.built = true;
+}
+
+int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags)
+{
+    if (nb < 1 || bs < 1 || bs > kMaxBs || k < 0 || !Ap || !Aj) return BILU_ERR_ARG;
+    int st = validate_pattern(nb, Ap, Aj);
+    if (st != BILU_OK) return st;
+    h.nb = nb;
+    h.bs = bs;
+    h.k = k;
+    h.flags = flags;
+    h.rpc = kWave / bs;
+    h.Ap.assign(Ap, Ap + nb + 1);
+    h.Aj.assign(Aj, Aj + Ap[nb]);
+    h.Arow.resize(h.Aj.size());
+    for (int32_t i = 0; i < nb; ++i)
+        for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) h.Arow[e] = i;
+
+    st = symbolic_iluk(nb, Ap, Aj, k, h.Pp, h.Pj, h.Plev);
+    if (st != BILU_OK) return st;
+    const size_t nP = h.Pj.size();
+    h.Pdiag.resize(static_cast<size_t>(nb));
+    h.Prow.resize(nP);
+    for (int32_t i = 0; i < nb; ++i)
+        for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e) {
+            h.Prow[e] = i;
+            if (h.Pj[e] == i) h.Pdiag[i] = e;
+        }
+    // A's blocks inside P (Algorithm 5, backfill): both rows are sorted.
+    h.AtoP.resize(h.Aj.size());
+    std::vector<char> inA(nP, 0);
+    for (int32_t i = 0; i < nb; ++i) {
+        int32_t f = h.Pp[i];
+        for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+            while (h.Pj[f] < Aj[e]) ++f;
+            h.AtoP[e] = f;
+            inA[f] = 1;
+        }
+    }
+    h.Pfill.clear();
+    for (size_t e = 0; e < nP; ++e)
+        if (!inA[e]) h.Pfill.push_back(static_cast<int32_t>(e));
+
+    build_sweep(h, BILU_SWEEP_L, h.rpc, h.sweep[BILU_SWEEP_L]);
+    build_sweep(h, BILU_SWEEP_U, h.rpc, h.sweep[BILU_SWEEP_U]);
+    if (flags & BILU_WANT_TRANSPOSE) {
+        build_sweep(h, BILU_SWEEP_UT, h.rpc, h.sweep[BILU_SWEEP_UT]);
+        build_sweep(h, BILU_SWEEP_LT, h.rpc, h.sweep[BILU_SWEEP_LT]);
+        h.ATp.assign(static_cast<size_t>(nb) + 1, 0);
+        for (int32_t j : h.Aj) h.ATp[j + 1]++;
+        for (int i = 0; i < nb; ++i) h.ATp[i + 1] += h.ATp[i];
+        h.ATj.resize(h.Aj.size());
+        h.ATsrc.resize(h.Aj.size());
+        std::vector<int32_t> fill(h.ATp.begin(), h.ATp.end() - 1);
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+                const int32_t j = Aj[e];
+                h.ATj[fill[j]] = i;
+                h.ATsrc[fill[j]++] = e;
+            }
+    }
+    return BILU_OK;
+}
+
+int validate_layout(const Host& h)
+{
+    const int nb = h.nb;
+    const int64_t nP = static_cast<int64_t>(h.Pj.size());
+    for (int w = 0; w < 4; ++w) {
+        const HostSweep& s = h.sweep[w];
+        if (!s.built) continue;
+        const int rpc = s.rpc;
+        if (rpc < 1 || rpc * h.bs > kWave) return BILU_ERR_STATE;
+        if (static_cast<int>(s.chunk_off.size()) != s.nchunks + 1 || s.chunk_off[0] != 0) return BILU_ERR_STATE;
+        if (static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc) return BILU_ERR_STATE;
+        if (s.chunk_off.back() != s.nslots || static_cast<int64_t>(s.cols.size()) != s.nslots ||
+            static_cast<int64_t>(s.src.size()) != s.nslots)
+            return BILU_ERR_STATE;
+        if (static_cast<int>(s.level_chunk_ptr.size()) != s.nlev + 1 || s.level_chunk_ptr[0] != 0 ||
+            s.level_chunk_ptr[s.nlev] != s.nchunks)
+            return BILU_ERR_STATE;
+        for (int l = 0; l < s.nlev; ++l)
+            if (s.level_chunk_ptr[l + 1] < s.level_chunk_ptr[l]) return BILU_ERR_STATE;
+        std::vector<int32_t> chunk_of(static_cast<size_t>(nb), -1);
+        for (int c = 0; c < s.nchunks; ++c) {
+            const int64_t span = s.chunk_off[c + 1] - s.chunk_off[c];
+            if (span < 0 || span % rpc != 0) return BILU_ERR_STATE;
+            for (int q = 0; q < rpc; ++q) {
+                const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
+                if (r < -1 || r >= nb) return BILU_ERR_STATE;
+                if (r >= 0) {
+                    if (chunk_of[r] != -1) return BILU_ERR_STATE;
+                    chunk_of[r] = c;
+                }
+            }
+        }
+        for (int i = 0; i < nb; ++i)
+            if (chunk_of[i] < 0) return BILU_ERR_STATE;
+        // dependency count per row straight from the pattern
+        std::vector<int32_t> ndep(static_cast<size_t>(nb), 0);
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e) {
+                const int32_t j = h.Pj[e];
+                if (w == BILU_SWEEP_L && j < i) ndep[i]++;
+                if (w == BILU_SWEEP_U && j > i) ndep[i]++;
+                if (w == BILU_SWEEP_UT && j > i) ndep[j]++;
+                if (w == BILU_SWEEP_LT && j < i) ndep[j]++;
+            }
+        for (int c = 0; c < s.nchunks; ++c) {
+            const int64_t off = s.chunk_off[c];
+            const int64_t width = (s.chunk_off[c + 1] - off) / rpc;
+            for (int q = 0; q < rpc; ++q) {
+                const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
+                int32_t seen = 0;
+                for (int64_t k = 0; k < width; ++k) {
+                    const int64_t slot = off + k * rpc + q;
+                    const int32_t j = s.cols[slot];
+                    const int64_t e = s.src[slot];
+                    if (j == -1 && e == -1) continue;
+                    if (r < 0 || j < 0 || j >= nb || e < 0 || e >= nP) return BILU_ERR_STATE;
+                    if (chunk_of[j] >= c) return BILU_ERR_STATE;        // must be strictly earlier
+                    const bool rowwise = (w == BILU_SWEEP_L || w == BILU_SWEEP_U);
+                    const int32_t pi = h.Prow[e], pj = h.Pj[e];
+                    if (rowwise ? (pi != r || pj != j) : (pi != j || pj != r)) return BILU_ERR_STATE;
+                    ++seen;
+                }
+                if (r >= 0 && seen != ndep[r]) return BILU_ERR_STATE;
+            }
+        }
+    }
+    return BILU_OK;
+}
+
+}  // namespace bilu

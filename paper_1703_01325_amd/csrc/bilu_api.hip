@@ -1,0 +1,783 @@
+// C ABI of the block ILU(k) library: context, device storage, launches and
+// the Krylov drivers.  See include/bilu.h for the contract of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "bilu.h"
+#include "bilu_internal.h"
+#include "kernels.h"
+
+using namespace bilu;
+using dev::KState;
+using dev::SweepArgs;
+
+#define CK(call)                                   \
+    do {                                           \
+        if ((call) != hipSuccess) return BILU_ERR_HIP; \
+    } while (0)
+
+struct bilu_ctx {
+    Host h;
+    int device = -1;
+    int num_cu = 0;
+    bool dev_ready = false;
+    bool factored = false;
+    bool laid_out = false;
+    int precision = BILU_FACTORS_FP64;
+    int sweep_mode = 1;
+    unsigned int spin_limit = 1u << 24;
+
+    int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
+    int32_t *d_Pp = nullptr, *d_Pj = nullptr, *d_Prow = nullptr, *d_Pdiag = nullptr, *d_PtoA = nullptr;
+    int32_t *d_Lrows = nullptr;
+    int32_t *d_ATp = nullptr, *d_ATj = nullptr;
+    int64_t *d_ATsrc = nullptr;
+    double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
+    DevSweep ds[4];
+    int persist_blocks[4] = {0, 0, 0, 0};
+
+    double* d_y = nullptr;
+    size_t y_cap = 0;
+    int* d_bad = nullptr;
+    int* d_status = nullptr;
+    unsigned int* d_done = nullptr;
+    unsigned long long* d_ticket = nullptr;
+
+    double* d_kv = nullptr;
+    size_t kv_cap = 0;
+    double* d_part = nullptr;
+    KState* d_state = nullptr;
+
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T>
+bilu_status dalloc(bilu_ctx* c, T** p, size_t count)
+{
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return BILU_ERR_ALLOC;
+    c->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return BILU_OK;
+}
+
+void dfree(bilu_ctx* c, void* p)
+{
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) {
+        (void)hipFree(p);
+        c->allocs.erase(it);
+    }
+}
+
+template <typename T>
+bilu_status upload(bilu_ctx* c, T** d, const std::vector<T>& h)
+{
+    bilu_status st = dalloc(c, d, h.size());
+    if (st != BILU_OK) return st;
+    if (!h.empty() && hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return BILU_ERR_HIP;
+    return BILU_OK;
+}
+
+int grid_for(int64_t work, int threads = 256, int cap = 65536)
+{
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+// ----- templated launch helpers ---------------------------------------------
+template <int B, typename T, int RT>
+void launch_sweep_t(int blocks, hipStream_t s, const SweepArgs& a)
+{
+    hipLaunchKernelGGL((dev::k_sweep<B, T, RT>), dim3(blocks), dim3(dev::kThreads), 0, s, a);
+}
+
+template <typename T, int RT>
+bool launch_sweep_b(int bs, int blocks, hipStream_t s, const SweepArgs& a)
+{
+    switch (bs) {
+    case 1: launch_sweep_t<1, T, RT>(blocks, s, a); return true;
+    case 2: launch_sweep_t<2, T, RT>(blocks, s, a); return true;
+    case 3: launch_sweep_t<3, T, RT>(blocks, s, a); return true;
+    case 4: launch_sweep_t<4, T, RT>(blocks, s, a); return true;
+    case 5: launch_sweep_t<5, T, RT>(blocks, s, a); return true;
+    case 6: launch_sweep_t<6, T, RT>(blocks, s, a); return true;
+    case 7: launch_sweep_t<7, T, RT>(blocks, s, a); return true;
+    case 8: launch_sweep_t<8, T, RT>(blocks, s, a); return true;
+    }
+    return false;
+}
+
+bool launch_sweep(int bs, int prec, int R, int blocks, hipStream_t s, const SweepArgs& a)
+{
+    if (prec == BILU_FACTORS_FP32)
+        return R == 1 ? launch_sweep_b<float, 1>(bs, blocks, s, a) : launch_sweep_b<float, 8>(bs, blocks, s, a);
+    return R == 1 ? launch_sweep_b<double, 1>(bs, blocks, s, a) : launch_sweep_b<double, 8>(bs, blocks, s, a);
+}
+
+template <int B, int RT, bool TR>
+void launch_spmv_t(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
+                   const double* x, double* y, int R, hipStream_t s)
+{
+    constexpr int RPC = 64 / B;
+    const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
+    const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+    hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src,
+                       Ax, x, y, R);
+}
+
+template <int RT, bool TR>
+bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src,
+                   const double* Ax, const double* x, double* y, int R, hipStream_t s)
+{
+    switch (bs) {
+    case 1: launch_spmv_t<1, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 2: launch_spmv_t<2, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 3: launch_spmv_t<3, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 4: launch_spmv_t<4, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 5: launch_spmv_t<5, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 6: launch_spmv_t<6, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 7: launch_spmv_t<7, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 8: launch_spmv_t<8, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    }
+    return false;
+}
+
+template <int B>
+void launch_factor_t(const int32_t* rows, int nrows, bilu_ctx* c, hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows, c->d_Pp, c->d_Pj,
+                       c->d_Pdiag, c->d_P, c->d_Dinv, c->d_bad);
+}
+
+bool launch_factor(int bs, const int32_t* rows, int nrows, bilu_ctx* c, hipStream_t s)
+{
+    switch (bs) {
+    case 1: launch_factor_t<1>(rows, nrows, c, s); return true;
+    case 2: launch_factor_t<2>(rows, nrows, c, s); return true;
+    case 3: launch_factor_t<3>(rows, nrows, c, s); return true;
+    case 4: launch_factor_t<4>(rows, nrows, c, s); return true;
+    case 5: launch_factor_t<5>(rows, nrows, c, s); return true;
+    case 6: launch_factor_t<6>(rows, nrows, c, s); return true;
+    case 7: launch_factor_t<7>(rows, nrows, c, s); return true;
+    case 8: launch_factor_t<8>(rows, nrows, c, s); return true;
+    }
+    return false;
+}
+
+template <int B>
+void launch_split_t(bilu_ctx* c, hipStream_t s)
+{
+    const int64_t nP = static_cast<int64_t>(c->h.Pj.size());
+    hipLaunchKernelGGL((dev::k_split<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP, c->d_Prow, c->d_Pj,
+                       c->d_P, c->d_Dinv, c->d_F);
+}
+
+bool launch_split(bilu_ctx* c, hipStream_t s)
+{
+    switch (c->h.bs) {
+    case 1: launch_split_t<1>(c, s); return true;
+    case 2: launch_split_t<2>(c, s); return true;
+    case 3: launch_split_t<3>(c, s); return true;
+    case 4: launch_split_t<4>(c, s); return true;
+    case 5: launch_split_t<5>(c, s); return true;
+    case 6: launch_split_t<6>(c, s); return true;
+    case 7: launch_split_t<7>(c, s); return true;
+    case 8: launch_split_t<8>(c, s); return true;
+    }
+    return false;
+}
+
+// ----- device setup --------------------------------------------------------
+bilu_status ensure_device(bilu_ctx* c)
+{
+    if (c->dev_ready) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != c->device) return BILU_ERR_STATE;
+        return BILU_OK;
+    }
+    CK(hipGetDevice(&c->device));
+    hipDeviceProp_t prop;
+    CK(hipGetDeviceProperties(&prop, c->device));
+    c->num_cu = prop.multiProcessorCount;
+    Host& h = c->h;
+    bilu_status st;
+    const size_t bb = static_cast<size_t>(h.bs) * h.bs;
+    if ((st = upload(c, &c->d_Ap, h.Ap)) || (st = upload(c, &c->d_Aj, h.Aj)) ||
+        (st = upload(c, &c->d_Arow, h.Arow)) || (st = upload(c, &c->d_Pp, h.Pp)) ||
+        (st = upload(c, &c->d_Pj, h.Pj)) || (st = upload(c, &c->d_Prow, h.Prow)) ||
+        (st = upload(c, &c->d_Pdiag, h.Pdiag)) ||
+        (st = upload(c, &c->d_Lrows, h.sweep[BILU_SWEEP_L].level_rows)))
+        return st;
+    {
+        std::vector<int32_t> PtoA(h.Pj.size(), -1);
+        for (size_t e = 0; e < h.AtoP.size(); ++e) PtoA[h.AtoP[e]] = static_cast<int32_t>(e);
+        if ((st = upload(c, &c->d_PtoA, PtoA))) return st;
+    }
+    if (h.flags & BILU_WANT_TRANSPOSE) {
+        if ((st = upload(c, &c->d_ATp, h.ATp)) || (st = upload(c, &c->d_ATj, h.ATj)) ||
+            (st = upload(c, &c->d_ATsrc, h.ATsrc)))
+            return st;
+    }
+    if ((st = dalloc(c, &c->d_P, h.Pj.size() * bb)) || (st = dalloc(c, &c->d_F, h.Pj.size() * bb)) ||
+        (st = dalloc(c, &c->d_Dinv, static_cast<size_t>(h.nb) * bb)) || (st = dalloc(c, &c->d_bad, 1)) ||
+        (st = dalloc(c, &c->d_status, 1)) || (st = dalloc(c, &c->d_done, 1)) ||
+        (st = dalloc(c, &c->d_ticket, 1)))
+        return st;
+    CK(hipMemset(c->d_status, 0, sizeof(int)));
+    CK(hipMemset(c->d_done, 0, sizeof(unsigned int)));
+    CK(hipMemset(c->d_ticket, 0, sizeof(unsigned long long)));
+    for (int w = 0; w < 4; ++w) {
+        HostSweep& hs = h.sweep[w];
+        if (!hs.built) continue;
+        DevSweep& d = c->ds[w];
+        if ((st = upload(c, &d.chunk_off, hs.chunk_off)) || (st = upload(c, &d.rows, hs.rows)) ||
+            (st = upload(c, &d.cols, hs.cols)) || (st = upload(c, &d.src, hs.src)) ||
+            (st = dalloc(c, &d.flags, static_cast<size_t>(h.nb))))
+            return st;
+        CK(hipMemset(d.flags, 0, static_cast<size_t>(h.nb) * sizeof(int32_t)));
+        d.epoch = 0;
+        // persistent grid: enough wavefronts to fill the device, never more than chunks
+        int occ = 0;
+        void* fn = h.bs == 3 ? reinterpret_cast<void*>(dev::k_sweep<3, double, 1>)
+                             : reinterpret_cast<void*>(dev::k_sweep<4, double, 1>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, dev::kThreads, 0) != hipSuccess || occ < 1)
+            occ = 2;
+        occ = std::min(occ, 8);
+        const int64_t want = (static_cast<int64_t>(hs.nchunks) + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
+        c->persist_blocks[w] = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, static_cast<int64_t>(c->num_cu) * occ)));
+    }
+    c->dev_ready = true;
+    return BILU_OK;
+}
+
+bilu_status ensure_y(bilu_ctx* c, int R)
+{
+    const size_t need = static_cast<size_t>(c->h.nb) * c->h.bs * R;
+    if (c->y_cap >= need) return BILU_OK;
+    dfree(c, c->d_y);
+    c->d_y = nullptr;
+    c->y_cap = 0;
+    bilu_status st = dalloc(c, &c->d_y, need);
+    if (st) return st;
+    c->y_cap = need;
+    return BILU_OK;
+}
+
+bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, int R, int fuse, hipStream_t s)
+{
+    HostSweep& hs = c->h.sweep[which];
+    DevSweep& d = c->ds[which];
+    SweepArgs a{};
+    a.chunk_off = d.chunk_off;
+    a.rows = d.rows;
+    a.cols = d.cols;
+    a.vals = d.vals;
+    a.dinv = d.dinv;
+    a.rhs = rhs;
+    a.out = out;
+    a.flags = d.flags;
+    a.ticket = c->d_ticket;
+    a.done = c->d_done;
+    a.status = c->d_status;
+    a.nchunks = hs.nchunks;
+    a.R = R;
+    a.fuse = fuse;
+    a.spin_limit = c->spin_limit;
+    if (hs.nchunks == 0) return BILU_OK;
+    if (c->sweep_mode == 1) {
+        if (d.epoch >= INT_MAX - 1) {
+            hipLaunchKernelGGL(dev::k_fill_i32, dim3(grid_for(c->h.nb)), dim3(256), 0, s,
+                               static_cast<int64_t>(c->h.nb), d.flags, 0);
+            d.epoch = 0;
+        }
+        a.epoch = ++d.epoch;
+        a.persistent = 1;
+        const int blocks = c->persist_blocks[which];
+        a.total_waves = static_cast<unsigned int>(blocks) * dev::kWavesPerBlock;
+        if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
+    } else {
+        a.persistent = 0;
+        for (int l = 0; l < hs.nlev; ++l) {
+            a.chunk_begin = hs.level_chunk_ptr[l];
+            a.chunk_end = hs.level_chunk_ptr[l + 1];
+            const int n = a.chunk_end - a.chunk_begin;
+            if (n <= 0) continue;
+            const int blocks = (n + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
+            if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
+        }
+    }
+    CK(hipGetLastError());
+    return BILU_OK;
+}
+
+bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transpose, hipStream_t s)
+{
+    if (!c || !r || !z || R < 1 || R > dev::kMaxRhs || r == z) return BILU_ERR_ARG;
+    if (!c->laid_out) return BILU_ERR_STATE;
+    const int first = transpose ? BILU_SWEEP_UT : BILU_SWEEP_L;
+    const int second = transpose ? BILU_SWEEP_LT : BILU_SWEEP_U;
+    if (!c->h.sweep[first].built || !c->h.sweep[second].built) return BILU_ERR_STATE;
+    bilu_status st = ensure_y(c, R);
+    if (st) return st;
+    if ((st = run_sweep(c, first, r, c->d_y, R, 0, s))) return st;
+    return run_sweep(c, second, c->d_y, z, R, 1, s);
+}
+
+bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, int R, int transpose,
+                    hipStream_t s)
+{
+    if (!c || !Ax || !x || !y || R < 1 || R > dev::kMaxRhs || x == y) return BILU_ERR_ARG;
+    bilu_status st = ensure_device(c);
+    if (st) return st;
+    const Host& h = c->h;
+    bool ok;
+    if (transpose) {
+        if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
+        ok = R == 1 ? launch_spmv_b<1, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s)
+                    : launch_spmv_b<8, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s);
+    } else {
+        ok = R == 1 ? launch_spmv_b<1, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s)
+                    : launch_spmv_b<8, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s);
+    }
+    if (!ok) return BILU_ERR_ARG;
+    CK(hipGetLastError());
+    return BILU_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI
+// ===========================================================================
+extern "C" {
+
+bilu_status bilu_analyze(int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags,
+                         bilu_ctx** out)
+{
+    if (!out) return BILU_ERR_ARG;
+    *out = nullptr;
+    bilu_ctx* c = new (std::nothrow) bilu_ctx();
+    if (!c) return BILU_ERR_ALLOC;
+    int st;
+    try {
+        st = analyze_host(c->h, nb, bs, Ap, Aj, k, flags);
+    } catch (const std::bad_alloc&) {
+        st = BILU_ERR_ALLOC;
+    }
+    if (st != BILU_OK) {
+        delete c;
+        return static_cast<bilu_status>(st);
+    }
+    *out = c;
+    return BILU_OK;
+}
+
+bilu_status bilu_get_pattern(const bilu_ctx* c, int64_t* nnzb, const int32_t** Pp, const int32_t** Pj,
+                             const int32_t** lev)
+{
+    if (!c) return BILU_ERR_ARG;
+    if (nnzb) *nnzb = static_cast<int64_t>(c->h.Pj.size());
+    if (Pp) *Pp = c->h.Pp.data();
+    if (Pj) *Pj = c->h.Pj.data();
+    if (lev) *lev = c->h.Plev.data();
+    return BILU_OK;
+}
+
+bilu_status bilu_get_levels(const bilu_ctx* c, int sweep, int* nlev, const int32_t** level_ptr,
+                            const int32_t** level_rows)
+{
+    if (!c || sweep < 0 || sweep > 3) return BILU_ERR_ARG;
+    const HostSweep& hs = c->h.sweep[sweep];
+    if (!hs.built) return BILU_ERR_STATE;
+    if (nlev) *nlev = hs.nlev;
+    if (level_ptr) *level_ptr = hs.level_ptr.data();
+    if (level_rows) *level_rows = hs.level_rows.data();
+    return BILU_OK;
+}
+
+bilu_status bilu_get_info(const bilu_ctx* c, bilu_info* info)
+{
+    if (!c || !info) return BILU_ERR_ARG;
+    const Host& h = c->h;
+    std::memset(info, 0, sizeof(*info));
+    info->nb = h.nb;
+    info->bs = h.bs;
+    info->k = h.k;
+    info->nnzb_A = static_cast<int64_t>(h.Aj.size());
+    info->nnzb_P = static_cast<int64_t>(h.Pj.size());
+    for (int i = 0; i < h.nb; ++i)
+        for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e) {
+            if (h.Pj[e] < i) info->nnzb_L++;
+            if (h.Pj[e] > i) info->nnzb_U++;
+        }
+    info->rows_per_chunk = h.rpc;
+    for (int w = 0; w < 4; ++w) {
+        info->nlev[w] = h.sweep[w].built ? h.sweep[w].nlev : 0;
+        info->sweep_slots[w] = h.sweep[w].built ? h.sweep[w].nslots : 0;
+    }
+    return BILU_OK;
+}
+
+bilu_status bilu_validate(const bilu_ctx* c)
+{
+    if (!c) return BILU_ERR_ARG;
+    return static_cast<bilu_status>(validate_layout(c->h));
+}
+
+bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, int* bad_row)
+{
+    if (bad_row) *bad_row = -1;
+    if (!c || !Ax) return BILU_ERR_ARG;
+    bilu_status st = ensure_device(c);
+    if (st) return st;
+    Host& h = c->h;
+    const int bb = h.bs * h.bs;
+    const int64_t nP = static_cast<int64_t>(h.Pj.size());
+    c->factored = false;
+    c->laid_out = false;
+    hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax, c->d_P);
+    hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(1), c->d_bad, INT_MAX);
+    const HostSweep& L = h.sweep[BILU_SWEEP_L];
+    for (int l = 0; l < L.nlev; ++l) {
+        const int n = L.level_ptr[l + 1] - L.level_ptr[l];
+        if (!launch_factor(h.bs, c->d_Lrows + L.level_ptr[l], n, c, s)) return BILU_ERR_ARG;
+    }
+    CK(hipGetLastError());
+    int bad = INT_MAX;
+    CK(hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    c->factored = true;
+    if (bad != INT_MAX) {
+        if (bad_row) *bad_row = bad;
+        return BILU_SINGULAR_PIVOT;
+    }
+    return BILU_OK;
+}
+
+bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
+{
+    if (!c || (precision != BILU_FACTORS_FP64 && precision != BILU_FACTORS_FP32)) return BILU_ERR_ARG;
+    if (!c->factored) return BILU_ERR_STATE;
+    Host& h = c->h;
+    const int bb = h.bs * h.bs;
+    if (!launch_split(c, s)) return BILU_ERR_ARG;
+    const size_t esz = precision == BILU_FACTORS_FP32 ? sizeof(float) : sizeof(double);
+    for (int w = 0; w < 4; ++w) {
+        HostSweep& hs = h.sweep[w];
+        if (!hs.built) continue;
+        DevSweep& d = c->ds[w];
+        if (c->precision != precision || !d.vals) {
+            dfree(c, d.vals);
+            dfree(c, d.dinv);
+            d.vals = d.dinv = nullptr;
+            char* p = nullptr;
+            bilu_status st = dalloc(c, &p, static_cast<size_t>(hs.nslots) * bb * esz);
+            if (st) return st;
+            d.vals = p;
+            if (w == BILU_SWEEP_U || w == BILU_SWEEP_LT) {
+                st = dalloc(c, &p, static_cast<size_t>(hs.nchunks) * hs.rpc * bb * esz);
+                if (st) return st;
+                d.dinv = p;
+            }
+        }
+        const int tr = hs.transposed_blocks ? 1 : 0;
+        const int64_t nrs = static_cast<int64_t>(hs.nchunks) * hs.rpc;
+        if (precision == BILU_FACTORS_FP32) {
+            hipLaunchKernelGGL(dev::k_layout<float>, dim3(grid_for(hs.nslots * bb)), dim3(256), 0, s, hs.nslots,
+                               h.bs, hs.rpc, d.src, c->d_F, tr, static_cast<float*>(d.vals));
+            if (d.dinv)
+                hipLaunchKernelGGL(dev::k_layout_dinv<float>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
+                                   hs.rpc, d.rows, c->d_Dinv, tr, static_cast<float*>(d.dinv));
+        } else {
+            hipLaunchKernelGGL(dev::k_layout<double>, dim3(grid_for(hs.nslots * bb)), dim3(256), 0, s, hs.nslots,
+                               h.bs, hs.rpc, d.src, c->d_F, tr, static_cast<double*>(d.vals));
+            if (d.dinv)
+                hipLaunchKernelGGL(dev::k_layout_dinv<double>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
+                                   hs.rpc, d.rows, c->d_Dinv, tr, static_cast<double*>(d.dinv));
+        }
+    }
+    CK(hipGetLastError());
+    c->precision = precision;
+    c->laid_out = true;
+    return BILU_OK;
+}
+
+bilu_status bilu_get_factors(const bilu_ctx* c, double* F, double* Dinv, hipStream_t s)
+{
+    if (!c) return BILU_ERR_ARG;
+    if (!c->laid_out) return BILU_ERR_STATE;
+    const size_t bb = static_cast<size_t>(c->h.bs) * c->h.bs;
+    if (F) CK(hipMemcpyAsync(F, c->d_F, c->h.Pj.size() * bb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (Dinv) CK(hipMemcpyAsync(Dinv, c->d_Dinv, static_cast<size_t>(c->h.nb) * bb * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+    return BILU_OK;
+}
+
+bilu_status bilu_get_factors_f32(const bilu_ctx* c, float* F, float* Dinv, hipStream_t s)
+{
+    if (!c) return BILU_ERR_ARG;
+    if (!c->laid_out || c->precision != BILU_FACTORS_FP32) return BILU_ERR_STATE;
+    const Host& h = c->h;
+    const int bb = h.bs * h.bs;
+    if (F) {
+        for (int w : {BILU_SWEEP_L, BILU_SWEEP_U}) {
+            const HostSweep& hs = h.sweep[w];
+            hipLaunchKernelGGL(dev::k_unlayout_f32, dim3(grid_for(hs.nslots * bb)), dim3(256), 0, s, hs.nslots, h.bs,
+                               hs.rpc, c->ds[w].src, static_cast<const float*>(c->ds[w].vals), F);
+        }
+        hipLaunchKernelGGL(dev::k_identity_f32, dim3(grid_for(static_cast<int64_t>(h.nb) * bb)), dim3(256), 0, s,
+                           h.nb, h.bs, c->d_Pdiag, F);
+    }
+    if (Dinv) {
+        const HostSweep& hs = h.sweep[BILU_SWEEP_U];
+        const int64_t nrs = static_cast<int64_t>(hs.nchunks) * hs.rpc;
+        hipLaunchKernelGGL(dev::k_unlayout_dinv_f32, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs, hs.rpc,
+                           c->ds[BILU_SWEEP_U].rows, static_cast<const float*>(c->ds[BILU_SWEEP_U].dinv), Dinv);
+    }
+    CK(hipGetLastError());
+    return BILU_OK;
+}
+
+bilu_status bilu_apply(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
+{
+    return do_apply(c, r, z, nrhs, false, s);
+}
+
+bilu_status bilu_apply_transpose(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
+{
+    return do_apply(c, r, z, nrhs, true, s);
+}
+
+bilu_status bilu_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, int nrhs, int transpose,
+                      hipStream_t s)
+{
+    return do_spmv(c, Ax, x, y, nrhs, transpose, s);
+}
+
+bilu_status bilu_grad_A(bilu_ctx* c, const double* lam, const double* x, double* dA, hipStream_t s)
+{
+    if (!c || !lam || !x || !dA) return BILU_ERR_ARG;
+    bilu_status st = ensure_device(c);
+    if (st) return st;
+    const int64_t nA = static_cast<int64_t>(c->h.Aj.size());
+    const int bb = c->h.bs * c->h.bs;
+    hipLaunchKernelGGL(dev::k_grad_A, dim3(grid_for(nA * bb)), dim3(256), 0, s, nA, c->h.bs, c->d_Arow, c->d_Aj,
+                       lam, x, dA);
+    CK(hipGetLastError());
+    return BILU_OK;
+}
+
+bilu_status bilu_set_sweep_mode(bilu_ctx* c, int mode)
+{
+    if (!c || (mode != 0 && mode != 1)) return BILU_ERR_ARG;
+    c->sweep_mode = mode;
+    return BILU_OK;
+}
+
+bilu_status bilu_check(bilu_ctx* c, hipStream_t s)
+{
+    if (!c) return BILU_ERR_ARG;
+    if (!c->dev_ready) return BILU_OK;
+    int v = 0;
+    CK(hipMemcpyAsync(&v, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (v) {
+        CK(hipMemset(c->d_status, 0, sizeof(int)));
+        return BILU_ERR_TIMEOUT;
+    }
+    return BILU_OK;
+}
+
+// ----- Krylov ---------------------------------------------------------------
+static bilu_status ensure_krylov(bilu_ctx* c, int R, int nvec)
+{
+    const size_t need = static_cast<size_t>(c->h.nb) * c->h.bs * R * nvec;
+    bilu_status st;
+    if (c->kv_cap < need) {
+        dfree(c, c->d_kv);
+        c->d_kv = nullptr;
+        c->kv_cap = 0;
+        if ((st = dalloc(c, &c->d_kv, need))) return st;
+        c->kv_cap = need;
+    }
+    if (!c->d_part) {
+        if ((st = dalloc(c, &c->d_part, static_cast<size_t>(dev::kSlots + 64) * dev::kMaxRhs * dev::kRedBlocks)))
+            return st;
+        if ((st = dalloc(c, &c->d_state, 1))) return st;
+    }
+    return BILU_OK;
+}
+
+static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, double* x, int R,
+                            const bilu_solve_opts* o, bilu_rhs_info* info, int tr, hipStream_t s)
+{
+    const int64_t n = static_cast<int64_t>(c->h.nb) * c->h.bs;
+    const size_t vb = static_cast<size_t>(n) * R * sizeof(double);
+    bilu_status st = ensure_krylov(c, R, 9);
+    if (st) return st;
+    double* kv = c->d_kv;
+    const size_t stride = static_cast<size_t>(n) * R;
+    double *r = kv, *rh = kv + stride, *p = kv + 2 * stride, *v = kv + 3 * stride, *ph = kv + 4 * stride;
+    double *sv = kv + 5 * stride, *sh = kv + 6 * stride, *t = kv + 7 * stride, *w = kv + 8 * stride;
+    double* part = c->d_part;
+    KState* S = c->d_state;
+    const int eg = grid_for(n * R);
+    auto apply = [&](const double* in, double* out) { return do_apply(c, in, out, R, tr != 0, s); };
+    auto spmv = [&](const double* in, double* out) { return do_spmv(c, Ax, in, out, R, tr, s); };
+
+    CK(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(rh, b, vb, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, x, 0.0);
+    hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, p, 0.0);
+    hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, v, 0.0);
+    hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, b, part, dev::SL_BB);
+    hipLaunchKernelGGL(dev::k_bicg_init, dim3(1), dim3(64), 0, s, R, part, S, o->rtol);
+    CK(hipGetLastError());
+
+    KState hs;
+    CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    std::vector<int> iters(R, 0), done(R, 0);
+    for (int j = 0; j < R; ++j)
+        if (!hs.active[j]) done[j] = 1;
+    int it = 0;
+    bool any_active = std::find(done.begin(), done.end(), 0) != done.end();
+    while (any_active && it < o->maxit) {
+        ++it;
+        hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, r, part, dev::SL_RHO);
+        hipLaunchKernelGGL(dev::k_bicg_s_rho, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_p, dim3(eg), dim3(256), 0, s, n, R, r, v, p, S);
+        if ((st = apply(p, ph)) || (st = spmv(ph, v))) return st;
+        hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, v, part, dev::SL_RV);
+        hipLaunchKernelGGL(dev::k_bicg_s_alpha, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_s, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, r, v, sv, S, part);
+        hipLaunchKernelGGL(dev::k_bicg_s_snorm, dim3(1), dim3(64), 0, s, R, part, S);
+        if ((st = apply(sv, sh)) || (st = spmv(sh, t))) return st;
+        hipLaunchKernelGGL(dev::k_dot2, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, t, sv, part,
+                           dev::SL_TS, dev::SL_TT);
+        hipLaunchKernelGGL(dev::k_bicg_s_omega, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_xr, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, x, r, ph, sh, sv, t,
+                           S, part);
+        hipLaunchKernelGGL(dev::k_bicg_s_end, dim3(1), dim3(64), 0, s, R, part, S);
+        CK(hipGetLastError());
+        CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        bool candidate = false;
+        for (int j = 0; j < R; ++j) {
+            if (done[j]) continue;
+            if (!hs.active[j]) {       // breakdown / non-finite
+                done[j] = 1;
+                iters[j] = it;
+                continue;
+            }
+            if (hs.half[j] || hs.rnorm2[j] <= hs.tol2[j]) candidate = true;
+        }
+        if (candidate) {
+            if ((st = spmv(x, w))) return st;
+            hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part,
+                               dev::SL_TRUE);
+            hipLaunchKernelGGL(dev::k_s_true, dim3(1), dim3(64), 0, s, R, part, S);
+            CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
+            CK(hipStreamSynchronize(s));
+            bool restart = false;
+            for (int j = 0; j < R; ++j) {
+                hs.restart[j] = 0;
+                if (done[j] || !hs.active[j]) continue;
+                if (!(hs.half[j] || hs.rnorm2[j] <= hs.tol2[j])) continue;
+                if (hs.tnorm2[j] <= hs.tol2[j]) {
+                    hs.active[j] = 0;
+                    hs.status[j] = dev::ST_OK;
+                    done[j] = 1;
+                    iters[j] = it;
+                } else {
+                    hs.restart[j] = 1;
+                    hs.fresh[j] = 1;
+                    hs.half[j] = 0;
+                    restart = true;
+                }
+            }
+            CK(hipMemcpyAsync(S, &hs, sizeof(KState), hipMemcpyHostToDevice, s));
+            CK(hipStreamSynchronize(s));
+            if (restart)
+                hipLaunchKernelGGL(dev::k_bicg_restart, dim3(eg), dim3(256), 0, s, n, R, w, r, rh, S);
+        }
+        any_active = std::find(done.begin(), done.end(), 0) != done.end();
+    }
+    // final true residuals for every column
+    if ((st = spmv(x, w))) return st;
+    hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part, dev::SL_TRUE);
+    hipLaunchKernelGGL(dev::k_s_true, dim3(1), dim3(64), 0, s, R, part, S);
+    CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    int sweep_err = 0;
+    CK(hipMemcpyAsync(&sweep_err, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    int worst = BILU_OK;
+    for (int j = 0; j < R; ++j) {
+        if (!done[j]) iters[j] = it;
+        int stj = hs.status[j];
+        if (!done[j]) stj = BILU_NOT_CONVERGED;
+        info[j].status = stj;
+        info[j].iters = iters[j];
+        info[j].relres = hs.bnorm2[j] > 0 ? std::sqrt(hs.tnorm2[j] / hs.bnorm2[j]) : 0.0;
+        if (stj > worst) worst = stj;
+    }
+    if (sweep_err) {
+        CK(hipMemset(c->d_status, 0, sizeof(int)));
+        return BILU_ERR_TIMEOUT;
+    }
+    return static_cast<bilu_status>(worst);
+}
+
+bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x, int nrhs,
+                       const bilu_solve_opts* o, bilu_rhs_info* info, int transpose, hipStream_t s)
+{
+    if (!c || !Ax || !b || !x || !o || !info || nrhs < 1 || nrhs > dev::kMaxRhs || b == x) return BILU_ERR_ARG;
+    if (!(o->rtol >= 0.0) || o->maxit < 1) return BILU_ERR_ARG;
+    if (!c->laid_out) return BILU_ERR_STATE;
+    if (transpose && !(c->h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
+    if (o->method == BILU_BICGSTAB) return bicgstab(c, Ax, b, x, nrhs, o, info, transpose, s);
+    return BILU_ERR_ARG;
+}
+
+void bilu_destroy(bilu_ctx* c)
+{
+    if (!c) return;
+    for (void* p : c->allocs) (void)hipFree(p);
+    delete c;
+}
+
+const char* bilu_status_string(int s)
+{
+    switch (s) {
+    case BILU_OK: return "ok";
+    case BILU_ERR_ARG: return "invalid argument";
+    case BILU_ERR_ALLOC: return "allocation failed";
+    case BILU_ERR_HIP: return "HIP runtime error";
+    case BILU_ERR_MISSING_DIAG: return "a block row has no diagonal block";
+    case BILU_ERR_PATTERN: return "unsorted, duplicate or out-of-range block columns";
+    case BILU_ERR_TIMEOUT: return "a sweep's bounded wait expired";
+    case BILU_ERR_STATE: return "call order violated";
+    case BILU_SINGULAR_PIVOT: return "singular or non-finite pivot block";
+    case BILU_NOT_CONVERGED: return "not converged";
+    case BILU_BREAKDOWN: return "Krylov breakdown";
+    case BILU_NONFINITE: return "non-finite value in the iteration";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal state shared by the host analysis (analysis.cpp) and the GPU
+// side (bilu_api.hip).  Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "bilu.h"
+
+namespace bilu {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxBs = 8;
+
+// Rows of a sweep grouped for the GPU: level by level (Eq 4), a level's rows
+// cut into chunks of `rpc` rows (one wavefront each), chunk c holding
+// w_c = (chunk_off[c+1]-chunk_off[c]) / rpc dependency slots per row.
+// Slot (c, k, q) = chunk_off[c] + k*rpc + q is the k-th dependency of the
+// q-th row of the chunk: cols[] names the row it reads, src[] the position
+// of the factor block in the pattern P (-1: padding).
+struct HostSweep {
+    bool built = false;
+    int which = 0;
+    int nlev = 0;
+    int rpc = 0;
+    int nchunks = 0;
+    int64_t nslots = 0;
+    bool transposed_blocks = false;        // U'^T and L^T read blocks transposed
+    std::vector<int32_t> level_ptr;        // [nlev+1]  canonical level sets
+    std::vector<int32_t> level_rows;       // [nb]      rows ascending in a level
+    std::vector<int32_t> level_chunk_ptr;  // [nlev+1]  first chunk of each level
+    std::vector<int64_t> chunk_off;        // [nchunks+1] slot offsets
+    std::vector<int32_t> rows;             // [nchunks*rpc] row ids, -1 = idle lane
+    std::vector<int32_t> cols;             // [nslots]
+    std::vector<int64_t> src;              // [nslots]
+};
+
+struct DevSweep {
+    int64_t* chunk_off = nullptr;
+    int32_t* rows = nullptr;
+    int32_t* cols = nullptr;
+    int64_t* src = nullptr;
+    void* vals = nullptr;     // [nslots * bs*bs] FP64 or FP32, layout [k][c][r][q]
+    void* dinv = nullptr;     // [nchunks*rpc * bs*bs] same layout, fused sweeps only
+    int32_t* flags = nullptr; // [nb] ready flags (value = epoch when row is final)
+    unsigned long long* ticket = nullptr;
+    unsigned long long ticket_base = 0;
+    int epoch = 0;
+    int32_t* level_chunk_ptr = nullptr;
+};
+
+struct Host {
+    int nb = 0, bs = 0, k = 0, flags = 0;
+    int rpc = 0;
+    std::vector<int32_t> Ap, Aj;
+    std::vector<int32_t> Arow;             // block row of each stored block of A
+    std::vector<int32_t> Pp, Pj, Plev;     // ILU(k) pattern
+    std::vector<int32_t> Pdiag;            // position of (i,i) in P
+    std::vector<int32_t> Prow;             // block row of each entry of P
+    std::vector<int64_t> AtoP;             // position in P of each stored block of A
+    std::vector<int32_t> Pfill;            // positions of P not stored in A
+    // A^T structure: row j lists the blocks (i, j) of A; ATsrc = their position in A
+    std::vector<int32_t> ATp, ATj;
+    std::vector<int64_t> ATsrc;
+    HostSweep sweep[4];
+};
+
+// Host analysis entry points (analysis.cpp).
+int validate_pattern(int nb, const int32_t* Ap, const int32_t* Aj);
+int symbolic_iluk(int nb, const int32_t* Ap, const int32_t* Aj, int k, std::vector<int32_t>& Pp,
+                  std::vector<int32_t>& Pj, std::vector<int32_t>& Plev);
+int sweep_levels(int nb, const std::vector<int32_t>& Pp, const std::vector<int32_t>& Pj,
+                 int which, std::vector<int32_t>& lvl);
+void build_sweep(const Host& h, int which, int rpc, HostSweep& out);
+int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags);
+int validate_layout(const Host& h);
+
+}  // namespace bilu

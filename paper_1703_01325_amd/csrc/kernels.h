@@ -1,0 +1,812 @@
+// HIP kernels for gfx950 (CDNA4, wave64).  Included once, by bilu_api.hip.
+//
+// Block values are column-major b x b (Section 2.1).  Vectors are
+// (nb*b) x R row-major.  All floating-point accumulation is FP64; factor
+// values may be stored as FP32 and are widened before they are multiplied.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bilu {
+namespace dev {
+
+constexpr int kThreads = 256;          // 4 wavefronts per workgroup
+constexpr int kWavesPerBlock = kThreads / 64;
+constexpr int kRedBlocks = 512;        // fixed grid of the two-stage reductions
+constexpr int kMaxRhs = 32;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) { return static_cast<double>(v); }
+
+// ---------------------------------------------------------------------------
+// Level-scheduled sweep (Eq 4, Algorithm 6) of one unit-diagonal block
+// triangular factor, optionally with the block-diagonal D^{-1} product of
+// Algorithm 7 fused in front:
+//     out_i = (fuse ? Dv_i rhs_i : rhs_i) - sum_k F_ik out_{col(i,k)}
+// One wavefront per chunk of rpc = 64/B block rows of one level; lane
+// (q, r) = (lane / B, lane % B) owns component r of the chunk's q-th row.
+// Values of a chunk are stored [k][c][r][q], so for a fixed dependency k
+// and block column c the wavefront reads B*rpc consecutive values.
+//
+// persistent = 0: the launch covers the chunks [chunk_begin, chunk_end) of
+// one level (all their dependencies are final before the launch).
+// persistent = 1: one launch covers the whole sweep.  Each wavefront takes
+// chunks in level order from an atomic ticket, waits until the rows it
+// reads carry the current epoch in flags[], computes, then publishes its
+// own rows.  A chunk only waits for chunks with smaller tickets, which are
+// held by wavefronts already running, so the sweep always drains.  Waits
+// are bounded: past the limit the wavefront records a timeout in *status
+// and carries on, so every wavefront still reaches the end.
+// ---------------------------------------------------------------------------
+struct SweepArgs {
+    const int64_t* chunk_off;
+    const int32_t* rows;
+    const int32_t* cols;
+    const void* vals;
+    const void* dinv;
+    const double* rhs;
+    double* out;
+    int32_t* flags;
+    unsigned long long* ticket;
+    unsigned int* done;
+    int* status;
+    int nchunks;
+    int chunk_begin;
+    int chunk_end;
+    int epoch;
+    int R;
+    int fuse;
+    int persistent;
+    unsigned int total_waves;
+    unsigned int spin_limit;
+};
+
+__device__ __forceinline__ int grab_chunk(unsigned long long* ticket)
+{
+    unsigned long long t = 0;
+    if (lane_id() == 0) t = atomicAdd(ticket, 1ULL);
+    t = __shfl(t, 0);
+    return t > 0x7fffffffULL ? 0x7fffffff : static_cast<int>(t);
+}
+
+__device__ __forceinline__ void wait_ready(int32_t* flag, int epoch, unsigned int limit, int* status)
+{
+    unsigned int spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <int B, typename T, int RT>
+__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int q = lane / B;
+    const int r = lane - q * B;
+    const bool lane_ok = q < RPC;
+    const T* __restrict__ vals = static_cast<const T*>(a.vals);
+    const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
+    const int R = a.R;
+    const int limit_chunk = a.persistent ? a.nchunks : a.chunk_end;
+
+    int chunk = a.persistent ? grab_chunk(a.ticket)
+                             : a.chunk_begin + static_cast<int>(blockIdx.x) * kWavesPerBlock + wave;
+    while (chunk < limit_chunk) {
+        const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
+        const int64_t off = a.chunk_off[chunk];
+        const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
+        if (a.persistent) {
+            if (row >= 0 && r == 0) {
+                for (int k = 0; k < w; ++k) {
+                    const int j = a.cols[off + static_cast<int64_t>(k) * RPC + q];
+                    if (j >= 0) wait_ready(a.flags + j, a.epoch, a.spin_limit, a.status);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if (row >= 0) {
+            for (int c0 = 0; c0 < R; c0 += RT) {
+                double acc[RT];
+#pragma unroll
+                for (int t = 0; t < RT; ++t) acc[t] = 0.0;
+                if (a.fuse) {
+                    const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + q;
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const double d = widen(dinv[dbase + c * B * RPC]);
+                        const double* src = a.rhs + (static_cast<int64_t>(row) * B + c) * R + c0;
+#pragma unroll
+                        for (int t = 0; t < RT; ++t)
+                            if (RT == 1 || c0 + t < R) acc[t] += d * src[t];
+                    }
+                } else {
+                    const double* src = a.rhs + (static_cast<int64_t>(row) * B + r) * R + c0;
+#pragma unroll
+                    for (int t = 0; t < RT; ++t)
+                        if (RT == 1 || c0 + t < R) acc[t] = src[t];
+                }
+                for (int k = 0; k < w; ++k) {
+                    const int64_t s = off + static_cast<int64_t>(k) * RPC;
+                    const int j = a.cols[s + q];
+                    if (j < 0) continue;
+                    const int64_t vbase = s * BB + r * RPC + q;
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const double v = widen(vals[vbase + c * B * RPC]);
+                        const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
+#pragma unroll
+                        for (int t = 0; t < RT; ++t)
+                            if (RT == 1 || c0 + t < R) acc[t] -= v * xj[t];
+                    }
+                }
+                double* dst = a.out + (static_cast<int64_t>(row) * B + r) * R + c0;
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    if (RT == 1 || c0 + t < R) dst[t] = acc[t];
+            }
+        }
+        if (!a.persistent) break;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (row >= 0 && r == 0)
+            __hip_atomic_store(a.flags + row, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        chunk = grab_chunk(a.ticket);
+    }
+    if (a.persistent && lane == 0) {
+        // the last wavefront to finish rewinds the ticket for the next launch
+        const unsigned int prev = atomicAdd(a.done, 1u);
+        if (prev + 1 == a.total_waves) {
+            __hip_atomic_store(a.ticket, 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block-CSR SpMV y = A x (transpose = 0) or y = A^T x (transpose = 1, with
+// the CSR of A^T whose entries point back at A's blocks).  One wavefront per
+// 64/B consecutive block rows, lane (q, r) owns component r of row q.
+// ---------------------------------------------------------------------------
+template <int B, int RT, bool TRANS>
+__global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ cj,
+                                                   const int64_t* __restrict__ srcpos,
+                                                   const double* __restrict__ Ax,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y, int R)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    const int lane = lane_id();
+    const int q = lane / B;
+    const int r = lane - q * B;
+    const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t row = wave_global * RPC + q;
+    if (q >= RPC || row >= nb) return;
+    const int e0 = rp[row], e1 = rp[row + 1];
+    for (int c0 = 0; c0 < R; c0 += RT) {
+        double acc[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[t] = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const int j = cj[e];
+            const int64_t blk = TRANS ? srcpos[e] : e;
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                const double v = TRANS ? Ax[blk * BB + r * B + c] : Ax[blk * BB + c * B + r];
+                const double* xj = x + (static_cast<int64_t>(j) * B + c) * R + c0;
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    if (RT == 1 || c0 + t < R) acc[t] += v * xj[t];
+            }
+        }
+        double* dst = y + (row * B + r) * R + c0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+            if (RT == 1 || c0 + t < R) dst[t] = acc[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backfill (Algorithm 5 steps 3-4): P takes A's block where A stores one
+// and a zero block at every fill position.
+// ---------------------------------------------------------------------------
+__global__ void k_backfill(int64_t nP, int bb, const int32_t* __restrict__ PtoA,
+                           const double* __restrict__ Ax, double* __restrict__ P)
+{
+    const int64_t total = nP * bb;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = g / bb;
+        const int t = static_cast<int>(g - e * bb);
+        const int32_t a = PtoA[e];
+        P[g] = a >= 0 ? Ax[static_cast<int64_t>(a) * bb + t] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block ILU(0) on P (Algorithm 4) for the block rows of one level of the L
+// schedule: one 64-thread workgroup per block row, thread t = c*B + r owns
+// element (r, c) of the block being formed.
+//   for p < i in row i, ascending:  A_ip <- A_ip * inv(A_pp)
+//       for j > p in row i with (p, j) in P:  A_ij <- A_ij - A_ip * A_pj
+//   then inv(A_ii) by Gauss-Jordan with partial pivoting inside the block.
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(64) void k_factor_rows(const int32_t* __restrict__ rows, int nrows,
+                                                    const int32_t* __restrict__ Pp,
+                                                    const int32_t* __restrict__ Pj,
+                                                    const int32_t* __restrict__ Pdiag,
+                                                    double* __restrict__ P,
+                                                    double* __restrict__ Dinv, int* bad_row)
+{
+    constexpr int BB = B * B;
+    constexpr int W = 2 * B;
+    __shared__ double sL[BB];
+    __shared__ double sW[B * W];
+    __shared__ int sPiv;
+    __shared__ int sBad;
+    if (static_cast<int>(blockIdx.x) >= nrows) return;
+    const int i = rows[blockIdx.x];
+    const int t = threadIdx.x;
+    const int r = t % B;
+    const int c = t / B;
+    const int eEnd = Pp[i + 1];
+    const int d = Pdiag[i];
+    if (t == 0) sBad = 0;
+    for (int e = Pp[i]; e < d; ++e) {
+        const int p = Pj[e];
+        double tv = 0.0;
+        if (t < BB) {
+            const double* Aip = P + static_cast<int64_t>(e) * BB;
+            const double* Dp = Dinv + static_cast<int64_t>(p) * BB;
+#pragma unroll
+            for (int u = 0; u < B; ++u) tv += Aip[u * B + r] * Dp[c * B + u];
+        }
+        __syncthreads();
+        if (t < BB) {
+            P[static_cast<int64_t>(e) * BB + t] = tv;
+            sL[t] = tv;
+        }
+        __syncthreads();
+        int f = e + 1;
+        int g = Pdiag[p] + 1;
+        const int gEnd = Pp[p + 1];
+        while (f < eEnd && g < gEnd) {
+            const int cf = Pj[f];
+            const int cg = Pj[g];
+            if (cf == cg) {
+                if (t < BB) {
+                    const double* Apj = P + static_cast<int64_t>(g) * BB;
+                    double s = 0.0;
+#pragma unroll
+                    for (int u = 0; u < B; ++u) s += sL[u * B + r] * Apj[c * B + u];
+                    P[static_cast<int64_t>(f) * BB + t] -= s;
+                }
+                ++f;
+                ++g;
+            } else if (cf < cg) {
+                ++f;
+            } else {
+                ++g;
+            }
+        }
+        __syncthreads();
+    }
+    // Gauss-Jordan on [U_ii | I], row-major in LDS.
+    if (t < BB) {
+        sW[r * W + c] = P[static_cast<int64_t>(d) * BB + t];
+        sW[r * W + B + c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int col = 0; col < B; ++col) {
+        if (t == 0) {
+            int piv = col;
+            double best = fabs(sW[col * W + col]);
+            for (int rr = col + 1; rr < B; ++rr) {
+                const double v = fabs(sW[rr * W + col]);
+                if (v > best) {
+                    best = v;
+                    piv = rr;
+                }
+            }
+            if (!(best > 0.0) || !isfinite(best)) sBad = 1;
+            sPiv = piv;
+        }
+        __syncthreads();
+        const int piv = sPiv;
+        if (piv != col && t < W) {
+            const double tmp = sW[col * W + t];
+            sW[col * W + t] = sW[piv * W + t];
+            sW[piv * W + t] = tmp;
+        }
+        __syncthreads();
+        const double dd = sW[col * W + col];
+        __syncthreads();
+        if (t < W) sW[col * W + t] /= dd;
+        __syncthreads();
+        double fct[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int idx = t + 64 * s;
+            fct[s] = idx < B * W ? sW[(idx / W) * W + col] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int idx = t + 64 * s;
+            if (idx < B * W) {
+                const int rr = idx / W;
+                const int cc = idx - rr * W;
+                if (rr != col) sW[idx] -= fct[s] * sW[col * W + cc];
+            }
+        }
+        __syncthreads();
+    }
+    if (t < BB) Dinv[static_cast<int64_t>(i) * BB + t] = sW[r * W + B + c];
+    if (t == 0 && sBad) atomicMin(bad_row, i);
+}
+
+// ---------------------------------------------------------------------------
+// U = D U' (Eq 5): F = L below the diagonal, U'_ij = D_i^{-1} U_ij above
+// it, the identity on the diagonal.
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ void k_split(int64_t nP, const int32_t* __restrict__ Prow, const int32_t* __restrict__ Pj,
+                        const double* __restrict__ P, const double* __restrict__ Dinv,
+                        double* __restrict__ F)
+{
+    constexpr int BB = B * B;
+    const int64_t total = nP * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = g / BB;
+        const int el = static_cast<int>(g - e * BB);
+        const int c = el / B;
+        const int r = el - c * B;
+        const int i = Prow[e];
+        const int j = Pj[e];
+        double v;
+        if (j < i) {
+            v = P[g];
+        } else if (j == i) {
+            v = (r == c) ? 1.0 : 0.0;
+        } else {
+            const double* Di = Dinv + static_cast<int64_t>(i) * BB;
+            const double* U = P + e * BB;
+            v = 0.0;
+#pragma unroll
+            for (int u = 0; u < B; ++u) v += Di[u * B + r] * U[c * B + u];
+        }
+        F[g] = v;
+    }
+}
+
+// Factor blocks gathered into a sweep layout ([k][c][r][q] per chunk),
+// transposed for the U'^T / L^T sweeps, converted to T (FP64 or FP32, RNE).
+template <typename T>
+__global__ void k_layout(int64_t nslots, int B, int rpc, const int64_t* __restrict__ src,
+                         const double* __restrict__ F, int transposed, T* __restrict__ vals)
+{
+    const int BB = B * B;
+    const int64_t total = nslots * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = g / BB;
+        const int el = static_cast<int>(g - s * BB);   // el = c*B + r
+        const int c = el / B;
+        const int r = el - c * B;
+        const int q = static_cast<int>(s % rpc);
+        const int64_t sp = src[s];
+        double v = 0.0;
+        if (sp >= 0) v = transposed ? F[sp * BB + r * B + c] : F[sp * BB + c * B + r];
+        vals[(s - q) * BB + static_cast<int64_t>(el) * rpc + q] = static_cast<T>(v);
+    }
+}
+
+template <typename T>
+__global__ void k_layout_dinv(int64_t nrowslots, int B, int rpc, const int32_t* __restrict__ rows,
+                              const double* __restrict__ Dinv, int transposed, T* __restrict__ out)
+{
+    const int BB = B * B;
+    const int64_t total = nrowslots * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = g / BB;
+        const int el = static_cast<int>(g - s * BB);
+        const int c = el / B;
+        const int r = el - c * B;
+        const int q = static_cast<int>(s % rpc);
+        const int row = rows[s];
+        double v = 0.0;
+        if (row >= 0)
+            v = transposed ? Dinv[static_cast<int64_t>(row) * BB + r * B + c]
+                           : Dinv[static_cast<int64_t>(row) * BB + c * B + r];
+        out[(s - q) * BB + static_cast<int64_t>(el) * rpc + q] = static_cast<T>(v);
+    }
+}
+
+// Inverse of k_layout for the non-transposed sweeps: FP32 values back to
+// pattern order (used to hand the exact FP32 factor bytes to a caller).
+__global__ void k_unlayout_f32(int64_t nslots, int B, int rpc, const int64_t* __restrict__ src,
+                               const float* __restrict__ vals, float* __restrict__ F)
+{
+    const int BB = B * B;
+    const int64_t total = nslots * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = g / BB;
+        const int el = static_cast<int>(g - s * BB);
+        const int q = static_cast<int>(s % rpc);
+        const int64_t sp = src[s];
+        if (sp >= 0) F[sp * BB + el] = vals[(s - q) * BB + static_cast<int64_t>(el) * rpc + q];
+    }
+}
+
+__global__ void k_unlayout_dinv_f32(int64_t nrowslots, int B, int rpc, const int32_t* __restrict__ rows,
+                                    const float* __restrict__ in, float* __restrict__ Dinv)
+{
+    const int BB = B * B;
+    const int64_t total = nrowslots * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = g / BB;
+        const int el = static_cast<int>(g - s * BB);
+        const int q = static_cast<int>(s % rpc);
+        const int row = rows[s];
+        if (row >= 0) Dinv[static_cast<int64_t>(row) * BB + el] = in[(s - q) * BB + static_cast<int64_t>(el) * rpc + q];
+    }
+}
+
+__global__ void k_identity_f32(int nb, int B, const int32_t* __restrict__ Pdiag, float* __restrict__ F)
+{
+    const int BB = B * B;
+    const int64_t total = static_cast<int64_t>(nb) * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t i = g / BB;
+        const int el = static_cast<int>(g - i * BB);
+        F[static_cast<int64_t>(Pdiag[i]) * BB + el] = (el % (B + 1) == 0) ? 1.0f : 0.0f;
+    }
+}
+
+// dA_ij = -lambda_i x_j^T on A's blocks.
+__global__ void k_grad_A(int64_t nA, int B, const int32_t* __restrict__ Arow, const int32_t* __restrict__ Aj,
+                         const double* __restrict__ lam, const double* __restrict__ x,
+                         double* __restrict__ dA)
+{
+    const int BB = B * B;
+    const int64_t total = nA * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = g / BB;
+        const int el = static_cast<int>(g - e * BB);
+        const int c = el / B;
+        const int r = el - c * B;
+        dA[g] = -lam[static_cast<int64_t>(Arow[e]) * B + r] * x[static_cast<int64_t>(Aj[e]) * B + c];
+    }
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t* p, int32_t v)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[g] = v;
+}
+
+__global__ void k_fill_f64(int64_t n, double* p, double v)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[g] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector kernels.  Vectors are n x R row-major (n = nb*B).  Dot
+// products are deterministic two-stage sums: the reduction kernels run on a
+// fixed grid of kRedBlocks workgroups with a grid stride that is a multiple
+// of R, so every thread stays on one column; each workgroup writes one
+// partial per column, summed in a fixed order by the scalar kernels.
+// Per-column scalars live in a device KState.
+// ---------------------------------------------------------------------------
+struct KState {
+    double rho[kMaxRhs], rho_old[kMaxRhs], alpha[kMaxRhs], omega[kMaxRhs], beta[kMaxRhs];
+    double bnorm2[kMaxRhs], tol2[kMaxRhs], snorm2[kMaxRhs], rnorm2[kMaxRhs], tnorm2[kMaxRhs];
+    int active[kMaxRhs], fresh[kMaxRhs], half[kMaxRhs], status[kMaxRhs], restart[kMaxRhs];
+    int sweep_status;
+};
+
+enum { ST_OK = 0, ST_NOT_CONV = 2, ST_BREAKDOWN = 3, ST_NONFINITE = 4 };
+
+// Per-thread column and the stride of the reduction loop.
+struct RedIdx {
+    int64_t start, stride;
+    int col;
+    bool live;
+};
+
+__device__ __forceinline__ RedIdx red_index(int R)
+{
+    const int64_t nthreads = static_cast<int64_t>(kRedBlocks) * kThreads;
+    const int64_t stride = (nthreads / R) * R;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    RedIdx ri;
+    ri.start = gid;
+    ri.stride = stride;
+    ri.col = static_cast<int>(gid % R);
+    ri.live = gid < stride;
+    return ri;
+}
+
+// Sums, per column, the thread values of one workgroup in a fixed order and
+// stores the partial for this workgroup.
+__device__ __forceinline__ void block_partial(double v, int R, double* part_slot)
+{
+    __shared__ double sred[kThreads];
+    __syncthreads();
+    sred[threadIdx.x] = v;
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < R) {
+        // threads of this workgroup whose global index is == col (mod R)
+        const int col = threadIdx.x;
+        const int base = static_cast<int>((static_cast<int64_t>(blockIdx.x) * kThreads) % R);
+        double s = 0.0;
+        for (int t = (col - base + R) % R; t < kThreads; t += R) s += sred[t];
+        part_slot[static_cast<int64_t>(col) * kRedBlocks + blockIdx.x] = s;
+    }
+}
+
+// part[slot][col][block]
+__device__ __forceinline__ double* slot_ptr(double* part, int slot)
+{
+    return part + static_cast<int64_t>(slot) * kMaxRhs * kRedBlocks;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot(int64_t n, int R, const double* __restrict__ a,
+                                                  const double* __restrict__ b, double* part, int slot)
+{
+    const RedIdx ri = red_index(R);
+    double acc = 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n * R; g += ri.stride) acc += a[g] * b[g];
+    block_partial(acc, R, slot_ptr(part, slot));
+}
+
+// t.s and t.t in one pass
+__global__ __launch_bounds__(kThreads) void k_dot2(int64_t n, int R, const double* __restrict__ t,
+                                                   const double* __restrict__ s, double* part,
+                                                   int slot_ts, int slot_tt)
+{
+    const RedIdx ri = red_index(R);
+    double ts = 0.0, tt = 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n * R; g += ri.stride) {
+            const double tv = t[g];
+            ts += tv * s[g];
+            tt += tv * tv;
+        }
+    block_partial(ts, R, slot_ptr(part, slot_ts));
+    block_partial(tt, R, slot_ptr(part, slot_tt));
+}
+
+__device__ __forceinline__ double sum_partials(const double* part, int slot, int col)
+{
+    const double* p = part + static_cast<int64_t>(slot) * kMaxRhs * kRedBlocks +
+                      static_cast<int64_t>(col) * kRedBlocks;
+    double s = 0.0;
+    for (int k = 0; k < kRedBlocks; ++k) s += p[k];
+    return s;
+}
+
+enum { SL_RHO = 0, SL_RV = 1, SL_SS = 2, SL_TS = 3, SL_TT = 4, SL_RR = 5, SL_BB = 6, SL_TRUE = 7 };
+constexpr int kSlots = 8;
+
+// BiCGSTAB setup: ||b||, tolerance, flags.  r = b, r^ = r, x = 0 are done
+// by copies on the host side.
+__global__ void k_bicg_init(int R, const double* part, KState* st, double rtol)
+{
+    const int c = threadIdx.x;
+    if (c >= R) return;
+    const double b2 = sum_partials(part, SL_BB, c);
+    st->bnorm2[c] = b2;
+    st->tol2[c] = rtol * rtol * b2;
+    st->active[c] = b2 > 0.0 ? 1 : 0;
+    st->status[c] = b2 > 0.0 ? ST_NOT_CONV : ST_OK;
+    st->fresh[c] = 1;
+    st->half[c] = 0;
+    st->restart[c] = 0;
+    st->rho_old[c] = 1.0;
+    st->alpha[c] = 1.0;
+    st->omega[c] = 1.0;
+    st->rnorm2[c] = b2;
+    st->tnorm2[c] = b2;
+    if (c == 0) st->sweep_status = 0;
+}
+
+__global__ void k_bicg_s_rho(int R, const double* part, KState* st)
+{
+    const int c = threadIdx.x;
+    if (c >= R || !st->active[c]) return;
+    const double rho = sum_partials(part, SL_RHO, c);
+    st->rho[c] = rho;
+    st->half[c] = 0;
+    if (!isfinite(rho)) {
+        st->status[c] = ST_NONFINITE;
+        st->active[c] = 0;
+    } else if (rho == 0.0) {
+        st->status[c] = ST_BREAKDOWN;
+        st->active[c] = 0;
+    } else {
+        st->beta[c] = st->fresh[c] ? 0.0 : (rho / st->rho_old[c]) * (st->alpha[c] / st->omega[c]);
+    }
+}
+
+__global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const double* __restrict__ v,
+                         double* __restrict__ p, const KState* st)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n * R;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int c = static_cast<int>(g % R);
+        if (!st->active[c]) continue;
+        p[g] = st->fresh[c] ? r[g] : r[g] + st->beta[c] * (p[g] - st->omega[c] * v[g]);
+    }
+}
+
+__global__ void k_bicg_s_alpha(int R, const double* part, KState* st)
+{
+    const int c = threadIdx.x;
+    if (c >= R || !st->active[c]) return;
+    const double rv = sum_partials(part, SL_RV, c);
+    st->fresh[c] = 0;
+    if (!isfinite(rv)) {
+        st->status[c] = ST_NONFINITE;
+        st->active[c] = 0;
+    } else if (rv == 0.0) {
+        st->status[c] = ST_BREAKDOWN;
+        st->active[c] = 0;
+    } else {
+        st->alpha[c] = st->rho[c] / rv;
+    }
+}
+
+// s = r - alpha v, partial of s.s
+__global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t n, int R, const double* __restrict__ r,
+                                                     const double* __restrict__ v, double* __restrict__ s,
+                                                     const KState* st, double* part)
+{
+    const RedIdx ri = red_index(R);
+    double acc = 0.0;
+    if (ri.live && st->active[ri.col]) {
+        const double al = st->alpha[ri.col];
+        for (int64_t g = ri.start; g < n * R; g += ri.stride) {
+            const double sv = r[g] - al * v[g];
+            s[g] = sv;
+            acc += sv * sv;
+        }
+    }
+    block_partial(acc, R, slot_ptr(part, SL_SS));
+}
+
+__global__ void k_bicg_s_snorm(int R, const double* part, KState* st)
+{
+    const int c = threadIdx.x;
+    if (c >= R || !st->active[c]) return;
+    const double s2 = sum_partials(part, SL_SS, c);
+    st->snorm2[c] = s2;
+    st->half[c] = (s2 <= st->tol2[c]) ? 1 : 0;
+    if (!isfinite(s2)) {
+        st->status[c] = ST_NONFINITE;
+        st->active[c] = 0;
+    }
+}
+
+__global__ void k_bicg_s_omega(int R, const double* part, KState* st)
+{
+    const int c = threadIdx.x;
+    if (c >= R || !st->active[c] || st->half[c]) return;
+    const double ts = sum_partials(part, SL_TS, c);
+    const double tt = sum_partials(part, SL_TT, c);
+    if (!isfinite(ts) || !isfinite(tt)) {
+        st->status[c] = ST_NONFINITE;
+        st->active[c] = 0;
+    } else if (tt == 0.0) {
+        st->status[c] = ST_BREAKDOWN;
+        st->active[c] = 0;
+    } else {
+        st->omega[c] = ts / tt;
+    }
+}
+
+// x += alpha p^ (+ omega s^ unless the half step already converged),
+// r = s - omega t; partial of r.r
+__global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t n, int R, double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ ph,
+                                                      const double* __restrict__ sh,
+                                                      const double* __restrict__ s,
+                                                      const double* __restrict__ t, const KState* st,
+                                                      double* part)
+{
+    const RedIdx ri = red_index(R);
+    double acc = 0.0;
+    if (ri.live && st->active[ri.col]) {
+        const int c = ri.col;
+        const double al = st->alpha[c];
+        if (st->half[c]) {
+            for (int64_t g = ri.start; g < n * R; g += ri.stride) x[g] += al * ph[g];
+        } else {
+            const double om = st->omega[c];
+            for (int64_t g = ri.start; g < n * R; g += ri.stride) {
+                x[g] += al * ph[g] + om * sh[g];
+                const double rv = s[g] - om * t[g];
+                r[g] = rv;
+                acc += rv * rv;
+            }
+        }
+    }
+    block_partial(acc, R, slot_ptr(part, SL_RR));
+}
+
+__global__ void k_bicg_s_end(int R, const double* part, KState* st)
+{
+    const int c = threadIdx.x;
+    if (c >= R || !st->active[c]) return;
+    if (st->half[c]) return;
+    const double r2 = sum_partials(part, SL_RR, c);
+    st->rnorm2[c] = r2;
+    st->rho_old[c] = st->rho[c];
+    if (!isfinite(r2)) {
+        st->status[c] = ST_NONFINITE;
+        st->active[c] = 0;
+    } else if (st->omega[c] == 0.0) {
+        st->status[c] = ST_BREAKDOWN;
+        st->active[c] = 0;
+    }
+}
+
+// w = b - w (w holds A x on entry), partial of w.w
+__global__ __launch_bounds__(kThreads) void k_resid(int64_t n, int R, const double* __restrict__ b,
+                                                    double* __restrict__ w, double* part, int slot)
+{
+    const RedIdx ri = red_index(R);
+    double acc = 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n * R; g += ri.stride) {
+            const double v = b[g] - w[g];
+            w[g] = v;
+            acc += v * v;
+        }
+    block_partial(acc, R, slot_ptr(part, slot));
+}
+
+__global__ void k_s_true(int R, const double* part, KState* st)
+{
+    const int c = threadIdx.x;
+    if (c >= R) return;
+    st->tnorm2[c] = sum_partials(part, SL_TRUE, c);
+}
+
+// Restart of the columns flagged in st->restart: r = r^ = w (true residual).
+__global__ void k_bicg_restart(int64_t n, int R, const double* __restrict__ w, double* __restrict__ r,
+                               double* __restrict__ rh, KState* st)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n * R;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int c = static_cast<int>(g % R);
+        if (!st->restart[c]) continue;
+        r[g] = w[g];
+        rh[g] = w[g];
+    }
+}
+
+}  // namespace dev
+}  // namespace bilu

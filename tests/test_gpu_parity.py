@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Tolerances: factors and single applications / SpMVs
+relative 1e-12 (max-abs error over max-abs value, per factor); FP64 solves
+to rtol 1e-8 within relative 1e-10 of the oracle's solution and +-1
+iteration; FP32-factor and multi-RHS solves converge to 1e-8."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1703_01325_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1703_01325_amd import api as A
+    return A
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+class Case:
+    def __init__(self, O, sysm, k, transpose=False):
+        self.s = sysm
+        self.k = k
+        self.O = O.OracleILU(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, k).factor(sysm.Ax)
+        self.Ax = cuda(sysm.Ax)
+        self.rhs = O.spmv(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, sysm.Ax, sysm.xstar)
+
+    def gpu(self, api, transpose=False, precision="fp64", mode=1):
+        M = api.BlockILU(self.s.nb, self.s.bs, self.s.Ap, self.s.Aj, self.k, transpose=transpose)
+        M.set_sweep_mode(mode)
+        bad = M.factor(self.Ax, precision=precision)
+        assert bad == -1
+        return M
+
+
+def small_cases():
+    out = [("cube10_b3", lambda: synth.small_10cube(), 0),
+           ("cube10_b3", lambda: synth.small_10cube(), 1)]
+    for bs in (1, 2, 4, 5, 6, 7, 8):
+        out.append((f"grid_b{bs}", (lambda b: (lambda: synth.reservoir(7, 6, 5, b, seed=30 + b)))(bs), 1))
+    out.append(("ragged_b3_k2", lambda: synth.reservoir(13, 3, 11, 3, seed=44), 2))
+    return out
+
+
+SMALL = small_cases()
+
+
+def factor_parts(O, s, F):
+    rows = np.repeat(np.arange(s.nb), np.diff(O.Pp))
+    bb = s.bs * s.bs
+    Fm = np.asarray(F).reshape(-1, bb)
+    return Fm[O.Pj < rows], Fm[O.Pj > rows]
+
+
+@pytest.mark.parametrize("name,make,k", SMALL, ids=[f"{c[0]}_k{c[2]}" for c in SMALL])
+def test_factor_parity(api, oracle_mod, name, make, k):
+    c = Case(oracle_mod, make(), k)
+    M = c.gpu(api)
+    F, D = M.factors()
+    F, D = F.cpu().numpy(), D.cpu().numpy()
+    gL, gU = factor_parts(c.O, c.s, F)
+    oL, oU = factor_parts(c.O, c.s, c.O.F)
+    if oL.size:
+        assert rel(gL, oL) <= 1e-12
+        assert rel(gU, oU) <= 1e-12
+    assert rel(D, c.O.Dinv) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["per_level", "persistent"])
+@pytest.mark.parametrize("name,make,k", SMALL, ids=[f"{c[0]}_k{c[2]}" for c in SMALL])
+def test_apply_and_spmv_parity(api, oracle_mod, name, make, k, mode):
+    c = Case(oracle_mod, make(), k)
+    M = c.gpu(api, transpose=True, mode=mode)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(c.s.n)
+    z = M.apply(cuda(r)).cpu().numpy()
+    assert rel(z, c.O.apply(r)) <= 1e-12
+    zt = M.apply(cuda(r), transpose=True).cpu().numpy()
+    assert rel(zt, c.O.apply(r, transpose=True)) <= 1e-12
+    y = M.spmv(c.Ax, cuda(r)).cpu().numpy()
+    assert rel(y, oracle_mod.spmv(c.s.nb, c.s.bs, c.s.Ap, c.s.Aj, c.s.Ax, r)) <= 1e-12
+    yt = M.spmv(c.Ax, cuda(r), transpose=True).cpu().numpy()
+    assert rel(yt, oracle_mod.spmv(c.s.nb, c.s.bs, c.s.Ap, c.s.Aj, c.s.Ax, r, True)) <= 1e-12
+    M.check()
+
+
+def test_apply_deterministic(api, oracle_mod):
+    c = Case(oracle_mod, synth.small_10cube(), 1)
+    M = c.gpu(api)
+    r = cuda(np.random.default_rng(1).standard_normal(c.s.n))
+    z1 = M.apply(r)
+    z2 = M.apply(r)
+    assert torch.equal(z1, z2)
+
+
+@pytest.mark.parametrize("R", [2, 8, 13, 32])
+def test_multi_rhs_columns(api, oracle_mod, R):
+    c = Case(oracle_mod, synth.reservoir(6, 5, 7, 3, seed=12), 1)
+    M = c.gpu(api, transpose=True)
+    B = np.random.default_rng(R).standard_normal((c.s.n, R))
+    Z = M.apply(cuda(B)).cpu().numpy()
+    Y = M.spmv(c.Ax, cuda(B)).cpu().numpy()
+    ZT = M.apply(cuda(B), transpose=True).cpu().numpy()
+    for j in range(R):
+        assert rel(Z[:, j], c.O.apply(B[:, j])) <= 1e-12
+        assert rel(ZT[:, j], c.O.apply(B[:, j], transpose=True)) <= 1e-12
+        assert rel(Y[:, j], oracle_mod.spmv(c.s.nb, c.s.bs, c.s.Ap, c.s.Aj, c.s.Ax, B[:, j])) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_solve_parity_small(api, oracle_mod, k):
+    c = Case(oracle_mod, synth.small_10cube(), k)
+    M = c.gpu(api)
+    x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
+    xo, ito, rro, sto = c.O.solve(c.s.Ax, c.rhs, rtol=1e-8)
+    assert st == 0 and sto == 0
+    (s1, it1, rr1), = info
+    assert abs(it1 - ito) <= 1 and rr1 <= 1e-8
+    x = x.cpu().numpy()
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-10
+
+
+def test_solve_transpose_parity(api, oracle_mod):
+    c = Case(oracle_mod, synth.small_10cube(), 1)
+    M = c.gpu(api, transpose=True)
+    g = np.random.default_rng(3).standard_normal(c.s.n)
+    lam, st, info = M.solve(c.Ax, cuda(g), rtol=1e-10, transpose=True)
+    lo, ito, rro, sto = c.O.solve(c.s.Ax, g, rtol=1e-10, transpose=True)
+    assert st == 0 and sto == 0 and abs(info[0][1] - ito) <= 1
+    assert np.linalg.norm(lam.cpu().numpy() - lo) / np.linalg.norm(lo) <= 1e-10
+
+
+def test_multi_rhs_solve(api, oracle_mod):
+    c = Case(oracle_mod, synth.small_10cube(), 1)
+    M = c.gpu(api)
+    B = synth.multi_rhs(c.s.n, 8, seed=41)
+    X, st, info = M.solve(c.Ax, cuda(B), rtol=1e-8)
+    assert st == 0
+    X = X.cpu().numpy()
+    for j in range(8):
+        xo, ito, rro, sto = c.O.solve(c.s.Ax, B[:, j], rtol=1e-8)
+        assert info[j][0] == 0 and info[j][2] <= 1e-8 and abs(info[j][1] - ito) <= 1
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-10
+
+
+def test_fp32_factors(api, oracle_mod):
+    c = Case(oracle_mod, synth.small_10cube(), 1)
+    M = c.gpu(api, precision="fp32")
+    F32, D32 = M.factors_f32()
+    F32, D32 = F32.cpu().numpy(), D32.cpu().numpy()
+    # the FP32 bytes are the round-to-nearest-even of the FP64 factors
+    assert np.array_equal(F32, oracle_mod.round_f32(M.factors()[0].cpu().numpy()))
+    r = np.random.default_rng(5).standard_normal(c.s.n)
+    z = M.apply(cuda(r)).cpu().numpy()
+    zo = oracle_mod.apply(c.s.nb, c.s.bs, c.O.Pp, c.O.Pj, F32, D32, r)
+    assert rel(z, zo) <= 1e-12
+    x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
+    assert st == 0 and info[0][2] <= 1e-8
+
+
+def test_singular_pivot(api, oracle_mod):
+    s = synth.reservoir(5, 4, 3, 3, seed=8)
+    Ax = s.Ax.copy()
+    rows = np.repeat(np.arange(s.nb), np.diff(s.Ap))
+    d = np.nonzero(s.Aj == rows)[0][7]
+    Ax[d * 9] = np.nan          # non-finite pivot block in block row 7
+    M = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, 0)
+    assert M.factor(cuda(Ax)) == 7
+    with pytest.raises(oracle_mod.OracleError) as ei:
+        oracle_mod.factor(s.nb, s.bs, s.Ap, s.Aj, Ax, s.Ap, s.Aj)
+    assert ei.value.row == 7
+
+
+def test_grad_A(api, oracle_mod):
+    s = synth.reservoir(5, 4, 3, 4, seed=21)
+    M = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, 1)
+    rng = np.random.default_rng(0)
+    lam, x = rng.standard_normal(s.n), rng.standard_normal(s.n)
+    dA = M.grad_A(cuda(lam), cuda(x)).cpu().numpy()
+    assert rel(dA, oracle_mod.grad_A(s.nb, s.bs, s.Ap, s.Aj, lam, x)) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [0, 1])
+def test_layered_full_size_apply_spmv(api, oracle_mod, k):
+    s = synth.layered_60x220x85()
+    c = Case(oracle_mod, s, k)
+    M = c.gpu(api, mode=1)
+    F, D = M.factors()
+    gL, gU = factor_parts(c.O, s, F.cpu().numpy())
+    oL, oU = factor_parts(c.O, s, c.O.F)
+    assert rel(gL, oL) <= 1e-12 and rel(gU, oU) <= 1e-12
+    assert rel(D.cpu().numpy(), c.O.Dinv) <= 1e-12
+    r = np.random.default_rng(11).standard_normal(s.n)
+    assert rel(M.apply(cuda(r)).cpu().numpy(), c.O.apply(r)) <= 1e-12
+    assert rel(M.spmv(c.Ax, cuda(r)).cpu().numpy(), oracle_mod.spmv(s.nb, s.bs, s.Ap, s.Aj, s.Ax, r)) <= 1e-12
+    M.check()
+
+
+def test_mid_full_size_solve(api, oracle_mod):
+    s = synth.mid_64cube()
+    c = Case(oracle_mod, s, 1)
+    M = c.gpu(api, mode=1)
+    x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
+    xo, ito, rro, sto = c.O.solve(s.Ax, c.rhs, rtol=1e-8)
+    assert st == 0 and sto == 0 and abs(info[0][1] - ito) <= 1 and info[0][2] <= 1e-8
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-10

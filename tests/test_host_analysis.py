@@ -1,0 +1,122 @@
+"""Host side of the library, on the CPU: the C ABI loads and exports every
+symbol include/bilu.h declares, and the symbolic phase and level sets are
+bit-exact with the oracle.  No GPU call is made here."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1703_01325_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_1703_01325_amd import _native
+    return _native
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "bilu.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bilu_[A-Za-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(N):
+    decl = declared_symbols()
+    assert len(decl) >= 15
+    assert sorted(N.EXPORTS) == decl
+    out = subprocess.run(["nm", "-D", "--defined-only", N.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (bilu_[A-Za-z0-9_]+)$", out, flags=re.M))
+    for name in decl:
+        assert name in exported, name
+        assert getattr(N.lib, name) is not None
+
+
+def lib_vs_oracle(N, O, nb, bs, Ap, Aj, k, transpose=True):
+    ctx = N.bilu_analyze(nb, bs, Ap, Aj, k, N.WANT_TRANSPOSE if transpose else 0)
+    try:
+        N.bilu_validate(ctx)
+        Pp, Pj, lev = N.bilu_get_pattern(ctx)
+        oPp, oPj, olev = O.symbolic(nb, Ap, Aj, k)
+        assert np.array_equal(Pp, oPp) and np.array_equal(Pj, oPj) and np.array_equal(lev, olev)
+        for w in range(4 if transpose else 2):
+            lp, lr = N.bilu_get_levels(ctx, w)
+            olp, olr = O.level_sets(*O.levels(nb, oPp, oPj, w))
+            assert np.array_equal(lp, olp) and np.array_equal(lr, olr), w
+        info = N.bilu_get_info(ctx)
+        rows = np.repeat(np.arange(nb), np.diff(Pp))
+        assert info.nnzb_L == int((Pj < rows).sum()) and info.nnzb_U == int((Pj > rows).sum())
+        assert info.nnzb_P == Pj.size and info.nnzb_A == Aj.size
+    finally:
+        N.bilu_destroy(ctx)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("k", [0, 1, 2, 4])
+def test_random_patterns_bit_exact(N, oracle_mod, seed, k):
+    nb = 60
+    Ap, Aj = synth.random_block_pattern(nb, 0.05, seed, symmetric=(seed % 2 == 0))
+    lib_vs_oracle(N, oracle_mod, nb, 1 + seed % 8, Ap, Aj, k)
+
+
+@pytest.mark.parametrize("grid,k", [((10, 10, 10), 0), ((10, 10, 10), 1), ((7, 5, 4), 2),
+                                    ((3, 9, 2), 3), ((1, 1, 1), 0), ((12, 1, 1), 1)])
+def test_grid_patterns_bit_exact(N, oracle_mod, grid, k):
+    Ap, Aj = synth.stencil7_pattern(*grid)
+    nb = int(np.prod(grid))
+    lib_vs_oracle(N, oracle_mod, nb, 3, Ap, Aj, k)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [1, 2])
+def test_mid_grid_bit_exact(N, oracle_mod, k):
+    Ap, Aj = synth.stencil7_pattern(64, 64, 64)
+    lib_vs_oracle(N, oracle_mod, 64 ** 3, 3, Ap, Aj, k, transpose=False)
+
+
+def test_large_k_full_fill(N, oracle_mod):
+    nb = 40
+    Ap, Aj = synth.random_block_pattern(nb, 0.06, 99)
+    lib_vs_oracle(N, oracle_mod, nb, 2, Ap, Aj, nb)
+
+
+def test_pattern_errors(N):
+    Ap = np.array([0, 2, 4], np.int32)
+    cases = [
+        (np.array([1, 0, 0, 1], np.int32), Ap, N.ERR_PATTERN),         # unsorted
+        (np.array([0, 0, 0, 1], np.int32), Ap, N.ERR_PATTERN),         # duplicate
+        (np.array([0, 2, 0, 1], np.int32), Ap, N.ERR_PATTERN),         # out of range
+        (np.array([1, 0], np.int32), np.array([0, 1, 2], np.int32), N.ERR_MISSING_DIAG),
+    ]
+    for Aj, ap, code in cases:
+        with pytest.raises(N.BiluError) as ei:
+            N.bilu_analyze(2, 3, ap, Aj, 0)
+        assert ei.value.code == code
+    for bs in (0, 9):
+        with pytest.raises(N.BiluError) as ei:
+            N.bilu_analyze(2, bs, Ap, np.array([0, 1, 0, 1], np.int32), 0)
+        assert ei.value.code == N.ERR_ARG
+    with pytest.raises(N.BiluError):
+        N.bilu_analyze(2, 3, Ap, np.array([0, 1, 0, 1], np.int32), -1)
+
+
+def test_gpu_calls_need_factor_first(N):
+    Ap, Aj = synth.stencil7_pattern(3, 3, 1)
+    ctx = N.bilu_analyze(9, 2, Ap, Aj, 0)
+    try:
+        # state errors are detected on the host before anything touches a GPU
+        with pytest.raises(N.BiluError) as ei:
+            N.bilu_apply(ctx, 1, 2, 1, 0)
+        assert ei.value.code == N.ERR_STATE
+        with pytest.raises(N.BiluError) as ei:
+            N.bilu_factor_diag(ctx, 0, 0)
+        assert ei.value.code == N.ERR_STATE
+        with pytest.raises(N.BiluError) as ei:
+            N.bilu_get_levels(ctx, N.SWEEP_UT)
+        assert ei.value.code == N.ERR_STATE
+    finally:
+        N.bilu_destroy(ctx)
