@@ -170,7 +170,7 @@ bilu_status bilu_get_factors(const bilu_ctx* ctx, double* F_dev, double* Dinv_de
                              hipStream_t stream);
 
 /* Same, for the FP32 factors the sweeps read when precision was FP32. */
-bilu_status bilu_get_factors_f32(const bilu_ctx* ctx, float* F_dev, float* Dinv_dev,
+bilu_status bilu_get_factors_f32(bilu_ctx* ctx, float* F_dev, float* Dinv_dev,
                                  hipStream_t stream);
 
 /*
@@ -209,13 +209,41 @@ bilu_status bilu_solve(bilu_ctx* ctx, const double* Ax_dev, const double* b, dou
 bilu_status bilu_grad_A(bilu_ctx* ctx, const double* lambda, const double* x, double* dAx_dev,
                         hipStream_t stream);
 
-/* Sweep scheduling: 0 = one kernel launch per level, 1 = one persistent
- * launch per sweep with per-row ready flags (default). */
-bilu_status bilu_set_sweep_mode(bilu_ctx* ctx, int mode);
+/* Launch tuning knobs (bilu_tune).  None changes any result bit. */
+enum {
+    BILU_TUNE_SWEEP_MODE = 0, /* 0: one launch per level; 1: one persistent launch per
+                                 sweep over level chunks (default); 2: one persistent
+                                 launch per sweep over row tiles (several right-hand
+                                 sides use mode 1)                                   */
+    BILU_TUNE_TILE_ROWS = 1,  /* block rows per tile in mode 2 (capped so a tile's
+                                 values fit 64 KiB of LDS)                           */
+    BILU_TUNE_BLOCKS = 3      /* persistent grid in workgroups, 0 = automatic        */
+};
+bilu_status bilu_tune(bilu_ctx* ctx, int param, int value);
 
 /* Synchronises `stream` and reports (then clears) a timeout recorded by any
  * sweep since the last check: BILU_ERR_TIMEOUT, else BILU_OK. */
 bilu_status bilu_check(bilu_ctx* ctx, hipStream_t stream);
+
+/* Kernel classes timed by bilu_timing. */
+enum {
+    BILU_K_SWEEP_L = 0, BILU_K_SWEEP_U = 1, BILU_K_SWEEP_UT = 2, BILU_K_SWEEP_LT = 3,
+    BILU_K_SPMV = 4, BILU_K_FACTOR = 5, BILU_K_SPLIT = 6, BILU_K_COUNT = 7
+};
+
+typedef struct {
+    int64_t launches;   /* timed launches (a whole factorisation counts once) */
+    double total_ms;    /* summed HIP-event time between their start and end  */
+} bilu_kernel_time;
+
+/* enable = 1 clears the counters and starts recording a HIP event pair on
+ * the launch stream around every sweep launch, SpMV launch, numeric
+ * factorisation and split; enable = 0 stops recording. */
+bilu_status bilu_timing(bilu_ctx* ctx, int enable);
+
+/* Synchronises `stream` and returns the accumulated times in
+ * out[BILU_K_COUNT] (host array). */
+bilu_status bilu_timing_read(bilu_ctx* ctx, hipStream_t stream, bilu_kernel_time* out);
 
 void bilu_destroy(bilu_ctx* ctx);
 const char* bilu_status_string(int status);

@@ -29,8 +29,11 @@ EXPORTS = (
     "bilu_analyze", "bilu_get_pattern", "bilu_get_levels", "bilu_get_info", "bilu_validate",
     "bilu_factor_numeric", "bilu_factor_diag", "bilu_get_factors", "bilu_get_factors_f32",
     "bilu_apply", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
-    "bilu_set_sweep_mode", "bilu_check", "bilu_destroy", "bilu_status_string",
+    "bilu_tune", "bilu_check", "bilu_timing", "bilu_timing_read",
+    "bilu_destroy", "bilu_status_string",
 )
+K_SWEEP_L, K_SWEEP_U, K_SWEEP_UT, K_SWEEP_LT, K_SPMV, K_FACTOR, K_SPLIT, K_COUNT = range(8)
+K_NAMES = ("sweep_L", "sweep_U", "sweep_UT", "sweep_LT", "spmv", "factor", "split")
 
 
 class BiluInfo(ct.Structure):
@@ -38,6 +41,10 @@ class BiluInfo(ct.Structure):
                 ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
                 ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
                 ("sweep_slots", ct.c_int64 * 4)]
+
+
+class KernelTime(ct.Structure):
+    _fields_ = [("launches", ct.c_int64), ("total_ms", ct.c_double)]
 
 
 class SolveOpts(ct.Structure):
@@ -75,8 +82,10 @@ def _load():
     L.bilu_spmv.argtypes = [VP, P, P, P, I, I, P]
     L.bilu_solve.argtypes = [VP, P, P, P, I, ct.POINTER(SolveOpts), ct.POINTER(RhsInfo), I, P]
     L.bilu_grad_A.argtypes = [VP, P, P, P, P]
-    L.bilu_set_sweep_mode.argtypes = [VP, I]
+    L.bilu_tune.argtypes = [VP, I, I]
     L.bilu_check.argtypes = [VP, P]
+    L.bilu_timing.argtypes = [VP, I]
+    L.bilu_timing_read.argtypes = [VP, P, ct.POINTER(KernelTime)]
     L.bilu_destroy.argtypes = [VP]
     L.bilu_destroy.restype = None
     L.bilu_status_string.argtypes = [I]
@@ -203,12 +212,25 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
                            ct.c_void_p(stream)), "bilu_grad_A")
 
 
-def bilu_set_sweep_mode(ctx, mode):
-    _check(lib.bilu_set_sweep_mode(ctx, int(mode)), "bilu_set_sweep_mode")
+TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS = 0, 1, 3
+
+
+def bilu_tune(ctx, param, value):
+    _check(lib.bilu_tune(ctx, int(param), int(value)), "bilu_tune")
 
 
 def bilu_check(ctx, stream):
     _check(lib.bilu_check(ctx, ct.c_void_p(stream)), "bilu_check")
+
+
+def bilu_timing(ctx, enable):
+    _check(lib.bilu_timing(ctx, int(enable)), "bilu_timing")
+
+
+def bilu_timing_read(ctx, stream):
+    out = (KernelTime * K_COUNT)()
+    _check(lib.bilu_timing_read(ctx, ct.c_void_p(stream), out), "bilu_timing_read")
+    return {K_NAMES[i]: (out[i].launches, out[i].total_ms) for i in range(K_COUNT)}
 
 
 def bilu_destroy(ctx):

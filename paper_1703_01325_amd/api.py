@@ -50,7 +50,13 @@ class BlockILU:
         return N.bilu_get_levels(self._ctx, sweep)
 
     def set_sweep_mode(self, mode):
-        N.bilu_set_sweep_mode(self._ctx, mode)
+        N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
+
+    def tune(self, mode=None, tile_rows=None, blocks=None):
+        """Launch knobs of the sweeps (results are bit-identical for all)."""
+        for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks)):
+            if val is not None:
+                N.bilu_tune(self._ctx, key, val)
 
     # ---- GPU --------------------------------------------------------------
     def factor(self, Ax: torch.Tensor, precision: str = "fp64"):
@@ -120,6 +126,13 @@ class BlockILU:
         D = torch.empty(self.nb * bb, dtype=torch.float32, device="cuda")
         N.bilu_get_factors_f32(self._ctx, F.data_ptr(), D.data_ptr(), _stream())
         return F, D
+
+    def timing(self, enable: bool):
+        N.bilu_timing(self._ctx, int(enable))
+
+    def timing_read(self):
+        """{kernel class: (launches, total ms)} from HIP events on the launch stream."""
+        return N.bilu_timing_read(self._ctx, _stream())
 
     def check(self):
         N.bilu_check(self._ctx, _stream())

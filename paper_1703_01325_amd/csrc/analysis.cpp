@@ -229,6 +229,87 @@ void build_sweep(const Host& h, int which, int rpc, HostSweep& s)
     s.built = true;
 }
 
+void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
+{
+    const int nb = h.nb;
+    const bool forward = (which == BILU_SWEEP_L || which == BILU_SWEEP_UT);
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, which, dptr, deps);
+    s.which = which;
+    s.rpc = rpc;
+    s.tile_rows = tile_rows;
+    s.ntiles = (nb + tile_rows - 1) / tile_rows;
+    s.tile_chunk_ptr.assign(static_cast<size_t>(s.ntiles) + 1, 0);
+    s.tile_lo.assign(static_cast<size_t>(s.ntiles), 0);
+    s.chunk_off.assign(1, 0);
+    s.rows.clear();
+    s.deps.clear();
+    s.src.clear();
+    std::vector<int32_t> il(static_cast<size_t>(tile_rows));   // level inside the tile
+    std::vector<int32_t> order;
+    for (int t = 0; t < s.ntiles; ++t) {
+        int lo, hi;
+        if (forward) {
+            lo = t * tile_rows;
+            hi = std::min(nb, lo + tile_rows) - 1;
+        } else {
+            hi = nb - 1 - t * tile_rows;
+            lo = std::max(0, hi - tile_rows + 1);
+        }
+        s.tile_lo[t] = lo;
+        s.tile_chunk_ptr[t] = static_cast<int32_t>(s.chunk_off.size() - 1);
+        // levels over the dependencies inside [lo, hi], rows in sweep order
+        int nlev = 0;
+        for (int step = 0; step <= hi - lo; ++step) {
+            const int32_t i = forward ? lo + step : hi - step;
+            int32_t l = 0;
+            for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+                const int32_t j = deps[d].col;
+                if (j >= lo && j <= hi) l = std::max(l, il[j - lo] + 1);
+            }
+            il[i - lo] = l;
+            nlev = std::max(nlev, l + 1);
+        }
+        order.resize(static_cast<size_t>(hi - lo + 1));
+        std::iota(order.begin(), order.end(), lo);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            if (il[a - lo] != il[b - lo]) return il[a - lo] < il[b - lo];
+            return (dptr[a + 1] - dptr[a]) > (dptr[b + 1] - dptr[b]);
+        });
+        size_t pos = 0;
+        while (pos < order.size()) {
+            const int32_t lev = il[order[pos] - lo];
+            size_t cn = 0;
+            while (pos + cn < order.size() && cn < static_cast<size_t>(rpc) && il[order[pos + cn] - lo] == lev) ++cn;
+            const int32_t w = dptr[order[pos] + 1] - dptr[order[pos]];
+            const int64_t base = s.chunk_off.back();
+            s.chunk_off.push_back(base + static_cast<int64_t>(w) * rpc);
+            s.deps.resize(static_cast<size_t>(base) + static_cast<size_t>(w) * rpc, -1);
+            s.src.resize(s.deps.size(), -1);
+            for (int q = 0; q < rpc; ++q) {
+                if (static_cast<size_t>(q) >= cn) {
+                    s.rows.push_back(-1);
+                    continue;
+                }
+                const int32_t i = order[pos + q];
+                s.rows.push_back(i);
+                for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+                    const size_t slot = static_cast<size_t>(base) + static_cast<size_t>(d - dptr[i]) * rpc + q;
+                    const int32_t j = deps[d].col;
+                    s.deps[slot] = (j >= lo && j <= hi) ? -2 - (j - lo) : j;
+                    s.src[slot] = deps[d].src;
+                }
+            }
+            pos += cn;
+        }
+    }
+    s.nchunks = static_cast<int>(s.chunk_off.size() - 1);
+    s.tile_chunk_ptr[s.ntiles] = s.nchunks;
+    s.nslots = s.chunk_off.back();
+    s.built = true;
+}
+
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags)
 {
     if (nb < 1 || bs < 1 || bs > kMaxBs || k < 0 || !Ap || !Aj) return BILU_ERR_ARG;
@@ -356,6 +437,82 @@ int validate_layout(const Host& h)
                 if (r >= 0 && seen != ndep[r]) return BILU_ERR_STATE;
             }
         }
+    }
+    for (int w = 0; w < 4; ++w) {
+        const HostTiled& s = h.tiled[w];
+        if (!s.built) continue;
+        const int rpc = s.rpc;
+        const bool forward = (w == BILU_SWEEP_L || w == BILU_SWEEP_UT);
+        const bool rowwise = (w == BILU_SWEEP_L || w == BILU_SWEEP_U);
+        if (rpc < 1 || rpc * h.bs > kWave || s.tile_rows < 1) return BILU_ERR_STATE;
+        if (static_cast<int>(s.tile_chunk_ptr.size()) != s.ntiles + 1 || s.tile_chunk_ptr[0] != 0 ||
+            s.tile_chunk_ptr[s.ntiles] != s.nchunks || static_cast<int>(s.tile_lo.size()) != s.ntiles)
+            return BILU_ERR_STATE;
+        if (static_cast<int>(s.chunk_off.size()) != s.nchunks + 1 || s.chunk_off[0] != 0 ||
+            s.chunk_off.back() != s.nslots || static_cast<int64_t>(s.deps.size()) != s.nslots ||
+            static_cast<int64_t>(s.src.size()) != s.nslots ||
+            static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc)
+            return BILU_ERR_STATE;
+        std::vector<int32_t> tile_of(static_cast<size_t>(nb), -1), chunk_of(static_cast<size_t>(nb), -1);
+        for (int t = 0; t < s.ntiles; ++t) {
+            const int lo = s.tile_lo[t];
+            if (lo < 0 || lo >= nb) return BILU_ERR_STATE;
+            if (s.tile_chunk_ptr[t + 1] < s.tile_chunk_ptr[t]) return BILU_ERR_STATE;
+            for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
+                const int64_t span = s.chunk_off[c + 1] - s.chunk_off[c];
+                if (span < 0 || span % rpc != 0) return BILU_ERR_STATE;
+                for (int q = 0; q < rpc; ++q) {
+                    const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
+                    if (r < -1 || r >= nb) return BILU_ERR_STATE;
+                    if (r < 0) continue;
+                    if (r < lo || r - lo >= s.tile_rows || tile_of[r] != -1) return BILU_ERR_STATE;
+                    tile_of[r] = t;
+                    chunk_of[r] = c;
+                }
+            }
+        }
+        for (int i = 0; i < nb; ++i)
+            if (tile_of[i] < 0) return BILU_ERR_STATE;
+        std::vector<int32_t> ndep(static_cast<size_t>(nb), 0), seen(static_cast<size_t>(nb), 0);
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e) {
+                const int32_t j = h.Pj[e];
+                if (w == BILU_SWEEP_L && j < i) ndep[i]++;
+                if (w == BILU_SWEEP_U && j > i) ndep[i]++;
+                if (w == BILU_SWEEP_UT && j > i) ndep[j]++;
+                if (w == BILU_SWEEP_LT && j < i) ndep[j]++;
+            }
+        for (int t = 0; t < s.ntiles; ++t) {
+            const int lo = s.tile_lo[t];
+            for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
+                const int64_t off = s.chunk_off[c];
+                const int64_t width = (s.chunk_off[c + 1] - off) / rpc;
+                for (int q = 0; q < rpc; ++q) {
+                    const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
+                    for (int64_t k = 0; k < width; ++k) {
+                        const int64_t slot = off + k * rpc + q;
+                        const int32_t code = s.deps[slot];
+                        const int64_t e = s.src[slot];
+                        if (code == -1 && e == -1) continue;
+                        if (r < 0 || code == -1 || e < 0 || e >= nP) return BILU_ERR_STATE;
+                        int32_t j;
+                        if (code <= -2) {
+                            j = lo + (-code - 2);
+                            if (j < 0 || j >= nb || tile_of[j] != t || chunk_of[j] >= c) return BILU_ERR_STATE;
+                        } else {
+                            j = code;
+                            if (j >= nb || tile_of[j] >= t) return BILU_ERR_STATE;   // strictly earlier tile
+                        }
+                        if (forward ? j >= r : j <= r) return BILU_ERR_STATE;
+                        const int32_t pi = h.Prow[e], pj = h.Pj[e];
+                        if (rowwise ? (pi != r || pj != j) : (pi != j || pj != r)) return BILU_ERR_STATE;
+                        ++seen[r];
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < nb; ++i)
+            if (seen[i] != ndep[i]) return BILU_ERR_STATE;
     }
     return BILU_OK;
 }

@@ -16,11 +16,18 @@
 using namespace bilu;
 using dev::KState;
 using dev::SweepArgs;
+using dev::TiledArgs;
 
-#define CK(call)                                   \
-    do {                                           \
+#define CK(call)                                       \
+    do {                                               \
         if ((call) != hipSuccess) return BILU_ERR_HIP; \
     } while (0)
+
+namespace {
+constexpr int kFormLevel = 0;   // level-chunk layout (sweep modes 0 and 1)
+constexpr int kFormTiled = 1;   // tiled layout (sweep mode 2)
+constexpr int kMaxTileDoubles = 8192;   // LDS of one tiled wavefront: 64 KiB
+}  // namespace
 
 struct bilu_ctx {
     Host h;
@@ -28,21 +35,23 @@ struct bilu_ctx {
     int num_cu = 0;
     bool dev_ready = false;
     bool factored = false;
-    bool laid_out = false;
+    bool split_done = false;
     int precision = BILU_FACTORS_FP64;
     int sweep_mode = 1;
+    int tile_rows = 1024;
+    int blocks_override = 0;
     unsigned int spin_limit = 1u << 24;
 
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
     int32_t *d_Pp = nullptr, *d_Pj = nullptr, *d_Prow = nullptr, *d_Pdiag = nullptr, *d_PtoA = nullptr;
-    int32_t *d_Lrows = nullptr;
+    int32_t* d_Lrows = nullptr;
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
-    int64_t *d_ATsrc = nullptr;
+    int64_t* d_ATsrc = nullptr;
     double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
-    DevSweep ds[4];
-    int persist_blocks[4] = {0, 0, 0, 0};
+    DevSweep ds[2][4];          // [form][sweep]
+    bool form_uploaded[2] = {false, false};
 
-    double* d_y = nullptr;
+    double* d_y = nullptr;      // intermediate of an application, kept at kNotReady
     size_t y_cap = 0;
     int* d_bad = nullptr;
     int* d_status = nullptr;
@@ -54,10 +63,40 @@ struct bilu_ctx {
     double* d_part = nullptr;
     KState* d_state = nullptr;
 
+    // HIP-event timing of kernel classes (bilu_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;   // (class, index of start event)
+
     std::vector<void*> allocs;
 };
 
 namespace {
+
+// Records the start event of a timed region; returns its slot or -1.
+long timing_begin(bilu_ctx* c, int cls, hipStream_t s)
+{
+    if (!c->timing) return -1;
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            c->ev_pool.push_back(e);
+        }
+    }
+    const size_t i = c->ev_used;
+    c->ev_used += 2;
+    if (hipEventRecord(c->ev_pool[i], s) != hipSuccess) return -1;
+    c->ev_marks.emplace_back(cls, i);
+    return static_cast<long>(i);
+}
+
+void timing_end(bilu_ctx* c, long slot, hipStream_t s)
+{
+    if (slot < 0) return;
+    (void)hipEventRecord(c->ev_pool[static_cast<size_t>(slot) + 1], s);
+}
 
 template <typename T>
 bilu_status dalloc(bilu_ctx* c, T** p, size_t count)
@@ -98,27 +137,27 @@ int grid_for(int64_t work, int threads = 256, int cap = 65536)
     return static_cast<int>(g);
 }
 
+bool fused_sweep(int w) { return w == BILU_SWEEP_U || w == BILU_SWEEP_LT; }
+bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; }
+
 // ----- templated launch helpers ---------------------------------------------
-template <int B, typename T, int RT>
-void launch_sweep_t(int blocks, hipStream_t s, const SweepArgs& a)
-{
-    hipLaunchKernelGGL((dev::k_sweep<B, T, RT>), dim3(blocks), dim3(dev::kThreads), 0, s, a);
-}
+#define BILU_SWITCH_B(bs, CALL)     \
+    switch (bs) {                   \
+    case 1: { constexpr int B = 1; CALL; return true; } \
+    case 2: { constexpr int B = 2; CALL; return true; } \
+    case 3: { constexpr int B = 3; CALL; return true; } \
+    case 4: { constexpr int B = 4; CALL; return true; } \
+    case 5: { constexpr int B = 5; CALL; return true; } \
+    case 6: { constexpr int B = 6; CALL; return true; } \
+    case 7: { constexpr int B = 7; CALL; return true; } \
+    case 8: { constexpr int B = 8; CALL; return true; } \
+    }                               \
+    return false;
 
 template <typename T, int RT>
 bool launch_sweep_b(int bs, int blocks, hipStream_t s, const SweepArgs& a)
 {
-    switch (bs) {
-    case 1: launch_sweep_t<1, T, RT>(blocks, s, a); return true;
-    case 2: launch_sweep_t<2, T, RT>(blocks, s, a); return true;
-    case 3: launch_sweep_t<3, T, RT>(blocks, s, a); return true;
-    case 4: launch_sweep_t<4, T, RT>(blocks, s, a); return true;
-    case 5: launch_sweep_t<5, T, RT>(blocks, s, a); return true;
-    case 6: launch_sweep_t<6, T, RT>(blocks, s, a); return true;
-    case 7: launch_sweep_t<7, T, RT>(blocks, s, a); return true;
-    case 8: launch_sweep_t<8, T, RT>(blocks, s, a); return true;
-    }
-    return false;
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep<B, T, RT>), dim3(blocks), dim3(dev::kThreads), 0, s, a))
 }
 
 bool launch_sweep(int bs, int prec, int R, int blocks, hipStream_t s, const SweepArgs& a)
@@ -128,80 +167,79 @@ bool launch_sweep(int bs, int prec, int R, int blocks, hipStream_t s, const Swee
     return R == 1 ? launch_sweep_b<double, 1>(bs, blocks, s, a) : launch_sweep_b<double, 8>(bs, blocks, s, a);
 }
 
-template <int B, int RT, bool TR>
-void launch_spmv_t(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
-                   const double* x, double* y, int R, hipStream_t s)
+template <typename T>
+bool launch_tiled_b(int bs, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
-    constexpr int RPC = 64 / B;
-    const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
-    const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
-    hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src,
-                       Ax, x, y, R);
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep_tiled<B, T>), dim3(blocks), dim3(64), lds, s, a))
 }
 
 template <int RT, bool TR>
-bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src,
-                   const double* Ax, const double* x, double* y, int R, hipStream_t s)
+bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
+                   const double* x, double* y, int R, hipStream_t s)
 {
-    switch (bs) {
-    case 1: launch_spmv_t<1, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 2: launch_spmv_t<2, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 3: launch_spmv_t<3, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 4: launch_spmv_t<4, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 5: launch_spmv_t<5, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 6: launch_spmv_t<6, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 7: launch_spmv_t<7, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 8: launch_spmv_t<8, RT, TR>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    }
-    return false;
-}
-
-template <int B>
-void launch_factor_t(const int32_t* rows, int nrows, bilu_ctx* c, hipStream_t s)
-{
-    hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows, c->d_Pp, c->d_Pj,
-                       c->d_Pdiag, c->d_P, c->d_Dinv, c->d_bad);
+    BILU_SWITCH_B(bs, {
+        constexpr int RPC = 64 / B;
+        const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
+        const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+        hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src,
+                           Ax, x, y, R);
+    })
 }
 
 bool launch_factor(int bs, const int32_t* rows, int nrows, bilu_ctx* c, hipStream_t s)
 {
-    switch (bs) {
-    case 1: launch_factor_t<1>(rows, nrows, c, s); return true;
-    case 2: launch_factor_t<2>(rows, nrows, c, s); return true;
-    case 3: launch_factor_t<3>(rows, nrows, c, s); return true;
-    case 4: launch_factor_t<4>(rows, nrows, c, s); return true;
-    case 5: launch_factor_t<5>(rows, nrows, c, s); return true;
-    case 6: launch_factor_t<6>(rows, nrows, c, s); return true;
-    case 7: launch_factor_t<7>(rows, nrows, c, s); return true;
-    case 8: launch_factor_t<8>(rows, nrows, c, s); return true;
-    }
-    return false;
-}
-
-template <int B>
-void launch_split_t(bilu_ctx* c, hipStream_t s)
-{
-    const int64_t nP = static_cast<int64_t>(c->h.Pj.size());
-    hipLaunchKernelGGL((dev::k_split<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP, c->d_Prow, c->d_Pj,
-                       c->d_P, c->d_Dinv, c->d_F);
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows,
+                                         c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_P, c->d_Dinv, c->d_bad))
 }
 
 bool launch_split(bilu_ctx* c, hipStream_t s)
 {
-    switch (c->h.bs) {
-    case 1: launch_split_t<1>(c, s); return true;
-    case 2: launch_split_t<2>(c, s); return true;
-    case 3: launch_split_t<3>(c, s); return true;
-    case 4: launch_split_t<4>(c, s); return true;
-    case 5: launch_split_t<5>(c, s); return true;
-    case 6: launch_split_t<6>(c, s); return true;
-    case 7: launch_split_t<7>(c, s); return true;
-    case 8: launch_split_t<8>(c, s); return true;
-    }
-    return false;
+    const int64_t nP = static_cast<int64_t>(c->h.Pj.size());
+    BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_split<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP,
+                                              c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, c->d_F))
 }
 
 // ----- device setup --------------------------------------------------------
+bilu_status upload_form(bilu_ctx* c, int form)
+{
+    Host& h = c->h;
+    bilu_status st;
+    for (int w = 0; w < 4; ++w) {
+        DevSweep& d = c->ds[form][w];
+        if (form == kFormLevel) {
+            const HostSweep& hs = h.sweep[w];
+            if (!hs.built) continue;
+            if ((st = upload(c, &d.chunk_off, hs.chunk_off)) || (st = upload(c, &d.rows, hs.rows)) ||
+                (st = upload(c, &d.cols, hs.cols)) || (st = upload(c, &d.src, hs.src)))
+                return st;
+        } else {
+            if (!h.sweep[w].built) continue;
+            HostTiled& ht = h.tiled[w];
+            if (!ht.built) build_tiled(h, w, h.rpc, c->tile_rows, ht);
+            if ((st = upload(c, &d.chunk_off, ht.chunk_off)) || (st = upload(c, &d.rows, ht.rows)) ||
+                (st = upload(c, &d.cols, ht.deps)) || (st = upload(c, &d.src, ht.src)) ||
+                (st = upload(c, &d.tile_chunk_ptr, ht.tile_chunk_ptr)) || (st = upload(c, &d.tile_lo, ht.tile_lo)))
+                return st;
+        }
+        d.vals_precision = -1;
+    }
+    c->form_uploaded[form] = true;
+    return BILU_OK;
+}
+
+void free_form(bilu_ctx* c, int form)
+{
+    for (int w = 0; w < 4; ++w) {
+        DevSweep& d = c->ds[form][w];
+        for (void* p : {static_cast<void*>(d.chunk_off), static_cast<void*>(d.rows), static_cast<void*>(d.cols),
+                        static_cast<void*>(d.src), static_cast<void*>(d.tile_chunk_ptr),
+                        static_cast<void*>(d.tile_lo), d.vals, d.dinv})
+            dfree(c, p);
+        d = DevSweep{};
+    }
+    c->form_uploaded[form] = false;
+}
+
 bilu_status ensure_device(bilu_ctx* c)
 {
     if (c->dev_ready) {
@@ -240,31 +278,59 @@ bilu_status ensure_device(bilu_ctx* c)
     CK(hipMemset(c->d_status, 0, sizeof(int)));
     CK(hipMemset(c->d_done, 0, sizeof(unsigned int)));
     CK(hipMemset(c->d_ticket, 0, sizeof(unsigned long long)));
-    for (int w = 0; w < 4; ++w) {
-        HostSweep& hs = h.sweep[w];
-        if (!hs.built) continue;
-        DevSweep& d = c->ds[w];
-        if ((st = upload(c, &d.chunk_off, hs.chunk_off)) || (st = upload(c, &d.rows, hs.rows)) ||
-            (st = upload(c, &d.cols, hs.cols)) || (st = upload(c, &d.src, hs.src)) ||
-            (st = dalloc(c, &d.flags, static_cast<size_t>(h.nb))))
-            return st;
-        CK(hipMemset(d.flags, 0, static_cast<size_t>(h.nb) * sizeof(int32_t)));
-        d.epoch = 0;
-        // persistent grid: enough wavefronts to fill the device, never more than chunks
-        int occ = 0;
-        void* fn = h.bs == 3 ? reinterpret_cast<void*>(dev::k_sweep<3, double, 1>)
-                             : reinterpret_cast<void*>(dev::k_sweep<4, double, 1>);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, dev::kThreads, 0) != hipSuccess || occ < 1)
-            occ = 2;
-        occ = std::min(occ, 8);
-        const int64_t want = (static_cast<int64_t>(hs.nchunks) + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
-        c->persist_blocks[w] = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, static_cast<int64_t>(c->num_cu) * occ)));
-    }
     c->dev_ready = true;
     return BILU_OK;
 }
 
-bilu_status ensure_y(bilu_ctx* c, int R)
+int form_of_mode(int mode) { return mode == 2 ? kFormTiled : kFormLevel; }
+
+// Factor values of one layout form in the current precision.
+bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
+{
+    Host& h = c->h;
+    const int bb = h.bs * h.bs;
+    const size_t esz = c->precision == BILU_FACTORS_FP32 ? sizeof(float) : sizeof(double);
+    bilu_status st;
+    if (!c->form_uploaded[form] && (st = upload_form(c, form))) return st;
+    for (int w = 0; w < 4; ++w) {
+        if (!h.sweep[w].built) continue;
+        DevSweep& d = c->ds[form][w];
+        if (d.vals_precision == c->precision) continue;
+        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots;
+        const int nchunks = form == kFormLevel ? h.sweep[w].nchunks : h.tiled[w].nchunks;
+        const int rpc = h.rpc;
+        dfree(c, d.vals);
+        dfree(c, d.dinv);
+        d.vals = d.dinv = nullptr;
+        char* p = nullptr;
+        if ((st = dalloc(c, &p, static_cast<size_t>(nslots) * bb * esz))) return st;
+        d.vals = p;
+        if (fused_sweep(w)) {
+            if ((st = dalloc(c, &p, static_cast<size_t>(nchunks) * rpc * bb * esz))) return st;
+            d.dinv = p;
+        }
+        const int tr = transposed_sweep(w) ? 1 : 0;
+        const int64_t nrs = static_cast<int64_t>(nchunks) * rpc;
+        if (c->precision == BILU_FACTORS_FP32) {
+            hipLaunchKernelGGL(dev::k_layout<float>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs, rpc,
+                               d.src, c->d_F, tr, static_cast<float*>(d.vals));
+            if (d.dinv)
+                hipLaunchKernelGGL(dev::k_layout_dinv<float>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
+                                   rpc, d.rows, c->d_Dinv, tr, static_cast<float*>(d.dinv));
+        } else {
+            hipLaunchKernelGGL(dev::k_layout<double>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs,
+                               rpc, d.src, c->d_F, tr, static_cast<double*>(d.vals));
+            if (d.dinv)
+                hipLaunchKernelGGL(dev::k_layout_dinv<double>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
+                                   rpc, d.rows, c->d_Dinv, tr, static_cast<double*>(d.dinv));
+        }
+        CK(hipGetLastError());
+        d.vals_precision = c->precision;
+    }
+    return BILU_OK;
+}
+
+bilu_status ensure_y(bilu_ctx* c, int R, hipStream_t s)
 {
     const size_t need = static_cast<size_t>(c->h.nb) * c->h.bs * R;
     if (c->y_cap >= need) return BILU_OK;
@@ -274,67 +340,105 @@ bilu_status ensure_y(bilu_ctx* c, int R)
     bilu_status st = dalloc(c, &c->d_y, need);
     if (st) return st;
     c->y_cap = need;
-    return BILU_OK;
-}
-
-bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, int R, int fuse, hipStream_t s)
-{
-    HostSweep& hs = c->h.sweep[which];
-    DevSweep& d = c->ds[which];
-    SweepArgs a{};
-    a.chunk_off = d.chunk_off;
-    a.rows = d.rows;
-    a.cols = d.cols;
-    a.vals = d.vals;
-    a.dinv = d.dinv;
-    a.rhs = rhs;
-    a.out = out;
-    a.flags = d.flags;
-    a.ticket = c->d_ticket;
-    a.done = c->d_done;
-    a.status = c->d_status;
-    a.nchunks = hs.nchunks;
-    a.R = R;
-    a.fuse = fuse;
-    a.spin_limit = c->spin_limit;
-    if (hs.nchunks == 0) return BILU_OK;
-    if (c->sweep_mode == 1) {
-        if (d.epoch >= INT_MAX - 1) {
-            hipLaunchKernelGGL(dev::k_fill_i32, dim3(grid_for(c->h.nb)), dim3(256), 0, s,
-                               static_cast<int64_t>(c->h.nb), d.flags, 0);
-            d.epoch = 0;
-        }
-        a.epoch = ++d.epoch;
-        a.persistent = 1;
-        const int blocks = c->persist_blocks[which];
-        a.total_waves = static_cast<unsigned int>(blocks) * dev::kWavesPerBlock;
-        if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
-    } else {
-        a.persistent = 0;
-        for (int l = 0; l < hs.nlev; ++l) {
-            a.chunk_begin = hs.level_chunk_ptr[l];
-            a.chunk_end = hs.level_chunk_ptr[l + 1];
-            const int n = a.chunk_end - a.chunk_begin;
-            if (n <= 0) continue;
-            const int blocks = (n + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
-            if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
-        }
-    }
+    hipLaunchKernelGGL(dev::k_fill_not_ready, dim3(grid_for(static_cast<int64_t>(need))), dim3(256), 0, s,
+                       static_cast<int64_t>(need), c->d_y);
     CK(hipGetLastError());
     return BILU_OK;
 }
 
+int persistent_blocks(bilu_ctx* c, int units, int units_per_block, int per_cu)
+{
+    const int want = std::max(1, (units + units_per_block - 1) / units_per_block);
+    const int cap = c->blocks_override > 0 ? c->blocks_override : c->num_cu * per_cu;
+    return std::max(1, std::min(want, cap));
+}
+
+bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, double* reset, int R, hipStream_t s)
+{
+    const int form = form_of_mode(c->sweep_mode == 2 && R > 1 ? 1 : c->sweep_mode);
+    const long tslot = timing_begin(c, BILU_K_SWEEP_L + which, s);
+    const int fuse = fused_sweep(which) ? 1 : 0;
+    if (form == kFormTiled) {
+        const HostTiled& ht = c->h.tiled[which];
+        const DevSweep& d = c->ds[kFormTiled][which];
+        TiledArgs a{};
+        a.tile_chunk_ptr = d.tile_chunk_ptr;
+        a.tile_lo = d.tile_lo;
+        a.chunk_off = d.chunk_off;
+        a.rows = d.rows;
+        a.deps = d.cols;
+        a.vals = d.vals;
+        a.dinv = d.dinv;
+        a.rhs = rhs;
+        a.out = out;
+        a.reset = reset;
+        a.ticket = c->d_ticket;
+        a.done = c->d_done;
+        a.status = c->d_status;
+        a.ntiles = ht.ntiles;
+        a.fuse = fuse;
+        a.spin_limit = c->spin_limit;
+        const int blocks = persistent_blocks(c, ht.ntiles, 1, 8);
+        a.total_waves = static_cast<unsigned int>(blocks);
+        const size_t lds = static_cast<size_t>(ht.tile_rows) * c->h.bs * sizeof(double);
+        const bool ok = c->precision == BILU_FACTORS_FP32 ? launch_tiled_b<float>(c->h.bs, blocks, lds, s, a)
+                                                          : launch_tiled_b<double>(c->h.bs, blocks, lds, s, a);
+        if (!ok) return BILU_ERR_ARG;
+    } else {
+        const HostSweep& hs = c->h.sweep[which];
+        const DevSweep& d = c->ds[kFormLevel][which];
+        SweepArgs a{};
+        a.chunk_off = d.chunk_off;
+        a.rows = d.rows;
+        a.cols = d.cols;
+        a.vals = d.vals;
+        a.dinv = d.dinv;
+        a.rhs = rhs;
+        a.out = out;
+        a.reset = reset;
+        a.ticket = c->d_ticket;
+        a.done = c->d_done;
+        a.status = c->d_status;
+        a.nchunks = hs.nchunks;
+        a.R = R;
+        a.fuse = fuse;
+        a.spin_limit = c->spin_limit;
+        if (c->sweep_mode != 0) {
+            a.persistent = 1;
+            const int blocks = persistent_blocks(c, hs.nchunks, dev::kWavesPerBlock, 1);
+            a.total_waves = static_cast<unsigned int>(blocks) * dev::kWavesPerBlock;
+            if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
+        } else {
+            a.persistent = 0;
+            for (int l = 0; l < hs.nlev; ++l) {
+                a.chunk_begin = hs.level_chunk_ptr[l];
+                a.chunk_end = hs.level_chunk_ptr[l + 1];
+                const int n = a.chunk_end - a.chunk_begin;
+                if (n <= 0) continue;
+                const int blocks = (n + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
+                if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
+            }
+        }
+    }
+    timing_end(c, tslot, s);
+    CK(hipGetLastError());
+    return BILU_OK;
+}
+
+// z = M^{-1} r: first sweep r -> y (resets z), second y -> z (resets y).
 bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transpose, hipStream_t s)
 {
     if (!c || !r || !z || R < 1 || R > dev::kMaxRhs || r == z) return BILU_ERR_ARG;
-    if (!c->laid_out) return BILU_ERR_STATE;
+    if (!c->split_done) return BILU_ERR_STATE;
     const int first = transpose ? BILU_SWEEP_UT : BILU_SWEEP_L;
     const int second = transpose ? BILU_SWEEP_LT : BILU_SWEEP_U;
     if (!c->h.sweep[first].built || !c->h.sweep[second].built) return BILU_ERR_STATE;
-    bilu_status st = ensure_y(c, R);
-    if (st) return st;
-    if ((st = run_sweep(c, first, r, c->d_y, R, 0, s))) return st;
-    return run_sweep(c, second, c->d_y, z, R, 1, s);
+    bilu_status st;
+    const int form = form_of_mode(c->sweep_mode == 2 && R > 1 ? 1 : c->sweep_mode);
+    if ((st = layout_form(c, form, s))) return st;
+    if ((st = ensure_y(c, R, s))) return st;
+    if ((st = run_sweep(c, first, r, c->d_y, z, R, s))) return st;
+    return run_sweep(c, second, c->d_y, z, c->d_y, R, s);
 }
 
 bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, int R, int transpose,
@@ -345,6 +449,7 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
     if (st) return st;
     const Host& h = c->h;
     bool ok;
+    const long tslot = timing_begin(c, BILU_K_SPMV, s);
     if (transpose) {
         if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
         ok = R == 1 ? launch_spmv_b<1, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s)
@@ -353,6 +458,7 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
         ok = R == 1 ? launch_spmv_b<1, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s)
                     : launch_spmv_b<8, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s);
     }
+    timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
     CK(hipGetLastError());
     return BILU_OK;
@@ -375,6 +481,11 @@ bilu_status bilu_analyze(int nb, int bs, const int32_t* Ap, const int32_t* Aj, i
     int st;
     try {
         st = analyze_host(c->h, nb, bs, Ap, Aj, k, flags);
+        if (st == BILU_OK) {
+            c->tile_rows = std::max(1, std::min(c->tile_rows, kMaxTileDoubles / bs));
+            for (int w = 0; w < 4; ++w)
+                if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->h.tiled[w]);
+        }
     } catch (const std::bad_alloc&) {
         st = BILU_ERR_ALLOC;
     }
@@ -448,7 +559,8 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     const int bb = h.bs * h.bs;
     const int64_t nP = static_cast<int64_t>(h.Pj.size());
     c->factored = false;
-    c->laid_out = false;
+    c->split_done = false;
+    const long tslot = timing_begin(c, BILU_K_FACTOR, s);
     hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax, c->d_P);
     hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(1), c->d_bad, INT_MAX);
     const HostSweep& L = h.sweep[BILU_SWEEP_L];
@@ -456,6 +568,7 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
         const int n = L.level_ptr[l + 1] - L.level_ptr[l];
         if (!launch_factor(h.bs, c->d_Lrows + L.level_ptr[l], n, c, s)) return BILU_ERR_ARG;
     }
+    timing_end(c, tslot, s);
     CK(hipGetLastError());
     int bad = INT_MAX;
     CK(hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -472,72 +585,45 @@ bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
 {
     if (!c || (precision != BILU_FACTORS_FP64 && precision != BILU_FACTORS_FP32)) return BILU_ERR_ARG;
     if (!c->factored) return BILU_ERR_STATE;
-    Host& h = c->h;
-    const int bb = h.bs * h.bs;
+    const long tslot = timing_begin(c, BILU_K_SPLIT, s);
     if (!launch_split(c, s)) return BILU_ERR_ARG;
-    const size_t esz = precision == BILU_FACTORS_FP32 ? sizeof(float) : sizeof(double);
-    for (int w = 0; w < 4; ++w) {
-        HostSweep& hs = h.sweep[w];
-        if (!hs.built) continue;
-        DevSweep& d = c->ds[w];
-        if (c->precision != precision || !d.vals) {
-            dfree(c, d.vals);
-            dfree(c, d.dinv);
-            d.vals = d.dinv = nullptr;
-            char* p = nullptr;
-            bilu_status st = dalloc(c, &p, static_cast<size_t>(hs.nslots) * bb * esz);
-            if (st) return st;
-            d.vals = p;
-            if (w == BILU_SWEEP_U || w == BILU_SWEEP_LT) {
-                st = dalloc(c, &p, static_cast<size_t>(hs.nchunks) * hs.rpc * bb * esz);
-                if (st) return st;
-                d.dinv = p;
-            }
-        }
-        const int tr = hs.transposed_blocks ? 1 : 0;
-        const int64_t nrs = static_cast<int64_t>(hs.nchunks) * hs.rpc;
-        if (precision == BILU_FACTORS_FP32) {
-            hipLaunchKernelGGL(dev::k_layout<float>, dim3(grid_for(hs.nslots * bb)), dim3(256), 0, s, hs.nslots,
-                               h.bs, hs.rpc, d.src, c->d_F, tr, static_cast<float*>(d.vals));
-            if (d.dinv)
-                hipLaunchKernelGGL(dev::k_layout_dinv<float>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
-                                   hs.rpc, d.rows, c->d_Dinv, tr, static_cast<float*>(d.dinv));
-        } else {
-            hipLaunchKernelGGL(dev::k_layout<double>, dim3(grid_for(hs.nslots * bb)), dim3(256), 0, s, hs.nslots,
-                               h.bs, hs.rpc, d.src, c->d_F, tr, static_cast<double*>(d.vals));
-            if (d.dinv)
-                hipLaunchKernelGGL(dev::k_layout_dinv<double>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
-                                   hs.rpc, d.rows, c->d_Dinv, tr, static_cast<double*>(d.dinv));
-        }
-    }
-    CK(hipGetLastError());
     c->precision = precision;
-    c->laid_out = true;
+    for (int f = 0; f < 2; ++f)
+        for (int w = 0; w < 4; ++w) c->ds[f][w].vals_precision = -1;
+    bilu_status st = layout_form(c, form_of_mode(c->sweep_mode), s);
+    if (st) return st;
+    timing_end(c, tslot, s);
+    CK(hipGetLastError());
+    c->split_done = true;
     return BILU_OK;
 }
 
 bilu_status bilu_get_factors(const bilu_ctx* c, double* F, double* Dinv, hipStream_t s)
 {
     if (!c) return BILU_ERR_ARG;
-    if (!c->laid_out) return BILU_ERR_STATE;
+    if (!c->split_done) return BILU_ERR_STATE;
     const size_t bb = static_cast<size_t>(c->h.bs) * c->h.bs;
     if (F) CK(hipMemcpyAsync(F, c->d_F, c->h.Pj.size() * bb * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (Dinv) CK(hipMemcpyAsync(Dinv, c->d_Dinv, static_cast<size_t>(c->h.nb) * bb * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
+    if (Dinv)
+        CK(hipMemcpyAsync(Dinv, c->d_Dinv, static_cast<size_t>(c->h.nb) * bb * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
     return BILU_OK;
 }
 
-bilu_status bilu_get_factors_f32(const bilu_ctx* c, float* F, float* Dinv, hipStream_t s)
+bilu_status bilu_get_factors_f32(bilu_ctx* c, float* F, float* Dinv, hipStream_t s)
 {
     if (!c) return BILU_ERR_ARG;
-    if (!c->laid_out || c->precision != BILU_FACTORS_FP32) return BILU_ERR_STATE;
+    if (!c->split_done || c->precision != BILU_FACTORS_FP32) return BILU_ERR_STATE;
+    bilu_status st = layout_form(c, kFormLevel, s);
+    if (st) return st;
     const Host& h = c->h;
     const int bb = h.bs * h.bs;
     if (F) {
         for (int w : {BILU_SWEEP_L, BILU_SWEEP_U}) {
             const HostSweep& hs = h.sweep[w];
             hipLaunchKernelGGL(dev::k_unlayout_f32, dim3(grid_for(hs.nslots * bb)), dim3(256), 0, s, hs.nslots, h.bs,
-                               hs.rpc, c->ds[w].src, static_cast<const float*>(c->ds[w].vals), F);
+                               hs.rpc, c->ds[kFormLevel][w].src, static_cast<const float*>(c->ds[kFormLevel][w].vals),
+                               F);
         }
         hipLaunchKernelGGL(dev::k_identity_f32, dim3(grid_for(static_cast<int64_t>(h.nb) * bb)), dim3(256), 0, s,
                            h.nb, h.bs, c->d_Pdiag, F);
@@ -546,7 +632,8 @@ bilu_status bilu_get_factors_f32(const bilu_ctx* c, float* F, float* Dinv, hipSt
         const HostSweep& hs = h.sweep[BILU_SWEEP_U];
         const int64_t nrs = static_cast<int64_t>(hs.nchunks) * hs.rpc;
         hipLaunchKernelGGL(dev::k_unlayout_dinv_f32, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs, hs.rpc,
-                           c->ds[BILU_SWEEP_U].rows, static_cast<const float*>(c->ds[BILU_SWEEP_U].dinv), Dinv);
+                           c->ds[kFormLevel][BILU_SWEEP_U].rows,
+                           static_cast<const float*>(c->ds[kFormLevel][BILU_SWEEP_U].dinv), Dinv);
     }
     CK(hipGetLastError());
     return BILU_OK;
@@ -581,10 +668,54 @@ bilu_status bilu_grad_A(bilu_ctx* c, const double* lam, const double* x, double*
     return BILU_OK;
 }
 
-bilu_status bilu_set_sweep_mode(bilu_ctx* c, int mode)
+bilu_status bilu_tune(bilu_ctx* c, int param, int value)
 {
-    if (!c || (mode != 0 && mode != 1)) return BILU_ERR_ARG;
-    c->sweep_mode = mode;
+    if (!c) return BILU_ERR_ARG;
+    switch (param) {
+    case BILU_TUNE_SWEEP_MODE:
+        if (value < 0 || value > 2) return BILU_ERR_ARG;
+        c->sweep_mode = value;
+        return BILU_OK;
+    case BILU_TUNE_TILE_ROWS: {
+        if (value < 1) return BILU_ERR_ARG;
+        const int rows = std::min(value, kMaxTileDoubles / c->h.bs);
+        if (rows == c->tile_rows) return BILU_OK;
+        c->tile_rows = rows;
+        free_form(c, kFormTiled);
+        for (int w = 0; w < 4; ++w)
+            if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->h.tiled[w]);
+        return BILU_OK;
+    }
+    case BILU_TUNE_BLOCKS:
+        if (value < 0 || value > (1 << 20)) return BILU_ERR_ARG;
+        c->blocks_override = value;
+        return BILU_OK;
+    }
+    return BILU_ERR_ARG;
+}
+
+bilu_status bilu_timing(bilu_ctx* c, int enable)
+{
+    if (!c) return BILU_ERR_ARG;
+    if (enable) {
+        c->ev_used = 0;
+        c->ev_marks.clear();
+    }
+    c->timing = enable != 0;
+    return BILU_OK;
+}
+
+bilu_status bilu_timing_read(bilu_ctx* c, hipStream_t s, bilu_kernel_time* out)
+{
+    if (!c || !out) return BILU_ERR_ARG;
+    for (int k = 0; k < BILU_K_COUNT; ++k) out[k] = bilu_kernel_time{0, 0.0};
+    CK(hipStreamSynchronize(s));
+    for (const auto& m : c->ev_marks) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, c->ev_pool[m.second], c->ev_pool[m.second + 1]));
+        out[m.first].launches += 1;
+        out[m.first].total_ms += ms;
+    }
     return BILU_OK;
 }
 
@@ -596,7 +727,8 @@ bilu_status bilu_check(bilu_ctx* c, hipStream_t s)
     CK(hipMemcpyAsync(&v, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     if (v) {
-        CK(hipMemset(c->d_status, 0, sizeof(int)));
+        CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
+        CK(hipStreamSynchronize(s));
         return BILU_ERR_TIMEOUT;
     }
     return BILU_OK;
@@ -722,7 +854,6 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part, dev::SL_TRUE);
     hipLaunchKernelGGL(dev::k_s_true, dim3(1), dim3(64), 0, s, R, part, S);
     CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
     int sweep_err = 0;
     CK(hipMemcpyAsync(&sweep_err, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
@@ -737,7 +868,8 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
         if (stj > worst) worst = stj;
     }
     if (sweep_err) {
-        CK(hipMemset(c->d_status, 0, sizeof(int)));
+        CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
+        CK(hipStreamSynchronize(s));
         return BILU_ERR_TIMEOUT;
     }
     return static_cast<bilu_status>(worst);
@@ -748,7 +880,7 @@ bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x
 {
     if (!c || !Ax || !b || !x || !o || !info || nrhs < 1 || nrhs > dev::kMaxRhs || b == x) return BILU_ERR_ARG;
     if (!(o->rtol >= 0.0) || o->maxit < 1) return BILU_ERR_ARG;
-    if (!c->laid_out) return BILU_ERR_STATE;
+    if (!c->split_done) return BILU_ERR_STATE;
     if (transpose && !(c->h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
     if (o->method == BILU_BICGSTAB) return bicgstab(c, Ax, b, x, nrhs, o, info, transpose, s);
     return BILU_ERR_ARG;
@@ -757,6 +889,7 @@ bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x
 void bilu_destroy(bilu_ctx* c)
 {
     if (!c) return;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
 }

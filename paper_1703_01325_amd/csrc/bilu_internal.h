@@ -35,18 +35,39 @@ struct HostSweep {
     std::vector<int64_t> src;              // [nslots]
 };
 
+// Tiled form of a sweep: tile t is a contiguous range of block rows
+// [tile_lo[t], tile_lo[t] + size), tiles numbered in sweep order (ascending
+// rows for forward sweeps, descending for backward ones).  The rows of a
+// tile are ordered by their level inside the tile (Eq 4 over dependencies
+// within the tile only) and cut into chunks of rpc rows of one such level;
+// chunk slots as in HostSweep, with deps[] encoding j >= 0 (row of another
+// tile), -2 - (j - tile_lo) (row of this tile) or -1 (padding).
+struct HostTiled {
+    bool built = false;
+    int which = 0;
+    int rpc = 0;
+    int tile_rows = 0;
+    int ntiles = 0;
+    int nchunks = 0;
+    int64_t nslots = 0;
+    std::vector<int32_t> tile_chunk_ptr;   // [ntiles+1]
+    std::vector<int32_t> tile_lo;          // [ntiles]
+    std::vector<int64_t> chunk_off;        // [nchunks+1]
+    std::vector<int32_t> rows;             // [nchunks*rpc]
+    std::vector<int32_t> deps;             // [nslots]
+    std::vector<int64_t> src;              // [nslots]
+};
+
 struct DevSweep {
     int64_t* chunk_off = nullptr;
     int32_t* rows = nullptr;
-    int32_t* cols = nullptr;
+    int32_t* cols = nullptr;  // level-chunk form: row read; tiled form: dependency code
     int64_t* src = nullptr;
+    int32_t* tile_chunk_ptr = nullptr;
+    int32_t* tile_lo = nullptr;
     void* vals = nullptr;     // [nslots * bs*bs] FP64 or FP32, layout [k][c][r][q]
     void* dinv = nullptr;     // [nchunks*rpc * bs*bs] same layout, fused sweeps only
-    int32_t* flags = nullptr; // [nb] ready flags (value = epoch when row is final)
-    unsigned long long* ticket = nullptr;
-    unsigned long long ticket_base = 0;
-    int epoch = 0;
-    int32_t* level_chunk_ptr = nullptr;
+    int vals_precision = -1;  // precision the values were laid out in (-1: none)
 };
 
 struct Host {
@@ -63,6 +84,7 @@ struct Host {
     std::vector<int32_t> ATp, ATj;
     std::vector<int64_t> ATsrc;
     HostSweep sweep[4];
+    HostTiled tiled[4];
 };
 
 // Host analysis entry points (analysis.cpp).
@@ -73,6 +95,7 @@ int sweep_levels(int nb, const std::vector<int32_t>& Pp, const std::vector<int32
                  int which, std::vector<int32_t>& lvl);
 void build_sweep(const Host& h, int which, int rpc, HostSweep& out);
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags);
+void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& out);
 int validate_layout(const Host& h);
 
 }  // namespace bilu

@@ -22,24 +22,100 @@ __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ double widen(float v) { return static_cast<double>(v); }
 
 // ---------------------------------------------------------------------------
+// Readiness inside one persistent sweep is carried by the values themselves.
+// Before a sweep starts, every entry of its output vector holds kNotReady,
+// a signalling-NaN bit pattern that no arithmetic result can have (results
+// are quiet NaNs at worst, and a result that would copy the pattern is
+// replaced by the canonical quiet NaN).  A row is published by writing its
+// values with device-coherent stores; a reader polls each value it needs
+// with device-coherent loads until it differs from kNotReady.  No flags, no
+// fences, no cache maintenance: one memory round trip per dependency.
+// The invariant "output starts at kNotReady" is kept by the two sweeps of
+// an application: the first resets the second's output rows, the second
+// resets the first's output rows after it has read them.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kNotReadyBits = 0x7FF4DEADBEEF1234ULL;
+constexpr unsigned long long kQuietNaNBits = 0x7FF8000000000000ULL;
+
+__device__ __forceinline__ double not_ready() { return __longlong_as_double(static_cast<long long>(kNotReadyBits)); }
+
+__device__ __forceinline__ bool is_not_ready(double v)
+{
+    return static_cast<unsigned long long>(__double_as_longlong(v)) == kNotReadyBits;
+}
+
+__device__ __forceinline__ double publishable(double v)
+{
+    return is_not_ready(v) ? __longlong_as_double(static_cast<long long>(kQuietNaNBits)) : v;
+}
+
+__device__ __forceinline__ double coherent_load(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void coherent_store(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits (bounded) until *p is published; returns the value.  Past the limit
+// the timeout is recorded in *status and whatever was read is returned, so
+// the wavefront still finishes.
+__device__ __forceinline__ double await_value(const double* p, double v, unsigned int limit, int* status)
+{
+    unsigned int spins = 0;
+    while (is_not_ready(v)) {
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = coherent_load(p);
+    }
+    return v;
+}
+
+__device__ __forceinline__ int grab_ticket(unsigned long long* ticket)
+{
+    unsigned long long t = 0;
+    if (lane_id() == 0) t = atomicAdd(ticket, 1ULL);
+    t = __shfl(t, 0);
+    return t > 0x3fffffffULL ? 0x3fffffff : static_cast<int>(t);
+}
+
+// The last wavefront of a persistent launch to finish rewinds the ticket
+// for the next launch on the stream (every wavefront takes exactly one
+// ticket past the end, so all tickets have been taken by then).
+__device__ __forceinline__ void finish_persistent(unsigned long long* ticket, unsigned int* done,
+                                                  unsigned int total_waves)
+{
+    if (lane_id() == 0) {
+        const unsigned int prev = atomicAdd(done, 1u);
+        if (prev + 1 == total_waves) {
+            __hip_atomic_store(ticket, 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Level-scheduled sweep (Eq 4, Algorithm 6) of one unit-diagonal block
 // triangular factor, optionally with the block-diagonal D^{-1} product of
 // Algorithm 7 fused in front:
 //     out_i = (fuse ? Dv_i rhs_i : rhs_i) - sum_k F_ik out_{col(i,k)}
-// One wavefront per chunk of rpc = 64/B block rows of one level; lane
-// (q, r) = (lane / B, lane % B) owns component r of the chunk's q-th row.
-// Values of a chunk are stored [k][c][r][q], so for a fixed dependency k
-// and block column c the wavefront reads B*rpc consecutive values.
+// Level-chunk form: one wavefront per chunk of rpc = 64/B block rows of one
+// level; lane (q, r) = (lane / B, lane % B) owns component r of the
+// chunk's q-th row.  Values of a chunk are stored [k][c][r][q], so for a
+// fixed dependency k and block column c the wavefront reads B*rpc
+// consecutive values.
 //
 // persistent = 0: the launch covers the chunks [chunk_begin, chunk_end) of
-// one level (all their dependencies are final before the launch).
-// persistent = 1: one launch covers the whole sweep.  Each wavefront takes
-// chunks in level order from an atomic ticket, waits until the rows it
-// reads carry the current epoch in flags[], computes, then publishes its
-// own rows.  A chunk only waits for chunks with smaller tickets, which are
-// held by wavefronts already running, so the sweep always drains.  Waits
-// are bounded: past the limit the wavefront records a timeout in *status
-// and carries on, so every wavefront still reaches the end.
+// one level, all of whose dependencies were written by earlier launches.
+// persistent = 1: one launch covers the whole sweep; wavefronts take chunks
+// in level order from an atomic ticket and poll the values they read.  A
+// chunk only reads rows of chunks with smaller tickets, held by wavefronts
+// that are already running, so the sweep always drains.
 // ---------------------------------------------------------------------------
 struct SweepArgs {
     const int64_t* chunk_off;
@@ -49,40 +125,19 @@ struct SweepArgs {
     const void* dinv;
     const double* rhs;
     double* out;
-    int32_t* flags;
+    double* reset;      // rows of this buffer are set to kNotReady (may be null)
     unsigned long long* ticket;
     unsigned int* done;
     int* status;
     int nchunks;
     int chunk_begin;
     int chunk_end;
-    int epoch;
     int R;
     int fuse;
     int persistent;
     unsigned int total_waves;
     unsigned int spin_limit;
 };
-
-__device__ __forceinline__ int grab_chunk(unsigned long long* ticket)
-{
-    unsigned long long t = 0;
-    if (lane_id() == 0) t = atomicAdd(ticket, 1ULL);
-    t = __shfl(t, 0);
-    return t > 0x7fffffffULL ? 0x7fffffff : static_cast<int>(t);
-}
-
-__device__ __forceinline__ void wait_ready(int32_t* flag, int epoch, unsigned int limit, int* status)
-{
-    unsigned int spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (++spins > limit) {
-            atomicOr(status, 1);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-}
 
 template <int B, typename T, int RT>
 __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
@@ -99,21 +154,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
     const int R = a.R;
     const int limit_chunk = a.persistent ? a.nchunks : a.chunk_end;
 
-    int chunk = a.persistent ? grab_chunk(a.ticket)
+    int chunk = a.persistent ? grab_ticket(a.ticket)
                              : a.chunk_begin + static_cast<int>(blockIdx.x) * kWavesPerBlock + wave;
     while (chunk < limit_chunk) {
         const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
         const int64_t off = a.chunk_off[chunk];
         const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
-        if (a.persistent) {
-            if (row >= 0 && r == 0) {
-                for (int k = 0; k < w; ++k) {
-                    const int j = a.cols[off + static_cast<int64_t>(k) * RPC + q];
-                    if (j >= 0) wait_ready(a.flags + j, a.epoch, a.spin_limit, a.status);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
         if (row >= 0) {
             for (int c0 = 0; c0 < R; c0 += RT) {
                 double acc[RT];
@@ -140,35 +186,140 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
                     const int j = a.cols[s + q];
                     if (j < 0) continue;
                     const int64_t vbase = s * BB + r * RPC + q;
+                    double xv[B][RT];
 #pragma unroll
                     for (int c = 0; c < B; ++c) {
-                        const double v = widen(vals[vbase + c * B * RPC]);
                         const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
 #pragma unroll
                         for (int t = 0; t < RT; ++t)
-                            if (RT == 1 || c0 + t < R) acc[t] -= v * xj[t];
+                            if (RT == 1 || c0 + t < R) xv[c][t] = a.persistent ? coherent_load(xj + t) : xj[t];
+                    }
+                    if (a.persistent) {
+#pragma unroll
+                        for (int c = 0; c < B; ++c) {
+                            const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
+#pragma unroll
+                            for (int t = 0; t < RT; ++t)
+                                if (RT == 1 || c0 + t < R) xv[c][t] = await_value(xj + t, xv[c][t], a.spin_limit, a.status);
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const double v = widen(vals[vbase + c * B * RPC]);
+#pragma unroll
+                        for (int t = 0; t < RT; ++t)
+                            if (RT == 1 || c0 + t < R) acc[t] -= v * xv[c][t];
                     }
                 }
-                double* dst = a.out + (static_cast<int64_t>(row) * B + r) * R + c0;
+                const int64_t o = (static_cast<int64_t>(row) * B + r) * R + c0;
 #pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    if (RT == 1 || c0 + t < R) dst[t] = acc[t];
+                for (int t = 0; t < RT; ++t) {
+                    if (RT == 1 || c0 + t < R) {
+                        if (a.reset) a.reset[o + t] = not_ready();
+                        if (a.persistent) coherent_store(a.out + o + t, publishable(acc[t]));
+                        else a.out[o + t] = publishable(acc[t]);
+                    }
+                }
             }
         }
         if (!a.persistent) break;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (row >= 0 && r == 0)
-            __hip_atomic_store(a.flags + row, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        chunk = grab_chunk(a.ticket);
+        chunk = grab_ticket(a.ticket);
     }
-    if (a.persistent && lane == 0) {
-        // the last wavefront to finish rewinds the ticket for the next launch
-        const unsigned int prev = atomicAdd(a.done, 1u);
-        if (prev + 1 == a.total_waves) {
-            __hip_atomic_store(a.ticket, 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(a.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a.persistent) finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled sweep: one wavefront owns a contiguous range of block rows (a tile)
+// and walks it in its own level order (levels of Eq 4 restricted to the
+// dependencies inside the tile), one chunk of up to 64/B rows at a time.
+// A dependency inside the tile is read from LDS, where the wavefront keeps
+// every row it has finished; a dependency on another tile is polled from
+// global memory.  Tiles are taken from a ticket in sweep order, and every
+// row a tile reads from outside lies in an earlier tile, so the sweep
+// drains.  Dependency codes: j >= 0 global row, j <= -2 tile-local row
+// (-j - 2), -1 padding.  Single right-hand side.
+// ---------------------------------------------------------------------------
+struct TiledArgs {
+    const int32_t* tile_chunk_ptr;
+    const int32_t* tile_lo;
+    const int64_t* chunk_off;
+    const int32_t* rows;
+    const int32_t* deps;
+    const void* vals;
+    const void* dinv;
+    const double* rhs;
+    double* out;
+    double* reset;
+    unsigned long long* ticket;
+    unsigned int* done;
+    int* status;
+    int ntiles;
+    int fuse;
+    unsigned int total_waves;
+    unsigned int spin_limit;
+};
+
+template <int B, typename T>
+__global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    extern __shared__ double tile_vals[];     // [tile rows][B]
+    const int lane = lane_id();
+    const int q = lane / B;
+    const int r = lane - q * B;
+    const bool lane_ok = q < RPC;
+    const T* __restrict__ vals = static_cast<const T*>(a.vals);
+    const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
+
+    for (int t = grab_ticket(a.ticket); t < a.ntiles; t = grab_ticket(a.ticket)) {
+        const int lo = a.tile_lo[t];
+        const int c_end = a.tile_chunk_ptr[t + 1];
+        for (int chunk = a.tile_chunk_ptr[t]; chunk < c_end; ++chunk) {
+            const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
+            const int64_t off = a.chunk_off[chunk];
+            const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
+            if (row >= 0) {
+                double acc;
+                if (a.fuse) {
+                    const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + q;
+                    acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < B; ++c)
+                        acc += widen(dinv[dbase + c * B * RPC]) * a.rhs[static_cast<int64_t>(row) * B + c];
+                } else {
+                    acc = a.rhs[static_cast<int64_t>(row) * B + r];
+                }
+                for (int k = 0; k < w; ++k) {
+                    const int64_t s = off + static_cast<int64_t>(k) * RPC;
+                    const int code = a.deps[s + q];
+                    if (code == -1) continue;
+                    double xv[B];
+                    if (code <= -2) {
+                        const int loc = -code - 2;
+#pragma unroll
+                        for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
+                    } else {
+                        const double* xj = a.out + static_cast<int64_t>(code) * B;
+#pragma unroll
+                        for (int c = 0; c < B; ++c) xv[c] = coherent_load(xj + c);
+#pragma unroll
+                        for (int c = 0; c < B; ++c) xv[c] = await_value(xj + c, xv[c], a.spin_limit, a.status);
+                    }
+                    const int64_t vbase = s * BB + r * RPC + q;
+#pragma unroll
+                    for (int c = 0; c < B; ++c) acc -= widen(vals[vbase + c * B * RPC]) * xv[c];
+                }
+                const double v = publishable(acc);
+                const int64_t o = static_cast<int64_t>(row) * B + r;
+                if (a.reset) a.reset[o] = not_ready();
+                coherent_store(a.out + o, v);
+                tile_vals[(row - lo) * B + r] = v;
+            }
+            __syncthreads();   // one wavefront: orders this chunk's LDS writes before the next reads
         }
     }
+    finish_persistent(a.ticket, a.done, a.total_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -501,6 +652,13 @@ __global__ void k_fill_i32(int64_t n, int32_t* p, int32_t v)
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x)
         p[g] = v;
+}
+
+__global__ void k_fill_not_ready(int64_t n, double* p)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[g] = not_ready();
 }
 
 __global__ void k_fill_f64(int64_t n, double* p, double v)

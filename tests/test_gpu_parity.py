@@ -37,9 +37,9 @@ class Case:
         self.Ax = cuda(sysm.Ax)
         self.rhs = O.spmv(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, sysm.Ax, sysm.xstar)
 
-    def gpu(self, api, transpose=False, precision="fp64", mode=1):
+    def gpu(self, api, transpose=False, precision="fp64", mode=2, tile_rows=None):
         M = api.BlockILU(self.s.nb, self.s.bs, self.s.Ap, self.s.Aj, self.k, transpose=transpose)
-        M.set_sweep_mode(mode)
+        M.tune(mode=mode, tile_rows=tile_rows)
         bad = M.factor(self.Ax, precision=precision)
         assert bad == -1
         return M
@@ -78,11 +78,15 @@ def test_factor_parity(api, oracle_mod, name, make, k):
     assert rel(D, c.O.Dinv) <= 1e-12
 
 
-@pytest.mark.parametrize("mode", [0, 1], ids=["per_level", "persistent"])
+MODES = [(0, None), (1, None), (2, None), (2, 1), (2, 13), (2, 64)]
+
+
+@pytest.mark.parametrize("mode,tile_rows", MODES,
+                         ids=["per_level", "level_chunks", "tiled", "tiled1", "tiled13", "tiled64"])
 @pytest.mark.parametrize("name,make,k", SMALL, ids=[f"{c[0]}_k{c[2]}" for c in SMALL])
-def test_apply_and_spmv_parity(api, oracle_mod, name, make, k, mode):
+def test_apply_and_spmv_parity(api, oracle_mod, name, make, k, mode, tile_rows):
     c = Case(oracle_mod, make(), k)
-    M = c.gpu(api, transpose=True, mode=mode)
+    M = c.gpu(api, transpose=True, mode=mode, tile_rows=tile_rows)
     rng = np.random.default_rng(7)
     r = rng.standard_normal(c.s.n)
     z = M.apply(cuda(r)).cpu().numpy()
@@ -96,13 +100,20 @@ def test_apply_and_spmv_parity(api, oracle_mod, name, make, k, mode):
     M.check()
 
 
-def test_apply_deterministic(api, oracle_mod):
+def test_apply_deterministic_across_modes(api, oracle_mod):
+    """Every schedule computes each row with the same arithmetic in the same
+    order, so all modes and repeated runs agree bit for bit."""
     c = Case(oracle_mod, synth.small_10cube(), 1)
-    M = c.gpu(api)
+    M = c.gpu(api, transpose=True)
     r = cuda(np.random.default_rng(1).standard_normal(c.s.n))
     z1 = M.apply(r)
-    z2 = M.apply(r)
-    assert torch.equal(z1, z2)
+    z1t = M.apply(r, transpose=True)
+    for mode, tile in MODES:
+        M.tune(mode=mode, tile_rows=tile)
+        for _ in range(2):
+            assert torch.equal(M.apply(r), z1)
+            assert torch.equal(M.apply(r, transpose=True), z1t)
+    M.check()
 
 
 @pytest.mark.parametrize("R", [2, 8, 13, 32])
@@ -199,7 +210,7 @@ def test_grad_A(api, oracle_mod):
 def test_layered_full_size_apply_spmv(api, oracle_mod, k):
     s = synth.layered_60x220x85()
     c = Case(oracle_mod, s, k)
-    M = c.gpu(api, mode=1)
+    M = c.gpu(api, mode=2)
     F, D = M.factors()
     gL, gU = factor_parts(c.O, s, F.cpu().numpy())
     oL, oU = factor_parts(c.O, s, c.O.F)
@@ -214,7 +225,7 @@ def test_layered_full_size_apply_spmv(api, oracle_mod, k):
 def test_mid_full_size_solve(api, oracle_mod):
     s = synth.mid_64cube()
     c = Case(oracle_mod, s, 1)
-    M = c.gpu(api, mode=1)
+    M = c.gpu(api, mode=2)
     x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
     xo, ito, rro, sto = c.O.solve(s.Ax, c.rhs, rtol=1e-8)
     assert st == 0 and sto == 0 and abs(info[0][1] - ito) <= 1 and info[0][2] <= 1e-8

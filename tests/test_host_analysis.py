@@ -120,3 +120,23 @@ def test_gpu_calls_need_factor_first(N):
         assert ei.value.code == N.ERR_STATE
     finally:
         N.bilu_destroy(ctx)
+
+
+@pytest.mark.parametrize("tile_rows", [1, 2, 7, 64, 333, 5000])
+def test_tiled_layouts_validate(N, tile_rows):
+    for grid, k in (((10, 10, 10), 1), ((7, 5, 4), 2)):
+        Ap, Aj = synth.stencil7_pattern(*grid)
+        nb = int(np.prod(grid))
+        ctx = N.bilu_analyze(nb, 3, Ap, Aj, k, N.WANT_TRANSPOSE)
+        try:
+            N.bilu_tune(ctx, N.TUNE_TILE_ROWS, tile_rows)
+            N.bilu_validate(ctx)
+        finally:
+            N.bilu_destroy(ctx)
+    Ap, Aj = synth.random_block_pattern(90, 0.05, 3)
+    ctx = N.bilu_analyze(90, 5, Ap, Aj, 2, N.WANT_TRANSPOSE)
+    try:
+        N.bilu_tune(ctx, N.TUNE_TILE_ROWS, tile_rows)
+        N.bilu_validate(ctx)
+    finally:
+        N.bilu_destroy(ctx)
