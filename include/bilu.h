@@ -92,6 +92,7 @@ typedef struct {
     int nlev[4];          /* levels per sweep (0 if not built)     */
     int rows_per_chunk;   /* block rows per wavefront in the sweeps */
     int64_t sweep_slots[4]; /* padded block slots of each sweep layout */
+    int tile_rows;        /* block rows per tile of the tiled sweeps (0: not chosen yet) */
 } bilu_info;
 
 typedef struct {
@@ -216,7 +217,8 @@ enum {
                                  launch per sweep over row tiles (several right-hand
                                  sides use mode 1)                                   */
     BILU_TUNE_TILE_ROWS = 1,  /* block rows per tile in mode 2 (capped so a tile's
-                                 values fit 64 KiB of LDS)                           */
+                                 values fit 64 KiB of LDS); 0 = chosen by a host
+                                 simulation of the tiled schedule (default)          */
     BILU_TUNE_BLOCKS = 3      /* persistent grid in workgroups, 0 = automatic        */
 };
 bilu_status bilu_tune(bilu_ctx* ctx, int param, int value);

@@ -40,7 +40,7 @@ class BiluInfo(ct.Structure):
     _fields_ = [("nb", ct.c_int), ("bs", ct.c_int), ("k", ct.c_int),
                 ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
                 ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
-                ("sweep_slots", ct.c_int64 * 4)]
+                ("sweep_slots", ct.c_int64 * 4), ("tile_rows", ct.c_int)]
 
 
 class KernelTime(ct.Structure):

@@ -2,6 +2,7 @@
 // chunked sweep layouts the GPU kernels stream.  Integer work only.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 #include "bilu_internal.h"
@@ -307,7 +308,147 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
     s.nchunks = static_cast<int>(s.chunk_off.size() - 1);
     s.tile_chunk_ptr[s.ntiles] = s.nchunks;
     s.nslots = s.chunk_off.back();
+    // one chunk of padding slots, so a kernel may read slot 0 of any chunk
+    s.deps.resize(static_cast<size_t>(s.nslots) + rpc, -1);
+    s.src.resize(s.deps.size(), -1);
     s.built = true;
+}
+
+// Event simulation of the tiled schedule: tiles run concurrently, a tile
+// walks its chunks in order, a chunk costs one step and may start once the
+// previous chunk of its tile is done and every row it reads from another
+// tile has been finished for `hop` steps.  Chunks are formed exactly as in
+// build_tiled.  Returns the finishing time of the last chunk.
+namespace {
+double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr, const std::vector<Dep>& deps,
+                     int rpc, int tile_rows, double hop, int row_limit);
+}
+
+double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, double hop, int row_limit)
+{
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, which, dptr, deps);
+    return simulate_deps(h, which, dptr, deps, rpc, tile_rows, hop, row_limit);
+}
+
+namespace {
+double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr, const std::vector<Dep>& deps,
+                     int rpc, int tile_rows, double hop, int row_limit)
+{
+    const int nb = row_limit > 0 ? std::min(h.nb, row_limit) : h.nb;
+    const bool forward = (which == BILU_SWEEP_L || which == BILU_SWEEP_UT);
+    std::vector<double> done(static_cast<size_t>(h.nb), 0.0);
+    std::vector<int32_t> il(static_cast<size_t>(tile_rows)), cnt, start, order;
+    // a forward sweep restricted to its first `nb` rows is itself a sweep
+    const int ntiles = forward ? (nb + tile_rows - 1) / tile_rows : (h.nb + tile_rows - 1) / tile_rows;
+    double makespan = 0.0;
+    for (int t = 0; t < ntiles; ++t) {
+        int lo, hi;
+        if (forward) {
+            lo = t * tile_rows;
+            hi = std::min(nb, lo + tile_rows) - 1;
+        } else {
+            hi = h.nb - 1 - t * tile_rows;
+            lo = std::max(0, hi - tile_rows + 1);
+        }
+        for (int step = 0; step <= hi - lo; ++step) {
+            const int32_t i = forward ? lo + step : hi - step;
+            int32_t l = 0;
+            for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+                const int32_t j = deps[d].col;
+                if (j >= lo && j <= hi) l = std::max(l, il[j - lo] + 1);
+            }
+            il[i - lo] = l;
+        }
+        // rows grouped by level (ties: more dependencies first, then row order)
+        order.resize(static_cast<size_t>(hi - lo + 1));
+        std::iota(order.begin(), order.end(), lo);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            if (il[a - lo] != il[b - lo]) return il[a - lo] < il[b - lo];
+            return (dptr[a + 1] - dptr[a]) > (dptr[b + 1] - dptr[b]);
+        });
+        double now = 0.0;
+        size_t pos = 0;
+        while (pos < order.size()) {
+            const int32_t lev = il[order[pos] - lo];
+            size_t cn = 0;
+            while (pos + cn < order.size() && cn < static_cast<size_t>(rpc) && il[order[pos + cn] - lo] == lev) ++cn;
+            double ready = now;
+            for (size_t q = 0; q < cn; ++q) {
+                const int32_t i = order[pos + q];
+                for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+                    const int32_t j = deps[d].col;
+                    if (j < lo || j > hi) ready = std::max(ready, done[j] + hop);
+                }
+            }
+            now = ready + 1.0;
+            for (size_t q = 0; q < cn; ++q) done[order[pos + q]] = now;
+            pos += cn;
+        }
+        makespan = std::max(makespan, now);
+    }
+    return makespan;
+}
+}  // namespace
+
+// Candidate tile sizes: a geometric grid, plus divisors and multiples of the
+// most frequent dependency distances (on a grid these are the line and plane
+// periods; a tile aligned with them keeps corresponding rows of consecutive
+// tiles at the same level inside their tiles).  The smallest simulated
+// makespan of the L sweep wins; ties go to the larger tile.
+int choose_tile_rows(const Host& h, int rpc, int max_rows)
+{
+    const int nb = h.nb;
+    max_rows = std::max(1, std::min(max_rows, nb));
+    const int min_rows = std::min(max_rows, std::max(1, 2 * rpc));
+    std::vector<int> cand;
+    for (double m = min_rows; m <= max_rows; m *= 1.5) cand.push_back(static_cast<int>(m));
+    cand.push_back(max_rows);
+    // dependency distance histogram of the L sweep
+    std::vector<std::pair<int64_t, int32_t>> hist;
+    {
+        std::vector<int32_t> dist;
+        dist.reserve(static_cast<size_t>(nb) * 4);
+        for (int32_t i = 0; i < nb; ++i)
+            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1] && h.Pj[e] < i; ++e) dist.push_back(i - h.Pj[e]);
+        std::sort(dist.begin(), dist.end());
+        for (size_t a = 0; a < dist.size();) {
+            size_t b = a;
+            while (b < dist.size() && dist[b] == dist[a]) ++b;
+            hist.emplace_back(static_cast<int64_t>(b - a), dist[a]);
+            a = b;
+        }
+        std::sort(hist.begin(), hist.end(), std::greater<>());
+    }
+    const size_t top = std::min<size_t>(hist.size(), 4);
+    for (size_t a = 0; a < top; ++a) {
+        const int d = hist[a].second;
+        for (int j = 1; j <= 64; ++j) {
+            if (d / j >= min_rows && d / j <= max_rows && d % j == 0) cand.push_back(d / j);
+            if (static_cast<int64_t>(d) * j >= min_rows && static_cast<int64_t>(d) * j <= max_rows) cand.push_back(d * j);
+        }
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    // A prefix of the sweep shows how tiles pipeline: a few multiples of the
+    // longest frequent dependency distance and of the largest tile.
+    int64_t longest = 1;
+    for (size_t a = 0; a < top; ++a) longest = std::max<int64_t>(longest, hist[a].second);
+    const int limit = static_cast<int>(std::min<int64_t>(nb, std::max<int64_t>({8 * longest, 16LL * max_rows, 65536})));
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, BILU_SWEEP_L, dptr, deps);
+    int best = cand.back();
+    double best_t = 1e300;
+    for (int m : cand) {
+        const double t = simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, m, 5.0, limit);
+        if (t < best_t * (1.0 - 1e-9) || (t <= best_t * (1.0 + 1e-9) && m > best)) {
+            best_t = std::min(best_t, t);
+            best = m;
+        }
+    }
+    return best;
 }
 
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags)
@@ -371,6 +512,79 @@ int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, 
     }
     return BILU_OK;
 }
+
+namespace {
+// Replays, for every chunk and every lane of a wavefront, the index
+// arithmetic of the tiled sweep kernel (batch loads, dependency reads, LDS
+// accesses, stores) and checks each index against the size of the array it
+// addresses.  Mirrors k_sweep_tiled / tile_load_a / tile_load_b /
+// tile_compute in kernels.h.
+bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
+{
+    const int B = h.bs;
+    const int RPC = kWave / B;
+    const int64_t BB = static_cast<int64_t>(B) * B;
+    const int KMAX = B <= 2 ? 8 : (B <= 4 ? 6 : 3);
+    const bool fuse = (which == BILU_SWEEP_U || which == BILU_SWEEP_LT);
+    const int64_t n_rows_arr = static_cast<int64_t>(s.rows.size());
+    const int64_t n_slots_arr = static_cast<int64_t>(s.deps.size());       // nslots + padding
+    const int64_t n_vals = n_slots_arr * BB;
+    const int64_t n_dinv = static_cast<int64_t>(s.nchunks) * RPC * BB;
+    const int64_t n_vec = static_cast<int64_t>(h.nb) * B;
+    const int64_t n_lds = static_cast<int64_t>(s.tile_rows) * B;
+    auto in = [](int64_t i, int64_t n) { return i >= 0 && i < n; };
+    for (int t = 0; t < s.ntiles; ++t) {
+        const int lo = s.tile_lo[t];
+        for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
+            const int64_t off = s.chunk_off[c];
+            const int w = static_cast<int>((s.chunk_off[c + 1] - off) / RPC);
+            for (int lane = 0; lane < kWave; ++lane) {
+                const int q = lane / B, r = lane - q * B;
+                const bool lane_ok = q < RPC;
+                const int qc = lane_ok ? q : RPC - 1;
+                const int64_t ri = static_cast<int64_t>(c) * RPC + qc;
+                if (!in(ri, n_rows_arr)) return false;
+                const int row = s.rows[ri];
+                std::vector<int> code(static_cast<size_t>(KMAX));
+                for (int k = 0; k < KMAX; ++k) {                     // batch (a)
+                    const int kk = k < w ? k : 0;
+                    const int64_t sl = off + static_cast<int64_t>(kk) * RPC;
+                    if (!in(sl + qc, n_slots_arr)) return false;
+                    code[k] = s.deps[sl + qc];
+                    const int64_t vb = sl * BB + static_cast<int64_t>(r) * RPC + qc;
+                    if (!in(vb, n_vals) || !in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
+                }
+                const int64_t rowc = row >= 0 ? row : 0;                // batch (b)
+                if (!in(rowc * B, n_vec) || !in(rowc * B + B - 1, n_vec)) return false;
+                if (fuse) {
+                    const int64_t db = static_cast<int64_t>(c) * RPC * BB + static_cast<int64_t>(r) * RPC + qc;
+                    if (!in(db, n_dinv) || !in(db + static_cast<int64_t>(B - 1) * B * RPC, n_dinv)) return false;
+                }
+                for (int k = 0; k < KMAX; ++k) {
+                    const int64_t j = (k < w && code[k] >= 0) ? code[k] : rowc;
+                    if (!in(j * B, n_vec) || !in(j * B + B - 1, n_vec)) return false;
+                }
+                if (!lane_ok || row < 0) continue;                       // compute
+                for (int k = 0; k < w; ++k) {
+                    const int64_t sl = off + static_cast<int64_t>(k) * RPC;
+                    if (!in(sl + qc, n_slots_arr)) return false;
+                    const int cd = s.deps[sl + qc];
+                    if (cd == -1) continue;
+                    if (cd <= -2) {
+                        const int64_t loc = -static_cast<int64_t>(cd) - 2;
+                        if (!in(loc * B, n_lds) || !in(loc * B + B - 1, n_lds)) return false;
+                    } else if (!in(static_cast<int64_t>(cd) * B + B - 1, n_vec)) {
+                        return false;
+                    }
+                }
+                if (!in(static_cast<int64_t>(row) * B + r, n_vec)) return false;
+                if (!in(static_cast<int64_t>(row - lo) * B + r, n_lds)) return false;
+            }
+        }
+    }
+    return true;
+}
+}  // namespace
 
 int validate_layout(const Host& h)
 {
@@ -449,8 +663,8 @@ int validate_layout(const Host& h)
             s.tile_chunk_ptr[s.ntiles] != s.nchunks || static_cast<int>(s.tile_lo.size()) != s.ntiles)
             return BILU_ERR_STATE;
         if (static_cast<int>(s.chunk_off.size()) != s.nchunks + 1 || s.chunk_off[0] != 0 ||
-            s.chunk_off.back() != s.nslots || static_cast<int64_t>(s.deps.size()) != s.nslots ||
-            static_cast<int64_t>(s.src.size()) != s.nslots ||
+            s.chunk_off.back() != s.nslots || static_cast<int64_t>(s.deps.size()) != s.nslots + rpc ||
+            static_cast<int64_t>(s.src.size()) != s.nslots + rpc ||
             static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc)
             return BILU_ERR_STATE;
         std::vector<int32_t> tile_of(static_cast<size_t>(nb), -1), chunk_of(static_cast<size_t>(nb), -1);
@@ -513,6 +727,7 @@ int validate_layout(const Host& h)
         }
         for (int i = 0; i < nb; ++i)
             if (seen[i] != ndep[i]) return BILU_ERR_STATE;
+        if (!tiled_accesses_in_bounds(h, s, w)) return BILU_ERR_STATE;
     }
     return BILU_OK;
 }

@@ -38,7 +38,7 @@ struct bilu_ctx {
     bool split_done = false;
     int precision = BILU_FACTORS_FP64;
     int sweep_mode = 1;
-    int tile_rows = 1024;
+    int tile_rows = 0;          // 0: chosen by schedule simulation on first tiled use
     int blocks_override = 0;
     unsigned int spin_limit = 1u << 24;
 
@@ -167,10 +167,19 @@ bool launch_sweep(int bs, int prec, int R, int blocks, hipStream_t s, const Swee
     return R == 1 ? launch_sweep_b<double, 1>(bs, blocks, s, a) : launch_sweep_b<double, 8>(bs, blocks, s, a);
 }
 
-template <typename T>
+template <typename T, bool FUSE>
 bool launch_tiled_b(int bs, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
-    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep_tiled<B, T>), dim3(blocks), dim3(64), lds, s, a))
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE>), dim3(blocks), dim3(64), lds, s, a))
+}
+
+bool launch_tiled(int bs, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+{
+    if (prec == BILU_FACTORS_FP32)
+        return fuse ? launch_tiled_b<float, true>(bs, blocks, lds, s, a)
+                    : launch_tiled_b<float, false>(bs, blocks, lds, s, a);
+    return fuse ? launch_tiled_b<double, true>(bs, blocks, lds, s, a)
+                : launch_tiled_b<double, false>(bs, blocks, lds, s, a);
 }
 
 template <int RT, bool TR>
@@ -214,8 +223,9 @@ bilu_status upload_form(bilu_ctx* c, int form)
                 return st;
         } else {
             if (!h.sweep[w].built) continue;
+            if (c->tile_rows <= 0) c->tile_rows = choose_tile_rows(h, h.rpc, kMaxTileDoubles / h.bs);
             HostTiled& ht = h.tiled[w];
-            if (!ht.built) build_tiled(h, w, h.rpc, c->tile_rows, ht);
+            if (!ht.built || ht.tile_rows != c->tile_rows) build_tiled(h, w, h.rpc, c->tile_rows, ht);
             if ((st = upload(c, &d.chunk_off, ht.chunk_off)) || (st = upload(c, &d.rows, ht.rows)) ||
                 (st = upload(c, &d.cols, ht.deps)) || (st = upload(c, &d.src, ht.src)) ||
                 (st = upload(c, &d.tile_chunk_ptr, ht.tile_chunk_ptr)) || (st = upload(c, &d.tile_lo, ht.tile_lo)))
@@ -223,6 +233,8 @@ bilu_status upload_form(bilu_ctx* c, int form)
         }
         d.vals_precision = -1;
     }
+    // no kernel ever runs on a layout that fails the host self-check
+    if (validate_layout(h) != BILU_OK) return BILU_ERR_STATE;
     c->form_uploaded[form] = true;
     return BILU_OK;
 }
@@ -296,7 +308,8 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         if (!h.sweep[w].built) continue;
         DevSweep& d = c->ds[form][w];
         if (d.vals_precision == c->precision) continue;
-        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots;
+        // the tiled form carries one chunk of padding slots (zero values)
+        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots + h.rpc;
         const int nchunks = form == kFormLevel ? h.sweep[w].nchunks : h.tiled[w].nchunks;
         const int rpc = h.rpc;
         dfree(c, d.vals);
@@ -376,14 +389,11 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.done = c->d_done;
         a.status = c->d_status;
         a.ntiles = ht.ntiles;
-        a.fuse = fuse;
         a.spin_limit = c->spin_limit;
         const int blocks = persistent_blocks(c, ht.ntiles, 1, 8);
         a.total_waves = static_cast<unsigned int>(blocks);
         const size_t lds = static_cast<size_t>(ht.tile_rows) * c->h.bs * sizeof(double);
-        const bool ok = c->precision == BILU_FACTORS_FP32 ? launch_tiled_b<float>(c->h.bs, blocks, lds, s, a)
-                                                          : launch_tiled_b<double>(c->h.bs, blocks, lds, s, a);
-        if (!ok) return BILU_ERR_ARG;
+        if (!launch_tiled(c->h.bs, c->precision, fuse != 0, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
         const HostSweep& hs = c->h.sweep[which];
         const DevSweep& d = c->ds[kFormLevel][which];
@@ -481,11 +491,6 @@ bilu_status bilu_analyze(int nb, int bs, const int32_t* Ap, const int32_t* Aj, i
     int st;
     try {
         st = analyze_host(c->h, nb, bs, Ap, Aj, k, flags);
-        if (st == BILU_OK) {
-            c->tile_rows = std::max(1, std::min(c->tile_rows, kMaxTileDoubles / bs));
-            for (int w = 0; w < 4; ++w)
-                if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->h.tiled[w]);
-        }
     } catch (const std::bad_alloc&) {
         st = BILU_ERR_ALLOC;
     }
@@ -536,6 +541,7 @@ bilu_status bilu_get_info(const bilu_ctx* c, bilu_info* info)
             if (h.Pj[e] > i) info->nnzb_U++;
         }
     info->rows_per_chunk = h.rpc;
+    info->tile_rows = c->tile_rows;
     for (int w = 0; w < 4; ++w) {
         info->nlev[w] = h.sweep[w].built ? h.sweep[w].nlev : 0;
         info->sweep_slots[w] = h.sweep[w].built ? h.sweep[w].nslots : 0;
@@ -677,8 +683,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         c->sweep_mode = value;
         return BILU_OK;
     case BILU_TUNE_TILE_ROWS: {
-        if (value < 1) return BILU_ERR_ARG;
-        const int rows = std::min(value, kMaxTileDoubles / c->h.bs);
+        if (value < 0) return BILU_ERR_ARG;
+        int rows = value == 0 ? choose_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs)
+                              : std::min(value, kMaxTileDoubles / c->h.bs);
+        rows = std::max(1, std::min(rows, c->h.nb));
         if (rows == c->tile_rows) return BILU_OK;
         c->tile_rows = rows;
         free_form(c, kFormTiled);
@@ -875,6 +883,135 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     return static_cast<bilu_status>(worst);
 }
 
+// Restarted right-preconditioned GMRES(m), one right-hand side: Arnoldi with
+// modified Gram-Schmidt on the device, Givens rotations and the small
+// triangular solve on the host (one readback of a Hessenberg column per
+// Arnoldi step), x += M^{-1} V y at the end of each cycle, exit on the true
+// residual at the start of a cycle.  maxit bounds the Arnoldi steps.
+static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double* x, const bilu_solve_opts* o,
+                         bilu_rhs_info* info, int tr, hipStream_t s)
+{
+    const int64_t n = static_cast<int64_t>(c->h.nb) * c->h.bs;
+    const int m = o->restart;
+    bilu_status st = ensure_krylov(c, 1, m + 4);
+    if (st) return st;
+    double* V = c->d_kv;                                   // (m+1) x n basis
+    double* w = V + static_cast<size_t>(m + 1) * n;
+    double* z = w + n;
+    double* u = z + n;
+    double* dH = nullptr;                                  // (m+1) x m, column j contiguous, + coef + y
+    if ((st = dalloc(c, &dH, static_cast<size_t>(m + 1) * m + 1 + m))) return st;
+    double* coef = dH + static_cast<size_t>(m + 1) * m;
+    double* dy = coef + 1;
+    double* part = c->d_part;
+    const int eg = grid_for(n);
+    const dim3 rb(dev::kRedBlocks), rt(dev::kThreads);
+    auto apply = [&](const double* in, double* out) { return do_apply(c, in, out, 1, tr != 0, s); };
+    auto spmv = [&](const double* in, double* out) { return do_spmv(c, Ax, in, out, 1, tr, s); };
+    auto fetch = [&](double* host, const double* devp, size_t count) -> bilu_status {
+        CK(hipMemcpyAsync(host, devp, count * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        return BILU_OK;
+    };
+
+    hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n, x, 0.0);
+    hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, 1, b, b, part, dev::SL_BB);
+    hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_BB, dH, coef, 1);
+    double bnorm = 0.0;
+    if ((st = fetch(&bnorm, dH, 1))) { dfree(c, dH); return st; }
+    std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 1);
+    int total = 0, status = BILU_NOT_CONVERGED;
+    double rres = bnorm;
+    if (bnorm == 0.0) status = BILU_OK;
+    while (status == BILU_NOT_CONVERGED) {
+        if ((st = spmv(x, w))) break;
+        hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE);
+        hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1);
+        double beta = 0.0;
+        if ((st = fetch(&beta, dH, 1))) break;
+        rres = beta;
+        if (!std::isfinite(beta)) { status = BILU_NONFINITE; break; }
+        if (beta <= o->rtol * bnorm) { status = BILU_OK; break; }
+        if (total >= o->maxit) break;
+        hipLaunchKernelGGL(dev::k_gm_scale, dim3(eg), dim3(256), 0, s, n, w, coef, V);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jend = 0;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + static_cast<size_t>(j) * n;
+            double* hcol = dH + static_cast<size_t>(j) * (m + 1);
+            if ((st = apply(vj, z)) || (st = spmv(z, w))) break;
+            hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, nullptr, coef, V, part, dev::SL_RHO);
+            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol, coef, 0);
+            for (int i = 1; i <= j; ++i) {
+                hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, V + static_cast<size_t>(i - 1) * n, coef,
+                                   V + static_cast<size_t>(i) * n, part, dev::SL_RHO);
+                hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol + i, coef, 0);
+            }
+            hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, vj, coef, nullptr, part, dev::SL_RHO);
+            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol + j + 1, coef, 1);
+            hipLaunchKernelGGL(dev::k_gm_scale, dim3(eg), dim3(256), 0, s, n, w, coef, vj + n);
+            if (hipGetLastError() != hipSuccess) { st = BILU_ERR_HIP; break; }
+            if ((st = fetch(col.data(), hcol, static_cast<size_t>(j) + 2))) break;
+            for (int i = 0; i <= j + 1; ++i) H[static_cast<size_t>(i) * m + j] = col[i];
+            for (int i = 0; i < j; ++i) {
+                const double a1 = H[static_cast<size_t>(i) * m + j], a2 = H[static_cast<size_t>(i + 1) * m + j];
+                H[static_cast<size_t>(i) * m + j] = cs[i] * a1 + sn[i] * a2;
+                H[static_cast<size_t>(i + 1) * m + j] = -sn[i] * a1 + cs[i] * a2;
+            }
+            const double a1 = H[static_cast<size_t>(j) * m + j], a2 = H[static_cast<size_t>(j + 1) * m + j];
+            const double rr = std::hypot(a1, a2);
+            if (rr == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+            else { cs[j] = a1 / rr; sn[j] = a2 / rr; }
+            H[static_cast<size_t>(j) * m + j] = cs[j] * a1 + sn[j] * a2;
+            H[static_cast<size_t>(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            jend = j + 1;
+            if (std::fabs(g[j + 1]) <= o->rtol * bnorm || total >= o->maxit || col[j + 1] == 0.0) break;
+        }
+        if (st) break;
+        for (int i = jend - 1; i >= 0; --i) {
+            double sum = g[i];
+            for (int k = i + 1; k < jend; ++k) sum -= H[static_cast<size_t>(i) * m + k] * y[k];
+            if (H[static_cast<size_t>(i) * m + i] == 0.0) { status = BILU_BREAKDOWN; break; }
+            y[i] = sum / H[static_cast<size_t>(i) * m + i];
+        }
+        if (status == BILU_BREAKDOWN) break;
+        if (hipMemcpyAsync(dy, y.data(), static_cast<size_t>(jend) * sizeof(double), hipMemcpyHostToDevice, s) !=
+            hipSuccess) { st = BILU_ERR_HIP; break; }
+        hipLaunchKernelGGL(dev::k_gm_combine, dim3(eg), dim3(256), 0, s, n, jend, V, dy, u);
+        if ((st = apply(u, z))) break;
+        hipLaunchKernelGGL(dev::k_axpy1, dim3(eg), dim3(256), 0, s, n, x, z);
+        if (hipStreamSynchronize(s) != hipSuccess) { st = BILU_ERR_HIP; break; }
+    }
+    if (!st && status == BILU_BREAKDOWN) {
+        if ((st = spmv(x, w)) == BILU_OK) {
+            hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE);
+            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1);
+            st = fetch(&rres, dH, 1);
+        }
+    }
+    int sweep_err = 0;
+    if (!st) {
+        if (hipMemcpyAsync(&sweep_err, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = BILU_ERR_HIP;
+    }
+    dfree(c, dH);
+    if (st) return st;
+    info[0].status = status;
+    info[0].iters = total;
+    info[0].relres = bnorm > 0.0 ? rres / bnorm : 0.0;
+    if (sweep_err) {
+        CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
+        CK(hipStreamSynchronize(s));
+        return BILU_ERR_TIMEOUT;
+    }
+    return static_cast<bilu_status>(status);
+}
+
 bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x, int nrhs,
                        const bilu_solve_opts* o, bilu_rhs_info* info, int transpose, hipStream_t s)
 {
@@ -883,6 +1020,10 @@ bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x
     if (!c->split_done) return BILU_ERR_STATE;
     if (transpose && !(c->h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
     if (o->method == BILU_BICGSTAB) return bicgstab(c, Ax, b, x, nrhs, o, info, transpose, s);
+    if (o->method == BILU_GMRES) {
+        if (nrhs != 1 || o->restart < 1 || o->restart > 1000) return BILU_ERR_ARG;
+        return gmres(c, Ax, b, x, o, info, transpose, s);
+    }
     return BILU_ERR_ARG;
 }
 

@@ -96,6 +96,11 @@ int sweep_levels(int nb, const std::vector<int32_t>& Pp, const std::vector<int32
 void build_sweep(const Host& h, int which, int rpc, HostSweep& out);
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags);
 void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& out);
+// Predicted duration (in units of `step`) of a tiled sweep with the given
+// tile size (forward sweeps may be restricted to their first row_limit rows;
+// 0 = all), and the tile size with the smallest prediction.
+double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, double hop_in_steps, int row_limit);
+int choose_tile_rows(const Host& h, int rpc, int max_rows);
 int validate_layout(const Host& h);
 
 }  // namespace bilu

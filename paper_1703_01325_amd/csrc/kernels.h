@@ -238,6 +238,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // row a tile reads from outside lies in an earlier tile, so the sweep
 // drains.  Dependency codes: j >= 0 global row, j <= -2 tile-local row
 // (-j - 2), -1 padding.  Single right-hand side.
+//
+// The walk is software-pipelined.  The loads of chunk c+1 are issued in two
+// branch-free batches with a fixed instruction count (addresses clamped
+// into range; the slot arrays carry one chunk of padding), so the compiler
+// can wait for exactly the older batch: (a) row ids, dependency codes and
+// factor values before chunk c is computed, (b) right-hand side, D^{-1}
+// row and the values read from other tiles right after.  Those values are
+// prefetched with plain, cacheable loads: during a sweep an output location
+// only ever holds kNotReady or its final value, so a stale cached copy can
+// only show kNotReady, and a value still showing it is then polled with
+// device-coherent loads.  Dependencies past the first KMAX of a row take an
+// unpipelined path.
 // ---------------------------------------------------------------------------
 struct TiledArgs {
     const int32_t* tile_chunk_ptr;
@@ -254,69 +266,171 @@ struct TiledArgs {
     unsigned int* done;
     int* status;
     int ntiles;
-    int fuse;
     unsigned int total_waves;
     unsigned int spin_limit;
 };
 
-template <int B, typename T>
-__global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
+template <int B>
+struct TiledKmax {
+    static constexpr int value = B <= 2 ? 8 : (B <= 4 ? 6 : 3);
+};
+
+template <int B, typename T, int KMAX, bool FUSE>
+struct TileChunk {
+    int row;             // as loaded (lanes past 64/B rows hold a copy; see lane_ok)
+    int w;
+    int64_t off;
+    int code[KMAX];      // as loaded (slots k >= w hold slot 0's code)
+    T f[KMAX][B];        // factor values as stored
+    double x[KMAX][B];
+    double h[FUSE ? B : 1];
+    T d[FUSE ? B : 1];
+};
+
+// batch (a): independent of any value of this sweep; nothing here consumes
+// a loaded value, so issuing it never waits
+template <int B, typename T, bool FUSE, int KMAX>
+__device__ __forceinline__ void tile_load_a(const TiledArgs& a, int chunk, int qc, int r,
+                                            TileChunk<B, T, KMAX, FUSE>& s)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
+    const T* __restrict__ vals = static_cast<const T*>(a.vals);
+    s.off = a.chunk_off[chunk];
+    s.w = static_cast<int>((a.chunk_off[chunk + 1] - s.off) / RPC);
+    s.row = a.rows[static_cast<int64_t>(chunk) * RPC + qc];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int kk = k < s.w ? k : 0;           // slot 0 exists: one chunk of padding at the end
+        const int64_t sl = s.off + static_cast<int64_t>(kk) * RPC;
+        s.code[k] = a.deps[sl + qc];
+        const int64_t vbase = sl * BB + r * RPC + qc;
+#pragma unroll
+        for (int c = 0; c < B; ++c) s.f[k][c] = vals[vbase + c * B * RPC];
+    }
+}
+
+// batch (b): needs the row ids and codes of batch (a)
+template <int B, typename T, bool FUSE, int KMAX>
+__device__ __forceinline__ void tile_load_b(const TiledArgs& a, int chunk, int qc, int r,
+                                            TileChunk<B, T, KMAX, FUSE>& s)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    // unused row slots of a partly filled chunk hold -1: read row 0 instead
+    const int64_t rowc = s.row >= 0 ? s.row : 0;
+    if (FUSE) {
+        const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
+        const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + qc;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            s.h[c] = a.rhs[rowc * B + c];
+            s.d[c] = dinv[dbase + c * B * RPC];
+        }
+    } else {
+        s.h[0] = a.rhs[rowc * B + r];
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int64_t j = (k < s.w && s.code[k] >= 0) ? s.code[k] : rowc;
+#pragma unroll
+        for (int c = 0; c < B; ++c) s.x[k][c] = a.out[j * B + c];
+    }
+}
+
+template <int B, typename T, bool FUSE, int KMAX>
+__device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool lane_ok,
+                                             double* tile_vals, TileChunk<B, T, KMAX, FUSE>& s)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    if (!lane_ok || s.row < 0) return;
+    double acc;
+    if (FUSE) {
+        acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc += widen(s.d[c]) * s.h[c];
+    } else {
+        acc = s.h[0];
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int code = s.code[k];
+        if (k < s.w && code != -1) {
+            double xv[B];
+            if (code <= -2) {
+                const int loc = -code - 2;
+#pragma unroll
+                for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
+            } else {
+                const double* xj = a.out + static_cast<int64_t>(code) * B;
+#pragma unroll
+                for (int c = 0; c < B; ++c) xv[c] = await_value(xj + c, s.x[k][c], a.spin_limit, a.status);
+            }
+#pragma unroll
+            for (int c = 0; c < B; ++c) acc -= widen(s.f[k][c]) * xv[c];
+        }
+    }
+    if (s.w > KMAX) {
+        const T* __restrict__ vals = static_cast<const T*>(a.vals);
+        for (int k = KMAX; k < s.w; ++k) {
+            const int64_t sl = s.off + static_cast<int64_t>(k) * RPC;
+            const int code = a.deps[sl + qc];
+            if (code == -1) continue;
+            double xv[B];
+            if (code <= -2) {
+                const int loc = -code - 2;
+#pragma unroll
+                for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
+            } else {
+                const double* xj = a.out + static_cast<int64_t>(code) * B;
+#pragma unroll
+                for (int c = 0; c < B; ++c) xv[c] = await_value(xj + c, coherent_load(xj + c), a.spin_limit, a.status);
+            }
+            const int64_t vbase = sl * BB + r * RPC + qc;
+#pragma unroll
+            for (int c = 0; c < B; ++c) acc -= widen(vals[vbase + c * B * RPC]) * xv[c];
+        }
+    }
+    const double v = publishable(acc);
+    const int64_t o = static_cast<int64_t>(s.row) * B + r;
+    if (a.reset) a.reset[o] = not_ready();
+    coherent_store(a.out + o, v);
+    tile_vals[(s.row - lo) * B + r] = v;
+}
+
+template <int B, typename T, bool FUSE>
+__global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int KMAX = TiledKmax<B>::value;
     extern __shared__ double tile_vals[];     // [tile rows][B]
     const int lane = lane_id();
     const int q = lane / B;
     const int r = lane - q * B;
     const bool lane_ok = q < RPC;
-    const T* __restrict__ vals = static_cast<const T*>(a.vals);
-    const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
+    const int qc = lane_ok ? q : RPC - 1;
+    TileChunk<B, T, KMAX, FUSE> s0, s1;
 
     for (int t = grab_ticket(a.ticket); t < a.ntiles; t = grab_ticket(a.ticket)) {
         const int lo = a.tile_lo[t];
-        const int c_end = a.tile_chunk_ptr[t + 1];
-        for (int chunk = a.tile_chunk_ptr[t]; chunk < c_end; ++chunk) {
-            const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
-            const int64_t off = a.chunk_off[chunk];
-            const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
-            if (row >= 0) {
-                double acc;
-                if (a.fuse) {
-                    const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + q;
-                    acc = 0.0;
-#pragma unroll
-                    for (int c = 0; c < B; ++c)
-                        acc += widen(dinv[dbase + c * B * RPC]) * a.rhs[static_cast<int64_t>(row) * B + c];
-                } else {
-                    acc = a.rhs[static_cast<int64_t>(row) * B + r];
-                }
-                for (int k = 0; k < w; ++k) {
-                    const int64_t s = off + static_cast<int64_t>(k) * RPC;
-                    const int code = a.deps[s + q];
-                    if (code == -1) continue;
-                    double xv[B];
-                    if (code <= -2) {
-                        const int loc = -code - 2;
-#pragma unroll
-                        for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
-                    } else {
-                        const double* xj = a.out + static_cast<int64_t>(code) * B;
-#pragma unroll
-                        for (int c = 0; c < B; ++c) xv[c] = coherent_load(xj + c);
-#pragma unroll
-                        for (int c = 0; c < B; ++c) xv[c] = await_value(xj + c, xv[c], a.spin_limit, a.status);
-                    }
-                    const int64_t vbase = s * BB + r * RPC + q;
-#pragma unroll
-                    for (int c = 0; c < B; ++c) acc -= widen(vals[vbase + c * B * RPC]) * xv[c];
-                }
-                const double v = publishable(acc);
-                const int64_t o = static_cast<int64_t>(row) * B + r;
-                if (a.reset) a.reset[o] = not_ready();
-                coherent_store(a.out + o, v);
-                tile_vals[(row - lo) * B + r] = v;
-            }
-            __syncthreads();   // one wavefront: orders this chunk's LDS writes before the next reads
+        const int c0 = a.tile_chunk_ptr[t];
+        const int c1 = a.tile_chunk_ptr[t + 1];
+        if (c0 >= c1) continue;
+        tile_load_a<B, T, FUSE, KMAX>(a, c0, qc, r, s0);
+        tile_load_b<B, T, FUSE, KMAX>(a, c0, qc, r, s0);
+        for (int c = c0; c < c1; c += 2) {
+            const bool more1 = c + 1 < c1;
+            if (more1) tile_load_a<B, T, FUSE, KMAX>(a, c + 1, qc, r, s1);
+            tile_compute<B, T, FUSE, KMAX>(a, lo, qc, r, lane_ok, tile_vals, s0);
+            __syncthreads();   // one wavefront: orders this chunk's LDS writes before later reads
+            if (!more1) break;
+            tile_load_b<B, T, FUSE, KMAX>(a, c + 1, qc, r, s1);
+            const bool more2 = c + 2 < c1;
+            if (more2) tile_load_a<B, T, FUSE, KMAX>(a, c + 2, qc, r, s0);
+            tile_compute<B, T, FUSE, KMAX>(a, lo, qc, r, lane_ok, tile_vals, s1);
+            __syncthreads();
+            if (more2) tile_load_b<B, T, FUSE, KMAX>(a, c + 2, qc, r, s0);
         }
     }
     finish_persistent(a.ticket, a.done, a.total_waves);
@@ -964,6 +1078,75 @@ __global__ void k_bicg_restart(int64_t n, int R, const double* __restrict__ w, d
         r[g] = w[g];
         rh[g] = w[g];
     }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m) vector kernels (one right-hand side).  Modified Gram-Schmidt is
+// run as a chain of fused passes over w: pass i subtracts the projection
+// on v_{i-1} found by the previous pass (coefficient in *coef) and forms the
+// partial dot product of the updated w with v_i; the last pass forms ||w||^2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_gm_mgs(int64_t n, double* __restrict__ w,
+                                                     const double* __restrict__ vprev,
+                                                     const double* __restrict__ coef,
+                                                     const double* __restrict__ vnext, double* part, int slot)
+{
+    const RedIdx ri = red_index(1);
+    double acc = 0.0;
+    const double h = vprev ? *coef : 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n; g += ri.stride) {
+            double wv = w[g];
+            if (vprev) {
+                wv -= h * vprev[g];
+                w[g] = wv;
+            }
+            acc += wv * (vnext ? vnext[g] : wv);
+        }
+    block_partial(acc, 1, slot_ptr(part, slot));
+}
+
+// h = sum of partials; mode 0: *hout = h, *coef = h (next projection);
+// mode 1: h = sqrt(sum), *hout = h, *coef = 1/h (normalisation, 0 if h == 0).
+__global__ void k_gm_h(const double* part, int slot, double* hout, double* coef, int mode)
+{
+    if (threadIdx.x != 0) return;
+    double h = sum_partials(part, slot, 0);
+    if (mode == 1) {
+        h = sqrt(h);
+        *coef = h != 0.0 ? 1.0 / h : 0.0;
+    } else {
+        *coef = h;
+    }
+    *hout = h;
+}
+
+__global__ void k_gm_scale(int64_t n, const double* __restrict__ w, const double* __restrict__ coef,
+                           double* __restrict__ v)
+{
+    const double s = *coef;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        v[g] = w[g] * s;
+}
+
+// u = sum_k y_k v_k over the first m basis vectors (fixed order per entry)
+__global__ void k_gm_combine(int64_t n, int m, const double* __restrict__ V, const double* __restrict__ y,
+                             double* __restrict__ u)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += y[k] * V[static_cast<int64_t>(k) * n + g];
+        u[g] = s;
+    }
+}
+
+__global__ void k_axpy1(int64_t n, double* __restrict__ x, const double* __restrict__ z)
+{
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        x[g] += z[g];
 }
 
 }  // namespace dev
