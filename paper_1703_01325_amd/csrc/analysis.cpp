@@ -308,6 +308,9 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
     s.nchunks = static_cast<int>(s.chunk_off.size() - 1);
     s.tile_chunk_ptr[s.ntiles] = s.nchunks;
     s.nslots = s.chunk_off.back();
+    int64_t max_width = 0;
+    for (int c = 0; c < s.nchunks; ++c) max_width = std::max(max_width, (s.chunk_off[c + 1] - s.chunk_off[c]) / rpc);
+    s.kmax = tiled_kmax(h.bs, static_cast<int>(max_width));
     // one chunk of padding slots, so a kernel may read slot 0 of any chunk
     s.deps.resize(static_cast<size_t>(s.nslots) + rpc, -1);
     s.src.resize(s.deps.size(), -1);
@@ -517,14 +520,17 @@ namespace {
 // Replays, for every chunk and every lane of a wavefront, the index
 // arithmetic of the tiled sweep kernel (batch loads, dependency reads, LDS
 // accesses, stores) and checks each index against the size of the array it
-// addresses.  Mirrors k_sweep_tiled / tile_load_a / tile_load_b /
-// tile_compute in kernels.h.
+// addresses.  Mirrors k_sweep_tiled / tile_meta_b / tile_data /
+// tile_compute in kernels.h (chunk indices past a tile's end clamp to its
+// last chunk, so visiting every chunk covers them).
 bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
 {
     const int B = h.bs;
     const int RPC = kWave / B;
     const int64_t BB = static_cast<int64_t>(B) * B;
-    const int KMAX = B <= 2 ? 8 : (B <= 4 ? 6 : 3);
+    const int KMAX = s.kmax;
+    if (!(KMAX == 3 || KMAX == 6 || KMAX == 9)) return false;
+    if (B >= 5 && KMAX != 3) return false;
     const bool fuse = (which == BILU_SWEEP_U || which == BILU_SWEEP_LT);
     const int64_t n_rows_arr = static_cast<int64_t>(s.rows.size());
     const int64_t n_slots_arr = static_cast<int64_t>(s.deps.size());       // nslots + padding
@@ -546,7 +552,7 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                 if (!in(ri, n_rows_arr)) return false;
                 const int row = s.rows[ri];
                 std::vector<int> code(static_cast<size_t>(KMAX));
-                for (int k = 0; k < KMAX; ++k) {                     // batch (a)
+                for (int k = 0; k < KMAX; ++k) {                     // metadata and factor values
                     const int kk = k < w ? k : 0;
                     const int64_t sl = off + static_cast<int64_t>(kk) * RPC;
                     if (!in(sl + qc, n_slots_arr)) return false;
@@ -554,7 +560,7 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                     const int64_t vb = sl * BB + static_cast<int64_t>(r) * RPC + qc;
                     if (!in(vb, n_vals) || !in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
-                const int64_t rowc = row >= 0 ? row : 0;                // batch (b)
+                const int64_t rowc = row >= 0 ? row : 0;                // right-hand side, D^{-1}, reads
                 if (!in(rowc * B, n_vec) || !in(rowc * B + B - 1, n_vec)) return false;
                 if (fuse) {
                     const int64_t db = static_cast<int64_t>(c) * RPC * BB + static_cast<int64_t>(r) * RPC + qc;

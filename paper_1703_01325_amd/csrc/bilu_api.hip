@@ -167,19 +167,36 @@ bool launch_sweep(int bs, int prec, int R, int blocks, hipStream_t s, const Swee
     return R == 1 ? launch_sweep_b<double, 1>(bs, blocks, s, a) : launch_sweep_b<double, 8>(bs, blocks, s, a);
 }
 
-template <typename T, bool FUSE>
-bool launch_tiled_b(int bs, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+template <typename T, bool FUSE, int B>
+bool launch_tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
-    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE>), dim3(blocks), dim3(64), lds, s, a))
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3>), dim3(blocks), dim3(64), lds, s, a);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 6>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 9>), dim3(blocks), dim3(64), lds, s, a); return true;
+        }
+        return false;
+    }
 }
 
-bool launch_tiled(int bs, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+template <typename T, bool FUSE>
+bool launch_tiled_b(int bs, int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+{
+    BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B>(kmax, blocks, lds, s, a))) return false)
+}
+
+bool launch_tiled(int bs, int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
     if (prec == BILU_FACTORS_FP32)
-        return fuse ? launch_tiled_b<float, true>(bs, blocks, lds, s, a)
-                    : launch_tiled_b<float, false>(bs, blocks, lds, s, a);
-    return fuse ? launch_tiled_b<double, true>(bs, blocks, lds, s, a)
-                : launch_tiled_b<double, false>(bs, blocks, lds, s, a);
+        return fuse ? launch_tiled_b<float, true>(bs, kmax, blocks, lds, s, a)
+                    : launch_tiled_b<float, false>(bs, kmax, blocks, lds, s, a);
+    return fuse ? launch_tiled_b<double, true>(bs, kmax, blocks, lds, s, a)
+                : launch_tiled_b<double, false>(bs, kmax, blocks, lds, s, a);
 }
 
 template <int RT, bool TR>
@@ -393,7 +410,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         const int blocks = persistent_blocks(c, ht.ntiles, 1, 8);
         a.total_waves = static_cast<unsigned int>(blocks);
         const size_t lds = static_cast<size_t>(ht.tile_rows) * c->h.bs * sizeof(double);
-        if (!launch_tiled(c->h.bs, c->precision, fuse != 0, blocks, lds, s, a)) return BILU_ERR_ARG;
+        if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
         const HostSweep& hs = c->h.sweep[which];
         const DevSweep& d = c->ds[kFormLevel][which];

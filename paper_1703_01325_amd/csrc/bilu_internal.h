@@ -50,6 +50,7 @@ struct HostTiled {
     int ntiles = 0;
     int nchunks = 0;
     int64_t nslots = 0;
+    int kmax = 0;                          // dependency slots the kernel keeps in registers
     std::vector<int32_t> tile_chunk_ptr;   // [ntiles+1]
     std::vector<int32_t> tile_lo;          // [ntiles]
     std::vector<int64_t> chunk_off;        // [nchunks+1]
@@ -57,6 +58,16 @@ struct HostTiled {
     std::vector<int32_t> deps;             // [nslots]
     std::vector<int64_t> src;              // [nslots]
 };
+
+// Dependency slots per row that the tiled sweep kernel loads ahead into
+// registers, from the widest chunk of the layout; wider rows finish their
+// remaining slots unpipelined.  Register budget: 3 for blocks of 5..8,
+// else 3, 6 or 9.
+inline int tiled_kmax(int bs, int max_width)
+{
+    if (bs >= 5 || max_width <= 3) return 3;
+    return max_width <= 6 ? 6 : 9;
+}
 
 struct DevSweep {
     int64_t* chunk_off = nullptr;

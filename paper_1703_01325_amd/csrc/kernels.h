@@ -76,6 +76,15 @@ __device__ __forceinline__ double await_value(const double* p, double v, unsigne
     return v;
 }
 
+// Read-only, wave-uniform load through the constant address space, which
+// the compiler turns into a scalar load (its own counter, so vector loads in
+// flight are not waited for).  Only for data no kernel writes while it runs.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p, int64_t i)
+{
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
 __device__ __forceinline__ int grab_ticket(unsigned long long* ticket)
 {
     unsigned long long t = 0;
@@ -239,12 +248,15 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // drains.  Dependency codes: j >= 0 global row, j <= -2 tile-local row
 // (-j - 2), -1 padding.  Single right-hand side.
 //
-// The walk is software-pipelined.  The loads of chunk c+1 are issued in two
-// branch-free batches with a fixed instruction count (addresses clamped
-// into range; the slot arrays carry one chunk of padding), so the compiler
-// can wait for exactly the older batch: (a) row ids, dependency codes and
-// factor values before chunk c is computed, (b) right-hand side, D^{-1}
-// row and the values read from other tiles right after.  Those values are
+// The walk is software-pipelined over a ring of NR register states: at step
+// i the wavefront issues the metadata loads of chunk i + 2(NR-1) (row ids,
+// dependency codes), the data loads of chunk i + NR - 1 (factor values,
+// right-hand side, D^{-1} row, values read from other tiles, addressed by
+// metadata that arrived NR - 1 steps earlier) and computes chunk i.  Every
+// batch is branch-free with a fixed instruction count (chunk indices past
+// the tile clamp to its last chunk, slot indices past a chunk's width clamp
+// to slot 0, the slot arrays carry one chunk of padding), so the compiler
+// waits for exactly the batch it needs.  Values from other tiles are
 // prefetched with plain, cacheable loads: during a sweep an output location
 // only ever holds kNotReady or its final value, so a stale cached copy can
 // only show kNotReady, and a value still showing it is then polled with
@@ -270,55 +282,63 @@ struct TiledArgs {
     unsigned int spin_limit;
 };
 
-template <int B>
-struct TiledKmax {
-    static constexpr int value = B <= 2 ? 8 : (B <= 4 ? 6 : 3);
+template <int KMAX>
+struct TileMeta {
+    int64_t off;         // first slot of the chunk (wave-uniform)
+    int w;               // slots per row (wave-uniform)
+    int row;             // as loaded (unused row slots hold -1)
+    int code[KMAX];      // as loaded (slots past the width hold slot 0's code)
 };
 
 template <int B, typename T, int KMAX, bool FUSE>
-struct TileChunk {
-    int row;             // as loaded (lanes past 64/B rows hold a copy; see lane_ok)
-    int w;
+struct TileData {
     int64_t off;
-    int code[KMAX];      // as loaded (slots k >= w hold slot 0's code)
+    int w;
+    int row;
+    int code[KMAX];      // -1 past the width
     T f[KMAX][B];        // factor values as stored
-    double x[KMAX][B];
+    double x[KMAX][B];   // values read from other tiles (may show kNotReady)
     double h[FUSE ? B : 1];
     T d[FUSE ? B : 1];
 };
 
-// batch (a): independent of any value of this sweep; nothing here consumes
-// a loaded value, so issuing it never waits
-template <int B, typename T, bool FUSE, int KMAX>
-__device__ __forceinline__ void tile_load_a(const TiledArgs& a, int chunk, int qc, int r,
-                                            TileChunk<B, T, KMAX, FUSE>& s)
+// `chunk` is wave-uniform, so the chunk offsets come in through the scalar
+// cache and the addresses of the vector loads below wait on nothing that
+// was issued in the same step.
+template <int B, int KMAX>
+__device__ __forceinline__ void tile_meta_b(const TiledArgs& a, int chunk, int qc, TileMeta<KMAX>& m)
+{
+    constexpr int RPC = 64 / B;
+    m.off = uniform_load(a.chunk_off, chunk);
+    m.w = static_cast<int>((uniform_load(a.chunk_off, chunk + 1) - m.off) / RPC);
+    m.row = a.rows[static_cast<int64_t>(chunk) * RPC + qc];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int kk = k < m.w ? k : 0;           // slot 0 exists: one chunk of padding at the end
+        m.code[k] = a.deps[m.off + static_cast<int64_t>(kk) * RPC + qc];
+    }
+}
+
+template <int B, typename T, int KMAX, bool FUSE>
+__device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc, int r, const TileMeta<KMAX>& m,
+                                          TileData<B, T, KMAX, FUSE>& s)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
     const T* __restrict__ vals = static_cast<const T*>(a.vals);
-    s.off = a.chunk_off[chunk];
-    s.w = static_cast<int>((a.chunk_off[chunk + 1] - s.off) / RPC);
-    s.row = a.rows[static_cast<int64_t>(chunk) * RPC + qc];
+    s.off = m.off;
+    s.w = m.w;
+    s.row = m.row;
+    // unused row slots of a partly filled chunk hold -1: read row 0 instead
+    const int64_t rowc = m.row >= 0 ? m.row : 0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const int kk = k < s.w ? k : 0;           // slot 0 exists: one chunk of padding at the end
-        const int64_t sl = s.off + static_cast<int64_t>(kk) * RPC;
-        s.code[k] = a.deps[sl + qc];
-        const int64_t vbase = sl * BB + r * RPC + qc;
+        const int kk = k < s.w ? k : 0;
+        s.code[k] = k < s.w ? m.code[k] : -1;
+        const int64_t vbase = (s.off + static_cast<int64_t>(kk) * RPC) * BB + r * RPC + qc;
 #pragma unroll
         for (int c = 0; c < B; ++c) s.f[k][c] = vals[vbase + c * B * RPC];
     }
-}
-
-// batch (b): needs the row ids and codes of batch (a)
-template <int B, typename T, bool FUSE, int KMAX>
-__device__ __forceinline__ void tile_load_b(const TiledArgs& a, int chunk, int qc, int r,
-                                            TileChunk<B, T, KMAX, FUSE>& s)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    // unused row slots of a partly filled chunk hold -1: read row 0 instead
-    const int64_t rowc = s.row >= 0 ? s.row : 0;
     if (FUSE) {
         const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
         const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + qc;
@@ -332,18 +352,29 @@ __device__ __forceinline__ void tile_load_b(const TiledArgs& a, int chunk, int q
     }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const int64_t j = (k < s.w && s.code[k] >= 0) ? s.code[k] : rowc;
+        const int64_t j = s.code[k] >= 0 ? s.code[k] : rowc;
 #pragma unroll
         for (int c = 0; c < B; ++c) s.x[k][c] = a.out[j * B + c];
     }
 }
 
-template <int B, typename T, bool FUSE, int KMAX>
+template <int B, typename T, int KMAX, bool FUSE>
 __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool lane_ok,
-                                             double* tile_vals, TileChunk<B, T, KMAX, FUSE>& s)
+                                             double* tile_vals, const TileData<B, T, KMAX, FUSE>& s)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
+    // Every lane takes delivery of the whole batch here, also lanes that
+    // compute nothing: the compiler then never finds a load of this batch
+    // still in flight when it reuses its registers, which would cost a wait
+    // for all later loads.
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+#pragma unroll
+        for (int c = 0; c < B; ++c) asm volatile("" ::"v"(s.f[k][c]), "v"(s.x[k][c]));
+    }
+#pragma unroll
+    for (int c = 0; c < (FUSE ? B : 1); ++c) asm volatile("" ::"v"(s.h[c]), "v"(s.d[c]));
     if (!lane_ok || s.row < 0) return;
     double acc;
     if (FUSE) {
@@ -356,7 +387,7 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int code = s.code[k];
-        if (k < s.w && code != -1) {
+        if (code != -1) {
             double xv[B];
             if (code <= -2) {
                 const int loc = -code - 2;
@@ -399,38 +430,59 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     tile_vals[(s.row - lo) * B + r] = v;
 }
 
-template <int B, typename T, bool FUSE>
+// Ring depth: three register states where they fit in half the register
+// file (two wavefronts per SIMD), else two.
+template <int B, typename T, bool FUSE, int KMAX>
+struct TiledRing {
+    static constexpr int w = sizeof(T) == 8 ? 2 : 1;
+    static constexpr int state = KMAX * B * (2 + w) + KMAX + (FUSE ? B * (2 + w) : 2) + 4 + KMAX + 3;
+    static constexpr int value = 3 * state + 40 <= 240 ? 3 : 2;
+};
+
+template <int B, typename T, bool FUSE, int KMAX>
 __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 {
     constexpr int RPC = 64 / B;
-    constexpr int KMAX = TiledKmax<B>::value;
-    extern __shared__ double tile_vals[];     // [tile rows][B]
+    constexpr int NR = TiledRing<B, T, FUSE, KMAX>::value;   // register states in flight
+    constexpr int LD = NR - 1;                       // data lookahead
+    constexpr int LM = 2 * LD;                       // metadata lookahead
+    extern __shared__ double tile_vals[];            // [tile rows][B]
     const int lane = lane_id();
     const int q = lane / B;
     const int r = lane - q * B;
     const bool lane_ok = q < RPC;
     const int qc = lane_ok ? q : RPC - 1;
-    TileChunk<B, T, KMAX, FUSE> s0, s1;
+    TileMeta<KMAX> mr[NR];
+    TileData<B, T, KMAX, FUSE> dr[NR];
 
-    for (int t = grab_ticket(a.ticket); t < a.ntiles; t = grab_ticket(a.ticket)) {
-        const int lo = a.tile_lo[t];
-        const int c0 = a.tile_chunk_ptr[t];
-        const int c1 = a.tile_chunk_ptr[t + 1];
-        if (c0 >= c1) continue;
-        tile_load_a<B, T, FUSE, KMAX>(a, c0, qc, r, s0);
-        tile_load_b<B, T, FUSE, KMAX>(a, c0, qc, r, s0);
-        for (int c = c0; c < c1; c += 2) {
-            const bool more1 = c + 1 < c1;
-            if (more1) tile_load_a<B, T, FUSE, KMAX>(a, c + 1, qc, r, s1);
-            tile_compute<B, T, FUSE, KMAX>(a, lo, qc, r, lane_ok, tile_vals, s0);
-            __syncthreads();   // one wavefront: orders this chunk's LDS writes before later reads
-            if (!more1) break;
-            tile_load_b<B, T, FUSE, KMAX>(a, c + 1, qc, r, s1);
-            const bool more2 = c + 2 < c1;
-            if (more2) tile_load_a<B, T, FUSE, KMAX>(a, c + 2, qc, r, s0);
-            tile_compute<B, T, FUSE, KMAX>(a, lo, qc, r, lane_ok, tile_vals, s1);
-            __syncthreads();
-            if (more2) tile_load_b<B, T, FUSE, KMAX>(a, c + 2, qc, r, s0);
+    for (int t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); t < a.ntiles;
+         t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int lo = uniform_load(a.tile_lo, t);
+        const int c0 = uniform_load(a.tile_chunk_ptr, t);
+        const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
+        if (nch <= 0) continue;
+        const int clast = c0 + nch - 1;
+        auto chunk_at = [&](int i) { return min(c0 + i, clast); };
+        // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
+        // metadata of LD..LM-1 issued as their slots free up
+#pragma unroll
+        for (int i = 0; i < NR; ++i) tile_meta_b<B, KMAX>(a, chunk_at(i), qc, mr[i]);
+#pragma unroll
+        for (int i = 0; i < LD; ++i) {
+            tile_data<B, T, KMAX, FUSE>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR]);
+            if (NR + i < LM) tile_meta_b<B, KMAX>(a, chunk_at(NR + i), qc, mr[(NR + i) % NR]);
+        }
+        // whole turns of the ring; steps past the tile's end load clamped
+        // chunks and compute nothing
+        for (int i0 = 0; i0 < nch; i0 += NR) {
+#pragma unroll
+            for (int p = 0; p < NR; ++p) {
+                const int i = i0 + p;
+                tile_meta_b<B, KMAX>(a, chunk_at(i + LM), qc, mr[(p + LM) % NR]);
+                tile_data<B, T, KMAX, FUSE>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR]);
+                tile_compute<B, T, KMAX, FUSE>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p]);
+                __syncthreads();   // one wavefront: orders this chunk's LDS writes before later reads
+            }
         }
     }
     finish_persistent(a.ticket, a.done, a.total_waves);
