@@ -213,8 +213,8 @@ bilu_status bilu_grad_A(bilu_ctx* ctx, const double* lambda, const double* x, do
 /* Launch tuning knobs (bilu_tune).  None changes any result bit. */
 enum {
     BILU_TUNE_SWEEP_MODE = 0, /* 0: one launch per level; 1: one persistent launch per
-                                 sweep over level chunks (default); 2: one persistent
-                                 launch per sweep over row tiles (several right-hand
+                                 sweep over level chunks; 2: one persistent launch per
+                                 sweep over row tiles (default; several right-hand
                                  sides use mode 1)                                   */
     BILU_TUNE_TILE_ROWS = 1,  /* block rows per tile in mode 2 (capped so a tile's
                                  values fit 64 KiB of LDS); 0 = chosen by a host
@@ -249,6 +249,72 @@ bilu_status bilu_timing_read(bilu_ctx* ctx, hipStream_t stream, bilu_kernel_time
 
 void bilu_destroy(bilu_ctx* ctx);
 const char* bilu_status_string(int status);
+
+/* ======================================================================
+ * Batches of independent systems of uneven sizes and block sizes.
+ *
+ * Every member is the method above on its own (Algorithm 5 for the
+ * factors, Algorithm 7 for the application, the Krylov loop as in
+ * bilu_solve); a batch runs the members side by side so that one sweep
+ * launch, one SpMV launch and one launch per vector step serve every
+ * member: the sweep launches take (member, level chunk) items from one
+ * work queue, merged level by level across members.
+ *
+ * Batch vectors (r, z, x, y, b) are the members' vectors laid end to end,
+ * member s owning unknowns [off[s], off[s+1]) with
+ * off[s+1] - off[s] = nb_s * bs_s (bilu_batch_offsets); one right-hand side
+ * per member.
+ * ====================================================================== */
+typedef struct bilu_batch bilu_batch;
+
+typedef struct {
+    int nb;              /* block rows                                     */
+    int bs;              /* block size, 1..8                               */
+    const int32_t* Ap;   /* block CSR structure (host, borrowed for the    */
+    const int32_t* Aj;   /* call), same rules as bilu_analyze              */
+} bilu_sys_desc;
+
+/* Host analysis (Algorithm 3, Eq 4) of every member with fill level k.
+ * Errors as bilu_analyze; *bad_sys (if given) names the first failing
+ * member, else -1. */
+bilu_status bilu_batch_create(int nsys, const bilu_sys_desc* sys, int k, bilu_batch** out,
+                              int* bad_sys);
+
+/* Host view of the vector offsets off[nsys+1] (batch-owned) and the total
+ * number of unknowns off[nsys]. */
+bilu_status bilu_batch_offsets(const bilu_batch* batch, const int64_t** off, int64_t* n);
+
+/* Numeric factorisation and split of every member (Algorithm 4, Eq 5):
+ * Ax_dev[s] is member s's device value array (laid out as for
+ * bilu_factor_numeric); the array of pointers is host memory, borrowed for
+ * the call, and the value arrays must stay valid and unchanged for later
+ * bilu_batch_spmv / bilu_batch_solve calls, which read them.  Factors are
+ * stored in `precision`.  On BILU_SINGULAR_PIVOT, *bad_sys and *bad_row name
+ * the member and its block row.  Synchronises `stream`. */
+bilu_status bilu_batch_factor(bilu_batch* batch, const double* const* Ax_dev, int precision,
+                              hipStream_t stream, int* bad_sys, int* bad_row);
+
+/* z = M_s^{-1} r for every member in one L-sweep launch and one U'-sweep
+ * launch; r, z are batch vectors on the device, z may not alias r. */
+bilu_status bilu_batch_apply(bilu_batch* batch, const double* r, double* z, hipStream_t stream);
+
+/* y = A_s x for every member in one launch. */
+bilu_status bilu_batch_spmv(bilu_batch* batch, const double* x, double* y, hipStream_t stream);
+
+/* BiCGSTAB (opts->method must be BILU_BICGSTAB) on every member at once,
+ * x0 = 0, with the member's own scalars and its own exit test
+ * ||b_s - A_s x_s||_2 <= rtol ||b_s||_2; a member that has converged (or
+ * failed) is frozen while the others go on.  info[nsys] (host) receives
+ * per-member results; the return value is the worst of them.  Synchronises
+ * `stream`. */
+bilu_status bilu_batch_solve(bilu_batch* batch, const double* b, double* x, const bilu_solve_opts* opts,
+                             bilu_rhs_info* info, hipStream_t stream);
+
+/* Member s as a single-system context (owned by the batch: do not destroy),
+ * e.g. for bilu_get_factors. */
+bilu_status bilu_batch_member(bilu_batch* batch, int s, bilu_ctx** ctx);
+
+void bilu_batch_destroy(bilu_batch* batch);
 
 #ifdef __cplusplus
 }

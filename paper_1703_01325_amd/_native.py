@@ -31,6 +31,8 @@ EXPORTS = (
     "bilu_apply", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
     "bilu_tune", "bilu_check", "bilu_timing", "bilu_timing_read",
     "bilu_destroy", "bilu_status_string",
+    "bilu_batch_create", "bilu_batch_offsets", "bilu_batch_factor", "bilu_batch_apply",
+    "bilu_batch_spmv", "bilu_batch_solve", "bilu_batch_member", "bilu_batch_destroy",
 )
 K_SWEEP_L, K_SWEEP_U, K_SWEEP_UT, K_SWEEP_LT, K_SPMV, K_FACTOR, K_SPLIT, K_COUNT = range(8)
 K_NAMES = ("sweep_L", "sweep_U", "sweep_UT", "sweep_LT", "spmv", "factor", "split")
@@ -54,6 +56,10 @@ class SolveOpts(ct.Structure):
 
 class RhsInfo(ct.Structure):
     _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("relres", ct.c_double)]
+
+
+class SysDesc(ct.Structure):
+    _fields_ = [("nb", ct.c_int), ("bs", ct.c_int), ("Ap", ct.c_void_p), ("Aj", ct.c_void_p)]
 
 
 class BiluError(RuntimeError):
@@ -90,8 +96,17 @@ def _load():
     L.bilu_destroy.restype = None
     L.bilu_status_string.argtypes = [I]
     L.bilu_status_string.restype = ct.c_char_p
+    L.bilu_batch_create.argtypes = [I, ct.POINTER(SysDesc), I, ct.POINTER(VP), ct.POINTER(I)]
+    L.bilu_batch_offsets.argtypes = [VP, ct.POINTER(P), ct.POINTER(ct.c_int64)]
+    L.bilu_batch_factor.argtypes = [VP, ct.POINTER(P), I, P, ct.POINTER(I), ct.POINTER(I)]
+    L.bilu_batch_apply.argtypes = [VP, P, P, P]
+    L.bilu_batch_spmv.argtypes = [VP, P, P, P]
+    L.bilu_batch_solve.argtypes = [VP, P, P, ct.POINTER(SolveOpts), ct.POINTER(RhsInfo), P]
+    L.bilu_batch_member.argtypes = [VP, I, ct.POINTER(VP)]
+    L.bilu_batch_destroy.argtypes = [VP]
+    L.bilu_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("bilu_destroy", "bilu_status_string"):
+        if name not in ("bilu_destroy", "bilu_status_string", "bilu_batch_destroy"):
             getattr(L, name).restype = I
     return L
 
@@ -235,3 +250,60 @@ def bilu_timing_read(ctx, stream):
 
 def bilu_destroy(ctx):
     lib.bilu_destroy(ctx)
+
+
+def bilu_batch_create(systems, k):
+    """systems: sequence of (nb, bs, Ap, Aj) with host structure arrays."""
+    keep = [(_i32(Ap), _i32(Aj)) for (_, _, Ap, Aj) in systems]
+    descs = (SysDesc * len(systems))()
+    for i, ((nb, bs, _, _), (Ap, Aj)) in enumerate(zip(systems, keep)):
+        descs[i] = SysDesc(int(nb), int(bs), Ap.ctypes.data, Aj.ctypes.data)
+    h = ct.c_void_p()
+    bad = ct.c_int(-1)
+    st = lib.bilu_batch_create(len(systems), descs, int(k), ct.byref(h), ct.byref(bad))
+    if st != OK:
+        raise BiluError(st, f"bilu_batch_create (system {bad.value})")
+    return h
+
+
+def bilu_batch_offsets(batch):
+    off = ct.c_void_p()
+    n = ct.c_int64()
+    _check(lib.bilu_batch_offsets(batch, ct.byref(off), ct.byref(n)), "bilu_batch_offsets")
+    return off, n.value
+
+
+def bilu_batch_factor(batch, Ax_ptrs, precision, stream):
+    arr = (ct.c_void_p * len(Ax_ptrs))(*[ct.c_void_p(int(p)) for p in Ax_ptrs])
+    bad_sys, bad_row = ct.c_int(-1), ct.c_int(-1)
+    st = _check(lib.bilu_batch_factor(batch, arr, int(precision), ct.c_void_p(stream), ct.byref(bad_sys),
+                                      ct.byref(bad_row)), "bilu_batch_factor", allow_positive=True)
+    return st, bad_sys.value, bad_row.value
+
+
+def bilu_batch_apply(batch, r_ptr, z_ptr, stream):
+    _check(lib.bilu_batch_apply(batch, ct.c_void_p(r_ptr), ct.c_void_p(z_ptr), ct.c_void_p(stream)),
+           "bilu_batch_apply")
+
+
+def bilu_batch_spmv(batch, x_ptr, y_ptr, stream):
+    _check(lib.bilu_batch_spmv(batch, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), ct.c_void_p(stream)),
+           "bilu_batch_spmv")
+
+
+def bilu_batch_solve(batch, nsys, b_ptr, x_ptr, rtol, maxit, stream):
+    opts = SolveOpts(BICGSTAB, 0, float(rtol), int(maxit))
+    info = (RhsInfo * int(nsys))()
+    st = _check(lib.bilu_batch_solve(batch, ct.c_void_p(b_ptr), ct.c_void_p(x_ptr), ct.byref(opts), info,
+                                     ct.c_void_p(stream)), "bilu_batch_solve", allow_positive=True)
+    return st, [(i.status, i.iters, i.relres) for i in info]
+
+
+def bilu_batch_member(batch, s):
+    h = ct.c_void_p()
+    _check(lib.bilu_batch_member(batch, int(s), ct.byref(h)), "bilu_batch_member")
+    return h
+
+
+def bilu_batch_destroy(batch):
+    lib.bilu_batch_destroy(batch)

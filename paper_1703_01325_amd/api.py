@@ -38,6 +38,7 @@ class BlockILU:
         self._ctx = N.bilu_analyze(nb, bs, self.Ap, self.Aj, k, N.WANT_TRANSPOSE if transpose else 0)
         self.transpose = bool(transpose)
         self.precision = None
+        self._owned = True
 
     # ---- host views -------------------------------------------------------
     def info(self):
@@ -139,8 +140,85 @@ class BlockILU:
 
     def close(self):
         if self._ctx is not None:
-            N.bilu_destroy(self._ctx)
+            if self._owned:
+                N.bilu_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BlockILUBatch:
+    """Independent systems of uneven sizes and block sizes, preconditioned
+    and solved together: one sweep launch, one SpMV launch and one launch
+    per vector step serve every member.
+
+    ``systems`` is a sequence of ``(nb, bs, Ap, Aj)``.  Batch vectors are the
+    members' vectors laid end to end (``offsets``).
+    """
+
+    def __init__(self, systems, k):
+        self.k = int(k)
+        self.systems = [(int(nb), int(bs), np.ascontiguousarray(Ap, np.int32), np.ascontiguousarray(Aj, np.int32))
+                        for (nb, bs, Ap, Aj) in systems]
+        self.nsys = len(self.systems)
+        self._b = N.bilu_batch_create(self.systems, k)
+        off_p, self.n = N.bilu_batch_offsets(self._b)
+        import ctypes as ct
+        self.offsets = np.ctypeslib.as_array(ct.cast(off_p, ct.POINTER(ct.c_int64)), shape=(self.nsys + 1,)).copy()
+        self._Ax = None
+
+    def factor(self, Ax_list, precision: str = "fp64"):
+        """Factor every member; ``Ax_list[s]`` stays referenced for the SpMVs.
+        Returns (system, block row) of a singular pivot, or None."""
+        for s, Ax in enumerate(Ax_list):
+            _dev_f64(Ax, f"Ax[{s}]")
+        self._Ax = list(Ax_list)
+        prec = N.FACTORS_FP32 if precision == "fp32" else N.FACTORS_FP64
+        st, bad_sys, bad_row = N.bilu_batch_factor(self._b, [a.data_ptr() for a in self._Ax], prec, _stream())
+        if st == N.SINGULAR_PIVOT:
+            return bad_sys, bad_row
+        return None
+
+    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None):
+        _dev_f64(r, "r")
+        z = torch.empty_like(r) if out is None else out
+        N.bilu_batch_apply(self._b, r.data_ptr(), z.data_ptr(), _stream())
+        return z
+
+    def spmv(self, x: torch.Tensor, out: torch.Tensor | None = None):
+        _dev_f64(x, "x")
+        y = torch.empty_like(x) if out is None else out
+        N.bilu_batch_spmv(self._b, x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
+    def solve(self, b: torch.Tensor, rtol=1e-8, maxit=2000, out=None):
+        """BiCGSTAB on every member; returns (x, worst status, per-member
+        (status, iterations, true relative residual))."""
+        _dev_f64(b, "b")
+        x = torch.empty_like(b) if out is None else out
+        st, info = N.bilu_batch_solve(self._b, self.nsys, b.data_ptr(), x.data_ptr(), rtol, maxit, _stream())
+        return x, st, info
+
+    def member(self, s: int) -> BlockILU:
+        """Member s as a BlockILU view (owned by the batch)."""
+        nb, bs, Ap, Aj = self.systems[s]
+        m = object.__new__(BlockILU)
+        m.nb, m.bs, m.k, m.n = nb, bs, self.k, nb * bs
+        m.Ap, m.Aj = Ap, Aj
+        m._ctx = N.bilu_batch_member(self._b, s)
+        m.transpose = False
+        m.precision = None
+        m._owned = False
+        return m
+
+    def close(self):
+        if self._b is not None:
+            N.bilu_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

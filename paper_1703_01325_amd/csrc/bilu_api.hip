@@ -12,6 +12,7 @@
 #include "bilu.h"
 #include "bilu_internal.h"
 #include "kernels.h"
+#include "kernels_batch.h"
 
 using namespace bilu;
 using dev::KState;
@@ -37,7 +38,7 @@ struct bilu_ctx {
     bool factored = false;
     bool split_done = false;
     int precision = BILU_FACTORS_FP64;
-    int sweep_mode = 1;
+    int sweep_mode = 2;
     int tile_rows = 0;          // 0: chosen by schedule simulation on first tiled use
     int blocks_override = 0;
     unsigned int spin_limit = 1u << 24;
@@ -98,8 +99,10 @@ void timing_end(bilu_ctx* c, long slot, hipStream_t s)
     (void)hipEventRecord(c->ev_pool[static_cast<size_t>(slot) + 1], s);
 }
 
-template <typename T>
-bilu_status dalloc(bilu_ctx* c, T** p, size_t count)
+// Device allocations are owned by a context or a batch (anything with an
+// `allocs` list) and freed with it.
+template <typename O, typename T>
+bilu_status dalloc(O* c, T** p, size_t count)
 {
     void* q = nullptr;
     if (count == 0) count = 1;
@@ -109,7 +112,8 @@ bilu_status dalloc(bilu_ctx* c, T** p, size_t count)
     return BILU_OK;
 }
 
-void dfree(bilu_ctx* c, void* p)
+template <typename O>
+void dfree(O* c, void* p)
 {
     if (!p) return;
     auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
@@ -119,8 +123,8 @@ void dfree(bilu_ctx* c, void* p)
     }
 }
 
-template <typename T>
-bilu_status upload(bilu_ctx* c, T** d, const std::vector<T>& h)
+template <typename O, typename T>
+bilu_status upload(O* c, T** d, const std::vector<T>& h)
 {
     bilu_status st = dalloc(c, d, h.size());
     if (st != BILU_OK) return st;
@@ -1072,3 +1076,6 @@ const char* bilu_status_string(int s)
 }
 
 }  // extern "C"
+
+// Batches of independent systems: part of this translation unit.
+#include "batch_api.inc"

@@ -85,6 +85,22 @@ __device__ __forceinline__ T uniform_load(const T* p, int64_t i)
     return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
+// The same for a trivially copyable record, word by word.
+template <typename T>
+__device__ __forceinline__ T uniform_record(const T* p, int64_t i)
+{
+    static_assert(sizeof(T) % 4 == 0, "record of whole words");
+    constexpr int kWords = static_cast<int>(sizeof(T) / 4);
+    const int* w = reinterpret_cast<const int*>(p + i);
+    union {
+        int words[kWords];
+        T rec;
+    } u;
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) u.words[k] = uniform_load(w, k);
+    return u.rec;
+}
+
 __device__ __forceinline__ int grab_ticket(unsigned long long* ticket)
 {
     unsigned long long t = 0;
@@ -148,93 +164,96 @@ struct SweepArgs {
     unsigned int spin_limit;
 };
 
+// One chunk of a level-chunk sweep, by one wavefront.
 template <int B, typename T, int RT>
-__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
+__device__ __forceinline__ void sweep_chunk(SweepArgs a, int chunk)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
     const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
     const int q = lane / B;
     const int r = lane - q * B;
     const bool lane_ok = q < RPC;
     const T* __restrict__ vals = static_cast<const T*>(a.vals);
     const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
     const int R = a.R;
-    const int limit_chunk = a.persistent ? a.nchunks : a.chunk_end;
-
-    int chunk = a.persistent ? grab_ticket(a.ticket)
-                             : a.chunk_begin + static_cast<int>(blockIdx.x) * kWavesPerBlock + wave;
-    while (chunk < limit_chunk) {
-        const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
-        const int64_t off = a.chunk_off[chunk];
-        const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
-        if (row >= 0) {
-            for (int c0 = 0; c0 < R; c0 += RT) {
-                double acc[RT];
+    const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
+    const int64_t off = a.chunk_off[chunk];
+    const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
+    if (row < 0) return;
+    for (int c0 = 0; c0 < R; c0 += RT) {
+        double acc[RT];
 #pragma unroll
-                for (int t = 0; t < RT; ++t) acc[t] = 0.0;
-                if (a.fuse) {
-                    const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + q;
+        for (int t = 0; t < RT; ++t) acc[t] = 0.0;
+        if (a.fuse) {
+            const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + q;
 #pragma unroll
-                    for (int c = 0; c < B; ++c) {
-                        const double d = widen(dinv[dbase + c * B * RPC]);
-                        const double* src = a.rhs + (static_cast<int64_t>(row) * B + c) * R + c0;
+            for (int c = 0; c < B; ++c) {
+                const double d = widen(dinv[dbase + c * B * RPC]);
+                const double* src = a.rhs + (static_cast<int64_t>(row) * B + c) * R + c0;
 #pragma unroll
-                        for (int t = 0; t < RT; ++t)
-                            if (RT == 1 || c0 + t < R) acc[t] += d * src[t];
-                    }
-                } else {
-                    const double* src = a.rhs + (static_cast<int64_t>(row) * B + r) * R + c0;
+                for (int t = 0; t < RT; ++t)
+                    if (RT == 1 || c0 + t < R) acc[t] += d * src[t];
+            }
+        } else {
+            const double* src = a.rhs + (static_cast<int64_t>(row) * B + r) * R + c0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                if (RT == 1 || c0 + t < R) acc[t] = src[t];
+        }
+        for (int k = 0; k < w; ++k) {
+            const int64_t s = off + static_cast<int64_t>(k) * RPC;
+            const int j = a.cols[s + q];
+            if (j < 0) continue;
+            const int64_t vbase = s * BB + r * RPC + q;
+            double xv[B][RT];
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    if (RT == 1 || c0 + t < R) xv[c][t] = a.persistent ? coherent_load(xj + t) : xj[t];
+            }
+            if (a.persistent) {
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
 #pragma unroll
                     for (int t = 0; t < RT; ++t)
-                        if (RT == 1 || c0 + t < R) acc[t] = src[t];
-                }
-                for (int k = 0; k < w; ++k) {
-                    const int64_t s = off + static_cast<int64_t>(k) * RPC;
-                    const int j = a.cols[s + q];
-                    if (j < 0) continue;
-                    const int64_t vbase = s * BB + r * RPC + q;
-                    double xv[B][RT];
-#pragma unroll
-                    for (int c = 0; c < B; ++c) {
-                        const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
-#pragma unroll
-                        for (int t = 0; t < RT; ++t)
-                            if (RT == 1 || c0 + t < R) xv[c][t] = a.persistent ? coherent_load(xj + t) : xj[t];
-                    }
-                    if (a.persistent) {
-#pragma unroll
-                        for (int c = 0; c < B; ++c) {
-                            const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
-#pragma unroll
-                            for (int t = 0; t < RT; ++t)
-                                if (RT == 1 || c0 + t < R) xv[c][t] = await_value(xj + t, xv[c][t], a.spin_limit, a.status);
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < B; ++c) {
-                        const double v = widen(vals[vbase + c * B * RPC]);
-#pragma unroll
-                        for (int t = 0; t < RT; ++t)
-                            if (RT == 1 || c0 + t < R) acc[t] -= v * xv[c][t];
-                    }
-                }
-                const int64_t o = (static_cast<int64_t>(row) * B + r) * R + c0;
-#pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    if (RT == 1 || c0 + t < R) {
-                        if (a.reset) a.reset[o + t] = not_ready();
-                        if (a.persistent) coherent_store(a.out + o + t, publishable(acc[t]));
-                        else a.out[o + t] = publishable(acc[t]);
-                    }
+                        if (RT == 1 || c0 + t < R) xv[c][t] = await_value(xj + t, xv[c][t], a.spin_limit, a.status);
                 }
             }
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                const double v = widen(vals[vbase + c * B * RPC]);
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    if (RT == 1 || c0 + t < R) acc[t] -= v * xv[c][t];
+            }
         }
-        if (!a.persistent) break;
-        chunk = grab_ticket(a.ticket);
+        const int64_t o = (static_cast<int64_t>(row) * B + r) * R + c0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            if (RT == 1 || c0 + t < R) {
+                if (a.reset) a.reset[o + t] = not_ready();
+                if (a.persistent) coherent_store(a.out + o + t, publishable(acc[t]));
+                else a.out[o + t] = publishable(acc[t]);
+            }
+        }
     }
-    if (a.persistent) finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
+template <int B, typename T, int RT>
+__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
+{
+    if (a.persistent) {
+        for (int chunk = grab_ticket(a.ticket); chunk < a.nchunks; chunk = grab_ticket(a.ticket))
+            sweep_chunk<B, T, RT>(a, chunk);
+        finish_persistent(a.ticket, a.done, a.total_waves);
+    } else {
+        const int chunk = a.chunk_begin + static_cast<int>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+        if (chunk < a.chunk_end) sweep_chunk<B, T, RT>(a, chunk);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -493,21 +512,20 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 // the CSR of A^T whose entries point back at A's blocks).  One wavefront per
 // 64/B consecutive block rows, lane (q, r) owns component r of row q.
 // ---------------------------------------------------------------------------
+// Rows [row0, row0 + 64/B) of y = A x (or A^T x through the transposed
+// structure), by one wavefront; lane (q, r) owns component r of row q.
 template <int B, int RT, bool TRANS>
-__global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ cj,
-                                                   const int64_t* __restrict__ srcpos,
-                                                   const double* __restrict__ Ax,
-                                                   const double* __restrict__ x,
-                                                   double* __restrict__ y, int R)
+__device__ __forceinline__ void spmv_rows(int64_t row0, int nb, const int32_t* __restrict__ rp,
+                                          const int32_t* __restrict__ cj, const int64_t* __restrict__ srcpos,
+                                          const double* __restrict__ Ax, const double* __restrict__ x,
+                                          double* __restrict__ y, int R)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
     const int lane = lane_id();
     const int q = lane / B;
     const int r = lane - q * B;
-    const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-    const int64_t row = wave_global * RPC + q;
+    const int64_t row = row0 + q;
     if (q >= RPC || row >= nb) return;
     const int e0 = rp[row], e1 = rp[row + 1];
     for (int c0 = 0; c0 < R; c0 += RT) {
@@ -531,6 +549,18 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __rest
         for (int t = 0; t < RT; ++t)
             if (RT == 1 || c0 + t < R) dst[t] = acc[t];
     }
+}
+
+template <int B, int RT, bool TRANS>
+__global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ cj,
+                                                   const int64_t* __restrict__ srcpos,
+                                                   const double* __restrict__ Ax,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y, int R)
+{
+    const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    spmv_rows<B, RT, TRANS>(wave_global * (64 / B), nb, rp, cj, srcpos, Ax, x, y, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -934,44 +964,103 @@ __device__ __forceinline__ double sum_partials(const double* part, int slot, int
 enum { SL_RHO = 0, SL_RV = 1, SL_SS = 2, SL_TS = 3, SL_TT = 4, SL_RR = 5, SL_BB = 6, SL_TRUE = 7 };
 constexpr int kSlots = 8;
 
+// Scalar steps of right-preconditioned BiCGSTAB for recurrence c of a state
+// S: KState holds the right-hand-side columns of one system, BatchState the
+// systems of a batch; both expose their per-recurrence values as arrays of
+// the same names.  A recurrence that breaks down or turns non-finite is
+// frozen with its status.
+template <class S>
+__device__ __forceinline__ void bicg_init_one(S& st, int c, double b2, double rtol)
+{
+    st.bnorm2[c] = b2;
+    st.tol2[c] = rtol * rtol * b2;
+    st.active[c] = b2 > 0.0 ? 1 : 0;
+    st.status[c] = b2 > 0.0 ? ST_NOT_CONV : ST_OK;
+    st.fresh[c] = 1;
+    st.half[c] = 0;
+    st.restart[c] = 0;
+    st.rho_old[c] = 1.0;
+    st.alpha[c] = 1.0;
+    st.omega[c] = 1.0;
+    st.rnorm2[c] = b2;
+    st.tnorm2[c] = b2;
+}
+
+template <class S>
+__device__ __forceinline__ void bicg_freeze(S& st, int c, int status)
+{
+    st.status[c] = status;
+    st.active[c] = 0;
+}
+
+// rho = <r^, r>; beta for the direction update
+template <class S>
+__device__ __forceinline__ void bicg_rho_one(S& st, int c, double rho)
+{
+    if (!st.active[c]) return;
+    st.rho[c] = rho;
+    st.half[c] = 0;
+    if (!isfinite(rho)) bicg_freeze(st, c, ST_NONFINITE);
+    else if (rho == 0.0) bicg_freeze(st, c, ST_BREAKDOWN);
+    else st.beta[c] = st.fresh[c] ? 0.0 : (rho / st.rho_old[c]) * (st.alpha[c] / st.omega[c]);
+}
+
+// alpha = rho / <r^, v>
+template <class S>
+__device__ __forceinline__ void bicg_alpha_one(S& st, int c, double rv)
+{
+    if (!st.active[c]) return;
+    st.fresh[c] = 0;
+    if (!isfinite(rv)) bicg_freeze(st, c, ST_NONFINITE);
+    else if (rv == 0.0) bicg_freeze(st, c, ST_BREAKDOWN);
+    else st.alpha[c] = st.rho[c] / rv;
+}
+
+// ||s||^2: the half step may already meet the tolerance
+template <class S>
+__device__ __forceinline__ void bicg_snorm_one(S& st, int c, double s2)
+{
+    if (!st.active[c]) return;
+    st.snorm2[c] = s2;
+    st.half[c] = (s2 <= st.tol2[c]) ? 1 : 0;
+    if (!isfinite(s2)) bicg_freeze(st, c, ST_NONFINITE);
+}
+
+// omega = <t, s> / <t, t>
+template <class S>
+__device__ __forceinline__ void bicg_omega_one(S& st, int c, double ts, double tt)
+{
+    if (!st.active[c] || st.half[c]) return;
+    if (!isfinite(ts) || !isfinite(tt)) bicg_freeze(st, c, ST_NONFINITE);
+    else if (tt == 0.0) bicg_freeze(st, c, ST_BREAKDOWN);
+    else st.omega[c] = ts / tt;
+}
+
+// ||r||^2 at the end of a full step
+template <class S>
+__device__ __forceinline__ void bicg_end_one(S& st, int c, double r2)
+{
+    if (!st.active[c] || st.half[c]) return;
+    st.rnorm2[c] = r2;
+    st.rho_old[c] = st.rho[c];
+    if (!isfinite(r2)) bicg_freeze(st, c, ST_NONFINITE);
+    else if (st.omega[c] == 0.0) bicg_freeze(st, c, ST_BREAKDOWN);
+}
+
 // BiCGSTAB setup: ||b||, tolerance, flags.  r = b, r^ = r, x = 0 are done
 // by copies on the host side.
 __global__ void k_bicg_init(int R, const double* part, KState* st, double rtol)
 {
     const int c = threadIdx.x;
     if (c >= R) return;
-    const double b2 = sum_partials(part, SL_BB, c);
-    st->bnorm2[c] = b2;
-    st->tol2[c] = rtol * rtol * b2;
-    st->active[c] = b2 > 0.0 ? 1 : 0;
-    st->status[c] = b2 > 0.0 ? ST_NOT_CONV : ST_OK;
-    st->fresh[c] = 1;
-    st->half[c] = 0;
-    st->restart[c] = 0;
-    st->rho_old[c] = 1.0;
-    st->alpha[c] = 1.0;
-    st->omega[c] = 1.0;
-    st->rnorm2[c] = b2;
-    st->tnorm2[c] = b2;
+    bicg_init_one(*st, c, sum_partials(part, SL_BB, c), rtol);
     if (c == 0) st->sweep_status = 0;
 }
 
 __global__ void k_bicg_s_rho(int R, const double* part, KState* st)
 {
     const int c = threadIdx.x;
-    if (c >= R || !st->active[c]) return;
-    const double rho = sum_partials(part, SL_RHO, c);
-    st->rho[c] = rho;
-    st->half[c] = 0;
-    if (!isfinite(rho)) {
-        st->status[c] = ST_NONFINITE;
-        st->active[c] = 0;
-    } else if (rho == 0.0) {
-        st->status[c] = ST_BREAKDOWN;
-        st->active[c] = 0;
-    } else {
-        st->beta[c] = st->fresh[c] ? 0.0 : (rho / st->rho_old[c]) * (st->alpha[c] / st->omega[c]);
-    }
+    if (c < R) bicg_rho_one(*st, c, sum_partials(part, SL_RHO, c));
 }
 
 __global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const double* __restrict__ v,
@@ -988,18 +1077,7 @@ __global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const d
 __global__ void k_bicg_s_alpha(int R, const double* part, KState* st)
 {
     const int c = threadIdx.x;
-    if (c >= R || !st->active[c]) return;
-    const double rv = sum_partials(part, SL_RV, c);
-    st->fresh[c] = 0;
-    if (!isfinite(rv)) {
-        st->status[c] = ST_NONFINITE;
-        st->active[c] = 0;
-    } else if (rv == 0.0) {
-        st->status[c] = ST_BREAKDOWN;
-        st->active[c] = 0;
-    } else {
-        st->alpha[c] = st->rho[c] / rv;
-    }
+    if (c < R) bicg_alpha_one(*st, c, sum_partials(part, SL_RV, c));
 }
 
 // s = r - alpha v, partial of s.s
@@ -1023,31 +1101,13 @@ __global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t n, int R, const dou
 __global__ void k_bicg_s_snorm(int R, const double* part, KState* st)
 {
     const int c = threadIdx.x;
-    if (c >= R || !st->active[c]) return;
-    const double s2 = sum_partials(part, SL_SS, c);
-    st->snorm2[c] = s2;
-    st->half[c] = (s2 <= st->tol2[c]) ? 1 : 0;
-    if (!isfinite(s2)) {
-        st->status[c] = ST_NONFINITE;
-        st->active[c] = 0;
-    }
+    if (c < R) bicg_snorm_one(*st, c, sum_partials(part, SL_SS, c));
 }
 
 __global__ void k_bicg_s_omega(int R, const double* part, KState* st)
 {
     const int c = threadIdx.x;
-    if (c >= R || !st->active[c] || st->half[c]) return;
-    const double ts = sum_partials(part, SL_TS, c);
-    const double tt = sum_partials(part, SL_TT, c);
-    if (!isfinite(ts) || !isfinite(tt)) {
-        st->status[c] = ST_NONFINITE;
-        st->active[c] = 0;
-    } else if (tt == 0.0) {
-        st->status[c] = ST_BREAKDOWN;
-        st->active[c] = 0;
-    } else {
-        st->omega[c] = ts / tt;
-    }
+    if (c < R) bicg_omega_one(*st, c, sum_partials(part, SL_TS, c), sum_partials(part, SL_TT, c));
 }
 
 // x += alpha p^ (+ omega s^ unless the half step already converged),
@@ -1083,18 +1143,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t n, int R, double* 
 __global__ void k_bicg_s_end(int R, const double* part, KState* st)
 {
     const int c = threadIdx.x;
-    if (c >= R || !st->active[c]) return;
-    if (st->half[c]) return;
-    const double r2 = sum_partials(part, SL_RR, c);
-    st->rnorm2[c] = r2;
-    st->rho_old[c] = st->rho[c];
-    if (!isfinite(r2)) {
-        st->status[c] = ST_NONFINITE;
-        st->active[c] = 0;
-    } else if (st->omega[c] == 0.0) {
-        st->status[c] = ST_BREAKDOWN;
-        st->active[c] = 0;
-    }
+    if (c < R) bicg_end_one(*st, c, sum_partials(part, SL_RR, c));
 }
 
 // w = b - w (w holds A x on entry), partial of w.w

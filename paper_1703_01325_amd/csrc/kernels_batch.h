@@ -1,0 +1,325 @@
+// Kernels for a batch of independent systems of uneven sizes and block
+// sizes, solved together: each sweep and each SpMV over the whole batch is
+// one launch with a work queue of (system, chunk) items, and the Krylov
+// scalars live per system in device memory.  Included once, by
+// bilu_api.hip, after kernels.h.
+//
+// Batch vectors are the systems' vectors laid end to end: system s owns
+// unknowns [voff_s, voff_s + nb_s * bs_s).
+#pragma once
+
+#include "kernels.h"
+
+namespace bilu {
+namespace dev {
+
+// One system as the batch kernels see it.
+struct BatchSys {
+    // level-chunk sweep layouts: [0] L (forward), [1] U' with D^{-1} fused
+    const int64_t* chunk_off[2];
+    const int32_t* rows[2];
+    const int32_t* cols[2];
+    const void* vals[2];
+    const void* dinv;
+    const int32_t* Ap;      // A's block structure and values, for the SpMV
+    const int32_t* Aj;
+    const double* Ax;
+    int64_t voff;           // first unknown of the system in the batch vectors
+    int nb;
+    int bs;
+};
+
+// Krylov scalars of every system (arrays of length nsys, device memory).
+struct BatchState {
+    double *rho, *rho_old, *alpha, *omega, *beta, *bnorm2, *tol2, *snorm2, *rnorm2, *tnorm2;
+    int *active, *fresh, *half, *status, *restart;
+};
+
+// A piece of the batch vectors: a range of unknowns inside one system.
+// Pieces are the work units of the vector kernels and the leaves of the
+// per-system reductions (fixed, so every sum has a fixed order).
+struct Piece {
+    int64_t begin, end;
+    int sys;
+    int pad;
+};
+
+constexpr int kPieceLen = 16384;
+
+#define BILU_BATCH_SWITCH_B(bs, CALL)                   \
+    switch (bs) {                                       \
+    case 1: { constexpr int B = 1; CALL; } break;       \
+    case 2: { constexpr int B = 2; CALL; } break;       \
+    case 3: { constexpr int B = 3; CALL; } break;       \
+    case 4: { constexpr int B = 4; CALL; } break;       \
+    case 5: { constexpr int B = 5; CALL; } break;       \
+    case 6: { constexpr int B = 6; CALL; } break;       \
+    case 7: { constexpr int B = 7; CALL; } break;       \
+    case 8: { constexpr int B = 8; CALL; } break;       \
+    default: break;                                     \
+    }
+
+// ---------------------------------------------------------------------------
+// Sweeps over the batch: one persistent launch per sweep.  Items are the
+// level chunks of every system, merged level by level (level l of every
+// system before level l + 1 of any), so each item depends only on items
+// with smaller tickets, as in the single-system persistent sweep.  Systems
+// whose Krylov recurrence is frozen are skipped by both sweeps of an
+// application alike, which keeps the kNotReady invariant of their buffers.
+// ---------------------------------------------------------------------------
+struct BatchSweepArgs {
+    const BatchSys* sys;
+    const int2* items;        // (system, chunk of that system's layout)
+    int nitems;
+    int which;                // 0: L sweep, 1: U' sweep with D^{-1} fused
+    const double* rhs;
+    double* out;
+    double* reset;
+    const int* active;        // per system, or null: every system
+    unsigned long long* ticket;
+    unsigned int* done;
+    int* status;
+    unsigned int total_waves;
+    unsigned int spin_limit;
+};
+
+template <int B, typename T>
+__device__ __forceinline__ void sweep_batch_item(const BatchSweepArgs& a, const BatchSys& S, int chunk)
+{
+    // selects, not an index: a dynamic index would put S in scratch memory
+    const bool u = a.which != 0;
+    SweepArgs s{};
+    s.chunk_off = u ? S.chunk_off[1] : S.chunk_off[0];
+    s.rows = u ? S.rows[1] : S.rows[0];
+    s.cols = u ? S.cols[1] : S.cols[0];
+    s.vals = u ? S.vals[1] : S.vals[0];
+    s.dinv = S.dinv;
+    s.rhs = a.rhs + S.voff;
+    s.out = a.out + S.voff;
+    s.reset = a.reset ? a.reset + S.voff : nullptr;
+    s.status = a.status;
+    s.R = 1;
+    s.fuse = a.which;
+    s.persistent = 1;
+    s.spin_limit = a.spin_limit;
+    sweep_chunk<B, T, 1>(s, chunk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sweep_batch(BatchSweepArgs a)
+{
+    for (int t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); t < a.nitems;
+         t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int2 it = uniform_record(a.items, t);
+        if (a.active && !uniform_load(a.active, it.x)) continue;
+        const BatchSys S = uniform_record(a.sys, it.x);
+        BILU_BATCH_SWITCH_B(S.bs, (sweep_batch_item<B, T>(a, S, it.y)))
+    }
+    finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
+// ---------------------------------------------------------------------------
+// y = A x over the batch: items are (system, first block row of a
+// wavefront's 64/b rows); wavefronts take items grid-stride.
+// ---------------------------------------------------------------------------
+struct BatchSpmvArgs {
+    const BatchSys* sys;
+    const int2* items;
+    int nitems;
+    const double* x;
+    double* y;
+    const int* active;        // per system, or null
+};
+
+__global__ __launch_bounds__(kThreads) void k_spmv_batch(BatchSpmvArgs a)
+{
+    const int waves = static_cast<int>(gridDim.x) * kWavesPerBlock;
+    const int first = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * kWavesPerBlock +
+                                                     static_cast<int>(threadIdx.x >> 6));
+    for (int w = first; w < a.nitems; w += waves) {
+        const int2 it = uniform_record(a.items, w);
+        if (a.active && !uniform_load(a.active, it.x)) continue;
+        const BatchSys S = uniform_record(a.sys, it.x);
+        BILU_BATCH_SWITCH_B(S.bs, (spmv_rows<B, 1, false>(it.y, S.nb, S.Ap, S.Aj, nullptr, S.Ax, a.x + S.voff,
+                                                          a.y + S.voff, 1)))
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels: one workgroup per piece.  Partials are stored as
+// part[slot * npieces + piece]; the per-system sums run over the system's
+// pieces in order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double sred[kThreads];
+    __syncthreads();
+    sred[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) sred[threadIdx.x] += sred[threadIdx.x + h];
+        __syncthreads();
+    }
+    return sred[0];
+}
+
+__device__ __forceinline__ bool piece_live(const Piece& pc, const int* active)
+{
+    return !active || active[pc.sys];
+}
+
+// part[slot] = <a, b> per piece (0 for frozen systems when active is given)
+__global__ __launch_bounds__(kThreads) void kb_dot(const Piece* pieces, int npieces, const double* __restrict__ a,
+                                                   const double* __restrict__ b, const int* active, double* part,
+                                                   int slot)
+{
+    const Piece pc = pieces[blockIdx.x];
+    double acc = 0.0;
+    if (piece_live(pc, active))
+        for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) acc += a[g] * b[g];
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) part[static_cast<int64_t>(slot) * npieces + blockIdx.x] = s;
+}
+
+// <t, s> and <t, t>
+__global__ __launch_bounds__(kThreads) void kb_dot2(const Piece* pieces, int npieces, const double* __restrict__ t,
+                                                    const double* __restrict__ s, const int* active, double* part,
+                                                    int slot_ts, int slot_tt)
+{
+    const Piece pc = pieces[blockIdx.x];
+    double ts = 0.0, tt = 0.0;
+    if (piece_live(pc, active))
+        for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
+            const double tv = t[g];
+            ts += tv * s[g];
+            tt += tv * tv;
+        }
+    const double a1 = block_sum(ts);
+    const double a2 = block_sum(tt);
+    if (threadIdx.x == 0) {
+        part[static_cast<int64_t>(slot_ts) * npieces + blockIdx.x] = a1;
+        part[static_cast<int64_t>(slot_tt) * npieces + blockIdx.x] = a2;
+    }
+}
+
+__device__ __forceinline__ double sum_pieces(const double* part, int slot, int npieces, int p0, int p1)
+{
+    const double* q = part + static_cast<int64_t>(slot) * npieces;
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) s += q[p];
+    return s;
+}
+
+// The scalar steps of BiCGSTAB for every system (one thread per system).
+enum { KB_INIT = 0, KB_RHO, KB_ALPHA, KB_SNORM, KB_OMEGA, KB_END, KB_TRUE };
+
+__global__ void kb_scalar(int nsys, const int32_t* __restrict__ piece_ptr, int npieces, const double* part,
+                          BatchState st, int op, double rtol)
+{
+    const int c = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= nsys) return;
+    const int p0 = piece_ptr[c], p1 = piece_ptr[c + 1];
+    switch (op) {
+    case KB_INIT: bicg_init_one(st, c, sum_pieces(part, SL_BB, npieces, p0, p1), rtol); break;
+    case KB_RHO: bicg_rho_one(st, c, sum_pieces(part, SL_RHO, npieces, p0, p1)); break;
+    case KB_ALPHA: bicg_alpha_one(st, c, sum_pieces(part, SL_RV, npieces, p0, p1)); break;
+    case KB_SNORM: bicg_snorm_one(st, c, sum_pieces(part, SL_SS, npieces, p0, p1)); break;
+    case KB_OMEGA:
+        bicg_omega_one(st, c, sum_pieces(part, SL_TS, npieces, p0, p1), sum_pieces(part, SL_TT, npieces, p0, p1));
+        break;
+    case KB_END: bicg_end_one(st, c, sum_pieces(part, SL_RR, npieces, p0, p1)); break;
+    case KB_TRUE: st.tnorm2[c] = sum_pieces(part, SL_TRUE, npieces, p0, p1); break;
+    default: break;
+    }
+}
+
+// p = r (first step) or r + beta (p - omega v)
+__global__ __launch_bounds__(kThreads) void kb_p(const Piece* pieces, const double* __restrict__ r,
+                                                 const double* __restrict__ v, double* __restrict__ p, BatchState st)
+{
+    const Piece pc = pieces[blockIdx.x];
+    const int c = pc.sys;
+    if (!st.active[c]) return;
+    const bool fresh = st.fresh[c] != 0;
+    const double be = st.beta[c], om = st.omega[c];
+    for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads)
+        p[g] = fresh ? r[g] : r[g] + be * (p[g] - om * v[g]);
+}
+
+// s = r - alpha v, partial of <s, s>
+__global__ __launch_bounds__(kThreads) void kb_s(const Piece* pieces, int npieces, const double* __restrict__ r,
+                                                 const double* __restrict__ v, double* __restrict__ s, BatchState st,
+                                                 double* part)
+{
+    const Piece pc = pieces[blockIdx.x];
+    const int c = pc.sys;
+    double acc = 0.0;
+    if (st.active[c]) {
+        const double al = st.alpha[c];
+        for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
+            const double sv = r[g] - al * v[g];
+            s[g] = sv;
+            acc += sv * sv;
+        }
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) part[static_cast<int64_t>(SL_SS) * npieces + blockIdx.x] = tot;
+}
+
+// x += alpha p^ (+ omega s^ unless the half step converged), r = s - omega t,
+// partial of <r, r>
+__global__ __launch_bounds__(kThreads) void kb_xr(const Piece* pieces, int npieces, double* __restrict__ x,
+                                                  double* __restrict__ r, const double* __restrict__ ph,
+                                                  const double* __restrict__ sh, const double* __restrict__ s,
+                                                  const double* __restrict__ t, BatchState st, double* part)
+{
+    const Piece pc = pieces[blockIdx.x];
+    const int c = pc.sys;
+    double acc = 0.0;
+    if (st.active[c]) {
+        const double al = st.alpha[c];
+        if (st.half[c]) {
+            for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) x[g] += al * ph[g];
+        } else {
+            const double om = st.omega[c];
+            for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
+                x[g] += al * ph[g] + om * sh[g];
+                const double rv = s[g] - om * t[g];
+                r[g] = rv;
+                acc += rv * rv;
+            }
+        }
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) part[static_cast<int64_t>(SL_RR) * npieces + blockIdx.x] = tot;
+}
+
+// w = b - w (w holds A x on entry), partial of <w, w>
+__global__ __launch_bounds__(kThreads) void kb_resid(const Piece* pieces, int npieces, const double* __restrict__ b,
+                                                     double* __restrict__ w, double* part, int slot)
+{
+    const Piece pc = pieces[blockIdx.x];
+    double acc = 0.0;
+    for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
+        const double v = b[g] - w[g];
+        w[g] = v;
+        acc += v * v;
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) part[static_cast<int64_t>(slot) * npieces + blockIdx.x] = tot;
+}
+
+// r = r^ = w for the systems flagged for a restart
+__global__ __launch_bounds__(kThreads) void kb_restart(const Piece* pieces, const double* __restrict__ w,
+                                                       double* __restrict__ r, double* __restrict__ rh, BatchState st)
+{
+    const Piece pc = pieces[blockIdx.x];
+    if (!st.restart[pc.sys]) return;
+    for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
+        r[g] = w[g];
+        rh[g] = w[g];
+    }
+}
+
+}  // namespace dev
+}  // namespace bilu
