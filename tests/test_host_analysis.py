@@ -140,3 +140,36 @@ def test_tiled_layouts_validate(N, tile_rows):
         N.bilu_validate(ctx)
     finally:
         N.bilu_destroy(ctx)
+
+
+def test_batch_create_host(N):
+    """Batch creation is host analysis only: offsets are the members' unknown
+    counts laid end to end, members keep their own bit-exact analysis, and a
+    bad member is named."""
+    members = [synth.uneven_batch_member(s, side_lo=3, side_hi=6) for s in range(6)]
+    b = N.bilu_batch_create([(m.nb, m.bs, m.Ap, m.Aj) for m in members], 1)
+    try:
+        import ctypes as ct
+        off_p, n = N.bilu_batch_offsets(b)
+        off = np.ctypeslib.as_array(ct.cast(off_p, ct.POINTER(ct.c_int64)), shape=(len(members) + 1,))
+        assert list(off) == list(np.concatenate([[0], np.cumsum([m.n for m in members])]))
+        assert n == off[-1]
+        for s, m in enumerate(members):
+            ctx = N.bilu_batch_member(b, s)
+            info = N.bilu_get_info(ctx)
+            assert (info.nb, info.bs, info.k) == (m.nb, m.bs, 1)
+            N.bilu_validate(ctx)
+        with pytest.raises(N.BiluError):
+            N.bilu_batch_member(b, len(members))
+    finally:
+        N.bilu_batch_destroy(b)
+    bad = list(members[:3])
+    Ap = bad[1].Ap.copy()
+    Aj = bad[1].Aj.copy()
+    Aj[[0, 1]] = Aj[[1, 0]]                      # unsorted row 0 of member 1
+    with pytest.raises(N.BiluError) as ei:
+        N.bilu_batch_create([(m.nb, m.bs, m.Ap, m.Aj) for m in bad[:1]] + [(bad[1].nb, bad[1].bs, Ap, Aj)], 0)
+    assert ei.value.code == N.ERR_PATTERN and "system 1" in str(ei.value)
+    with pytest.raises(N.BiluError) as ei:
+        N.bilu_batch_create([(0, 3, np.zeros(1, np.int32), np.zeros(0, np.int32))], 0)
+    assert ei.value.code == N.ERR_ARG
