@@ -219,9 +219,31 @@ enum {
     BILU_TUNE_TILE_ROWS = 1,  /* block rows per tile in mode 2 (capped so a tile's
                                  values fit 64 KiB of LDS); 0 = chosen by a host
                                  simulation of the tiled schedule (default)          */
-    BILU_TUNE_BLOCKS = 3      /* persistent grid in workgroups, 0 = automatic        */
+    BILU_TUNE_BLOCKS = 3,     /* persistent grid in workgroups, 0 = automatic        */
+    BILU_TUNE_RHS_TILE = 4    /* right-hand-side columns per pass of the level-chunk
+                                 sweeps and the SpMV when nrhs > 1: 1, 4 or 8;
+                                 0 = 8 (default)                                     */
 };
 bilu_status bilu_tune(bilu_ctx* ctx, int param, int value);
+
+typedef struct {
+    int sweep_mode;     /* chosen BILU_TUNE_SWEEP_MODE                          */
+    int tile_rows;      /* chosen rows per wavefront tile (mode 2)              */
+    int rhs_tile;       /* chosen right-hand-side columns per pass              */
+    int candidates;     /* configurations timed                                 */
+    double apply_us;    /* median bilu_apply time of the chosen configuration   */
+    double default_us;  /* the same for the configuration in force on entry     */
+} bilu_tune_result;
+
+/* Autotuner: times bilu_apply with nrhs columns (device scratch input, 2
+ * warm-ups + median of 5, HIP events on `stream`) for candidate launch
+ * configurations and keeps the fastest (the one in force on entry if none
+ * beats it).  Candidates: nrhs = 1, the row tiles of the four tile sizes
+ * with the shortest simulated schedules and the level-chunk form; nrhs > 1,
+ * the level-chunk form with 1, 4 and 8 columns per pass.  Needs the factors
+ * (after bilu_factor_diag); results of later calls are bit-identical to
+ * those before it.  Synchronises `stream`. */
+bilu_status bilu_autotune(bilu_ctx* ctx, int nrhs, hipStream_t stream, bilu_tune_result* out);
 
 /* Synchronises `stream` and reports (then clears) a timeout recorded by any
  * sweep since the last check: BILU_ERR_TIMEOUT, else BILU_OK. */

@@ -29,7 +29,7 @@ EXPORTS = (
     "bilu_analyze", "bilu_get_pattern", "bilu_get_levels", "bilu_get_info", "bilu_validate",
     "bilu_factor_numeric", "bilu_factor_diag", "bilu_get_factors", "bilu_get_factors_f32",
     "bilu_apply", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
-    "bilu_tune", "bilu_check", "bilu_timing", "bilu_timing_read",
+    "bilu_tune", "bilu_autotune", "bilu_check", "bilu_timing", "bilu_timing_read",
     "bilu_destroy", "bilu_status_string",
     "bilu_batch_create", "bilu_batch_offsets", "bilu_batch_factor", "bilu_batch_apply",
     "bilu_batch_spmv", "bilu_batch_solve", "bilu_batch_member", "bilu_batch_destroy",
@@ -56,6 +56,11 @@ class SolveOpts(ct.Structure):
 
 class RhsInfo(ct.Structure):
     _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("relres", ct.c_double)]
+
+
+class TuneResult(ct.Structure):
+    _fields_ = [("sweep_mode", ct.c_int), ("tile_rows", ct.c_int), ("rhs_tile", ct.c_int),
+                ("candidates", ct.c_int), ("apply_us", ct.c_double), ("default_us", ct.c_double)]
 
 
 class SysDesc(ct.Structure):
@@ -89,6 +94,7 @@ def _load():
     L.bilu_solve.argtypes = [VP, P, P, P, I, ct.POINTER(SolveOpts), ct.POINTER(RhsInfo), I, P]
     L.bilu_grad_A.argtypes = [VP, P, P, P, P]
     L.bilu_tune.argtypes = [VP, I, I]
+    L.bilu_autotune.argtypes = [VP, I, P, ct.POINTER(TuneResult)]
     L.bilu_check.argtypes = [VP, P]
     L.bilu_timing.argtypes = [VP, I]
     L.bilu_timing_read.argtypes = [VP, P, ct.POINTER(KernelTime)]
@@ -227,11 +233,18 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
                            ct.c_void_p(stream)), "bilu_grad_A")
 
 
-TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS = 0, 1, 3
+TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE = 0, 1, 3, 4
 
 
 def bilu_tune(ctx, param, value):
     _check(lib.bilu_tune(ctx, int(param), int(value)), "bilu_tune")
+
+
+def bilu_autotune(ctx, nrhs, stream):
+    out = TuneResult()
+    _check(lib.bilu_autotune(ctx, int(nrhs), ct.c_void_p(stream), ct.byref(out)), "bilu_autotune")
+    return {"sweep_mode": out.sweep_mode, "tile_rows": out.tile_rows, "rhs_tile": out.rhs_tile,
+            "candidates": out.candidates, "apply_us": out.apply_us, "default_us": out.default_us}
 
 
 def bilu_check(ctx, stream):

@@ -53,11 +53,17 @@ class BlockILU:
     def set_sweep_mode(self, mode):
         N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
 
-    def tune(self, mode=None, tile_rows=None, blocks=None):
+    def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None):
         """Launch knobs of the sweeps (results are bit-identical for all)."""
-        for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks)):
+        for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
+                         (N.TUNE_RHS_TILE, rhs_tile)):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)
+
+    def autotune(self, nrhs: int = 1):
+        """Times candidate launch configurations on the device and keeps the
+        fastest (after factor); returns the choice and its timings."""
+        return N.bilu_autotune(self._ctx, nrhs, _stream())
 
     # ---- GPU --------------------------------------------------------------
     def factor(self, Ax: torch.Tensor, precision: str = "fp64"):

@@ -1,6 +1,7 @@
 // Host analysis: pattern validation, symbolic ILU(k), level sets and the
 // chunked sweep layouts the GPU kernels stream.  Integer work only.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -400,7 +401,7 @@ double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr,
 // periods; a tile aligned with them keeps corresponding rows of consecutive
 // tiles at the same level inside their tiles).  The smallest simulated
 // makespan of the L sweep wins; ties go to the larger tile.
-int choose_tile_rows(const Host& h, int rpc, int max_rows)
+std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int max_rows)
 {
     const int nb = h.nb;
     max_rows = std::max(1, std::min(max_rows, nb));
@@ -442,17 +443,21 @@ int choose_tile_rows(const Host& h, int rpc, int max_rows)
     std::vector<int32_t> dptr;
     std::vector<Dep> deps;
     sweep_deps(h, BILU_SWEEP_L, dptr, deps);
-    int best = cand.back();
-    double best_t = 1e300;
-    for (int m : cand) {
-        const double t = simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, m, 5.0, limit);
-        if (t < best_t * (1.0 - 1e-9) || (t <= best_t * (1.0 + 1e-9) && m > best)) {
-            best_t = std::min(best_t, t);
-            best = m;
-        }
-    }
-    return best;
+    std::vector<std::pair<double, int>> ranked;
+    for (int m : cand) ranked.emplace_back(simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, m, 5.0, limit), m);
+    // shortest predicted sweep first; on (near) ties the larger tile
+    std::sort(ranked.begin(), ranked.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        if (std::fabs(a.first - b.first) > 1e-9 * std::max(a.first, b.first)) return a.first < b.first;
+        return a.second > b.second;
+    });
+    return ranked;
 }
+
+int choose_tile_rows(const Host& h, int rpc, int max_rows)
+{
+    return rank_tile_rows(h, rpc, max_rows).front().second;
+}
+
 
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags)
 {

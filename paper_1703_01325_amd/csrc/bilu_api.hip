@@ -41,6 +41,7 @@ struct bilu_ctx {
     int sweep_mode = 2;
     int tile_rows = 0;          // 0: chosen by schedule simulation on first tiled use
     int blocks_override = 0;
+    int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
     unsigned int spin_limit = 1u << 24;
 
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
@@ -142,6 +143,13 @@ int grid_for(int64_t work, int threads = 256, int cap = 65536)
 }
 
 bool fused_sweep(int w) { return w == BILU_SWEEP_U || w == BILU_SWEEP_LT; }
+
+// Right-hand-side columns per pass of the level-chunk sweeps and the SpMV.
+int rhs_tile(const bilu_ctx* c, int R)
+{
+    if (R == 1) return 1;
+    return c->rhs_tile > 0 ? c->rhs_tile : 8;
+}
 bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; }
 
 // ----- templated launch helpers ---------------------------------------------
@@ -164,11 +172,17 @@ bool launch_sweep_b(int bs, int blocks, hipStream_t s, const SweepArgs& a)
     BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep<B, T, RT>), dim3(blocks), dim3(dev::kThreads), 0, s, a))
 }
 
-bool launch_sweep(int bs, int prec, int R, int blocks, hipStream_t s, const SweepArgs& a)
+// rt: right-hand-side columns per pass (1, 4 or 8)
+bool launch_sweep(int bs, int prec, int rt, int blocks, hipStream_t s, const SweepArgs& a)
 {
-    if (prec == BILU_FACTORS_FP32)
-        return R == 1 ? launch_sweep_b<float, 1>(bs, blocks, s, a) : launch_sweep_b<float, 8>(bs, blocks, s, a);
-    return R == 1 ? launch_sweep_b<double, 1>(bs, blocks, s, a) : launch_sweep_b<double, 8>(bs, blocks, s, a);
+    if (prec == BILU_FACTORS_FP32) {
+        if (rt == 1) return launch_sweep_b<float, 1>(bs, blocks, s, a);
+        if (rt == 4) return launch_sweep_b<float, 4>(bs, blocks, s, a);
+        return rt == 8 && launch_sweep_b<float, 8>(bs, blocks, s, a);
+    }
+    if (rt == 1) return launch_sweep_b<double, 1>(bs, blocks, s, a);
+    if (rt == 4) return launch_sweep_b<double, 4>(bs, blocks, s, a);
+    return rt == 8 && launch_sweep_b<double, 8>(bs, blocks, s, a);
 }
 
 template <typename T, bool FUSE, int B>
@@ -438,7 +452,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
             a.persistent = 1;
             const int blocks = persistent_blocks(c, hs.nchunks, dev::kWavesPerBlock, 1);
             a.total_waves = static_cast<unsigned int>(blocks) * dev::kWavesPerBlock;
-            if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
+            if (!launch_sweep(c->h.bs, c->precision, rhs_tile(c, R), blocks, s, a)) return BILU_ERR_ARG;
         } else {
             a.persistent = 0;
             for (int l = 0; l < hs.nlev; ++l) {
@@ -447,7 +461,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
                 const int n = a.chunk_end - a.chunk_begin;
                 if (n <= 0) continue;
                 const int blocks = (n + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
-                if (!launch_sweep(c->h.bs, c->precision, R, blocks, s, a)) return BILU_ERR_ARG;
+                if (!launch_sweep(c->h.bs, c->precision, rhs_tile(c, R), blocks, s, a)) return BILU_ERR_ARG;
             }
         }
     }
@@ -483,11 +497,17 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
     const long tslot = timing_begin(c, BILU_K_SPMV, s);
     if (transpose) {
         if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
-        ok = R == 1 ? launch_spmv_b<1, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s)
-                    : launch_spmv_b<8, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s);
+        switch (rhs_tile(c, R)) {
+        case 1: ok = launch_spmv_b<1, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s); break;
+        case 4: ok = launch_spmv_b<4, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s); break;
+        default: ok = launch_spmv_b<8, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s); break;
+        }
     } else {
-        ok = R == 1 ? launch_spmv_b<1, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s)
-                    : launch_spmv_b<8, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s);
+        switch (rhs_tile(c, R)) {
+        case 1: ok = launch_spmv_b<1, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s); break;
+        case 4: ok = launch_spmv_b<4, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s); break;
+        default: ok = launch_spmv_b<8, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s); break;
+        }
     }
     timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
@@ -719,8 +739,110 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (value < 0 || value > (1 << 20)) return BILU_ERR_ARG;
         c->blocks_override = value;
         return BILU_OK;
+    case BILU_TUNE_RHS_TILE:
+        if (value != 0 && value != 1 && value != 4 && value != 8) return BILU_ERR_ARG;
+        c->rhs_tile = value;
+        return BILU_OK;
     }
     return BILU_ERR_ARG;
+}
+
+// Times one configuration: median of `reps` applications (after warm-ups).
+static bilu_status time_apply(bilu_ctx* c, const double* r, double* z, int R, hipStream_t s, double* us)
+{
+    constexpr int warm = 2, reps = 5;
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return BILU_ERR_HIP;
+    }
+    bilu_status st = BILU_OK;
+    std::vector<double> t;
+    for (int i = 0; i < warm + reps && st == BILU_OK; ++i) {
+        if (hipEventRecord(e0, s) != hipSuccess) { st = BILU_ERR_HIP; break; }
+        st = do_apply(c, r, z, R, false, s);
+        if (st) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = BILU_ERR_HIP;
+            break;
+        }
+        if (i >= warm) t.push_back(1e3 * ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    std::sort(t.begin(), t.end());
+    *us = t[t.size() / 2];
+    return BILU_OK;
+}
+
+bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result* out)
+{
+    if (!c || !out || nrhs < 1 || nrhs > dev::kMaxRhs) return BILU_ERR_ARG;
+    if (!c->split_done) return BILU_ERR_STATE;
+    std::memset(out, 0, sizeof(*out));
+    struct Cand {
+        int mode, tile_rows, rhs_tile;
+    };
+    std::vector<Cand> cands;
+    const Cand before{c->sweep_mode, c->tile_rows, c->rhs_tile};
+    if (nrhs == 1) {
+        const auto ranked = rank_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs);
+        for (size_t i = 0; i < ranked.size() && i < 4; ++i) cands.push_back({2, ranked[i].second, 0});
+        cands.push_back({1, c->tile_rows, 0});
+    } else {
+        for (int rt : {1, 4, 8}) cands.push_back({1, c->tile_rows, rt});
+    }
+    const size_t n = static_cast<size_t>(c->h.nb) * c->h.bs * nrhs;
+    double* r = nullptr;
+    double* z = nullptr;
+    bilu_status st;
+    if ((st = dalloc(c, &r, n)) || (st = dalloc(c, &z, n))) {
+        dfree(c, r);
+        return st;
+    }
+    hipLaunchKernelGGL(dev::k_fill_f64, dim3(grid_for(static_cast<int64_t>(n))), dim3(256), 0, s,
+                       static_cast<int64_t>(n), r, 1.0);
+    auto set = [&](const Cand& k) -> bilu_status {
+        bilu_status e;
+        if ((e = bilu_tune(c, BILU_TUNE_SWEEP_MODE, k.mode)) || (e = bilu_tune(c, BILU_TUNE_RHS_TILE, k.rhs_tile)))
+            return e;
+        // tile_rows 0 restores the simulated choice
+        if (k.mode == 2) return bilu_tune(c, BILU_TUNE_TILE_ROWS, k.tile_rows);
+        return BILU_OK;
+    };
+    double best_us = 1e300;
+    Cand best = before;
+    // the configuration in force first, as the reference
+    double ref_us = 0.0;
+    st = time_apply(c, r, z, nrhs, s, &ref_us);
+    for (size_t i = 0; i < cands.size() && st == BILU_OK; ++i) {
+        double us = 0.0;
+        if ((st = set(cands[i])) || (st = time_apply(c, r, z, nrhs, s, &us))) break;
+        ++out->candidates;
+        if (us < best_us) {
+            best_us = us;
+            best = cands[i];
+        }
+    }
+    if (st == BILU_OK && ref_us <= best_us) {
+        best = before;
+        best_us = ref_us;
+    }
+    const bilu_status st2 = set(best);
+    dfree(c, r);
+    dfree(c, z);
+    if (st) return st;
+    if (st2) return st2;
+    out->sweep_mode = c->sweep_mode;
+    out->tile_rows = c->tile_rows;
+    out->rhs_tile = rhs_tile(c, nrhs);
+    out->apply_us = best_us;
+    out->default_us = ref_us;
+    return bilu_check(c, s);
 }
 
 bilu_status bilu_timing(bilu_ctx* c, int enable)

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "bilu.h"
@@ -112,6 +113,8 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& ou
 // 0 = all), and the tile size with the smallest prediction.
 double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, double hop_in_steps, int row_limit);
 int choose_tile_rows(const Host& h, int rpc, int max_rows);
+// Every candidate tile size with its predicted duration, best first.
+std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int max_rows);
 int validate_layout(const Host& h);
 
 }  // namespace bilu

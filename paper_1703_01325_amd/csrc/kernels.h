@@ -76,6 +76,53 @@ __device__ __forceinline__ double await_value(const double* p, double v, unsigne
     return v;
 }
 
+// Waits (bounded) until none of the values v[(g*B + c)*RT + t] shows
+// kNotReady, for the rows j[g] >= 0 (g < G), components c < B and columns
+// t < RT with c0 + t < R; the value lives at out[(j[g]*B + c)*R + c0 + t].
+// Each poll re-reads every value still missing with a device-coherent load,
+// all in one round trip.  Past the limit the timeout is recorded in *status
+// and whatever was read is kept, so the wavefront still finishes.
+template <int G, int B, int RT>
+__device__ __forceinline__ bool rows_missing(const double (&v)[G * B * RT], const int (&j)[G], int R, int c0)
+{
+    bool pending = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                if (j[g] >= 0 && (RT == 1 || c0 + t < R)) pending = pending || is_not_ready(v[(g * B + c) * RT + t]);
+    return pending;
+}
+
+template <int G, int B, int RT>
+__device__ __forceinline__ void await_rows(double (&v)[G * B * RT], const int (&j)[G], const double* out, int R,
+                                           int c0, unsigned int limit, int* status)
+{
+    // the first test reads only the values at hand, outside the loop, so
+    // the common case waits for nothing else
+    bool pending = rows_missing<G, B, RT>(v, j, R, c0);
+    for (unsigned int spins = 0; pending;) {
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int c = 0; c < B; ++c)
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    const int i = (g * B + c) * RT + t;
+                    if (j[g] >= 0 && (RT == 1 || c0 + t < R) && is_not_ready(v[i]))
+                        v[i] = coherent_load(out + (static_cast<int64_t>(j[g]) * B + c) * R + c0 + t);
+                }
+        pending = rows_missing<G, B, RT>(v, j, R, c0);
+    }
+}
+
 // Read-only, wave-uniform load through the constant address space, which
 // the compiler turns into a scalar load (its own counter, so vector loads in
 // flight are not waited for).  Only for data no kernel writes while it runs.
@@ -201,34 +248,37 @@ __device__ __forceinline__ void sweep_chunk(SweepArgs a, int chunk)
             for (int t = 0; t < RT; ++t)
                 if (RT == 1 || c0 + t < R) acc[t] = src[t];
         }
-        for (int k = 0; k < w; ++k) {
-            const int64_t s = off + static_cast<int64_t>(k) * RPC;
-            const int j = a.cols[s + q];
-            if (j < 0) continue;
-            const int64_t vbase = s * BB + r * RPC + q;
-            double xv[B][RT];
+        // dependencies in groups of KG: all their values are requested
+        // together and missing ones polled together (one round trip each)
+        constexpr int KG = RT == 1 ? (B <= 4 ? 4 : 2) : 1;
+        for (int k0 = 0; k0 < w; k0 += KG) {
+            int j[KG];
 #pragma unroll
-            for (int c = 0; c < B; ++c) {
-                const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
+            for (int g = 0; g < KG; ++g)
+                j[g] = k0 + g < w ? a.cols[off + static_cast<int64_t>(k0 + g) * RPC + q] : -1;
+            double xv[KG * B * RT];
 #pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    if (RT == 1 || c0 + t < R) xv[c][t] = a.persistent ? coherent_load(xj + t) : xj[t];
-            }
-            if (a.persistent) {
+            for (int g = 0; g < KG; ++g)
+#pragma unroll
+                for (int c = 0; c < B; ++c)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        const double* xp = a.out + (static_cast<int64_t>(j[g]) * B + c) * R + c0 + t;
+                        const bool want = j[g] >= 0 && (RT == 1 || c0 + t < R);
+                        xv[(g * B + c) * RT + t] = want ? (a.persistent ? coherent_load(xp) : *xp) : 0.0;
+                    }
+            if (a.persistent) await_rows<KG, B, RT>(xv, j, a.out, R, c0, a.spin_limit, a.status);
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                if (j[g] < 0) continue;
+                const int64_t vbase = (off + static_cast<int64_t>(k0 + g) * RPC) * BB + r * RPC + q;
 #pragma unroll
                 for (int c = 0; c < B; ++c) {
-                    const double* xj = a.out + (static_cast<int64_t>(j) * B + c) * R + c0;
+                    const double v = widen(vals[vbase + c * B * RPC]);
 #pragma unroll
                     for (int t = 0; t < RT; ++t)
-                        if (RT == 1 || c0 + t < R) xv[c][t] = await_value(xj + t, xv[c][t], a.spin_limit, a.status);
+                        if (RT == 1 || c0 + t < R) acc[t] -= v * xv[(g * B + c) * RT + t];
                 }
-            }
-#pragma unroll
-            for (int c = 0; c < B; ++c) {
-                const double v = widen(vals[vbase + c * B * RPC]);
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    if (RT == 1 || c0 + t < R) acc[t] -= v * xv[c][t];
             }
         }
         const int64_t o = (static_cast<int64_t>(row) * B + r) * R + c0;
@@ -403,6 +453,14 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     } else {
         acc = s.h[0];
     }
+    // values from other tiles: the prefetched copies, with the ones still
+    // showing kNotReady polled together
+    double xg[KMAX * B];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
+    await_rows<KMAX, B, 1>(xg, s.code, a.out, 1, 0, a.spin_limit, a.status);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int code = s.code[k];
@@ -413,9 +471,8 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
 #pragma unroll
                 for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
             } else {
-                const double* xj = a.out + static_cast<int64_t>(code) * B;
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = await_value(xj + c, s.x[k][c], a.spin_limit, a.status);
+                for (int c = 0; c < B; ++c) xv[c] = xg[k * B + c];
             }
 #pragma unroll
             for (int c = 0; c < B; ++c) acc -= widen(s.f[k][c]) * xv[c];
@@ -435,7 +492,9 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
             } else {
                 const double* xj = a.out + static_cast<int64_t>(code) * B;
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = await_value(xj + c, coherent_load(xj + c), a.spin_limit, a.status);
+                for (int c = 0; c < B; ++c) xv[c] = coherent_load(xj + c);
+                const int one[1] = {code};
+                await_rows<1, B, 1>(xv, one, a.out, 1, 0, a.spin_limit, a.status);
             }
             const int64_t vbase = sl * BB + r * RPC + qc;
 #pragma unroll

@@ -356,3 +356,43 @@ def test_autograd_thermal_full_size_fd(api):
         bm[int(q)] -= h
         fd = (L(Ad, bp) - L(Ad, bm)) / (2 * h)
         assert abs(fd - float(b.grad[int(q)])) <= 1e-6 * max(1.0, abs(fd)) + 1e-9
+
+
+@pytest.mark.parametrize("rt", [1, 4, 8])
+def test_rhs_tile_parity(api, oracle_mod, rt):
+    """Columns per pass change only how the columns are grouped: every
+    column's arithmetic is the same, so results are bit-identical."""
+    c = Case(oracle_mod, synth.reservoir(9, 7, 5, 3, seed=61), 1)
+    M = c.gpu(api)
+    R = 13
+    B = synth.multi_rhs(c.s.n, R, seed=41)
+    M.tune(rhs_tile=8)
+    z8 = M.apply(cuda(B))
+    y8 = M.spmv(c.Ax, cuda(B))
+    M.tune(rhs_tile=rt)
+    z = M.apply(cuda(B))
+    y = M.spmv(c.Ax, cuda(B))
+    assert torch.equal(z, z8) and torch.equal(y, y8)
+    zc = z.cpu().numpy()
+    for j in (0, 5, 12):
+        assert rel(zc[:, j], c.O.apply(B[:, j])) <= 1e-12
+    M.check()
+
+
+def test_autotune(api, oracle_mod):
+    c = Case(oracle_mod, synth.small_10cube(), 1)
+    M = c.gpu(api)
+    r = cuda(np.random.default_rng(4).standard_normal(c.s.n))
+    z0 = M.apply(r)
+    res = M.autotune(1)
+    assert res["candidates"] >= 2 and res["sweep_mode"] in (1, 2)
+    assert 0 < res["apply_us"] <= res["default_us"]
+    assert torch.equal(M.apply(r), z0)
+    B = cuda(synth.multi_rhs(c.s.n, 8, seed=41))
+    Z0 = M.apply(B)
+    res8 = M.autotune(8)
+    assert res8["rhs_tile"] in (1, 4, 8) and 0 < res8["apply_us"] <= res8["default_us"]
+    assert torch.equal(M.apply(B), Z0)
+    x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
+    assert st == 0
+    M.check()
