@@ -1,6 +1,8 @@
 // Host analysis: pattern validation, symbolic ILU(k), level sets and the
 // chunked sweep layouts the GPU kernels stream.  Integer work only.
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -312,8 +314,9 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
     int64_t max_width = 0;
     for (int c = 0; c < s.nchunks; ++c) max_width = std::max(max_width, (s.chunk_off[c + 1] - s.chunk_off[c]) / rpc);
     s.kmax = tiled_kmax(h.bs, static_cast<int>(max_width));
-    // one chunk of padding slots, so a kernel may read slot 0 of any chunk
-    s.deps.resize(static_cast<size_t>(s.nslots) + rpc, -1);
+    // padding slot rows, so a kernel may read the first kTilePadRows slot
+    // rows of any chunk
+    s.deps.resize(static_cast<size_t>(s.nslots) + static_cast<size_t>(kTilePadRows) * rpc, -1);
     s.src.resize(s.deps.size(), -1);
     s.built = true;
 }
@@ -525,16 +528,16 @@ namespace {
 // Replays, for every chunk and every lane of a wavefront, the index
 // arithmetic of the tiled sweep kernel (batch loads, dependency reads, LDS
 // accesses, stores) and checks each index against the size of the array it
-// addresses.  Mirrors k_sweep_tiled / tile_meta_b / tile_data /
-// tile_compute in kernels.h (chunk indices past a tile's end clamp to its
-// last chunk, so visiting every chunk covers them).
+// addresses.  Mirrors k_sweep_tiled / tile_meta / tile_data / tile_compute
+// in kernels.h (chunk indices past a tile's end clamp to its last chunk, so
+// visiting every chunk covers them).
 bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
 {
     const int B = h.bs;
     const int RPC = kWave / B;
     const int64_t BB = static_cast<int64_t>(B) * B;
     const int KMAX = s.kmax;
-    if (!(KMAX == 3 || KMAX == 6 || KMAX == 9)) return false;
+    if (!(KMAX == 3 || KMAX == 6 || KMAX == 9) || KMAX > kTilePadRows) return false;
     if (B >= 5 && KMAX != 3) return false;
     const bool fuse = (which == BILU_SWEEP_U || which == BILU_SWEEP_LT);
     const int64_t n_rows_arr = static_cast<int64_t>(s.rows.size());
@@ -543,6 +546,8 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
     const int64_t n_dinv = static_cast<int64_t>(s.nchunks) * RPC * BB;
     const int64_t n_vec = static_cast<int64_t>(h.nb) * B;
     const int64_t n_lds = static_cast<int64_t>(s.tile_rows) * B;
+    // vector loads use 32-bit byte offsets
+    if (n_vec * 8 > static_cast<int64_t>(UINT32_MAX)) return false;
     auto in = [](int64_t i, int64_t n) { return i >= 0 && i < n; };
     for (int t = 0; t < s.ntiles; ++t) {
         const int lo = s.tile_lo[t];
@@ -553,30 +558,32 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                 const int q = lane / B, r = lane - q * B;
                 const bool lane_ok = q < RPC;
                 const int qc = lane_ok ? q : RPC - 1;
-                const int64_t ri = static_cast<int64_t>(c) * RPC + qc;
+                const int64_t lane_off = static_cast<int64_t>(r) * RPC + qc;
+                const int64_t ri = static_cast<int64_t>(c) * RPC + qc;          // tile_meta
                 if (!in(ri, n_rows_arr)) return false;
                 const int row = s.rows[ri];
                 std::vector<int> code(static_cast<size_t>(KMAX));
-                for (int k = 0; k < KMAX; ++k) {                     // metadata and factor values
-                    const int kk = k < w ? k : 0;
-                    const int64_t sl = off + static_cast<int64_t>(kk) * RPC;
-                    if (!in(sl + qc, n_slots_arr)) return false;
-                    code[k] = s.deps[sl + qc];
-                    const int64_t vb = sl * BB + static_cast<int64_t>(r) * RPC + qc;
+                for (int k = 0; k < KMAX; ++k) {
+                    const int64_t di = off + static_cast<int64_t>(k) * RPC + qc;
+                    if (!in(di, n_slots_arr)) return false;
+                    code[k] = k < w ? s.deps[di] : -1;                       // tile_data
+                    const int64_t vb = off * BB + k * RPC * BB + lane_off;
                     if (!in(vb, n_vals) || !in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
-                const int64_t rowc = row >= 0 ? row : 0;                // right-hand side, D^{-1}, reads
+                const int64_t rowc = row >= 0 ? row : 0;
                 if (!in(rowc * B, n_vec) || !in(rowc * B + B - 1, n_vec)) return false;
                 if (fuse) {
-                    const int64_t db = static_cast<int64_t>(c) * RPC * BB + static_cast<int64_t>(r) * RPC + qc;
+                    const int64_t db = static_cast<int64_t>(c) * RPC * BB + lane_off;
                     if (!in(db, n_dinv) || !in(db + static_cast<int64_t>(B - 1) * B * RPC, n_dinv)) return false;
                 }
                 for (int k = 0; k < KMAX; ++k) {
-                    const int64_t j = (k < w && code[k] >= 0) ? code[k] : rowc;
+                    const int64_t j = code[k] >= 0 ? code[k] : rowc;
                     if (!in(j * B, n_vec) || !in(j * B + B - 1, n_vec)) return false;
+                    const int64_t loc = code[k] <= -2 ? -static_cast<int64_t>(code[k]) - 2 : 0;   // tile_compute
+                    if (!in(loc * B, n_lds) || !in(loc * B + B - 1, n_lds)) return false;
                 }
-                if (!lane_ok || row < 0) continue;                       // compute
-                for (int k = 0; k < w; ++k) {
+                if (!lane_ok || row < 0) continue;
+                for (int k = KMAX; k < w; ++k) {                                // unpipelined slots
                     const int64_t sl = off + static_cast<int64_t>(k) * RPC;
                     if (!in(sl + qc, n_slots_arr)) return false;
                     const int cd = s.deps[sl + qc];
@@ -587,6 +594,8 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                     } else if (!in(static_cast<int64_t>(cd) * B + B - 1, n_vec)) {
                         return false;
                     }
+                    const int64_t vb = sl * BB + lane_off;
+                    if (!in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
                 if (!in(static_cast<int64_t>(row) * B + r, n_vec)) return false;
                 if (!in(static_cast<int64_t>(row - lo) * B + r, n_lds)) return false;
@@ -674,8 +683,9 @@ int validate_layout(const Host& h)
             s.tile_chunk_ptr[s.ntiles] != s.nchunks || static_cast<int>(s.tile_lo.size()) != s.ntiles)
             return BILU_ERR_STATE;
         if (static_cast<int>(s.chunk_off.size()) != s.nchunks + 1 || s.chunk_off[0] != 0 ||
-            s.chunk_off.back() != s.nslots || static_cast<int64_t>(s.deps.size()) != s.nslots + rpc ||
-            static_cast<int64_t>(s.src.size()) != s.nslots + rpc ||
+            s.chunk_off.back() != s.nslots ||
+            static_cast<int64_t>(s.deps.size()) != s.nslots + static_cast<int64_t>(kTilePadRows) * rpc ||
+            static_cast<int64_t>(s.src.size()) != s.nslots + static_cast<int64_t>(kTilePadRows) * rpc ||
             static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc)
             return BILU_ERR_STATE;
         std::vector<int32_t> tile_of(static_cast<size_t>(nb), -1), chunk_of(static_cast<size_t>(nb), -1);

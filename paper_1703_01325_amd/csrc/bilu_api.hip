@@ -261,9 +261,15 @@ bilu_status upload_form(bilu_ctx* c, int form)
             if (c->tile_rows <= 0) c->tile_rows = choose_tile_rows(h, h.rpc, kMaxTileDoubles / h.bs);
             HostTiled& ht = h.tiled[w];
             if (!ht.built || ht.tile_rows != c->tile_rows) build_tiled(h, w, h.rpc, c->tile_rows, ht);
+            std::vector<int32_t> crow(ht.chunk_off.size());
+            for (size_t i = 0; i < crow.size(); ++i) {
+                if (ht.chunk_off[i] % h.rpc != 0 || ht.chunk_off[i] / h.rpc > INT32_MAX) return BILU_ERR_STATE;
+                crow[i] = static_cast<int32_t>(ht.chunk_off[i] / h.rpc);
+            }
             if ((st = upload(c, &d.chunk_off, ht.chunk_off)) || (st = upload(c, &d.rows, ht.rows)) ||
                 (st = upload(c, &d.cols, ht.deps)) || (st = upload(c, &d.src, ht.src)) ||
-                (st = upload(c, &d.tile_chunk_ptr, ht.tile_chunk_ptr)) || (st = upload(c, &d.tile_lo, ht.tile_lo)))
+                (st = upload(c, &d.tile_chunk_ptr, ht.tile_chunk_ptr)) || (st = upload(c, &d.tile_lo, ht.tile_lo)) ||
+                (st = upload(c, &d.chunk_row, crow)))
                 return st;
         }
         d.vals_precision = -1;
@@ -280,7 +286,7 @@ void free_form(bilu_ctx* c, int form)
         DevSweep& d = c->ds[form][w];
         for (void* p : {static_cast<void*>(d.chunk_off), static_cast<void*>(d.rows), static_cast<void*>(d.cols),
                         static_cast<void*>(d.src), static_cast<void*>(d.tile_chunk_ptr),
-                        static_cast<void*>(d.tile_lo), d.vals, d.dinv})
+                        static_cast<void*>(d.tile_lo), static_cast<void*>(d.chunk_row), d.vals, d.dinv})
             dfree(c, p);
         d = DevSweep{};
     }
@@ -329,7 +335,14 @@ bilu_status ensure_device(bilu_ctx* c)
     return BILU_OK;
 }
 
-int form_of_mode(int mode) { return mode == 2 ? kFormTiled : kFormLevel; }
+// Layout form the sweeps use: row tiles in mode 2 for one right-hand side
+// (their vector loads take 32-bit byte offsets, so vectors must stay below
+// 4 GiB), level chunks otherwise.
+int sweep_form(const bilu_ctx* c, int R)
+{
+    const bool fits = static_cast<int64_t>(c->h.nb) * c->h.bs * 8 <= static_cast<int64_t>(UINT32_MAX);
+    return c->sweep_mode == 2 && R == 1 && fits ? kFormTiled : kFormLevel;
+}
 
 // Factor values of one layout form in the current precision.
 bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
@@ -343,8 +356,9 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         if (!h.sweep[w].built) continue;
         DevSweep& d = c->ds[form][w];
         if (d.vals_precision == c->precision) continue;
-        // the tiled form carries one chunk of padding slots (zero values)
-        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots + h.rpc;
+        // the tiled form carries kTilePadRows slot rows of padding (zero values)
+        const int64_t nslots =
+            form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots + static_cast<int64_t>(kTilePadRows) * h.rpc;
         const int nchunks = form == kFormLevel ? h.sweep[w].nchunks : h.tiled[w].nchunks;
         const int rpc = h.rpc;
         dfree(c, d.vals);
@@ -403,7 +417,7 @@ int persistent_blocks(bilu_ctx* c, int units, int units_per_block, int per_cu)
 
 bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, double* reset, int R, hipStream_t s)
 {
-    const int form = form_of_mode(c->sweep_mode == 2 && R > 1 ? 1 : c->sweep_mode);
+    const int form = sweep_form(c, R);
     const long tslot = timing_begin(c, BILU_K_SWEEP_L + which, s);
     const int fuse = fused_sweep(which) ? 1 : 0;
     if (form == kFormTiled) {
@@ -412,7 +426,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         TiledArgs a{};
         a.tile_chunk_ptr = d.tile_chunk_ptr;
         a.tile_lo = d.tile_lo;
-        a.chunk_off = d.chunk_off;
+        a.chunk_row = d.chunk_row;
         a.rows = d.rows;
         a.deps = d.cols;
         a.vals = d.vals;
@@ -479,7 +493,7 @@ bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transp
     const int second = transpose ? BILU_SWEEP_LT : BILU_SWEEP_U;
     if (!c->h.sweep[first].built || !c->h.sweep[second].built) return BILU_ERR_STATE;
     bilu_status st;
-    const int form = form_of_mode(c->sweep_mode == 2 && R > 1 ? 1 : c->sweep_mode);
+    const int form = sweep_form(c, R);
     if ((st = layout_form(c, form, s))) return st;
     if ((st = ensure_y(c, R, s))) return st;
     if ((st = run_sweep(c, first, r, c->d_y, z, R, s))) return st;
@@ -637,7 +651,7 @@ bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
     c->precision = precision;
     for (int f = 0; f < 2; ++f)
         for (int w = 0; w < 4; ++w) c->ds[f][w].vals_precision = -1;
-    bilu_status st = layout_form(c, form_of_mode(c->sweep_mode), s);
+    bilu_status st = layout_form(c, sweep_form(c, 1), s);
     if (st) return st;
     timing_end(c, tslot, s);
     CK(hipGetLastError());

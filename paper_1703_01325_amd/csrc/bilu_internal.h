@@ -70,6 +70,10 @@ inline int tiled_kmax(int bs, int max_width)
     return max_width <= 6 ? 6 : 9;
 }
 
+// Slot rows of padding after the last chunk of a tiled layout: the kernel
+// reads the first KMAX (<= 9) slot rows of every chunk whatever its width.
+constexpr int kTilePadRows = 9;
+
 struct DevSweep {
     int64_t* chunk_off = nullptr;
     int32_t* rows = nullptr;
@@ -77,6 +81,7 @@ struct DevSweep {
     int64_t* src = nullptr;
     int32_t* tile_chunk_ptr = nullptr;
     int32_t* tile_lo = nullptr;
+    int32_t* chunk_row = nullptr;  // tiled form: chunk_off / rpc (first slot row)
     void* vals = nullptr;     // [nslots * bs*bs] FP64 or FP32, layout [k][c][r][q]
     void* dinv = nullptr;     // [nchunks*rpc * bs*bs] same layout, fused sweeps only
     int vals_precision = -1;  // precision the values were laid out in (-1: none)

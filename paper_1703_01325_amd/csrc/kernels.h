@@ -85,6 +85,7 @@ __device__ __forceinline__ double await_value(const double* p, double v, unsigne
 template <int G, int B, int RT>
 __device__ __forceinline__ bool rows_missing(const double (&v)[G * B * RT], const int (&j)[G], int R, int c0)
 {
+    // bitwise, not short-circuit: no branches
     bool pending = false;
 #pragma unroll
     for (int g = 0; g < G; ++g)
@@ -92,7 +93,7 @@ __device__ __forceinline__ bool rows_missing(const double (&v)[G * B * RT], cons
         for (int c = 0; c < B; ++c)
 #pragma unroll
             for (int t = 0; t < RT; ++t)
-                if (j[g] >= 0 && (RT == 1 || c0 + t < R)) pending = pending || is_not_ready(v[(g * B + c) * RT + t]);
+                pending |= (j[g] >= 0) & (RT == 1 || c0 + t < R) & is_not_ready(v[(g * B + c) * RT + t]);
     return pending;
 }
 
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // and walks it in its own level order (levels of Eq 4 restricted to the
 // dependencies inside the tile), one chunk of up to 64/B rows at a time.
 // A dependency inside the tile is read from LDS, where the wavefront keeps
-// every row it has finished; a dependency on another tile is polled from
+// every row it has finished; a dependency on another tile is read from
 // global memory.  Tiles are taken from a ticket in sweep order, and every
 // row a tile reads from outside lies in an earlier tile, so the sweep
 // drains.  Dependency codes: j >= 0 global row, j <= -2 tile-local row
@@ -322,20 +323,22 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // dependency codes), the data loads of chunk i + NR - 1 (factor values,
 // right-hand side, D^{-1} row, values read from other tiles, addressed by
 // metadata that arrived NR - 1 steps earlier) and computes chunk i.  Every
-// batch is branch-free with a fixed instruction count (chunk indices past
-// the tile clamp to its last chunk, slot indices past a chunk's width clamp
-// to slot 0, the slot arrays carry one chunk of padding), so the compiler
-// waits for exactly the batch it needs.  Values from other tiles are
-// prefetched with plain, cacheable loads: during a sweep an output location
-// only ever holds kNotReady or its final value, so a stale cached copy can
-// only show kNotReady, and a value still showing it is then polled with
+// batch is branch-free with a fixed instruction count: chunk indices past
+// the tile clamp to its last chunk, and the first KMAX slot rows of a chunk
+// are always read (the layout carries KMAX slot rows of padding after the
+// last chunk) and masked past the chunk's width.  Chunk-wide addresses are
+// scalar; a lane adds a fixed offset, so the per-slot loads need no vector
+// address arithmetic.  Values from other tiles are prefetched with plain,
+// cacheable loads: during a sweep an output location only ever holds
+// kNotReady or its final value, so a stale cached copy can only show
+// kNotReady, and the values still showing it are then polled together with
 // device-coherent loads.  Dependencies past the first KMAX of a row take an
 // unpipelined path.
 // ---------------------------------------------------------------------------
 struct TiledArgs {
     const int32_t* tile_chunk_ptr;
     const int32_t* tile_lo;
-    const int64_t* chunk_off;
+    const int32_t* chunk_row;     // first slot row of each chunk (slot offset / (64/B))
     const int32_t* rows;
     const int32_t* deps;
     const void* vals;
@@ -351,12 +354,20 @@ struct TiledArgs {
     unsigned int spin_limit;
 };
 
+// Load at a 32-bit byte offset from a (wave-uniform) base: the address is
+// formed by the load itself.  Vectors of the tiled sweep are below 4 GiB.
+template <typename T>
+__device__ __forceinline__ T load_at(const T* base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 template <int KMAX>
 struct TileMeta {
     int64_t off;         // first slot of the chunk (wave-uniform)
     int w;               // slots per row (wave-uniform)
     int row;             // as loaded (unused row slots hold -1)
-    int code[KMAX];      // as loaded (slots past the width hold slot 0's code)
+    int code[KMAX];      // slot rows 0..KMAX-1 as loaded (past w: not this chunk's)
 };
 
 template <int B, typename T, int KMAX, bool FUSE>
@@ -365,27 +376,27 @@ struct TileData {
     int w;
     int row;
     int code[KMAX];      // -1 past the width
-    T f[KMAX][B];        // factor values as stored
+    T f[KMAX][B];        // factor values as stored (past the width: unused)
     double x[KMAX][B];   // values read from other tiles (may show kNotReady)
     double h[FUSE ? B : 1];
     T d[FUSE ? B : 1];
 };
 
-// `chunk` is wave-uniform, so the chunk offsets come in through the scalar
-// cache and the addresses of the vector loads below wait on nothing that
-// was issued in the same step.
+// `chunk` is wave-uniform; its first slot row and width (srow, w) were
+// read through the scalar cache a step earlier, and every address below is
+// a scalar base plus a per-lane constant.
 template <int B, int KMAX>
-__device__ __forceinline__ void tile_meta_b(const TiledArgs& a, int chunk, int qc, TileMeta<KMAX>& m)
+__device__ __forceinline__ void tile_meta(const TiledArgs& a, int chunk, int srow, int w, int qc,
+                                          TileMeta<KMAX>& m)
 {
     constexpr int RPC = 64 / B;
-    m.off = uniform_load(a.chunk_off, chunk);
-    m.w = static_cast<int>((uniform_load(a.chunk_off, chunk + 1) - m.off) / RPC);
-    m.row = a.rows[static_cast<int64_t>(chunk) * RPC + qc];
+    m.off = static_cast<int64_t>(srow) * RPC;
+    m.w = w;
+    const int32_t* rp = a.rows + static_cast<int64_t>(chunk) * RPC;
+    const int32_t* dp = a.deps + m.off;
+    m.row = rp[qc];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const int kk = k < m.w ? k : 0;           // slot 0 exists: one chunk of padding at the end
-        m.code[k] = a.deps[m.off + static_cast<int64_t>(kk) * RPC + qc];
-    }
+    for (int k = 0; k < KMAX; ++k) m.code[k] = dp[k * RPC + qc];
 }
 
 template <int B, typename T, int KMAX, bool FUSE>
@@ -394,41 +405,39 @@ __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc,
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
-    const T* __restrict__ vals = static_cast<const T*>(a.vals);
+    const int lane_off = r * RPC + qc;
     s.off = m.off;
     s.w = m.w;
     s.row = m.row;
-    // unused row slots of a partly filled chunk hold -1: read row 0 instead
-    const int64_t rowc = m.row >= 0 ? m.row : 0;
+    const T* vp = static_cast<const T*>(a.vals) + m.off * BB;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const int kk = k < s.w ? k : 0;
-        s.code[k] = k < s.w ? m.code[k] : -1;
-        const int64_t vbase = (s.off + static_cast<int64_t>(kk) * RPC) * BB + r * RPC + qc;
+        s.code[k] = k < m.w ? m.code[k] : -1;
 #pragma unroll
-        for (int c = 0; c < B; ++c) s.f[k][c] = vals[vbase + c * B * RPC];
+        for (int c = 0; c < B; ++c) s.f[k][c] = vp[k * RPC * BB + c * B * RPC + lane_off];
     }
+    // unused row slots of a partly filled chunk hold -1: read row 0 instead
+    const uint32_t rowc = static_cast<uint32_t>(m.row >= 0 ? m.row : 0);
     if (FUSE) {
-        const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
-        const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + qc;
+        const T* dp = static_cast<const T*>(a.dinv) + static_cast<int64_t>(chunk) * RPC * BB;
 #pragma unroll
         for (int c = 0; c < B; ++c) {
-            s.h[c] = a.rhs[rowc * B + c];
-            s.d[c] = dinv[dbase + c * B * RPC];
+            s.h[c] = load_at(a.rhs, (rowc * B + c) * 8u);
+            s.d[c] = dp[c * B * RPC + lane_off];
         }
     } else {
-        s.h[0] = a.rhs[rowc * B + r];
+        s.h[0] = load_at(a.rhs, (rowc * B + r) * 8u);
     }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const int64_t j = s.code[k] >= 0 ? s.code[k] : rowc;
+        const uint32_t j = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : rowc;
 #pragma unroll
-        for (int c = 0; c < B; ++c) s.x[k][c] = a.out[j * B + c];
+        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), (j * B + c) * 8u);
     }
 }
 
 template <int B, typename T, int KMAX, bool FUSE>
-__device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool lane_ok,
+__device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
                                              double* tile_vals, const TileData<B, T, KMAX, FUSE>& s)
 {
     constexpr int RPC = 64 / B;
@@ -444,7 +453,15 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     }
 #pragma unroll
     for (int c = 0; c < (FUSE ? B : 1); ++c) asm volatile("" ::"v"(s.h[c]), "v"(s.d[c]));
-    if (!lane_ok || s.row < 0) return;
+    // values from other tiles: the prefetched copies, the ones still showing
+    // kNotReady polled together
+    double xg[KMAX * B];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
+    await_rows<KMAX, B, 1>(xg, s.code, a.out, 1, 0, a.spin_limit, a.status);
+    if (!active || s.row < 0) return;
     double acc;
     if (FUSE) {
         acc = 0.0;
@@ -453,29 +470,29 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     } else {
         acc = s.h[0];
     }
-    // values from other tiles: the prefetched copies, with the ones still
-    // showing kNotReady polled together
-    double xg[KMAX * B];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-        for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
-    await_rows<KMAX, B, 1>(xg, s.code, a.out, 1, 0, a.spin_limit, a.status);
+    // branch-free: every slot reads LDS (row 0 of the tile unless the slot is
+    // tile-local) and selects; padding slots leave acc unchanged.  Each LDS
+    // value is handed to an empty asm statement once all are issued, so the
+    // compiler keeps the reads unconditional (instead of turning each select
+    // into a branch around its read) and waits for them once.
+    double lv[KMAX * B];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int code = s.code[k];
-        if (code != -1) {
-            double xv[B];
-            if (code <= -2) {
-                const int loc = -code - 2;
+        const int loc = code <= -2 ? -code - 2 : 0;
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
-            } else {
+        for (int c = 0; c < B; ++c) lv[k * B + c] = tile_vals[loc * B + c];
+    }
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = xg[k * B + c];
-            }
+    for (int i = 0; i < KMAX * B; ++i) asm volatile("" : "+v"(lv[i]));
 #pragma unroll
-            for (int c = 0; c < B; ++c) acc -= widen(s.f[k][c]) * xv[c];
+    for (int k = 0; k < KMAX; ++k) {
+        const int code = s.code[k];
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const double xv = code <= -2 ? lv[k * B + c] : xg[k * B + c];
+            const double t = acc - widen(s.f[k][c]) * xv;
+            acc = code != -1 ? t : acc;
         }
     }
     if (s.w > KMAX) {
@@ -522,9 +539,9 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 {
     constexpr int RPC = 64 / B;
     constexpr int NR = TiledRing<B, T, FUSE, KMAX>::value;   // register states in flight
-    constexpr int LD = NR - 1;                       // data lookahead
-    constexpr int LM = 2 * LD;                       // metadata lookahead
-    extern __shared__ double tile_vals[];            // [tile rows][B]
+    constexpr int LD = NR - 1;                               // data lookahead
+    constexpr int LM = 2 * LD;                               // metadata lookahead
+    extern __shared__ double tile_vals[];                    // [tile rows][B]
     const int lane = lane_id();
     const int q = lane / B;
     const int r = lane - q * B;
@@ -541,36 +558,46 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
         if (nch <= 0) continue;
         const int clast = c0 + nch - 1;
         auto chunk_at = [&](int i) { return min(c0 + i, clast); };
+        auto meta_at = [&](int i, TileMeta<KMAX>& m) {
+            const int ch = chunk_at(i);
+            const int sr = uniform_load(a.chunk_row, ch);
+            tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
+        };
         // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
         // metadata of LD..LM-1 issued as their slots free up
 #pragma unroll
-        for (int i = 0; i < NR; ++i) tile_meta_b<B, KMAX>(a, chunk_at(i), qc, mr[i]);
+        for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
 #pragma unroll
         for (int i = 0; i < LD; ++i) {
             tile_data<B, T, KMAX, FUSE>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR]);
-            if (NR + i < LM) tile_meta_b<B, KMAX>(a, chunk_at(NR + i), qc, mr[(NR + i) % NR]);
+            if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
         }
+        // slot row range of the next chunk whose metadata is due, read a step
+        // ahead so that no step waits on the scalar cache
+        int pre_lo = uniform_load(a.chunk_row, chunk_at(LM));
+        int pre_hi = uniform_load(a.chunk_row, chunk_at(LM) + 1);
         // whole turns of the ring; steps past the tile's end load clamped
         // chunks and compute nothing
         for (int i0 = 0; i0 < nch; i0 += NR) {
 #pragma unroll
             for (int p = 0; p < NR; ++p) {
                 const int i = i0 + p;
-                tile_meta_b<B, KMAX>(a, chunk_at(i + LM), qc, mr[(p + LM) % NR]);
+                tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
+                pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
+                pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
                 tile_data<B, T, KMAX, FUSE>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR]);
                 tile_compute<B, T, KMAX, FUSE>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p]);
-                __syncthreads();   // one wavefront: orders this chunk's LDS writes before later reads
+                // one wavefront: its LDS accesses complete in issue order, so
+                // only the compiler must keep this chunk's writes before the
+                // next chunk's reads
+                __builtin_amdgcn_wave_barrier();
+                asm volatile("" ::: "memory");
             }
         }
     }
     finish_persistent(a.ticket, a.done, a.total_waves);
 }
 
-// ---------------------------------------------------------------------------
-// Block-CSR SpMV y = A x (transpose = 0) or y = A^T x (transpose = 1, with
-// the CSR of A^T whose entries point back at A's blocks).  One wavefront per
-// 64/B consecutive block rows, lane (q, r) owns component r of row q.
-// ---------------------------------------------------------------------------
 // Rows [row0, row0 + 64/B) of y = A x (or A^T x through the transposed
 // structure), by one wavefront; lane (q, r) owns component r of row q.
 template <int B, int RT, bool TRANS>
