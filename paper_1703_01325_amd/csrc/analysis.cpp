@@ -236,10 +236,17 @@ void build_sweep(const Host& h, int which, int rpc, HostSweep& s)
 void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
 {
     const int nb = h.nb;
+    const int bs = h.bs;
     const bool forward = (which == BILU_SWEEP_L || which == BILU_SWEEP_UT);
+    s = HostTiled{};
+    // dependency codes are byte offsets into int32
+    if (static_cast<int64_t>(nb) * bs * 8 > INT32_MAX) return;
     std::vector<int32_t> dptr;
     std::vector<Dep> deps;
     sweep_deps(h, which, dptr, deps);
+    int max_ndep = 0;
+    for (int i = 0; i < nb; ++i) max_ndep = std::max(max_ndep, dptr[i + 1] - dptr[i]);
+    s.kmax = tiled_kmax(bs, max_ndep);
     s.which = which;
     s.rpc = rpc;
     s.tile_rows = tile_rows;
@@ -247,10 +254,8 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
     s.tile_chunk_ptr.assign(static_cast<size_t>(s.ntiles) + 1, 0);
     s.tile_lo.assign(static_cast<size_t>(s.ntiles), 0);
     s.chunk_off.assign(1, 0);
-    s.rows.clear();
-    s.deps.clear();
-    s.src.clear();
-    std::vector<int32_t> il(static_cast<size_t>(tile_rows));   // level inside the tile
+    const int32_t pad_code = tiled_local_code(tile_rows, bs);      // the zero row
+    std::vector<int32_t> il(static_cast<size_t>(tile_rows));       // level inside the tile
     std::vector<int32_t> order;
     for (int t = 0; t < s.ntiles; ++t) {
         int lo, hi;
@@ -264,7 +269,6 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
         s.tile_lo[t] = lo;
         s.tile_chunk_ptr[t] = static_cast<int32_t>(s.chunk_off.size() - 1);
         // levels over the dependencies inside [lo, hi], rows in sweep order
-        int nlev = 0;
         for (int step = 0; step <= hi - lo; ++step) {
             const int32_t i = forward ? lo + step : hi - step;
             int32_t l = 0;
@@ -273,7 +277,6 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
                 if (j >= lo && j <= hi) l = std::max(l, il[j - lo] + 1);
             }
             il[i - lo] = l;
-            nlev = std::max(nlev, l + 1);
         }
         order.resize(static_cast<size_t>(hi - lo + 1));
         std::iota(order.begin(), order.end(), lo);
@@ -286,10 +289,11 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
             const int32_t lev = il[order[pos] - lo];
             size_t cn = 0;
             while (pos + cn < order.size() && cn < static_cast<size_t>(rpc) && il[order[pos + cn] - lo] == lev) ++cn;
-            const int32_t w = dptr[order[pos] + 1] - dptr[order[pos]];
+            // at least kmax slot rows: the kernel reads the first kmax of every chunk
+            const int32_t w = std::max(dptr[order[pos] + 1] - dptr[order[pos]], s.kmax);
             const int64_t base = s.chunk_off.back();
             s.chunk_off.push_back(base + static_cast<int64_t>(w) * rpc);
-            s.deps.resize(static_cast<size_t>(base) + static_cast<size_t>(w) * rpc, -1);
+            s.deps.resize(static_cast<size_t>(base) + static_cast<size_t>(w) * rpc, pad_code);
             s.src.resize(s.deps.size(), -1);
             for (int q = 0; q < rpc; ++q) {
                 if (static_cast<size_t>(q) >= cn) {
@@ -301,7 +305,7 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
                 for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
                     const size_t slot = static_cast<size_t>(base) + static_cast<size_t>(d - dptr[i]) * rpc + q;
                     const int32_t j = deps[d].col;
-                    s.deps[slot] = (j >= lo && j <= hi) ? -2 - (j - lo) : j;
+                    s.deps[slot] = (j >= lo && j <= hi) ? tiled_local_code(j - lo, bs) : tiled_global_code(j, bs);
                     s.src[slot] = deps[d].src;
                 }
             }
@@ -311,13 +315,6 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
     s.nchunks = static_cast<int>(s.chunk_off.size() - 1);
     s.tile_chunk_ptr[s.ntiles] = s.nchunks;
     s.nslots = s.chunk_off.back();
-    int64_t max_width = 0;
-    for (int c = 0; c < s.nchunks; ++c) max_width = std::max(max_width, (s.chunk_off[c + 1] - s.chunk_off[c]) / rpc);
-    s.kmax = tiled_kmax(h.bs, static_cast<int>(max_width));
-    // padding slot rows, so a kernel may read the first kTilePadRows slot
-    // rows of any chunk
-    s.deps.resize(static_cast<size_t>(s.nslots) + static_cast<size_t>(kTilePadRows) * rpc, -1);
-    s.src.resize(s.deps.size(), -1);
     s.built = true;
 }
 
@@ -537,23 +534,24 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
     const int RPC = kWave / B;
     const int64_t BB = static_cast<int64_t>(B) * B;
     const int KMAX = s.kmax;
-    if (!(KMAX == 3 || KMAX == 6 || KMAX == 9) || KMAX > kTilePadRows) return false;
+    if (!(KMAX == 3 || KMAX == 6 || KMAX == 9)) return false;
     if (B >= 5 && KMAX != 3) return false;
     const bool fuse = (which == BILU_SWEEP_U || which == BILU_SWEEP_LT);
     const int64_t n_rows_arr = static_cast<int64_t>(s.rows.size());
-    const int64_t n_slots_arr = static_cast<int64_t>(s.deps.size());       // nslots + padding
+    const int64_t n_slots_arr = static_cast<int64_t>(s.deps.size());
     const int64_t n_vals = n_slots_arr * BB;
     const int64_t n_dinv = static_cast<int64_t>(s.nchunks) * RPC * BB;
-    const int64_t n_vec = static_cast<int64_t>(h.nb) * B;
-    const int64_t n_lds = static_cast<int64_t>(s.tile_rows) * B;
-    // vector loads use 32-bit byte offsets
-    if (n_vec * 8 > static_cast<int64_t>(UINT32_MAX)) return false;
+    const int64_t vec_bytes = static_cast<int64_t>(h.nb) * B * 8;
+    const int64_t lds_bytes = (static_cast<int64_t>(s.tile_rows) + 1) * B * 8;   // + the zero row
+    if (vec_bytes > INT32_MAX) return false;
     auto in = [](int64_t i, int64_t n) { return i >= 0 && i < n; };
+    auto in8 = [](int64_t byte, int64_t nbytes) { return byte >= 0 && byte % 8 == 0 && byte + 8 <= nbytes; };
     for (int t = 0; t < s.ntiles; ++t) {
         const int lo = s.tile_lo[t];
         for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
             const int64_t off = s.chunk_off[c];
             const int w = static_cast<int>((s.chunk_off[c + 1] - off) / RPC);
+            if (w < KMAX) return false;
             for (int lane = 0; lane < kWave; ++lane) {
                 const int q = lane / B, r = lane - q * B;
                 const bool lane_ok = q < RPC;
@@ -562,43 +560,40 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                 const int64_t ri = static_cast<int64_t>(c) * RPC + qc;          // tile_meta
                 if (!in(ri, n_rows_arr)) return false;
                 const int row = s.rows[ri];
-                std::vector<int> code(static_cast<size_t>(KMAX));
+                std::vector<int32_t> code(static_cast<size_t>(KMAX));
                 for (int k = 0; k < KMAX; ++k) {
                     const int64_t di = off + static_cast<int64_t>(k) * RPC + qc;
                     if (!in(di, n_slots_arr)) return false;
-                    code[k] = k < w ? s.deps[di] : -1;                       // tile_data
+                    code[k] = s.deps[di];                                   // tile_data
                     const int64_t vb = off * BB + k * RPC * BB + lane_off;
                     if (!in(vb, n_vals) || !in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
-                const int64_t rowc = row >= 0 ? row : 0;
-                if (!in(rowc * B, n_vec) || !in(rowc * B + B - 1, n_vec)) return false;
+                const int64_t rowc_b = static_cast<int64_t>(row >= 0 ? row : 0) * B * 8;
+                if (!in8(rowc_b, vec_bytes) || !in8(rowc_b + (B - 1) * 8, vec_bytes)) return false;
                 if (fuse) {
                     const int64_t db = static_cast<int64_t>(c) * RPC * BB + lane_off;
                     if (!in(db, n_dinv) || !in(db + static_cast<int64_t>(B - 1) * B * RPC, n_dinv)) return false;
                 }
                 for (int k = 0; k < KMAX; ++k) {
-                    const int64_t j = code[k] >= 0 ? code[k] : rowc;
-                    if (!in(j * B, n_vec) || !in(j * B + B - 1, n_vec)) return false;
-                    const int64_t loc = code[k] <= -2 ? -static_cast<int64_t>(code[k]) - 2 : 0;   // tile_compute
-                    if (!in(loc * B, n_lds) || !in(loc * B + B - 1, n_lds)) return false;
+                    const int64_t xb = code[k] >= 0 ? code[k] : rowc_b;
+                    if (!in8(xb, vec_bytes) || !in8(xb + (B - 1) * 8, vec_bytes)) return false;
+                    const int64_t lb = code[k] < 0 ? (code[k] & INT32_MAX) : 0;     // tile_compute
+                    if (!in8(lb, lds_bytes) || !in8(lb + (B - 1) * 8, lds_bytes)) return false;
                 }
                 if (!lane_ok || row < 0) continue;
                 for (int k = KMAX; k < w; ++k) {                                // unpipelined slots
                     const int64_t sl = off + static_cast<int64_t>(k) * RPC;
                     if (!in(sl + qc, n_slots_arr)) return false;
-                    const int cd = s.deps[sl + qc];
-                    if (cd == -1) continue;
-                    if (cd <= -2) {
-                        const int64_t loc = -static_cast<int64_t>(cd) - 2;
-                        if (!in(loc * B, n_lds) || !in(loc * B + B - 1, n_lds)) return false;
-                    } else if (!in(static_cast<int64_t>(cd) * B + B - 1, n_vec)) {
+                    const int32_t cd = s.deps[sl + qc];
+                    const int64_t b0 = cd < 0 ? (cd & INT32_MAX) : cd;
+                    if (!in8(b0, cd < 0 ? lds_bytes : vec_bytes) ||
+                        !in8(b0 + (B - 1) * 8, cd < 0 ? lds_bytes : vec_bytes))
                         return false;
-                    }
                     const int64_t vb = sl * BB + lane_off;
                     if (!in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
-                if (!in(static_cast<int64_t>(row) * B + r, n_vec)) return false;
-                if (!in(static_cast<int64_t>(row - lo) * B + r, n_lds)) return false;
+                if (!in8((static_cast<int64_t>(row) * B + r) * 8, vec_bytes)) return false;
+                if (!in8((static_cast<int64_t>(row - lo) * B + r) * 8, lds_bytes - B * 8)) return false;
             }
         }
     }
@@ -683,11 +678,13 @@ int validate_layout(const Host& h)
             s.tile_chunk_ptr[s.ntiles] != s.nchunks || static_cast<int>(s.tile_lo.size()) != s.ntiles)
             return BILU_ERR_STATE;
         if (static_cast<int>(s.chunk_off.size()) != s.nchunks + 1 || s.chunk_off[0] != 0 ||
-            s.chunk_off.back() != s.nslots ||
-            static_cast<int64_t>(s.deps.size()) != s.nslots + static_cast<int64_t>(kTilePadRows) * rpc ||
-            static_cast<int64_t>(s.src.size()) != s.nslots + static_cast<int64_t>(kTilePadRows) * rpc ||
+            s.chunk_off.back() != s.nslots || static_cast<int64_t>(s.deps.size()) != s.nslots ||
+            static_cast<int64_t>(s.src.size()) != s.nslots ||
             static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc)
             return BILU_ERR_STATE;
+        if (static_cast<int64_t>(nb) * h.bs * 8 > INT32_MAX) return BILU_ERR_STATE;
+        const int32_t row_bytes = h.bs * 8;
+        const int32_t pad_code = tiled_local_code(s.tile_rows, h.bs);
         std::vector<int32_t> tile_of(static_cast<size_t>(nb), -1), chunk_of(static_cast<size_t>(nb), -1);
         for (int t = 0; t < s.ntiles; ++t) {
             const int lo = s.tile_lo[t];
@@ -695,7 +692,7 @@ int validate_layout(const Host& h)
             if (s.tile_chunk_ptr[t + 1] < s.tile_chunk_ptr[t]) return BILU_ERR_STATE;
             for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
                 const int64_t span = s.chunk_off[c + 1] - s.chunk_off[c];
-                if (span < 0 || span % rpc != 0) return BILU_ERR_STATE;
+                if (span < 0 || span % rpc != 0 || span / rpc < s.kmax) return BILU_ERR_STATE;
                 for (int q = 0; q < rpc; ++q) {
                     const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
                     if (r < -1 || r >= nb) return BILU_ERR_STATE;
@@ -728,14 +725,17 @@ int validate_layout(const Host& h)
                         const int64_t slot = off + k * rpc + q;
                         const int32_t code = s.deps[slot];
                         const int64_t e = s.src[slot];
-                        if (code == -1 && e == -1) continue;
-                        if (r < 0 || code == -1 || e < 0 || e >= nP) return BILU_ERR_STATE;
+                        if (code == pad_code && e == -1) continue;
+                        if (r < 0 || code == pad_code || e < 0 || e >= nP) return BILU_ERR_STATE;
                         int32_t j;
-                        if (code <= -2) {
-                            j = lo + (-code - 2);
+                        if (code < 0) {          // tile-local: byte offset of the row in LDS
+                            const int32_t off = code & INT32_MAX;
+                            if (off % row_bytes != 0) return BILU_ERR_STATE;
+                            j = lo + off / row_bytes;
                             if (j < 0 || j >= nb || tile_of[j] != t || chunk_of[j] >= c) return BILU_ERR_STATE;
-                        } else {
-                            j = code;
+                        } else {                 // another tile: byte offset of the row
+                            if (code % row_bytes != 0) return BILU_ERR_STATE;
+                            j = code / row_bytes;
                             if (j >= nb || tile_of[j] >= t) return BILU_ERR_STATE;   // strictly earlier tile
                         }
                         if (forward ? j >= r : j <= r) return BILU_ERR_STATE;

@@ -258,7 +258,7 @@ bilu_status upload_form(bilu_ctx* c, int form)
                 return st;
         } else {
             if (!h.sweep[w].built) continue;
-            if (c->tile_rows <= 0) c->tile_rows = choose_tile_rows(h, h.rpc, kMaxTileDoubles / h.bs);
+            if (c->tile_rows <= 0) c->tile_rows = choose_tile_rows(h, h.rpc, kMaxTileDoubles / h.bs - 1);
             HostTiled& ht = h.tiled[w];
             if (!ht.built || ht.tile_rows != c->tile_rows) build_tiled(h, w, h.rpc, c->tile_rows, ht);
             std::vector<int32_t> crow(ht.chunk_off.size());
@@ -336,11 +336,11 @@ bilu_status ensure_device(bilu_ctx* c)
 }
 
 // Layout form the sweeps use: row tiles in mode 2 for one right-hand side
-// (their vector loads take 32-bit byte offsets, so vectors must stay below
-// 4 GiB), level chunks otherwise.
+// (their dependency codes are 31-bit byte offsets, so vectors must stay
+// below 2 GiB), level chunks otherwise.
 int sweep_form(const bilu_ctx* c, int R)
 {
-    const bool fits = static_cast<int64_t>(c->h.nb) * c->h.bs * 8 <= static_cast<int64_t>(UINT32_MAX);
+    const bool fits = static_cast<int64_t>(c->h.nb) * c->h.bs * 8 <= static_cast<int64_t>(INT32_MAX);
     return c->sweep_mode == 2 && R == 1 && fits ? kFormTiled : kFormLevel;
 }
 
@@ -356,9 +356,7 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         if (!h.sweep[w].built) continue;
         DevSweep& d = c->ds[form][w];
         if (d.vals_precision == c->precision) continue;
-        // the tiled form carries kTilePadRows slot rows of padding (zero values)
-        const int64_t nslots =
-            form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots + static_cast<int64_t>(kTilePadRows) * h.rpc;
+        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots;
         const int nchunks = form == kFormLevel ? h.sweep[w].nchunks : h.tiled[w].nchunks;
         const int rpc = h.rpc;
         dfree(c, d.vals);
@@ -441,7 +439,9 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.spin_limit = c->spin_limit;
         const int blocks = persistent_blocks(c, ht.ntiles, 1, 8);
         a.total_waves = static_cast<unsigned int>(blocks);
-        const size_t lds = static_cast<size_t>(ht.tile_rows) * c->h.bs * sizeof(double);
+        a.tile_rows = ht.tile_rows;
+        // the tile's rows plus one row kept at zero (padding slots read it)
+        const size_t lds = static_cast<size_t>(ht.tile_rows + 1) * c->h.bs * sizeof(double);
         if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
         const HostSweep& hs = c->h.sweep[which];
@@ -739,8 +739,8 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         return BILU_OK;
     case BILU_TUNE_TILE_ROWS: {
         if (value < 0) return BILU_ERR_ARG;
-        int rows = value == 0 ? choose_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs)
-                              : std::min(value, kMaxTileDoubles / c->h.bs);
+        int rows = value == 0 ? choose_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs - 1)
+                              : std::min(value, kMaxTileDoubles / c->h.bs - 1);
         rows = std::max(1, std::min(rows, c->h.nb));
         if (rows == c->tile_rows) return BILU_OK;
         c->tile_rows = rows;
@@ -804,7 +804,7 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
     std::vector<Cand> cands;
     const Cand before{c->sweep_mode, c->tile_rows, c->rhs_tile};
     if (nrhs == 1) {
-        const auto ranked = rank_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs);
+        const auto ranked = rank_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs - 1);
         for (size_t i = 0; i < ranked.size() && i < 4; ++i) cands.push_back({2, ranked[i].second, 0});
         cands.push_back({1, c->tile_rows, 0});
     } else {

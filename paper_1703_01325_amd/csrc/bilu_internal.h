@@ -41,8 +41,8 @@ struct HostSweep {
 // rows for forward sweeps, descending for backward ones).  The rows of a
 // tile are ordered by their level inside the tile (Eq 4 over dependencies
 // within the tile only) and cut into chunks of rpc rows of one such level;
-// chunk slots as in HostSweep, with deps[] encoding j >= 0 (row of another
-// tile), -2 - (j - tile_lo) (row of this tile) or -1 (padding).
+// chunk slots as in HostSweep, with deps[] holding the byte-offset codes
+// below (tiled_global_code / tiled_local_code).
 struct HostTiled {
     bool built = false;
     int which = 0;
@@ -70,9 +70,16 @@ inline int tiled_kmax(int bs, int max_width)
     return max_width <= 6 ? 6 : 9;
 }
 
-// Slot rows of padding after the last chunk of a tiled layout: the kernel
-// reads the first KMAX (<= 9) slot rows of every chunk whatever its width.
-constexpr int kTilePadRows = 9;
+// Dependency codes of the tiled layout are byte offsets: a row of another
+// tile is j*bs*8 (>= 0, into the vectors), a row of the same tile is
+// INT32_MIN | (local row)*bs*8 (into the tile's LDS).  Padding slots point at
+// local row tile_rows, which the kernel keeps at zero, with zero factor
+// values.  Every chunk has at least kmax slot rows.
+inline int32_t tiled_global_code(int32_t j, int bs) { return j * bs * 8; }
+inline int32_t tiled_local_code(int32_t local_row, int bs)
+{
+    return static_cast<int32_t>(0x80000000u | static_cast<uint32_t>(local_row * bs * 8));
+}
 
 struct DevSweep {
     int64_t* chunk_off = nullptr;

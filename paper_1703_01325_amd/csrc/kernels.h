@@ -315,8 +315,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // every row it has finished; a dependency on another tile is read from
 // global memory.  Tiles are taken from a ticket in sweep order, and every
 // row a tile reads from outside lies in an earlier tile, so the sweep
-// drains.  Dependency codes: j >= 0 global row, j <= -2 tile-local row
-// (-j - 2), -1 padding.  Single right-hand side.
+// drains.  Dependency codes are byte offsets: code >= 0 is row code/(8B) of
+// the vectors, code < 0 is byte (code & INT32_MAX) of the tile's LDS; a
+// padding slot points at LDS row tile_rows, kept at zero, and has zero
+// factor values.  Single right-hand side.
 //
 // The walk is software-pipelined over a ring of NR register states: at step
 // i the wavefront issues the metadata loads of chunk i + 2(NR-1) (row ids,
@@ -325,10 +327,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // metadata that arrived NR - 1 steps earlier) and computes chunk i.  Every
 // batch is branch-free with a fixed instruction count: chunk indices past
 // the tile clamp to its last chunk, and the first KMAX slot rows of a chunk
-// are always read (the layout carries KMAX slot rows of padding after the
-// last chunk) and masked past the chunk's width.  Chunk-wide addresses are
-// scalar; a lane adds a fixed offset, so the per-slot loads need no vector
-// address arithmetic.  Values from other tiles are prefetched with plain,
+// are always read (every chunk has at least KMAX).  Chunk-wide addresses
+// are scalar; a lane adds a fixed offset, so the per-slot loads need no
+// vector address arithmetic.  Values from other tiles are prefetched with plain,
 // cacheable loads: during a sweep an output location only ever holds
 // kNotReady or its final value, so a stale cached copy can only show
 // kNotReady, and the values still showing it are then polled together with
@@ -350,6 +351,7 @@ struct TiledArgs {
     unsigned int* done;
     int* status;
     int ntiles;
+    int tile_rows;                // LDS row tile_rows is kept at zero
     unsigned int total_waves;
     unsigned int spin_limit;
 };
@@ -367,7 +369,7 @@ struct TileMeta {
     int64_t off;         // first slot of the chunk (wave-uniform)
     int w;               // slots per row (wave-uniform)
     int row;             // as loaded (unused row slots hold -1)
-    int code[KMAX];      // slot rows 0..KMAX-1 as loaded (past w: not this chunk's)
+    int code[KMAX];      // dependency codes of slot rows 0..KMAX-1
 };
 
 template <int B, typename T, int KMAX, bool FUSE>
@@ -375,8 +377,8 @@ struct TileData {
     int64_t off;
     int w;
     int row;
-    int code[KMAX];      // -1 past the width
-    T f[KMAX][B];        // factor values as stored (past the width: unused)
+    int code[KMAX];
+    T f[KMAX][B];        // factor values as stored
     double x[KMAX][B];   // values read from other tiles (may show kNotReady)
     double h[FUSE ? B : 1];
     T d[FUSE ? B : 1];
@@ -412,27 +414,60 @@ __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc,
     const T* vp = static_cast<const T*>(a.vals) + m.off * BB;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        s.code[k] = k < m.w ? m.code[k] : -1;
+        s.code[k] = m.code[k];
 #pragma unroll
         for (int c = 0; c < B; ++c) s.f[k][c] = vp[k * RPC * BB + c * B * RPC + lane_off];
     }
     // unused row slots of a partly filled chunk hold -1: read row 0 instead
-    const uint32_t rowc = static_cast<uint32_t>(m.row >= 0 ? m.row : 0);
+    const uint32_t rowc_b = static_cast<uint32_t>(m.row >= 0 ? m.row : 0) * (B * 8u);
     if (FUSE) {
         const T* dp = static_cast<const T*>(a.dinv) + static_cast<int64_t>(chunk) * RPC * BB;
 #pragma unroll
         for (int c = 0; c < B; ++c) {
-            s.h[c] = load_at(a.rhs, (rowc * B + c) * 8u);
+            s.h[c] = load_at(a.rhs, rowc_b + c * 8u);
             s.d[c] = dp[c * B * RPC + lane_off];
         }
     } else {
-        s.h[0] = load_at(a.rhs, (rowc * B + r) * 8u);
+        s.h[0] = load_at(a.rhs, rowc_b + r * 8u);
     }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const uint32_t j = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : rowc;
+        const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : rowc_b;
 #pragma unroll
-        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), (j * B + c) * 8u);
+        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), xb + c * 8u);
+    }
+}
+
+// Waits (bounded) until no value of another tile that a lane needs shows
+// kNotReady; every value still missing is re-read with a device-coherent
+// load, all in one round trip per poll.
+template <int K, int B>
+__device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)[K], const double* out,
+                                           unsigned int limit, int* status)
+{
+    bool pending = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & is_not_ready(v[k * B + c]);
+    for (unsigned int spins = 0; pending;) {
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        pending = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < B; ++c)
+                if (code[k] >= 0 && is_not_ready(v[k * B + c]))
+                    v[k * B + c] = coherent_load(reinterpret_cast<const double*>(
+                        reinterpret_cast<const char*>(out) + static_cast<uint32_t>(code[k]) + c * 8u));
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & is_not_ready(v[k * B + c]);
     }
 }
 
@@ -460,7 +495,7 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     for (int k = 0; k < KMAX; ++k)
 #pragma unroll
         for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
-    await_rows<KMAX, B, 1>(xg, s.code, a.out, 1, 0, a.spin_limit, a.status);
+    await_tile<KMAX, B>(xg, s.code, a.out, a.spin_limit, a.status);
     if (!active || s.row < 0) return;
     double acc;
     if (FUSE) {
@@ -470,48 +505,44 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     } else {
         acc = s.h[0];
     }
-    // branch-free: every slot reads LDS (row 0 of the tile unless the slot is
-    // tile-local) and selects; padding slots leave acc unchanged.  Each LDS
-    // value is handed to an empty asm statement once all are issued, so the
-    // compiler keeps the reads unconditional (instead of turning each select
-    // into a branch around its read) and waits for them once.
+    // branch-free: every slot reads LDS (its own row for tile-local and
+    // padding slots, row 0 otherwise) and selects.  Each LDS value is handed
+    // to an empty asm statement once all are issued, so the compiler keeps
+    // the reads unconditional (instead of turning each select into a branch
+    // around its read) and waits for them once.
+    const char* lds = reinterpret_cast<const char*>(tile_vals);
     double lv[KMAX * B];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const int code = s.code[k];
-        const int loc = code <= -2 ? -code - 2 : 0;
+        const uint32_t lb = s.code[k] < 0 ? static_cast<uint32_t>(s.code[k]) & 0x7fffffffu : 0u;
 #pragma unroll
-        for (int c = 0; c < B; ++c) lv[k * B + c] = tile_vals[loc * B + c];
+        for (int c = 0; c < B; ++c) lv[k * B + c] = *reinterpret_cast<const double*>(lds + lb + c * 8u);
     }
 #pragma unroll
     for (int i = 0; i < KMAX * B; ++i) asm volatile("" : "+v"(lv[i]));
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const int code = s.code[k];
+        const bool local = s.code[k] < 0;
 #pragma unroll
-        for (int c = 0; c < B; ++c) {
-            const double xv = code <= -2 ? lv[k * B + c] : xg[k * B + c];
-            const double t = acc - widen(s.f[k][c]) * xv;
-            acc = code != -1 ? t : acc;
-        }
+        for (int c = 0; c < B; ++c) acc -= widen(s.f[k][c]) * (local ? lv[k * B + c] : xg[k * B + c]);
     }
     if (s.w > KMAX) {
         const T* __restrict__ vals = static_cast<const T*>(a.vals);
         for (int k = KMAX; k < s.w; ++k) {
             const int64_t sl = s.off + static_cast<int64_t>(k) * RPC;
             const int code = a.deps[sl + qc];
-            if (code == -1) continue;
             double xv[B];
-            if (code <= -2) {
-                const int loc = -code - 2;
+            if (code < 0) {
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = tile_vals[loc * B + c];
+                for (int c = 0; c < B; ++c)
+                    xv[c] = *reinterpret_cast<const double*>(lds + (static_cast<uint32_t>(code) & 0x7fffffffu) + c * 8u);
             } else {
-                const double* xj = a.out + static_cast<int64_t>(code) * B;
+                const double* xj = reinterpret_cast<const double*>(reinterpret_cast<const char*>(a.out) +
+                                                                   static_cast<uint32_t>(code));
 #pragma unroll
                 for (int c = 0; c < B; ++c) xv[c] = coherent_load(xj + c);
                 const int one[1] = {code};
-                await_rows<1, B, 1>(xv, one, a.out, 1, 0, a.spin_limit, a.status);
+                await_tile<1, B>(xv, one, a.out, a.spin_limit, a.status);
             }
             const int64_t vbase = sl * BB + r * RPC + qc;
 #pragma unroll
@@ -549,6 +580,8 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
     const int qc = lane_ok ? q : RPC - 1;
     TileMeta<KMAX> mr[NR];
     TileData<B, T, KMAX, FUSE> dr[NR];
+    // LDS row tile_rows stays zero: padding slots read it
+    if (lane < B) tile_vals[a.tile_rows * B + lane] = 0.0;
 
     for (int t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); t < a.ntiles;
          t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
