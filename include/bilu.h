@@ -214,8 +214,8 @@ bilu_status bilu_grad_A(bilu_ctx* ctx, const double* lambda, const double* x, do
 enum {
     BILU_TUNE_SWEEP_MODE = 0, /* 0: one launch per level; 1: one persistent launch per
                                  sweep over level chunks; 2: one persistent launch per
-                                 sweep over row tiles (default; several right-hand
-                                 sides use mode 1)                                   */
+                                 sweep over row tiles, one wavefront per (tile,
+                                 right-hand side) (default)                          */
     BILU_TUNE_TILE_ROWS = 1,  /* block rows per tile in mode 2 (capped so a tile's
                                  values fit 64 KiB of LDS); 0 = chosen by a host
                                  simulation of the tiled schedule (default)          */
@@ -240,7 +240,8 @@ typedef struct {
  * configurations and keeps the fastest (the one in force on entry if none
  * beats it).  Candidates: nrhs = 1, the row tiles of the four tile sizes
  * with the shortest simulated schedules and the level-chunk form; nrhs > 1,
- * the level-chunk form with 1, 4 and 8 columns per pass.  Needs the factors
+ * the row tiles of the simulated tile size and the level-chunk form with 1,
+ * 4 and 8 columns per pass.  Needs the factors
  * (after bilu_factor_diag); results of later calls are bit-identical to
  * those before it.  Synchronises `stream`. */
 bilu_status bilu_autotune(bilu_ctx* ctx, int nrhs, hipStream_t stream, bilu_tune_result* out);

@@ -185,36 +185,40 @@ bool launch_sweep(int bs, int prec, int rt, int blocks, hipStream_t s, const Swe
     return rt == 8 && launch_sweep_b<double, 8>(bs, blocks, s, a);
 }
 
-template <typename T, bool FUSE, int B>
+template <typename T, bool FUSE, int B, bool MULTI>
 bool launch_tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
     if constexpr (B >= 5) {
         if (kmax != 3) return false;
-        hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3>), dim3(blocks), dim3(64), lds, s, a);
+        hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a);
         return true;
     } else {
         switch (kmax) {
-        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3>), dim3(blocks), dim3(64), lds, s, a); return true;
-        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 6>), dim3(blocks), dim3(64), lds, s, a); return true;
-        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 9>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 6, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 9, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
         }
         return false;
     }
 }
 
 template <typename T, bool FUSE>
-bool launch_tiled_b(int bs, int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+bool launch_tiled_b(int bs, int kmax, bool multi, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
-    BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B>(kmax, blocks, lds, s, a))) return false)
+    if (multi) {
+        BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B, true>(kmax, blocks, lds, s, a))) return false)
+    }
+    BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B, false>(kmax, blocks, lds, s, a))) return false)
 }
 
-bool launch_tiled(int bs, int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hipStream_t s,
+                  const TiledArgs& a)
 {
     if (prec == BILU_FACTORS_FP32)
-        return fuse ? launch_tiled_b<float, true>(bs, kmax, blocks, lds, s, a)
-                    : launch_tiled_b<float, false>(bs, kmax, blocks, lds, s, a);
-    return fuse ? launch_tiled_b<double, true>(bs, kmax, blocks, lds, s, a)
-                : launch_tiled_b<double, false>(bs, kmax, blocks, lds, s, a);
+        return fuse ? launch_tiled_b<float, true>(bs, kmax, multi, blocks, lds, s, a)
+                    : launch_tiled_b<float, false>(bs, kmax, multi, blocks, lds, s, a);
+    return fuse ? launch_tiled_b<double, true>(bs, kmax, multi, blocks, lds, s, a)
+                : launch_tiled_b<double, false>(bs, kmax, multi, blocks, lds, s, a);
 }
 
 template <int RT, bool TR>
@@ -335,13 +339,13 @@ bilu_status ensure_device(bilu_ctx* c)
     return BILU_OK;
 }
 
-// Layout form the sweeps use: row tiles in mode 2 for one right-hand side
-// (their dependency codes are 31-bit byte offsets, so vectors must stay
-// below 2 GiB), level chunks otherwise.
+// Layout form the sweeps use: row tiles in mode 2 (their vector accesses are
+// 31-bit byte offsets, so the (n x R) vectors must stay below 2 GiB), level
+// chunks otherwise.
 int sweep_form(const bilu_ctx* c, int R)
 {
-    const bool fits = static_cast<int64_t>(c->h.nb) * c->h.bs * 8 <= static_cast<int64_t>(INT32_MAX);
-    return c->sweep_mode == 2 && R == 1 && fits ? kFormTiled : kFormLevel;
+    const bool fits = static_cast<int64_t>(c->h.nb) * c->h.bs * 8 * R <= static_cast<int64_t>(INT32_MAX);
+    return c->sweep_mode == 2 && fits ? kFormTiled : kFormLevel;
 }
 
 // Factor values of one layout form in the current precision.
@@ -436,13 +440,14 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.done = c->d_done;
         a.status = c->d_status;
         a.ntiles = ht.ntiles;
+        a.R = R;
         a.spin_limit = c->spin_limit;
-        const int blocks = persistent_blocks(c, ht.ntiles, 1, 8);
+        const int blocks = persistent_blocks(c, ht.ntiles * R, 1, 8);
         a.total_waves = static_cast<unsigned int>(blocks);
         a.tile_rows = ht.tile_rows;
         // the tile's rows plus one row kept at zero (padding slots read it)
         const size_t lds = static_cast<size_t>(ht.tile_rows + 1) * c->h.bs * sizeof(double);
-        if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, blocks, lds, s, a)) return BILU_ERR_ARG;
+        if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
         const HostSweep& hs = c->h.sweep[which];
         const DevSweep& d = c->ds[kFormLevel][which];
@@ -808,6 +813,7 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
         for (size_t i = 0; i < ranked.size() && i < 4; ++i) cands.push_back({2, ranked[i].second, 0});
         cands.push_back({1, c->tile_rows, 0});
     } else {
+        cands.push_back({2, 0, 0});
         for (int rt : {1, 4, 8}) cands.push_back({1, c->tile_rows, rt});
     }
     const size_t n = static_cast<size_t>(c->h.nb) * c->h.bs * nrhs;

@@ -352,12 +352,27 @@ struct TiledArgs {
     int* status;
     int ntiles;
     int tile_rows;                // LDS row tile_rows is kept at zero
+    int R;                        // right-hand sides (vectors are (n x R) row-major)
     unsigned int total_waves;
     unsigned int spin_limit;
 };
 
+// Byte offset of component c of a block row (row_byte = row * B * 8) in the
+// column this wavefront sweeps.  One right-hand side: row_byte + 8c.
+// Several (MULTI): the vectors are (n x R) row-major, element (i, j) at
+// i*R + j.
+template <bool MULTI>
+struct ColMap {
+    uint32_t R;
+    uint32_t j8;      // 8 * column
+    __device__ __forceinline__ uint32_t at(uint32_t row_byte, int c) const
+    {
+        return MULTI ? row_byte * R + static_cast<uint32_t>(c) * 8u * R + j8 : row_byte + static_cast<uint32_t>(c) * 8u;
+    }
+};
+
 // Load at a 32-bit byte offset from a (wave-uniform) base: the address is
-// formed by the load itself.  Vectors of the tiled sweep are below 4 GiB.
+// formed by the load itself.  Vectors of the tiled sweep are below 2 GiB.
 template <typename T>
 __device__ __forceinline__ T load_at(const T* base, uint32_t byte_off)
 {
@@ -401,9 +416,9 @@ __device__ __forceinline__ void tile_meta(const TiledArgs& a, int chunk, int sro
     for (int k = 0; k < KMAX; ++k) m.code[k] = dp[k * RPC + qc];
 }
 
-template <int B, typename T, int KMAX, bool FUSE>
+template <int B, typename T, int KMAX, bool FUSE, bool MULTI>
 __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc, int r, const TileMeta<KMAX>& m,
-                                          TileData<B, T, KMAX, FUSE>& s)
+                                          TileData<B, T, KMAX, FUSE>& s, const ColMap<MULTI>& cm)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
@@ -424,26 +439,26 @@ __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc,
         const T* dp = static_cast<const T*>(a.dinv) + static_cast<int64_t>(chunk) * RPC * BB;
 #pragma unroll
         for (int c = 0; c < B; ++c) {
-            s.h[c] = load_at(a.rhs, rowc_b + c * 8u);
+            s.h[c] = load_at(a.rhs, cm.at(rowc_b, c));
             s.d[c] = dp[c * B * RPC + lane_off];
         }
     } else {
-        s.h[0] = load_at(a.rhs, rowc_b + r * 8u);
+        s.h[0] = load_at(a.rhs, cm.at(rowc_b, r));
     }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : rowc_b;
 #pragma unroll
-        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), xb + c * 8u);
+        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), cm.at(xb, c));
     }
 }
 
 // Waits (bounded) until no value of another tile that a lane needs shows
 // kNotReady; every value still missing is re-read with a device-coherent
 // load, all in one round trip per poll.
-template <int K, int B>
+template <int K, int B, bool MULTI>
 __device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)[K], const double* out,
-                                           unsigned int limit, int* status)
+                                           const ColMap<MULTI>& cm, unsigned int limit, int* status)
 {
     bool pending = false;
 #pragma unroll
@@ -463,7 +478,7 @@ __device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)
             for (int c = 0; c < B; ++c)
                 if (code[k] >= 0 && is_not_ready(v[k * B + c]))
                     v[k * B + c] = coherent_load(reinterpret_cast<const double*>(
-                        reinterpret_cast<const char*>(out) + static_cast<uint32_t>(code[k]) + c * 8u));
+                        reinterpret_cast<const char*>(out) + cm.at(static_cast<uint32_t>(code[k]), c)));
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -471,9 +486,10 @@ __device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)
     }
 }
 
-template <int B, typename T, int KMAX, bool FUSE>
+template <int B, typename T, int KMAX, bool FUSE, bool MULTI>
 __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
-                                             double* tile_vals, const TileData<B, T, KMAX, FUSE>& s)
+                                             double* tile_vals, const TileData<B, T, KMAX, FUSE>& s,
+                                             const ColMap<MULTI>& cm)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
@@ -495,7 +511,7 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     for (int k = 0; k < KMAX; ++k)
 #pragma unroll
         for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
-    await_tile<KMAX, B>(xg, s.code, a.out, a.spin_limit, a.status);
+    await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
     if (!active || s.row < 0) return;
     double acc;
     if (FUSE) {
@@ -537,12 +553,12 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
                 for (int c = 0; c < B; ++c)
                     xv[c] = *reinterpret_cast<const double*>(lds + (static_cast<uint32_t>(code) & 0x7fffffffu) + c * 8u);
             } else {
-                const double* xj = reinterpret_cast<const double*>(reinterpret_cast<const char*>(a.out) +
-                                                                   static_cast<uint32_t>(code));
+                const char* ob = reinterpret_cast<const char*>(a.out);
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = coherent_load(xj + c);
+                for (int c = 0; c < B; ++c)
+                    xv[c] = coherent_load(reinterpret_cast<const double*>(ob + cm.at(static_cast<uint32_t>(code), c)));
                 const int one[1] = {code};
-                await_tile<1, B>(xv, one, a.out, a.spin_limit, a.status);
+                await_tile<1, B, MULTI>(xv, one, a.out, cm, a.spin_limit, a.status);
             }
             const int64_t vbase = sl * BB + r * RPC + qc;
 #pragma unroll
@@ -550,9 +566,9 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
         }
     }
     const double v = publishable(acc);
-    const int64_t o = static_cast<int64_t>(s.row) * B + r;
-    if (a.reset) a.reset[o] = not_ready();
-    coherent_store(a.out + o, v);
+    const uint32_t ob = cm.at(static_cast<uint32_t>(s.row) * (B * 8u), r);
+    if (a.reset) *reinterpret_cast<double*>(reinterpret_cast<char*>(a.reset) + ob) = not_ready();
+    coherent_store(reinterpret_cast<double*>(reinterpret_cast<char*>(a.out) + ob), v);
     tile_vals[(s.row - lo) * B + r] = v;
 }
 
@@ -565,7 +581,10 @@ struct TiledRing {
     static constexpr int value = 3 * state + 40 <= 240 ? 3 : 2;
 };
 
-template <int B, typename T, bool FUSE, int KMAX>
+// MULTI: R right-hand sides swept side by side, one wavefront per (tile,
+// column); tickets run tile by tile, the columns of a tile together, so
+// every dependency of a ticket (same column, earlier tile) has a smaller one.
+template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
 __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 {
     constexpr int RPC = 64 / B;
@@ -583,8 +602,13 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
     // LDS row tile_rows stays zero: padding slots read it
     if (lane < B) tile_vals[a.tile_rows * B + lane] = 0.0;
 
-    for (int t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); t < a.ntiles;
-         t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+    const int nticket = MULTI ? a.ntiles * a.R : a.ntiles;
+    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < nticket;
+         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int t = MULTI ? tk / a.R : tk;
+        ColMap<MULTI> cm;
+        cm.R = static_cast<uint32_t>(a.R);
+        cm.j8 = MULTI ? static_cast<uint32_t>(tk - t * a.R) * 8u : 0u;
         const int lo = uniform_load(a.tile_lo, t);
         const int c0 = uniform_load(a.tile_chunk_ptr, t);
         const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
@@ -602,7 +626,7 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
         for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
 #pragma unroll
         for (int i = 0; i < LD; ++i) {
-            tile_data<B, T, KMAX, FUSE>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR]);
+            tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
             if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
         }
         // slot row range of the next chunk whose metadata is due, read a step
@@ -618,8 +642,9 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
                 tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
                 pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
                 pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
-                tile_data<B, T, KMAX, FUSE>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR]);
-                tile_compute<B, T, KMAX, FUSE>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p]);
+                tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR],
+                                                   cm);
+                tile_compute<B, T, KMAX, FUSE, MULTI>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p], cm);
                 // one wavefront: its LDS accesses complete in issue order, so
                 // only the compiler must keep this chunk's writes before the
                 // next chunk's reads

@@ -366,13 +366,14 @@ def test_rhs_tile_parity(api, oracle_mod, rt):
     M = c.gpu(api)
     R = 13
     B = synth.multi_rhs(c.s.n, R, seed=41)
-    M.tune(rhs_tile=8)
+    zt = M.apply(cuda(B))                 # row tiles, one wavefront per (tile, column)
+    M.tune(mode=1, rhs_tile=8)
     z8 = M.apply(cuda(B))
     y8 = M.spmv(c.Ax, cuda(B))
     M.tune(rhs_tile=rt)
     z = M.apply(cuda(B))
     y = M.spmv(c.Ax, cuda(B))
-    assert torch.equal(z, z8) and torch.equal(y, y8)
+    assert torch.equal(z, z8) and torch.equal(y, y8) and torch.equal(zt, z8)
     zc = z.cpu().numpy()
     for j in (0, 5, 12):
         assert rel(zc[:, j], c.O.apply(B[:, j])) <= 1e-12
