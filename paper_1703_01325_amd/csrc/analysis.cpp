@@ -426,9 +426,10 @@ std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int m
         std::sort(hist.begin(), hist.end(), std::greater<>());
     }
     const size_t top = std::min<size_t>(hist.size(), 4);
+    static const int kMult[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64};
     for (size_t a = 0; a < top; ++a) {
         const int d = hist[a].second;
-        for (int j = 1; j <= 64; ++j) {
+        for (int j : kMult) {
             if (d / j >= min_rows && d / j <= max_rows && d % j == 0) cand.push_back(d / j);
             if (static_cast<int64_t>(d) * j >= min_rows && static_cast<int64_t>(d) * j <= max_rows) cand.push_back(d * j);
         }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "bilu.h"
@@ -52,6 +53,7 @@ struct bilu_ctx {
     double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
     DevSweep ds[2][4];          // [form][sweep]
     bool form_uploaded[2] = {false, false};
+    bool layouts_checked = false;   // validate_layout passed on the layouts as built
 
     double* d_y = nullptr;      // intermediate of an application, kept at kNotReady
     size_t y_cap = 0;
@@ -264,7 +266,10 @@ bilu_status upload_form(bilu_ctx* c, int form)
             if (!h.sweep[w].built) continue;
             if (c->tile_rows <= 0) c->tile_rows = choose_tile_rows(h, h.rpc, kMaxTileDoubles / h.bs - 1);
             HostTiled& ht = h.tiled[w];
-            if (!ht.built || ht.tile_rows != c->tile_rows) build_tiled(h, w, h.rpc, c->tile_rows, ht);
+            if (!ht.built || ht.tile_rows != c->tile_rows) {
+                build_tiled(h, w, h.rpc, c->tile_rows, ht);
+                c->layouts_checked = false;
+            }
             std::vector<int32_t> crow(ht.chunk_off.size());
             for (size_t i = 0; i < crow.size(); ++i) {
                 if (ht.chunk_off[i] % h.rpc != 0 || ht.chunk_off[i] / h.rpc > INT32_MAX) return BILU_ERR_STATE;
@@ -279,7 +284,10 @@ bilu_status upload_form(bilu_ctx* c, int form)
         d.vals_precision = -1;
     }
     // no kernel ever runs on a layout that fails the host self-check
-    if (validate_layout(h) != BILU_OK) return BILU_ERR_STATE;
+    if (!c->layouts_checked) {
+        if (validate_layout(h) != BILU_OK) return BILU_ERR_STATE;
+        c->layouts_checked = true;
+    }
     c->form_uploaded[form] = true;
     return BILU_OK;
 }
@@ -750,6 +758,7 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (rows == c->tile_rows) return BILU_OK;
         c->tile_rows = rows;
         free_form(c, kFormTiled);
+        c->layouts_checked = false;
         for (int w = 0; w < 4; ++w)
             if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->h.tiled[w]);
         return BILU_OK;

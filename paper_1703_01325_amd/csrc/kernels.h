@@ -581,17 +581,15 @@ struct TiledRing {
     static constexpr int value = 3 * state + 40 <= 240 ? 3 : 2;
 };
 
-// MULTI: R right-hand sides swept side by side, one wavefront per (tile,
-// column); tickets run tile by tile, the columns of a tile together, so
-// every dependency of a ticket (same column, earlier tile) has a smaller one.
+// One tile of a tiled sweep by one wavefront (column cm of the vectors).
+// tile_vals: the wavefront's LDS, row a.tile_rows already zero.
 template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
-__global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
+__device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap<MULTI>& cm, double* tile_vals)
 {
     constexpr int RPC = 64 / B;
     constexpr int NR = TiledRing<B, T, FUSE, KMAX>::value;   // register states in flight
     constexpr int LD = NR - 1;                               // data lookahead
     constexpr int LM = 2 * LD;                               // metadata lookahead
-    extern __shared__ double tile_vals[];                    // [tile rows][B]
     const int lane = lane_id();
     const int q = lane / B;
     const int r = lane - q * B;
@@ -599,9 +597,59 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
     const int qc = lane_ok ? q : RPC - 1;
     TileMeta<KMAX> mr[NR];
     TileData<B, T, KMAX, FUSE> dr[NR];
-    // LDS row tile_rows stays zero: padding slots read it
-    if (lane < B) tile_vals[a.tile_rows * B + lane] = 0.0;
+    const int lo = uniform_load(a.tile_lo, t);
+    const int c0 = uniform_load(a.tile_chunk_ptr, t);
+    const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
+    if (nch <= 0) return;
+    const int clast = c0 + nch - 1;
+    auto chunk_at = [&](int i) { return min(c0 + i, clast); };
+    auto meta_at = [&](int i, TileMeta<KMAX>& m) {
+        const int ch = chunk_at(i);
+        const int sr = uniform_load(a.chunk_row, ch);
+        tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
+    };
+    // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
+    // metadata of LD..LM-1 issued as their slots free up
+#pragma unroll
+    for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
+#pragma unroll
+    for (int i = 0; i < LD; ++i) {
+        tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
+        if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
+    }
+    // slot row range of the next chunk whose metadata is due, read a step
+    // ahead so that no step waits on the scalar cache
+    int pre_lo = uniform_load(a.chunk_row, chunk_at(LM));
+    int pre_hi = uniform_load(a.chunk_row, chunk_at(LM) + 1);
+    // whole turns of the ring; steps past the tile's end load clamped
+    // chunks and compute nothing
+    for (int i0 = 0; i0 < nch; i0 += NR) {
+#pragma unroll
+        for (int p = 0; p < NR; ++p) {
+            const int i = i0 + p;
+            tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
+            pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
+            pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
+            tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
+            tile_compute<B, T, KMAX, FUSE, MULTI>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p], cm);
+            // one wavefront: its LDS accesses complete in issue order, so
+            // only the compiler must keep this chunk's writes before the
+            // next chunk's reads
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
+        }
+    }
+}
 
+// MULTI: R right-hand sides swept side by side, one wavefront per (tile,
+// column); tickets run tile by tile, the columns of a tile together, so
+// every dependency of a ticket (same column, earlier tile) has a smaller one.
+template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
+__global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
+{
+    extern __shared__ double tile_vals[];                    // [tile rows + 1][B]
+    // LDS row tile_rows stays zero: padding slots read it
+    if (lane_id() < B) tile_vals[a.tile_rows * B + lane_id()] = 0.0;
     const int nticket = MULTI ? a.ntiles * a.R : a.ntiles;
     for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < nticket;
          tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
@@ -609,49 +657,7 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
         ColMap<MULTI> cm;
         cm.R = static_cast<uint32_t>(a.R);
         cm.j8 = MULTI ? static_cast<uint32_t>(tk - t * a.R) * 8u : 0u;
-        const int lo = uniform_load(a.tile_lo, t);
-        const int c0 = uniform_load(a.tile_chunk_ptr, t);
-        const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
-        if (nch <= 0) continue;
-        const int clast = c0 + nch - 1;
-        auto chunk_at = [&](int i) { return min(c0 + i, clast); };
-        auto meta_at = [&](int i, TileMeta<KMAX>& m) {
-            const int ch = chunk_at(i);
-            const int sr = uniform_load(a.chunk_row, ch);
-            tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
-        };
-        // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
-        // metadata of LD..LM-1 issued as their slots free up
-#pragma unroll
-        for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
-#pragma unroll
-        for (int i = 0; i < LD; ++i) {
-            tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
-            if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
-        }
-        // slot row range of the next chunk whose metadata is due, read a step
-        // ahead so that no step waits on the scalar cache
-        int pre_lo = uniform_load(a.chunk_row, chunk_at(LM));
-        int pre_hi = uniform_load(a.chunk_row, chunk_at(LM) + 1);
-        // whole turns of the ring; steps past the tile's end load clamped
-        // chunks and compute nothing
-        for (int i0 = 0; i0 < nch; i0 += NR) {
-#pragma unroll
-            for (int p = 0; p < NR; ++p) {
-                const int i = i0 + p;
-                tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
-                pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
-                pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
-                tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR],
-                                                   cm);
-                tile_compute<B, T, KMAX, FUSE, MULTI>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p], cm);
-                // one wavefront: its LDS accesses complete in issue order, so
-                // only the compiler must keep this chunk's writes before the
-                // next chunk's reads
-                __builtin_amdgcn_wave_barrier();
-                asm volatile("" ::: "memory");
-            }
-        }
+        run_tile<B, T, FUSE, KMAX, MULTI>(a, t, cm, tile_vals);
     }
     finish_persistent(a.ticket, a.done, a.total_waves);
 }

@@ -1,7 +1,7 @@
 // Kernels for a batch of independent systems of uneven sizes and block
 // sizes, solved together: each sweep and each SpMV over the whole batch is
-// one launch with a work queue of (system, chunk) items, and the Krylov
-// scalars live per system in device memory.  Included once, by
+// one launch with a work queue of (system, tile) or (system, rows) items,
+// and the Krylov scalars live per system in device memory.  Included once, by
 // bilu_api.hip, after kernels.h.
 //
 // Batch vectors are the systems' vectors laid end to end: system s owns
@@ -15,12 +15,6 @@ namespace dev {
 
 // One system as the batch kernels see it.
 struct BatchSys {
-    // level-chunk sweep layouts: [0] L (forward), [1] U' with D^{-1} fused
-    const int64_t* chunk_off[2];
-    const int32_t* rows[2];
-    const int32_t* cols[2];
-    const void* vals[2];
-    const void* dinv;
     const int32_t* Ap;      // A's block structure and values, for the SpMV
     const int32_t* Aj;
     const double* Ax;
@@ -60,22 +54,37 @@ constexpr int kPieceLen = 16384;
     }
 
 // ---------------------------------------------------------------------------
-// Sweeps over the batch: one persistent launch per sweep.  Items are the
-// level chunks of every system, merged level by level (level l of every
-// system before level l + 1 of any), so each item depends only on items
-// with smaller tickets, as in the single-system persistent sweep.  Systems
-// whose Krylov recurrence is frozen are skipped by both sweeps of an
-// application alike, which keeps the kNotReady invariant of their buffers.
+// Sweeps over the batch: one persistent launch per sweep on the members'
+// row-tile layouts.  Items are (member, tile), merged tile index by tile
+// index (tile t of every member before tile t + 1 of any), so each item
+// depends only on items with smaller tickets, as in the single-system tiled
+// sweep.  Members whose Krylov recurrence is frozen are skipped by both
+// sweeps of an application alike, which keeps the kNotReady invariant of
+// their buffers.
 // ---------------------------------------------------------------------------
+struct BatchTiled {               // one member's tiled layout of one sweep
+    const int32_t* tile_chunk_ptr;
+    const int32_t* tile_lo;
+    const int32_t* chunk_row;
+    const int32_t* rows;
+    const int32_t* deps;
+    const void* vals;
+    const void* dinv;
+    int64_t voff;                 // first unknown of the member in the batch vectors
+    int tile_rows;
+    int kmax;
+    int bs;
+    int pad;
+};
+
 struct BatchSweepArgs {
-    const BatchSys* sys;
-    const int2* items;        // (system, chunk of that system's layout)
+    const BatchTiled* mem;        // per member, this sweep
+    const int2* items;            // (member, tile)
     int nitems;
-    int which;                // 0: L sweep, 1: U' sweep with D^{-1} fused
     const double* rhs;
     double* out;
     double* reset;
-    const int* active;        // per system, or null: every system
+    const int* active;            // per member, or null: every member
     unsigned long long* ticket;
     unsigned int* done;
     int* status;
@@ -83,37 +92,53 @@ struct BatchSweepArgs {
     unsigned int spin_limit;
 };
 
-template <int B, typename T>
-__device__ __forceinline__ void sweep_batch_item(const BatchSweepArgs& a, const BatchSys& S, int chunk)
+template <int B, typename T, bool FUSE, int KMAX>
+__device__ __forceinline__ void batch_tile(const BatchSweepArgs& a, const BatchTiled& M, int tile, double* tile_vals)
 {
-    // selects, not an index: a dynamic index would put S in scratch memory
-    const bool u = a.which != 0;
-    SweepArgs s{};
-    s.chunk_off = u ? S.chunk_off[1] : S.chunk_off[0];
-    s.rows = u ? S.rows[1] : S.rows[0];
-    s.cols = u ? S.cols[1] : S.cols[0];
-    s.vals = u ? S.vals[1] : S.vals[0];
-    s.dinv = S.dinv;
-    s.rhs = a.rhs + S.voff;
-    s.out = a.out + S.voff;
-    s.reset = a.reset ? a.reset + S.voff : nullptr;
-    s.status = a.status;
-    s.R = 1;
-    s.fuse = a.which;
-    s.persistent = 1;
-    s.spin_limit = a.spin_limit;
-    sweep_chunk<B, T, 1>(s, chunk);
+    TiledArgs t{};
+    t.tile_chunk_ptr = M.tile_chunk_ptr;
+    t.tile_lo = M.tile_lo;
+    t.chunk_row = M.chunk_row;
+    t.rows = M.rows;
+    t.deps = M.deps;
+    t.vals = M.vals;
+    t.dinv = M.dinv;
+    t.rhs = a.rhs + M.voff;
+    t.out = a.out + M.voff;
+    t.reset = a.reset ? a.reset + M.voff : nullptr;
+    t.status = a.status;
+    t.tile_rows = M.tile_rows;
+    t.R = 1;
+    t.spin_limit = a.spin_limit;
+    // this member's zero row (an earlier item may have used that LDS)
+    if (lane_id() < B) tile_vals[M.tile_rows * B + lane_id()] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    ColMap<false> cm;
+    cm.R = 1;
+    cm.j8 = 0;
+    run_tile<B, T, FUSE, KMAX, false>(t, tile, cm, tile_vals);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sweep_batch(BatchSweepArgs a)
+template <typename T, bool FUSE>
+__global__ __launch_bounds__(64) void k_sweep_batch(BatchSweepArgs a)
 {
-    for (int t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); t < a.nitems;
-         t = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
-        const int2 it = uniform_record(a.items, t);
+    extern __shared__ double tile_vals[];
+    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < a.nitems;
+         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int2 it = uniform_record(a.items, tk);
         if (a.active && !uniform_load(a.active, it.x)) continue;
-        const BatchSys S = uniform_record(a.sys, it.x);
-        BILU_BATCH_SWITCH_B(S.bs, (sweep_batch_item<B, T>(a, S, it.y)))
+        const BatchTiled M = uniform_record(a.mem, it.x);
+        switch (M.bs * 16 + M.kmax) {
+#define BILU_BATCH_TILE(BS, K) \
+    case BS * 16 + K: batch_tile<BS, T, FUSE, K>(a, M, it.y, tile_vals); break;
+        BILU_BATCH_TILE(1, 3) BILU_BATCH_TILE(2, 3) BILU_BATCH_TILE(3, 3) BILU_BATCH_TILE(4, 3)
+        BILU_BATCH_TILE(5, 3) BILU_BATCH_TILE(6, 3) BILU_BATCH_TILE(7, 3) BILU_BATCH_TILE(8, 3)
+        BILU_BATCH_TILE(1, 6) BILU_BATCH_TILE(2, 6) BILU_BATCH_TILE(3, 6) BILU_BATCH_TILE(4, 6)
+        BILU_BATCH_TILE(1, 9) BILU_BATCH_TILE(2, 9) BILU_BATCH_TILE(3, 9) BILU_BATCH_TILE(4, 9)
+#undef BILU_BATCH_TILE
+        default: break;
+        }
     }
     finish_persistent(a.ticket, a.done, a.total_waves);
 }
