@@ -220,9 +220,13 @@ enum {
                                  values fit 64 KiB of LDS); 0 = chosen by a host
                                  simulation of the tiled schedule (default)          */
     BILU_TUNE_BLOCKS = 3,     /* persistent grid in workgroups, 0 = automatic        */
-    BILU_TUNE_RHS_TILE = 4    /* right-hand-side columns per pass of the level-chunk
+    BILU_TUNE_RHS_TILE = 4,   /* right-hand-side columns per pass of the level-chunk
                                  sweeps and the SpMV when nrhs > 1: 1, 4 or 8;
                                  0 = 8 (default)                                     */
+    BILU_TUNE_FUSE_SPMV = 5   /* 1: inside bilu_solve, each U' sweep of an application
+                                 followed by an SpMV of its output runs with that
+                                 SpMV in one launch (row tiles, one right-hand side,
+                                 not transposed); 0 (default): separate launches    */
 };
 bilu_status bilu_tune(bilu_ctx* ctx, int param, int value);
 
@@ -253,7 +257,9 @@ bilu_status bilu_check(bilu_ctx* ctx, hipStream_t stream);
 /* Kernel classes timed by bilu_timing. */
 enum {
     BILU_K_SWEEP_L = 0, BILU_K_SWEEP_U = 1, BILU_K_SWEEP_UT = 2, BILU_K_SWEEP_LT = 3,
-    BILU_K_SPMV = 4, BILU_K_FACTOR = 5, BILU_K_SPLIT = 6, BILU_K_COUNT = 7
+    BILU_K_SPMV = 4, BILU_K_FACTOR = 5, BILU_K_SPLIT = 6,
+    BILU_K_SWEEP_U_SPMV = 7,    /* U' sweep with the SpMV of its output (solvers) */
+    BILU_K_COUNT = 8
 };
 
 typedef struct {

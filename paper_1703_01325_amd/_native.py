@@ -34,8 +34,8 @@ EXPORTS = (
     "bilu_batch_create", "bilu_batch_offsets", "bilu_batch_factor", "bilu_batch_apply",
     "bilu_batch_spmv", "bilu_batch_solve", "bilu_batch_member", "bilu_batch_destroy",
 )
-K_SWEEP_L, K_SWEEP_U, K_SWEEP_UT, K_SWEEP_LT, K_SPMV, K_FACTOR, K_SPLIT, K_COUNT = range(8)
-K_NAMES = ("sweep_L", "sweep_U", "sweep_UT", "sweep_LT", "spmv", "factor", "split")
+K_SWEEP_L, K_SWEEP_U, K_SWEEP_UT, K_SWEEP_LT, K_SPMV, K_FACTOR, K_SPLIT, K_SWEEP_U_SPMV, K_COUNT = range(9)
+K_NAMES = ("sweep_L", "sweep_U", "sweep_UT", "sweep_LT", "spmv", "factor", "split", "sweep_U_spmv")
 
 
 class BiluInfo(ct.Structure):
@@ -233,7 +233,7 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
                            ct.c_void_p(stream)), "bilu_grad_A")
 
 
-TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE = 0, 1, 3, 4
+TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV = 0, 1, 3, 4, 5
 
 
 def bilu_tune(ctx, param, value):

@@ -750,7 +750,60 @@ int validate_layout(const Host& h)
         for (int i = 0; i < nb; ++i)
             if (seen[i] != ndep[i]) return BILU_ERR_STATE;
         if (!tiled_accesses_in_bounds(h, s, w)) return BILU_ERR_STATE;
+        if (w == BILU_SWEEP_U) {        // the order of the U' sweep fused with the SpMV
+            std::vector<int32_t> sched;
+            if (build_fused_schedule(h, s, sched) != BILU_OK) return BILU_ERR_STATE;
+        }
     }
+    return BILU_OK;
+}
+
+int build_fused_schedule(const Host& h, const HostTiled& u, std::vector<int32_t>& sched)
+{
+    sched.clear();
+    if (!u.built || u.which != BILU_SWEEP_U) return BILU_ERR_STATE;
+    const int nb = h.nb;
+    const int rpc = u.rpc;
+    const int T = u.ntiles;
+    // tile of a row in the backward sweep
+    auto tile_of = [&](int32_t j) { return (nb - 1 - j) / u.tile_rows; };
+    for (int t = 0; t < T; ++t) {
+        const int hi = nb - 1 - t * u.tile_rows;     // backward tiles: the last one may be short
+        const int lo = u.tile_lo[t];
+        if (lo != std::max(0, hi - u.tile_rows + 1) || tile_of(lo) != t || tile_of(hi) != t) return BILU_ERR_STATE;
+    }
+    const int nblocks = (nb + rpc - 1) / rpc;
+    std::vector<std::vector<int32_t>> after(static_cast<size_t>(T));
+    for (int b = 0; b < nblocks; ++b) {
+        int32_t minj = nb;
+        for (int32_t i = b * rpc; i < std::min(nb, (b + 1) * rpc); ++i)
+            for (int32_t e = h.Ap[i]; e < h.Ap[i + 1]; ++e) minj = std::min(minj, h.Aj[e]);
+        after[static_cast<size_t>(tile_of(minj))].push_back(b);
+    }
+    // every tile first, so that no tile waits for a wavefront held by an
+    // SpMV block; then the blocks in the order their tiles finish
+    for (int t = 0; t < T; ++t) sched.push_back(t);
+    for (int t = 0; t < T; ++t)
+        for (int32_t b : after[t]) sched.push_back(-1 - b);
+    // check: tiles once and in order; every block once, after every tile
+    // holding a row it reads
+    std::vector<int32_t> seen_b(static_cast<size_t>(nblocks), 0);
+    int next_tile = 0;
+    for (int32_t it : sched) {
+        if (it >= 0) {
+            if (it != next_tile) return BILU_ERR_STATE;
+            ++next_tile;
+            continue;
+        }
+        const int b = -1 - it;
+        if (b >= nblocks || seen_b[b]++) return BILU_ERR_STATE;
+        for (int32_t i = b * rpc; i < std::min(nb, (b + 1) * rpc); ++i)
+            for (int32_t e = h.Ap[i]; e < h.Ap[i + 1]; ++e)
+                if (tile_of(h.Aj[e]) >= next_tile) return BILU_ERR_STATE;
+    }
+    if (next_tile != T) return BILU_ERR_STATE;
+    for (int32_t v : seen_b)
+        if (v != 1) return BILU_ERR_STATE;
     return BILU_OK;
 }
 

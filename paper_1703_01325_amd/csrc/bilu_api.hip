@@ -43,6 +43,7 @@ struct bilu_ctx {
     int tile_rows = 0;          // 0: chosen by schedule simulation on first tiled use
     int blocks_override = 0;
     int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
+    bool fuse_spmv = false;     // solvers run U' sweep + SpMV as one launch
     unsigned int spin_limit = 1u << 24;
 
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
@@ -223,6 +224,30 @@ bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks,
                 : launch_tiled_b<double, false>(bs, kmax, multi, blocks, lds, s, a);
 }
 
+template <typename T, int B>
+bool launch_fused_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a, const dev::FusedSpmvArgs& m)
+{
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 3>), dim3(blocks), dim3(64), lds, s, a, m);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 3>), dim3(blocks), dim3(64), lds, s, a, m); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 6>), dim3(blocks), dim3(64), lds, s, a, m); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 9>), dim3(blocks), dim3(64), lds, s, a, m); return true;
+        }
+        return false;
+    }
+}
+
+template <typename T>
+bool launch_fused_b(int bs, int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a,
+                    const dev::FusedSpmvArgs& m)
+{
+    BILU_SWITCH_B(bs, if (!(launch_fused_k<T, B>(kmax, blocks, lds, s, a, m))) return false)
+}
+
 template <int RT, bool TR>
 bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
                    const double* x, double* y, int R, hipStream_t s)
@@ -298,7 +323,8 @@ void free_form(bilu_ctx* c, int form)
         DevSweep& d = c->ds[form][w];
         for (void* p : {static_cast<void*>(d.chunk_off), static_cast<void*>(d.rows), static_cast<void*>(d.cols),
                         static_cast<void*>(d.src), static_cast<void*>(d.tile_chunk_ptr),
-                        static_cast<void*>(d.tile_lo), static_cast<void*>(d.chunk_row), d.vals, d.dinv})
+                        static_cast<void*>(d.tile_lo), static_cast<void*>(d.chunk_row), static_cast<void*>(d.fused),
+                        d.vals, d.dinv})
             dfree(c, p);
         d = DevSweep{};
     }
@@ -542,6 +568,70 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
     return BILU_OK;
 }
 
+// z = M^{-1} r and y = A z for one right-hand side: the L sweep, then the
+// U' sweep and the SpMV in one launch (tiles and SpMV blocks share its
+// ticket order).  Falls back to the separate calls where the fused launch
+// does not apply (other sweep forms, transposes, several columns).
+bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double* z, double* y, int R,
+                          bool transpose, hipStream_t s)
+{
+    if (transpose || R != 1 || sweep_form(c, 1) != kFormTiled || !c->fuse_spmv) {
+        bilu_status st = do_apply(c, r, z, R, transpose, s);
+        return st ? st : do_spmv(c, Ax, z, y, R, transpose ? 1 : 0, s);
+    }
+    if (!c || !Ax || !r || !z || !y || r == z || y == z) return BILU_ERR_ARG;
+    if (!c->split_done) return BILU_ERR_STATE;
+    bilu_status st;
+    if ((st = layout_form(c, kFormTiled, s))) return st;
+    if ((st = ensure_y(c, 1, s))) return st;
+    HostTiled& hu = c->h.tiled[BILU_SWEEP_U];
+    DevSweep& du = c->ds[kFormTiled][BILU_SWEEP_U];
+    if (!du.fused) {
+        if (build_fused_schedule(c->h, hu, hu.fused) != BILU_OK) return BILU_ERR_STATE;
+        if ((st = upload(c, &du.fused, hu.fused))) return st;
+    }
+    if ((st = run_sweep(c, BILU_SWEEP_L, r, c->d_y, z, 1, s))) return st;
+    // U' sweep + SpMV
+    const long tslot = timing_begin(c, BILU_K_SWEEP_U_SPMV, s);
+    TiledArgs a{};
+    a.tile_chunk_ptr = du.tile_chunk_ptr;
+    a.tile_lo = du.tile_lo;
+    a.chunk_row = du.chunk_row;
+    a.rows = du.rows;
+    a.deps = du.cols;
+    a.vals = du.vals;
+    a.dinv = du.dinv;
+    a.rhs = c->d_y;
+    a.out = z;
+    a.reset = c->d_y;
+    a.ticket = c->d_ticket;
+    a.done = c->d_done;
+    a.status = c->d_status;
+    a.ntiles = hu.ntiles;
+    a.tile_rows = hu.tile_rows;
+    a.R = 1;
+    a.spin_limit = c->spin_limit;
+    dev::FusedSpmvArgs m{};
+    m.sched = du.fused;
+    m.nsched = static_cast<int>(hu.fused.size());
+    m.nb = c->h.nb;
+    m.Ap = c->d_Ap;
+    m.Aj = c->d_Aj;
+    m.Ax = Ax;
+    m.y = y;
+    // one wavefront per tile plus one per compute unit: SpMV blocks mostly
+    // run on wavefronts whose tile is done, few wait and poll
+    const int blocks = persistent_blocks(c, std::min(m.nsched, hu.ntiles + c->num_cu), 1, 8);
+    a.total_waves = static_cast<unsigned int>(blocks);
+    const size_t lds = static_cast<size_t>(hu.tile_rows + 1) * c->h.bs * sizeof(double);
+    const bool ok = c->precision == BILU_FACTORS_FP32 ? launch_fused_b<float>(c->h.bs, hu.kmax, blocks, lds, s, a, m)
+                                                      : launch_fused_b<double>(c->h.bs, hu.kmax, blocks, lds, s, a, m);
+    timing_end(c, tslot, s);
+    if (!ok) return BILU_ERR_ARG;
+    CK(hipGetLastError());
+    return BILU_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -771,6 +861,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (value != 0 && value != 1 && value != 4 && value != 8) return BILU_ERR_ARG;
         c->rhs_tile = value;
         return BILU_OK;
+    case BILU_TUNE_FUSE_SPMV:
+        if (value != 0 && value != 1) return BILU_ERR_ARG;
+        c->fuse_spmv = value != 0;
+        return BILU_OK;
     }
     return BILU_ERR_ARG;
 }
@@ -948,7 +1042,6 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     double* part = c->d_part;
     KState* S = c->d_state;
     const int eg = grid_for(n * R);
-    auto apply = [&](const double* in, double* out) { return do_apply(c, in, out, R, tr != 0, s); };
     auto spmv = [&](const double* in, double* out) { return do_spmv(c, Ax, in, out, R, tr, s); };
 
     CK(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, s));
@@ -973,12 +1066,12 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
         hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, r, part, dev::SL_RHO);
         hipLaunchKernelGGL(dev::k_bicg_s_rho, dim3(1), dim3(64), 0, s, R, part, S);
         hipLaunchKernelGGL(dev::k_bicg_p, dim3(eg), dim3(256), 0, s, n, R, r, v, p, S);
-        if ((st = apply(p, ph)) || (st = spmv(ph, v))) return st;
+        if ((st = do_apply_spmv(c, Ax, p, ph, v, R, tr != 0, s))) return st;
         hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, v, part, dev::SL_RV);
         hipLaunchKernelGGL(dev::k_bicg_s_alpha, dim3(1), dim3(64), 0, s, R, part, S);
         hipLaunchKernelGGL(dev::k_bicg_s, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, r, v, sv, S, part);
         hipLaunchKernelGGL(dev::k_bicg_s_snorm, dim3(1), dim3(64), 0, s, R, part, S);
-        if ((st = apply(sv, sh)) || (st = spmv(sh, t))) return st;
+        if ((st = do_apply_spmv(c, Ax, sv, sh, t, R, tr != 0, s))) return st;
         hipLaunchKernelGGL(dev::k_dot2, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, t, sv, part,
                            dev::SL_TS, dev::SL_TT);
         hipLaunchKernelGGL(dev::k_bicg_s_omega, dim3(1), dim3(64), 0, s, R, part, S);
@@ -1112,7 +1205,7 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
         for (int j = 0; j < m; ++j) {
             double* vj = V + static_cast<size_t>(j) * n;
             double* hcol = dH + static_cast<size_t>(j) * (m + 1);
-            if ((st = apply(vj, z)) || (st = spmv(z, w))) break;
+            if ((st = do_apply_spmv(c, Ax, vj, z, w, 1, tr != 0, s))) break;
             hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, nullptr, coef, V, part, dev::SL_RHO);
             hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol, coef, 0);
             for (int i = 1; i <= j; ++i) {

@@ -58,6 +58,9 @@ struct HostTiled {
     std::vector<int32_t> rows;             // [nchunks*rpc]
     std::vector<int32_t> deps;             // [nslots]
     std::vector<int64_t> src;              // [nslots]
+    // U' sweep fused with y = A x on its output (built on demand): ticket
+    // order of tiles (>= 0) and SpMV blocks of rpc rows (-(1 + block))
+    std::vector<int32_t> fused;
 };
 
 // Dependency slots per row that the tiled sweep kernel loads ahead into
@@ -89,6 +92,7 @@ struct DevSweep {
     int32_t* tile_chunk_ptr = nullptr;
     int32_t* tile_lo = nullptr;
     int32_t* chunk_row = nullptr;  // tiled form: chunk_off / rpc (first slot row)
+    int32_t* fused = nullptr;      // tiled U' form: fused sweep + SpMV ticket order
     void* vals = nullptr;     // [nslots * bs*bs] FP64 or FP32, layout [k][c][r][q]
     void* dinv = nullptr;     // [nchunks*rpc * bs*bs] same layout, fused sweeps only
     int vals_precision = -1;  // precision the values were laid out in (-1: none)
@@ -128,5 +132,10 @@ int choose_tile_rows(const Host& h, int rpc, int max_rows);
 // Every candidate tile size with its predicted duration, best first.
 std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int max_rows);
 int validate_layout(const Host& h);
+// Ticket order of the backward U' tiled sweep fused with the SpMV on its
+// output: all tiles, then each block of rpc rows of A, ordered by the tile
+// that finishes the lowest row the block reads.  Checked before it is
+// returned.
+int build_fused_schedule(const Host& h, const HostTiled& u, std::vector<int32_t>& sched);
 
 }  // namespace bilu

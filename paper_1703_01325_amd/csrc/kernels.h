@@ -662,6 +662,86 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
     finish_persistent(a.ticket, a.done, a.total_waves);
 }
 
+// ---------------------------------------------------------------------------
+// U' sweep fused with y = A x on its output x: one persistent launch whose
+// tickets are the sweep's tiles and then the blocks of 64/B rows of A,
+// ordered by the tile that finishes the lowest row each reads (host-built
+// order, so every item depends only on earlier tickets, and every tile has
+// a wavefront before any wavefront waits in an SpMV block).  An SpMV block
+// requests A's values and the x values (device-coherent) of a group of
+// blocks of a row together, polls any x value still showing kNotReady, then
+// forms its rows exactly as k_spmv does (same operations, same order).
+// ---------------------------------------------------------------------------
+struct FusedSpmvArgs {
+    const int32_t* sched;        // >= 0 tile, < 0 SpMV block -(1 + b)
+    int nsched;
+    int nb;
+    const int32_t* Ap;
+    const int32_t* Aj;
+    const double* Ax;
+    double* y;
+};
+
+template <int B>
+__device__ __forceinline__ void spmv_block_ready(const FusedSpmvArgs& m, int64_t row0, const double* x,
+                                                 unsigned int limit, int* status)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int EG = B <= 4 ? 8 : 4;          // blocks of a row read together
+    const int lane = lane_id();
+    const int q = lane / B;
+    const int r = lane - q * B;
+    const int64_t row = row0 + q;
+    if (q >= RPC || row >= m.nb) return;
+    const int e0 = m.Ap[row], e1 = m.Ap[row + 1];
+    double acc = 0.0;
+    for (int g = e0; g < e1; g += EG) {
+        int j[EG];
+#pragma unroll
+        for (int k = 0; k < EG; ++k) j[k] = g + k < e1 ? m.Aj[g + k] : -1;
+        // A's values and x's values requested together (the x values with
+        // device-coherent loads: cached copies would be stale)
+        double av[EG * B], xv[EG * B];
+#pragma unroll
+        for (int k = 0; k < EG; ++k)
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                const int64_t blk = g + k;
+                av[k * B + c] = j[k] >= 0 ? m.Ax[blk * BB + c * B + r] : 0.0;
+                xv[k * B + c] = j[k] >= 0 ? coherent_load(x + static_cast<int64_t>(j[k]) * B + c) : 0.0;
+            }
+        await_rows<EG, B, 1>(xv, j, x, 1, 0, limit, status);
+#pragma unroll
+        for (int k = 0; k < EG; ++k) {
+            if (j[k] < 0) continue;
+#pragma unroll
+            for (int c = 0; c < B; ++c) acc += av[k * B + c] * xv[k * B + c];
+        }
+    }
+    m.y[row * B + r] = acc;
+}
+
+template <int B, typename T, int KMAX>
+__global__ __launch_bounds__(64) void k_sweep_tiled_spmv(TiledArgs a, FusedSpmvArgs m)
+{
+    extern __shared__ double tile_vals[];                    // [tile rows + 1][B]
+    if (lane_id() < B) tile_vals[a.tile_rows * B + lane_id()] = 0.0;
+    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < m.nsched;
+         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int it = uniform_load(m.sched, tk);
+        if (it >= 0) {
+            ColMap<false> cm;
+            cm.R = 1;
+            cm.j8 = 0;
+            run_tile<B, T, true, KMAX, false>(a, it, cm, tile_vals);
+        } else {
+            spmv_block_ready<B>(m, static_cast<int64_t>(-1 - it) * (64 / B), a.out, a.spin_limit, a.status);
+        }
+    }
+    finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
 // Rows [row0, row0 + 64/B) of y = A x (or A^T x through the transposed
 // structure), by one wavefront; lane (q, r) owns component r of row q.
 template <int B, int RT, bool TRANS>

@@ -397,3 +397,29 @@ def test_autotune(api, oracle_mod):
     x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
     assert st == 0
     M.check()
+
+
+@pytest.mark.parametrize("name,make,k", [SMALL[0], SMALL[1], SMALL[-1], SMALL[5]],
+                         ids=["cube10_k0", "cube10_k1", "ragged_k2", "b5_k1"])
+def test_fused_sweep_spmv_identical(api, oracle_mod, name, make, k):
+    """The solvers run each U' sweep together with the SpMV of its output;
+    the SpMV rows are formed with the same operations in the same order, so
+    solves with and without the fused launch agree bit for bit."""
+    c = Case(oracle_mod, make(), k)
+    M = c.gpu(api)
+    b = cuda(c.rhs)
+    M.tune(fuse_spmv=False)
+    x0, st0, info0 = M.solve(c.Ax, b, rtol=1e-10)
+    M.tune(fuse_spmv=True)
+    M.timing(True)
+    x1, st1, info1 = M.solve(c.Ax, b, rtol=1e-10)
+    t = M.timing_read()
+    M.timing(False)
+    assert t["sweep_U_spmv"][0] > 0           # the fused launch ran
+    assert st0 == st1 == 0 and info0 == info1 and torch.equal(x0, x1)
+    g0, _, _ = M.solve(c.Ax, b, method="gmres", restart=20, rtol=1e-10)
+    M.tune(fuse_spmv=False)
+    g1, _, _ = M.solve(c.Ax, b, method="gmres", restart=20, rtol=1e-10)
+    assert torch.equal(g0, g1)
+    M.check()
+    M.tune(fuse_spmv=False)
