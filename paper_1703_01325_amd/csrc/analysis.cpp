@@ -576,7 +576,7 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                     if (!in(db, n_dinv) || !in(db + static_cast<int64_t>(B - 1) * B * RPC, n_dinv)) return false;
                 }
                 for (int k = 0; k < KMAX; ++k) {
-                    const int64_t xb = code[k] >= 0 ? code[k] : rowc_b;
+                    const int64_t xb = code[k] >= 0 ? code[k] : 0;
                     if (!in8(xb, vec_bytes) || !in8(xb + (B - 1) * 8, vec_bytes)) return false;
                     const int64_t lb = code[k] < 0 ? (code[k] & INT32_MAX) : 0;     // tile_compute
                     if (!in8(lb, lds_bytes) || !in8(lb + (B - 1) * 8, lds_bytes)) return false;

@@ -445,9 +445,11 @@ __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc,
     } else {
         s.h[0] = load_at(a.rhs, cm.at(rowc_b, r));
     }
+    // tile-local and padding slots do not use the value: every such lane
+    // reads row 0, so the wavefront touches one cache line for them
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : rowc_b;
+        const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : 0u;
 #pragma unroll
         for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), cm.at(xb, c));
     }
