@@ -93,6 +93,8 @@ typedef struct {
     int rows_per_chunk;   /* block rows per wavefront in the sweeps */
     int64_t sweep_slots[4]; /* padded block slots of each sweep layout */
     int tile_rows;        /* block rows per tile of the tiled sweeps (0: not chosen yet) */
+    int tile_group;       /* tiles per workgroup of the tiled sweeps (1: one wavefront
+                             per tile; see BILU_TUNE_TILE_GROUP)                         */
 } bilu_info;
 
 typedef struct {
@@ -223,10 +225,20 @@ enum {
     BILU_TUNE_RHS_TILE = 4,   /* right-hand-side columns per pass of the level-chunk
                                  sweeps and the SpMV when nrhs > 1: 1, 4 or 8;
                                  0 = 8 (default)                                     */
-    BILU_TUNE_FUSE_SPMV = 5   /* 1: inside bilu_solve, each U' sweep of an application
+    BILU_TUNE_FUSE_SPMV = 5,  /* 1: inside bilu_solve, each U' sweep of an application
                                  followed by an SpMV of its output runs with that
                                  SpMV in one launch (row tiles, one right-hand side,
-                                 not transposed); 0 (default): separate launches    */
+                                 not transposed, tiles not grouped); 0 (default):
+                                 separate launches                                   */
+    BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
+                                 wavefronts of one workgroup, handing rows to each
+                                 other through its LDS instead of global memory; a
+                                 group takes tiles a fixed tile distance apart (the
+                                 most frequent one between dependent rows: on a grid,
+                                 the same tile of consecutive planes).  Smaller groups
+                                 are used where the device's LDS or the ticket order
+                                 forbids larger ones.  0 = chosen with the tile size
+                                 by the host simulation (default)                    */
 };
 bilu_status bilu_tune(bilu_ctx* ctx, int param, int value);
 
@@ -237,15 +249,17 @@ typedef struct {
     int candidates;     /* configurations timed                                 */
     double apply_us;    /* median bilu_apply time of the chosen configuration   */
     double default_us;  /* the same for the configuration in force on entry     */
+    int tile_group;     /* chosen tiles per workgroup (mode 2)                  */
 } bilu_tune_result;
 
 /* Autotuner: times bilu_apply with nrhs columns (device scratch input, 2
  * warm-ups + median of 5, HIP events on `stream`) for candidate launch
  * configurations and keeps the fastest (the one in force on entry if none
- * beats it).  Candidates: nrhs = 1, the row tiles of the four tile sizes
- * with the shortest simulated schedules and the level-chunk form; nrhs > 1,
- * the row tiles of the simulated tile size and the level-chunk form with 1,
- * 4 and 8 columns per pass.  Needs the factors
+ * beats it).  Candidates: nrhs = 1, the row tiles of the four (tile size,
+ * group size) pairs with the shortest simulated schedules, the best
+ * ungrouped tile size, and the level-chunk form; nrhs > 1, the row tiles of
+ * the simulated choice, grouped and not, and the level-chunk form with 1, 4
+ * and 8 columns per pass.  Needs the factors
  * (after bilu_factor_diag); results of later calls are bit-identical to
  * those before it.  Synchronises `stream`. */
 bilu_status bilu_autotune(bilu_ctx* ctx, int nrhs, hipStream_t stream, bilu_tune_result* out);

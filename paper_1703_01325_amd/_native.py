@@ -42,7 +42,8 @@ class BiluInfo(ct.Structure):
     _fields_ = [("nb", ct.c_int), ("bs", ct.c_int), ("k", ct.c_int),
                 ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
                 ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
-                ("sweep_slots", ct.c_int64 * 4), ("tile_rows", ct.c_int)]
+                ("sweep_slots", ct.c_int64 * 4), ("tile_rows", ct.c_int),
+                ("tile_group", ct.c_int)]
 
 
 class KernelTime(ct.Structure):
@@ -60,7 +61,8 @@ class RhsInfo(ct.Structure):
 
 class TuneResult(ct.Structure):
     _fields_ = [("sweep_mode", ct.c_int), ("tile_rows", ct.c_int), ("rhs_tile", ct.c_int),
-                ("candidates", ct.c_int), ("apply_us", ct.c_double), ("default_us", ct.c_double)]
+                ("candidates", ct.c_int), ("apply_us", ct.c_double), ("default_us", ct.c_double),
+                ("tile_group", ct.c_int)]
 
 
 class SysDesc(ct.Structure):
@@ -233,7 +235,7 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
                            ct.c_void_p(stream)), "bilu_grad_A")
 
 
-TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV = 0, 1, 3, 4, 5
+TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV, TUNE_TILE_GROUP = 0, 1, 3, 4, 5, 6
 
 
 def bilu_tune(ctx, param, value):
@@ -243,8 +245,9 @@ def bilu_tune(ctx, param, value):
 def bilu_autotune(ctx, nrhs, stream):
     out = TuneResult()
     _check(lib.bilu_autotune(ctx, int(nrhs), ct.c_void_p(stream), ct.byref(out)), "bilu_autotune")
-    return {"sweep_mode": out.sweep_mode, "tile_rows": out.tile_rows, "rhs_tile": out.rhs_tile,
-            "candidates": out.candidates, "apply_us": out.apply_us, "default_us": out.default_us}
+    return {"sweep_mode": out.sweep_mode, "tile_rows": out.tile_rows, "tile_group": out.tile_group,
+            "rhs_tile": out.rhs_tile, "candidates": out.candidates, "apply_us": out.apply_us,
+            "default_us": out.default_us}
 
 
 def bilu_check(ctx, stream):

@@ -53,10 +53,10 @@ class BlockILU:
     def set_sweep_mode(self, mode):
         N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
 
-    def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None):
+    def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None):
         """Launch knobs of the sweeps (results are bit-identical for all)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
-                         (N.TUNE_RHS_TILE, rhs_tile),
+                         (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <numeric>
 
 #include "bilu_internal.h"
@@ -233,7 +234,69 @@ void build_sweep(const Host& h, int which, int rpc, HostSweep& s)
     s.built = true;
 }
 
-void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
+namespace {
+
+// Rows [lo, hi] of tile t; tiles are numbered in sweep order.
+inline void tile_range(int nb, int tile_rows, bool forward, int t, int& lo, int& hi)
+{
+    if (forward) {
+        lo = t * tile_rows;
+        hi = std::min(nb, lo + tile_rows) - 1;
+    } else {
+        hi = nb - 1 - t * tile_rows;
+        lo = std::max(0, hi - tile_rows + 1);
+    }
+}
+
+inline int tile_of_row(int nb, int tile_rows, bool forward, int j)
+{
+    return forward ? j / tile_rows : (nb - 1 - j) / tile_rows;
+}
+
+// The most frequent distance (in tiles) of the dependencies that cross
+// tiles, over the first `rows` rows in sweep order; 0 if none cross.
+int group_stride(int nb, int tile_rows, bool forward, const std::vector<int32_t>& dptr, const std::vector<Dep>& deps,
+                 int rows)
+{
+    const int ntiles = (nb + tile_rows - 1) / tile_rows;
+    std::vector<int64_t> cnt(static_cast<size_t>(ntiles) + 1, 0);
+    for (int step = 0; step < rows; ++step) {
+        const int32_t i = forward ? step : nb - 1 - step;
+        const int ti = tile_of_row(nb, tile_rows, forward, i);
+        for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+            const int tj = tile_of_row(nb, tile_rows, forward, deps[d].col);
+            if (tj != ti) cnt[static_cast<size_t>(ti - tj)]++;
+        }
+    }
+    int best = 0;
+    for (int d = 1; d <= ntiles; ++d)
+        if (cnt[d] > cnt[best]) best = d;
+    return cnt[best] > 0 ? best : 0;
+}
+
+// Whether grouping keeps the ticket order over the first `rows` rows in
+// sweep order: a dependency on another tile of the group is on an earlier
+// member (all members run together), one on another group is on a group
+// with a smaller ticket.
+bool groups_ordered(int nb, int tile_rows, bool forward, const TileGroups& tg, const std::vector<int32_t>& dptr,
+                    const std::vector<Dep>& deps, int rows)
+{
+    for (int step = 0; step < rows; ++step) {
+        const int32_t i = forward ? step : nb - 1 - step;
+        const int ti = tile_of_row(nb, tile_rows, forward, i);
+        for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+            const int tj = tile_of_row(nb, tile_rows, forward, deps[d].col);
+            if (tj == ti) continue;
+            const int gi = tg.group(ti), gj = tg.group(tj);
+            if (gi == gj ? tg.member(tj) >= tg.member(ti) : gj >= gi) return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, int64_t lds_limit, HostTiled& s)
 {
     const int nb = h.nb;
     const int bs = h.bs;
@@ -251,23 +314,38 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
     s.rpc = rpc;
     s.tile_rows = tile_rows;
     s.ntiles = (nb + tile_rows - 1) / tile_rows;
+    // the largest usable group not above the request
+    TileGroups tg{1, 1, s.ntiles};
+    s.group_req = group;
+    group = std::max(1, std::min(group, kGroupMax));
+    while (group > 1 && tiled_lds_bytes(tile_rows, group, bs) > lds_limit) --group;
+    const int D = group > 1 ? group_stride(nb, tile_rows, forward, dptr, deps, nb) : 0;
+    for (int g = group; g > 1 && D > 0; --g) {
+        const TileGroups cand{g, D, s.ntiles};
+        if (groups_ordered(nb, tile_rows, forward, cand, dptr, deps, nb)) {
+            tg = cand;
+            break;
+        }
+    }
+    s.group = tg.G;
+    s.gstride = tg.D;
+    s.ngroups = tg.count();
+    s.group_tiles.assign(static_cast<size_t>(s.ngroups) * tg.G, -1);
+    for (int g = 0; g < s.ngroups; ++g)
+        for (int m = 0; m < tg.G; ++m) s.group_tiles[static_cast<size_t>(g) * tg.G + m] = tg.tile(g, m);
     s.tile_chunk_ptr.assign(static_cast<size_t>(s.ntiles) + 1, 0);
     s.tile_lo.assign(static_cast<size_t>(s.ntiles), 0);
     s.chunk_off.assign(1, 0);
-    const int32_t pad_code = tiled_local_code(tile_rows, bs);      // the zero row
-    std::vector<int32_t> il(static_cast<size_t>(tile_rows));       // level inside the tile
+    const int32_t pad_code = tiled_local_code(tg.G * tile_rows, bs);      // the zero row
+    std::vector<int32_t> il(static_cast<size_t>(tile_rows));            // level inside the tile
+    std::vector<int32_t> cit(tg.G > 1 ? static_cast<size_t>(nb) : 0);   // chunk of a row inside its tile
     std::vector<int32_t> order;
     for (int t = 0; t < s.ntiles; ++t) {
         int lo, hi;
-        if (forward) {
-            lo = t * tile_rows;
-            hi = std::min(nb, lo + tile_rows) - 1;
-        } else {
-            hi = nb - 1 - t * tile_rows;
-            lo = std::max(0, hi - tile_rows + 1);
-        }
+        tile_range(nb, tile_rows, forward, t, lo, hi);
         s.tile_lo[t] = lo;
         s.tile_chunk_ptr[t] = static_cast<int32_t>(s.chunk_off.size() - 1);
+        const int gt = tg.group(t);
         // levels over the dependencies inside [lo, hi], rows in sweep order
         for (int step = 0; step <= hi - lo; ++step) {
             const int32_t i = forward ? lo + step : hi - step;
@@ -292,9 +370,11 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
             // at least kmax slot rows: the kernel reads the first kmax of every chunk
             const int32_t w = std::max(dptr[order[pos] + 1] - dptr[order[pos]], s.kmax);
             const int64_t base = s.chunk_off.back();
+            const int32_t chunk_in_tile = static_cast<int32_t>(s.chunk_off.size() - 1) - s.tile_chunk_ptr[t];
             s.chunk_off.push_back(base + static_cast<int64_t>(w) * rpc);
             s.deps.resize(static_cast<size_t>(base) + static_cast<size_t>(w) * rpc, pad_code);
             s.src.resize(s.deps.size(), -1);
+            int32_t wait[kGroupMax] = {0, 0, 0, 0};
             for (int q = 0; q < rpc; ++q) {
                 if (static_cast<size_t>(q) >= cn) {
                     s.rows.push_back(-1);
@@ -302,13 +382,24 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
                 }
                 const int32_t i = order[pos + q];
                 s.rows.push_back(i);
+                if (tg.G > 1) cit[i] = chunk_in_tile;
                 for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
                     const size_t slot = static_cast<size_t>(base) + static_cast<size_t>(d - dptr[i]) * rpc + q;
                     const int32_t j = deps[d].col;
-                    s.deps[slot] = (j >= lo && j <= hi) ? tiled_local_code(j - lo, bs) : tiled_global_code(j, bs);
+                    const int tj = tile_of_row(nb, tile_rows, forward, j);
+                    int32_t code;
+                    if (tg.group(tj) == gt) {          // a row of this group: in its LDS
+                        const int mj = tg.member(tj);
+                        code = tiled_local_code(mj * tile_rows + (j - s.tile_lo[tj]), bs);
+                        if (tj != t) wait[mj] = std::max(wait[mj], cit[j] + 1);
+                    } else {
+                        code = tiled_global_code(j, bs);
+                    }
+                    s.deps[slot] = code;
                     s.src[slot] = deps[d].src;
                 }
             }
+            if (tg.G > 1) s.chunk_wait.insert(s.chunk_wait.end(), wait, wait + kGroupMax);
             pos += cn;
         }
     }
@@ -321,31 +412,31 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& s)
 // Event simulation of the tiled schedule: tiles run concurrently, a tile
 // walks its chunks in order, a chunk costs one step and may start once the
 // previous chunk of its tile is done and every row it reads from another
-// tile has been finished for `hop` steps.  Chunks are formed exactly as in
-// build_tiled.  Returns the finishing time of the last chunk.
+// tile has been finished for `hop` steps (a tile of the same group: for
+// kLocalHop steps, the cost of an LDS handoff).  Chunks are formed exactly as
+// in build_tiled.  Returns the finishing time of the last chunk, or +inf
+// where the grouping breaks the ticket order.
 namespace {
-double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr, const std::vector<Dep>& deps,
-                     int rpc, int tile_rows, double hop, int row_limit);
-}
+constexpr double kLocalHop = 0.5;
 
-double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, double hop, int row_limit)
-{
-    std::vector<int32_t> dptr;
-    std::vector<Dep> deps;
-    sweep_deps(h, which, dptr, deps);
-    return simulate_deps(h, which, dptr, deps, rpc, tile_rows, hop, row_limit);
-}
-
-namespace {
 double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr, const std::vector<Dep>& deps,
-                     int rpc, int tile_rows, double hop, int row_limit)
+                     int rpc, int tile_rows, int group, double hop, int row_limit)
 {
     const int nb = row_limit > 0 ? std::min(h.nb, row_limit) : h.nb;
     const bool forward = (which == BILU_SWEEP_L || which == BILU_SWEEP_UT);
-    std::vector<double> done(static_cast<size_t>(h.nb), 0.0);
-    std::vector<int32_t> il(static_cast<size_t>(tile_rows)), cnt, start, order;
     // a forward sweep restricted to its first `nb` rows is itself a sweep
     const int ntiles = forward ? (nb + tile_rows - 1) / tile_rows : (h.nb + tile_rows - 1) / tile_rows;
+    TileGroups tg{1, 1, ntiles};
+    if (group > 1) {
+        const int rows = forward ? nb : h.nb;
+        const int D = group_stride(h.nb, tile_rows, forward, dptr, deps, rows);
+        if (D <= 0) return std::numeric_limits<double>::infinity();
+        tg = TileGroups{group, D, ntiles};
+        if (!groups_ordered(h.nb, tile_rows, forward, tg, dptr, deps, rows))
+            return std::numeric_limits<double>::infinity();
+    }
+    std::vector<double> done(static_cast<size_t>(h.nb), 0.0);
+    std::vector<int32_t> il(static_cast<size_t>(tile_rows)), order;
     double makespan = 0.0;
     for (int t = 0; t < ntiles; ++t) {
         int lo, hi;
@@ -353,9 +444,9 @@ double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr,
             lo = t * tile_rows;
             hi = std::min(nb, lo + tile_rows) - 1;
         } else {
-            hi = h.nb - 1 - t * tile_rows;
-            lo = std::max(0, hi - tile_rows + 1);
+            tile_range(h.nb, tile_rows, false, t, lo, hi);
         }
+        const int gt = tg.group(t);
         for (int step = 0; step <= hi - lo; ++step) {
             const int32_t i = forward ? lo + step : hi - step;
             int32_t l = 0;
@@ -383,7 +474,9 @@ double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr,
                 const int32_t i = order[pos + q];
                 for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
                     const int32_t j = deps[d].col;
-                    if (j < lo || j > hi) ready = std::max(ready, done[j] + hop);
+                    if (j >= lo && j <= hi) continue;
+                    const bool same = tg.G > 1 && tg.group(tile_of_row(h.nb, tile_rows, forward, j)) == gt;
+                    ready = std::max(ready, done[j] + (same ? kLocalHop : hop));
                 }
             }
             now = ready + 1.0;
@@ -394,37 +487,37 @@ double simulate_deps(const Host& h, int which, const std::vector<int32_t>& dptr,
     }
     return makespan;
 }
-}  // namespace
+
+// Dependency distance histogram of the L sweep, most frequent first.
+std::vector<std::pair<int64_t, int32_t>> distance_histogram(const Host& h)
+{
+    std::vector<std::pair<int64_t, int32_t>> hist;
+    std::vector<int32_t> dist;
+    dist.reserve(static_cast<size_t>(h.nb) * 4);
+    for (int32_t i = 0; i < h.nb; ++i)
+        for (int32_t e = h.Pp[i]; e < h.Pp[i + 1] && h.Pj[e] < i; ++e) dist.push_back(i - h.Pj[e]);
+    std::sort(dist.begin(), dist.end());
+    for (size_t a = 0; a < dist.size();) {
+        size_t b = a;
+        while (b < dist.size() && dist[b] == dist[a]) ++b;
+        hist.emplace_back(static_cast<int64_t>(b - a), dist[a]);
+        a = b;
+    }
+    std::sort(hist.begin(), hist.end(), std::greater<>());
+    return hist;
+}
 
 // Candidate tile sizes: a geometric grid, plus divisors and multiples of the
 // most frequent dependency distances (on a grid these are the line and plane
 // periods; a tile aligned with them keeps corresponding rows of consecutive
-// tiles at the same level inside their tiles).  The smallest simulated
-// makespan of the L sweep wins; ties go to the larger tile.
-std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int max_rows)
+// tiles at the same level inside their tiles).
+std::vector<int> tile_candidates(const Host& h, int rpc, int max_rows,
+                                 const std::vector<std::pair<int64_t, int32_t>>& hist)
 {
-    const int nb = h.nb;
-    max_rows = std::max(1, std::min(max_rows, nb));
     const int min_rows = std::min(max_rows, std::max(1, 2 * rpc));
     std::vector<int> cand;
     for (double m = min_rows; m <= max_rows; m *= 1.5) cand.push_back(static_cast<int>(m));
     cand.push_back(max_rows);
-    // dependency distance histogram of the L sweep
-    std::vector<std::pair<int64_t, int32_t>> hist;
-    {
-        std::vector<int32_t> dist;
-        dist.reserve(static_cast<size_t>(nb) * 4);
-        for (int32_t i = 0; i < nb; ++i)
-            for (int32_t e = h.Pp[i]; e < h.Pp[i + 1] && h.Pj[e] < i; ++e) dist.push_back(i - h.Pj[e]);
-        std::sort(dist.begin(), dist.end());
-        for (size_t a = 0; a < dist.size();) {
-            size_t b = a;
-            while (b < dist.size() && dist[b] == dist[a]) ++b;
-            hist.emplace_back(static_cast<int64_t>(b - a), dist[a]);
-            a = b;
-        }
-        std::sort(hist.begin(), hist.end(), std::greater<>());
-    }
     const size_t top = std::min<size_t>(hist.size(), 4);
     static const int kMult[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64};
     for (size_t a = 0; a < top; ++a) {
@@ -436,22 +529,92 @@ std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int m
     }
     std::sort(cand.begin(), cand.end());
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    // A prefix of the sweep shows how tiles pipeline: a few multiples of the
-    // longest frequent dependency distance and of the largest tile.
+    (void)h;
+    return cand;
+}
+
+// A prefix of the sweep shows how tiles pipeline: a few multiples of the
+// longest frequent dependency distance and of the largest tile.
+int sim_row_limit(const Host& h, int max_rows, const std::vector<std::pair<int64_t, int32_t>>& hist)
+{
     int64_t longest = 1;
-    for (size_t a = 0; a < top; ++a) longest = std::max<int64_t>(longest, hist[a].second);
-    const int limit = static_cast<int>(std::min<int64_t>(nb, std::max<int64_t>({8 * longest, 16LL * max_rows, 65536})));
+    for (size_t a = 0; a < std::min<size_t>(hist.size(), 4); ++a) longest = std::max<int64_t>(longest, hist[a].second);
+    return static_cast<int>(std::min<int64_t>(h.nb, std::max<int64_t>({8 * longest, 16LL * max_rows, 65536})));
+}
+}  // namespace
+
+double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, int group, double hop, int row_limit)
+{
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, which, dptr, deps);
+    return simulate_deps(h, which, dptr, deps, rpc, tile_rows, group, hop, row_limit);
+}
+
+// The smallest simulated makespan of the L sweep wins; ties go to the larger
+// tile.
+std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int max_rows)
+{
+    max_rows = std::max(1, std::min(max_rows, h.nb));
+    const auto hist = distance_histogram(h);
+    const std::vector<int> cand = tile_candidates(h, rpc, max_rows, hist);
+    const int limit = sim_row_limit(h, max_rows, hist);
     std::vector<int32_t> dptr;
     std::vector<Dep> deps;
     sweep_deps(h, BILU_SWEEP_L, dptr, deps);
     std::vector<std::pair<double, int>> ranked;
-    for (int m : cand) ranked.emplace_back(simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, m, 5.0, limit), m);
+    for (int m : cand) ranked.emplace_back(simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, m, 1, 5.0, limit), m);
     // shortest predicted sweep first; on (near) ties the larger tile
     std::sort(ranked.begin(), ranked.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
         if (std::fabs(a.first - b.first) > 1e-9 * std::max(a.first, b.first)) return a.first < b.first;
         return a.second > b.second;
     });
     return ranked;
+}
+
+// Group sizes in order of preference.  The simulation above models the
+// dependency structure only; measured on MI355X (60x220x85 and 64^3 grids,
+// ILU(0)), groups of 3 beat groups of 4 and 2: the member tiles of a group
+// share one compute unit and near the sweep front all of them issue loads
+// at once, which the model does not see.
+constexpr int kGroupPreference[] = {3, 4, 2};
+
+std::vector<TileChoice> rank_tile_layouts(const Host& h, int rpc, int64_t lds_limit, int tile_req, int group_req)
+{
+    // one tile's rows stay within 64 KiB of LDS, so several tiles share a CU
+    const int64_t tile_lds = std::min<int64_t>(lds_limit, 65536);
+    const int max_rows = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(h.nb, tile_lds / (8LL * h.bs) - 1)));
+    const auto hist = distance_histogram(h);
+    const int limit = sim_row_limit(h, max_rows, hist);
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, BILU_SWEEP_L, dptr, deps);
+    // tile sizes with one wavefront per tile, best first
+    std::vector<TileChoice> single;
+    const std::vector<int> cand = tile_req > 0 ? std::vector<int>{std::min(tile_req, max_rows)}
+                                               : tile_candidates(h, rpc, max_rows, hist);
+    for (int m : cand) single.push_back(TileChoice{simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, m, 1, 5.0, limit), m, 1});
+    std::sort(single.begin(), single.end(), [](const TileChoice& a, const TileChoice& b) {
+        if (std::fabs(a.t - b.t) > 1e-9 * std::max(a.t, b.t)) return a.t < b.t;
+        return a.tile_rows > b.tile_rows;
+    });
+    if (group_req == 1) return single;
+    // groups of the best tile size: usable (LDS, ticket order) and shorter
+    // than the single tiles in the simulation, in order of preference
+    const TileChoice best = single.front();
+    std::vector<TileChoice> grouped;
+    auto consider = [&](int g) {
+        if (g < 2 || g > kGroupMax || tiled_lds_bytes(best.tile_rows, g, h.bs) > lds_limit) return;
+        const double t = simulate_deps(h, BILU_SWEEP_L, dptr, deps, rpc, best.tile_rows, g, 5.0, limit);
+        if (std::isfinite(t) && (group_req > 1 || t < best.t)) grouped.push_back(TileChoice{t, best.tile_rows, g});
+    };
+    if (group_req > 1) {
+        consider(std::min(group_req, kGroupMax));
+    } else {
+        for (int g : kGroupPreference) consider(g);
+    }
+    grouped.insert(grouped.end(), single.begin(), single.end());
+    return grouped;
 }
 
 int choose_tile_rows(const Host& h, int rpc, int max_rows)
@@ -543,13 +706,29 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
     const int64_t n_vals = n_slots_arr * BB;
     const int64_t n_dinv = static_cast<int64_t>(s.nchunks) * RPC * BB;
     const int64_t vec_bytes = static_cast<int64_t>(h.nb) * B * 8;
-    const int64_t lds_bytes = (static_cast<int64_t>(s.tile_rows) + 1) * B * 8;   // + the zero row
+    const int G = s.group;
+    // the member tiles' rows + the zero row (progress counters follow)
+    const int64_t lds_bytes = (static_cast<int64_t>(G) * s.tile_rows + 1) * B * 8;
     if (vec_bytes > INT32_MAX) return false;
+    if (G < 1 || G > kGroupMax) return false;
     auto in = [](int64_t i, int64_t n) { return i >= 0 && i < n; };
     auto in8 = [](int64_t byte, int64_t nbytes) { return byte >= 0 && byte % 8 == 0 && byte + 8 <= nbytes; };
+    // k_sweep_grouped: member m of group g sweeps group_tiles[g*G + m]
+    if (G > 1 && static_cast<int64_t>(s.group_tiles.size()) != static_cast<int64_t>(s.ngroups) * G) return false;
+    std::vector<int> member_of(static_cast<size_t>(s.ntiles), 0);
+    if (G > 1)
+        for (int64_t e = 0; e < static_cast<int64_t>(s.group_tiles.size()); ++e) {
+            const int t = s.group_tiles[e];
+            if (t < -1 || t >= s.ntiles) return false;
+            if (t >= 0) member_of[t] = static_cast<int>(e % G);
+        }
     for (int t = 0; t < s.ntiles; ++t) {
         const int lo = s.tile_lo[t];
+        const int64_t own = static_cast<int64_t>(member_of[t]) * s.tile_rows;   // first LDS row of the tile
         for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
+            if (G > 1 && !in(static_cast<int64_t>(c) * kGroupMax + kGroupMax - 1,
+                             static_cast<int64_t>(s.chunk_wait.size())))
+                return false;
             const int64_t off = s.chunk_off[c];
             const int w = static_cast<int>((s.chunk_off[c + 1] - off) / RPC);
             if (w < KMAX) return false;
@@ -594,7 +773,8 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                     if (!in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
                 if (!in8((static_cast<int64_t>(row) * B + r) * 8, vec_bytes)) return false;
-                if (!in8((static_cast<int64_t>(row - lo) * B + r) * 8, lds_bytes - B * 8)) return false;
+                if (row - lo < 0 || row - lo >= s.tile_rows) return false;
+                if (!in8(((own + row - lo) * B + r) * 8, lds_bytes - B * 8)) return false;
             }
         }
     }
@@ -684,8 +864,30 @@ int validate_layout(const Host& h)
             static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc)
             return BILU_ERR_STATE;
         if (static_cast<int64_t>(nb) * h.bs * 8 > INT32_MAX) return BILU_ERR_STATE;
+        // groups: the arithmetic numbering, every tile in exactly one slot
+        const int G = s.group;
+        if (G < 1 || G > kGroupMax || s.gstride < 1) return BILU_ERR_STATE;
+        const TileGroups tg{G, s.gstride, s.ntiles};
+        if (s.ngroups != tg.count() || static_cast<int64_t>(s.group_tiles.size()) != static_cast<int64_t>(s.ngroups) * G)
+            return BILU_ERR_STATE;
+        if (G > 1 ? static_cast<int64_t>(s.chunk_wait.size()) != static_cast<int64_t>(s.nchunks) * kGroupMax
+                  : !s.chunk_wait.empty())
+            return BILU_ERR_STATE;
+        {
+            std::vector<char> placed(static_cast<size_t>(s.ntiles), 0);
+            for (int g = 0; g < s.ngroups; ++g)
+                for (int m = 0; m < G; ++m) {
+                    const int t = s.group_tiles[static_cast<size_t>(g) * G + m];
+                    if (t != tg.tile(g, m)) return BILU_ERR_STATE;
+                    if (t < 0) continue;
+                    if (placed[t] || tg.group(t) != g || tg.member(t) != m) return BILU_ERR_STATE;
+                    placed[t] = 1;
+                }
+            for (int t = 0; t < s.ntiles; ++t)
+                if (!placed[t]) return BILU_ERR_STATE;
+        }
         const int32_t row_bytes = h.bs * 8;
-        const int32_t pad_code = tiled_local_code(s.tile_rows, h.bs);
+        const int32_t pad_code = tiled_local_code(G * s.tile_rows, h.bs);
         std::vector<int32_t> tile_of(static_cast<size_t>(nb), -1), chunk_of(static_cast<size_t>(nb), -1);
         for (int t = 0; t < s.ntiles; ++t) {
             const int lo = s.tile_lo[t];
@@ -716,10 +918,19 @@ int validate_layout(const Host& h)
                 if (w == BILU_SWEEP_LT && j < i) ndep[j]++;
             }
         for (int t = 0; t < s.ntiles; ++t) {
-            const int lo = s.tile_lo[t];
+            const int mt = tg.member(t);
+            const int gt = tg.group(t);
             for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c) {
                 const int64_t off = s.chunk_off[c];
                 const int64_t width = (s.chunk_off[c + 1] - off) / rpc;
+                // waits: only on earlier members, never past their last chunk
+                for (int m = 0; G > 1 && m < kGroupMax; ++m) {
+                    const int32_t need = s.chunk_wait[static_cast<size_t>(c) * kGroupMax + m];
+                    if (need == 0) continue;
+                    if (need < 0 || m >= mt) return BILU_ERR_STATE;
+                    const int tm = tg.tile(gt, m);
+                    if (tm < 0 || need > s.tile_chunk_ptr[tm + 1] - s.tile_chunk_ptr[tm]) return BILU_ERR_STATE;
+                }
                 for (int q = 0; q < rpc; ++q) {
                     const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
                     for (int64_t k = 0; k < width; ++k) {
@@ -729,15 +940,28 @@ int validate_layout(const Host& h)
                         if (code == pad_code && e == -1) continue;
                         if (r < 0 || code == pad_code || e < 0 || e >= nP) return BILU_ERR_STATE;
                         int32_t j;
-                        if (code < 0) {          // tile-local: byte offset of the row in LDS
+                        if (code < 0) {          // the group's LDS: byte offset of the row
                             const int32_t off = code & INT32_MAX;
                             if (off % row_bytes != 0) return BILU_ERR_STATE;
-                            j = lo + off / row_bytes;
-                            if (j < 0 || j >= nb || tile_of[j] != t || chunk_of[j] >= c) return BILU_ERR_STATE;
-                        } else {                 // another tile: byte offset of the row
+                            const int32_t lr = off / row_bytes;
+                            const int mj = lr / s.tile_rows;
+                            if (mj >= G) return BILU_ERR_STATE;
+                            const int tj = tg.tile(gt, mj);
+                            if (tj < 0) return BILU_ERR_STATE;
+                            j = s.tile_lo[tj] + lr % s.tile_rows;
+                            if (j < 0 || j >= nb || tile_of[j] != tj) return BILU_ERR_STATE;
+                            if (tj == t) {
+                                if (chunk_of[j] >= c) return BILU_ERR_STATE;
+                            } else {             // an earlier member, covered by the chunk's wait
+                                if (mj >= mt) return BILU_ERR_STATE;
+                                const int32_t need = s.chunk_wait[static_cast<size_t>(c) * kGroupMax + mj];
+                                if (need < chunk_of[j] - s.tile_chunk_ptr[tj] + 1) return BILU_ERR_STATE;
+                            }
+                        } else {                 // another group: byte offset of the row
                             if (code % row_bytes != 0) return BILU_ERR_STATE;
                             j = code / row_bytes;
-                            if (j >= nb || tile_of[j] >= t) return BILU_ERR_STATE;   // strictly earlier tile
+                            // a tile of a group with a smaller ticket
+                            if (j >= nb || tg.group(tile_of[j]) >= gt) return BILU_ERR_STATE;
                         }
                         if (forward ? j >= r : j <= r) return BILU_ERR_STATE;
                         const int32_t pi = h.Prow[e], pj = h.Pj[e];
@@ -750,7 +974,7 @@ int validate_layout(const Host& h)
         for (int i = 0; i < nb; ++i)
             if (seen[i] != ndep[i]) return BILU_ERR_STATE;
         if (!tiled_accesses_in_bounds(h, s, w)) return BILU_ERR_STATE;
-        if (w == BILU_SWEEP_U) {        // the order of the U' sweep fused with the SpMV
+        if (w == BILU_SWEEP_U && G == 1) {   // the order of the U' sweep fused with the SpMV
             std::vector<int32_t> sched;
             if (build_fused_schedule(h, s, sched) != BILU_OK) return BILU_ERR_STATE;
         }
@@ -760,6 +984,7 @@ int validate_layout(const Host& h)
 
 int build_fused_schedule(const Host& h, const HostTiled& u, std::vector<int32_t>& sched)
 {
+    if (u.group != 1) return BILU_ERR_STATE;      // tickets of single tiles only
     sched.clear();
     if (!u.built || u.which != BILU_SWEEP_U) return BILU_ERR_STATE;
     const int nb = h.nb;

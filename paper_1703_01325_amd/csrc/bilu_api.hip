@@ -40,7 +40,12 @@ struct bilu_ctx {
     bool split_done = false;
     int precision = BILU_FACTORS_FP64;
     int sweep_mode = 2;
-    int tile_rows = 0;          // 0: chosen by schedule simulation on first tiled use
+    int tile_rows = 0;          // rows per tile of the tiled layouts (0: not chosen yet)
+    int tile_group = 1;         // tiles per workgroup of the tiled layouts
+    int tile_rows_req = 0;      // requested rows per tile (0: by schedule simulation)
+    int tile_group_req = 0;     // requested tiles per group (0: by schedule simulation)
+    int64_t lds_max = 65536;    // LDS bytes a workgroup may use (the device's, once known)
+    int64_t layout_lds = 0;     // lds_max the tiled layouts were chosen for
     int blocks_override = 0;
     int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
     bool fuse_spmv = false;     // solvers run U' sweep + SpMV as one launch
@@ -205,15 +210,42 @@ bool launch_tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const Tiled
     }
 }
 
+// Tile groups: a.group wavefronts per workgroup.
+template <typename T, bool FUSE, int B, bool MULTI>
+bool launch_grouped_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+{
+    const dim3 threads(64 * a.group);
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 6, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 9, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+        }
+        return false;
+    }
+}
+
 template <typename T, bool FUSE>
 bool launch_tiled_b(int bs, int kmax, bool multi, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
 {
+    if (a.group > 1) {
+        if (a.group > kGroupMax) return false;
+        if (multi) {
+            BILU_SWITCH_B(bs, if (!(launch_grouped_k<T, FUSE, B, true>(kmax, blocks, lds, s, a))) return false)
+        }
+        BILU_SWITCH_B(bs, if (!(launch_grouped_k<T, FUSE, B, false>(kmax, blocks, lds, s, a))) return false)
+    }
     if (multi) {
         BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B, true>(kmax, blocks, lds, s, a))) return false)
     }
     BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B, false>(kmax, blocks, lds, s, a))) return false)
 }
 
+// One wavefront per tile (a.group == 1) or per member tile of a group.
 bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hipStream_t s,
                   const TiledArgs& a)
 {
@@ -274,6 +306,50 @@ bool launch_split(bilu_ctx* c, hipStream_t s)
                                               c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, c->d_F))
 }
 
+void free_form(bilu_ctx* c, int form);
+
+// Tile size and group size of the tiled layouts from the requests (0: the
+// host simulation's choice), for the device's LDS.
+void choose_layout(bilu_ctx* c)
+{
+    if (c->tile_rows_req > 0 && c->tile_group_req > 0) {
+        // both given: no simulation (a tile's rows stay within 64 KiB of LDS)
+        const int64_t cap = std::min<int64_t>(c->lds_max, 65536) / (8LL * c->h.bs) - 1;
+        c->tile_rows = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({c->tile_rows_req, c->h.nb, cap})));
+        c->tile_group = std::min(c->tile_group_req, kGroupMax);
+    } else {
+        const TileChoice best =
+            rank_tile_layouts(c->h, c->h.rpc, c->lds_max, c->tile_rows_req, c->tile_group_req).front();
+        c->tile_rows = std::max(1, std::min(best.tile_rows, c->h.nb));
+        c->tile_group = best.group;
+    }
+    c->layout_lds = c->lds_max;
+}
+
+// Group size the tiled layouts were built with (they fall back to smaller
+// groups where a larger one cannot be used).
+int built_group(const bilu_ctx* c)
+{
+    const HostTiled& ht = c->h.tiled[BILU_SWEEP_L];
+    return ht.built ? ht.group : c->tile_group;
+}
+
+// New layout requests: the tiled layouts are rebuilt (host) if the choice
+// changes, and uploaded again on their next use.
+bilu_status set_layout(bilu_ctx* c, int tile_rows_req, int tile_group_req)
+{
+    const int rows0 = c->tile_rows, group0 = c->tile_group;
+    c->tile_rows_req = tile_rows_req;
+    c->tile_group_req = tile_group_req;
+    choose_layout(c);
+    if (c->tile_rows == rows0 && c->tile_group == group0) return BILU_OK;
+    free_form(c, kFormTiled);
+    c->layouts_checked = false;
+    for (int w = 0; w < 4; ++w)
+        if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->tile_group, c->lds_max, c->h.tiled[w]);
+    return BILU_OK;
+}
+
 // ----- device setup --------------------------------------------------------
 bilu_status upload_form(bilu_ctx* c, int form)
 {
@@ -289,10 +365,10 @@ bilu_status upload_form(bilu_ctx* c, int form)
                 return st;
         } else {
             if (!h.sweep[w].built) continue;
-            if (c->tile_rows <= 0) c->tile_rows = choose_tile_rows(h, h.rpc, kMaxTileDoubles / h.bs - 1);
+            if (c->tile_rows <= 0 || c->layout_lds != c->lds_max) choose_layout(c);
             HostTiled& ht = h.tiled[w];
-            if (!ht.built || ht.tile_rows != c->tile_rows) {
-                build_tiled(h, w, h.rpc, c->tile_rows, ht);
+            if (!ht.built || ht.tile_rows != c->tile_rows || ht.group_req != c->tile_group) {
+                build_tiled(h, w, h.rpc, c->tile_rows, c->tile_group, c->lds_max, ht);
                 c->layouts_checked = false;
             }
             std::vector<int32_t> crow(ht.chunk_off.size());
@@ -303,7 +379,8 @@ bilu_status upload_form(bilu_ctx* c, int form)
             if ((st = upload(c, &d.chunk_off, ht.chunk_off)) || (st = upload(c, &d.rows, ht.rows)) ||
                 (st = upload(c, &d.cols, ht.deps)) || (st = upload(c, &d.src, ht.src)) ||
                 (st = upload(c, &d.tile_chunk_ptr, ht.tile_chunk_ptr)) || (st = upload(c, &d.tile_lo, ht.tile_lo)) ||
-                (st = upload(c, &d.chunk_row, crow)))
+                (st = upload(c, &d.chunk_row, crow)) || (st = upload(c, &d.group_tiles, ht.group_tiles)) ||
+                (st = upload(c, &d.chunk_wait, ht.chunk_wait)))
                 return st;
         }
         d.vals_precision = -1;
@@ -324,7 +401,7 @@ void free_form(bilu_ctx* c, int form)
         for (void* p : {static_cast<void*>(d.chunk_off), static_cast<void*>(d.rows), static_cast<void*>(d.cols),
                         static_cast<void*>(d.src), static_cast<void*>(d.tile_chunk_ptr),
                         static_cast<void*>(d.tile_lo), static_cast<void*>(d.chunk_row), static_cast<void*>(d.fused),
-                        d.vals, d.dinv})
+                        static_cast<void*>(d.group_tiles), static_cast<void*>(d.chunk_wait), d.vals, d.dinv})
             dfree(c, p);
         d = DevSweep{};
     }
@@ -342,6 +419,12 @@ bilu_status ensure_device(bilu_ctx* c)
     hipDeviceProp_t prop;
     CK(hipGetDeviceProperties(&prop, c->device));
     c->num_cu = prop.multiProcessorCount;
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
+            lds >= 65536)
+            c->lds_max = lds;
+    }
     Host& h = c->h;
     bilu_status st;
     const size_t bb = static_cast<size_t>(h.bs) * h.bs;
@@ -476,11 +559,19 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.ntiles = ht.ntiles;
         a.R = R;
         a.spin_limit = c->spin_limit;
-        const int blocks = persistent_blocks(c, ht.ntiles * R, 1, 8);
+        a.group = ht.group;
+        a.ngroups = ht.ngroups;
+        a.group_tiles = d.group_tiles;
+        a.chunk_wait = d.chunk_wait;
+        // tickets: tiles (or groups of tiles) times right-hand sides
+        const int blocks = ht.group > 1 ? persistent_blocks(c, ht.ngroups * R, 1, std::max(1, 8 / ht.group))
+                                        : persistent_blocks(c, ht.ntiles * R, 1, 8);
         a.total_waves = static_cast<unsigned int>(blocks);
         a.tile_rows = ht.tile_rows;
-        // the tile's rows plus one row kept at zero (padding slots read it)
-        const size_t lds = static_cast<size_t>(ht.tile_rows + 1) * c->h.bs * sizeof(double);
+        // the member tiles' rows, one row kept at zero (padding slots read
+        // it) and the members' progress counts
+        const size_t lds = static_cast<size_t>(tiled_lds_bytes(ht.tile_rows, ht.group, c->h.bs));
+        if (static_cast<int64_t>(lds) > c->lds_max) return BILU_ERR_STATE;
         if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
         const HostSweep& hs = c->h.sweep[which];
@@ -583,6 +674,10 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
     if (!c->split_done) return BILU_ERR_STATE;
     bilu_status st;
     if ((st = layout_form(c, kFormTiled, s))) return st;
+    if (c->h.tiled[BILU_SWEEP_U].group > 1) {      // the fused ticket order is for single tiles
+        st = do_apply(c, r, z, R, false, s);
+        return st ? st : do_spmv(c, Ax, z, y, R, 0, s);
+    }
     if ((st = ensure_y(c, 1, s))) return st;
     HostTiled& hu = c->h.tiled[BILU_SWEEP_U];
     DevSweep& du = c->ds[kFormTiled][BILU_SWEEP_U];
@@ -700,6 +795,7 @@ bilu_status bilu_get_info(const bilu_ctx* c, bilu_info* info)
         }
     info->rows_per_chunk = h.rpc;
     info->tile_rows = c->tile_rows;
+    info->tile_group = built_group(c);
     for (int w = 0; w < 4; ++w) {
         info->nlev[w] = h.sweep[w].built ? h.sweep[w].nlev : 0;
         info->sweep_slots[w] = h.sweep[w].built ? h.sweep[w].nslots : 0;
@@ -840,19 +936,12 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (value < 0 || value > 2) return BILU_ERR_ARG;
         c->sweep_mode = value;
         return BILU_OK;
-    case BILU_TUNE_TILE_ROWS: {
+    case BILU_TUNE_TILE_ROWS:
         if (value < 0) return BILU_ERR_ARG;
-        int rows = value == 0 ? choose_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs - 1)
-                              : std::min(value, kMaxTileDoubles / c->h.bs - 1);
-        rows = std::max(1, std::min(rows, c->h.nb));
-        if (rows == c->tile_rows) return BILU_OK;
-        c->tile_rows = rows;
-        free_form(c, kFormTiled);
-        c->layouts_checked = false;
-        for (int w = 0; w < 4; ++w)
-            if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->h.tiled[w]);
-        return BILU_OK;
-    }
+        return set_layout(c, value, c->tile_group_req);
+    case BILU_TUNE_TILE_GROUP:
+        if (value < 0 || value > kGroupMax) return BILU_ERR_ARG;
+        return set_layout(c, c->tile_rows_req, value);
     case BILU_TUNE_BLOCKS:
         if (value < 0 || value > (1 << 20)) return BILU_ERR_ARG;
         c->blocks_override = value;
@@ -906,18 +995,30 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
     if (!c || !out || nrhs < 1 || nrhs > dev::kMaxRhs) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
     std::memset(out, 0, sizeof(*out));
+    // tile_rows / group: the layout requests (0: by schedule simulation)
     struct Cand {
-        int mode, tile_rows, rhs_tile;
+        int mode, tile_rows, group, rhs_tile;
     };
     std::vector<Cand> cands;
-    const Cand before{c->sweep_mode, c->tile_rows, c->rhs_tile};
+    const Cand before{c->sweep_mode, c->tile_rows_req, c->tile_group_req, c->rhs_tile};
     if (nrhs == 1) {
-        const auto ranked = rank_tile_rows(c->h, c->h.rpc, kMaxTileDoubles / c->h.bs - 1);
-        for (size_t i = 0; i < ranked.size() && i < 4; ++i) cands.push_back({2, ranked[i].second, 0});
-        cands.push_back({1, c->tile_rows, 0});
+        // the preferred layouts, every group size of the best tile size, and
+        // the next single-tile sizes
+        auto add = [&](int rows, int group) {
+            for (const Cand& k : cands)
+                if (k.mode == 2 && k.tile_rows == rows && k.group == group) return;
+            cands.push_back({2, rows, group, 0});
+        };
+        const auto ranked = rank_tile_layouts(c->h, c->h.rpc, c->lds_max, 0, 0);
+        for (size_t i = 0; i < ranked.size() && i < 4; ++i) add(ranked[i].tile_rows, ranked[i].group);
+        const int best_rows = ranked.front().tile_rows;
+        for (int g = 1; g <= kGroupMax; ++g)
+            if (tiled_lds_bytes(best_rows, g, c->h.bs) <= c->lds_max) add(best_rows, g);
+        cands.push_back({1, before.tile_rows, before.group, 0});
     } else {
-        cands.push_back({2, 0, 0});
-        for (int rt : {1, 4, 8}) cands.push_back({1, c->tile_rows, rt});
+        cands.push_back({2, 0, 0, 0});
+        cands.push_back({2, 0, 1, 0});
+        for (int rt : {1, 4, 8}) cands.push_back({1, before.tile_rows, before.group, rt});
     }
     const size_t n = static_cast<size_t>(c->h.nb) * c->h.bs * nrhs;
     double* r = nullptr;
@@ -933,9 +1034,7 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
         bilu_status e;
         if ((e = bilu_tune(c, BILU_TUNE_SWEEP_MODE, k.mode)) || (e = bilu_tune(c, BILU_TUNE_RHS_TILE, k.rhs_tile)))
             return e;
-        // tile_rows 0 restores the simulated choice
-        if (k.mode == 2) return bilu_tune(c, BILU_TUNE_TILE_ROWS, k.tile_rows);
-        return BILU_OK;
+        return k.mode == 2 ? set_layout(c, k.tile_rows, k.group) : BILU_OK;
     };
     double best_us = 1e300;
     Cand best = before;
@@ -962,6 +1061,7 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
     if (st2) return st2;
     out->sweep_mode = c->sweep_mode;
     out->tile_rows = c->tile_rows;
+    out->tile_group = built_group(c);
     out->rhs_tile = rhs_tile(c, nrhs);
     out->apply_us = best_us;
     out->default_us = ref_us;

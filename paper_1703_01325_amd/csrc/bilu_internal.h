@@ -2,6 +2,7 @@
 // side (bilu_api.hip).  Not part of the ABI.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <utility>
 #include <vector>
@@ -61,7 +62,47 @@ struct HostTiled {
     // U' sweep fused with y = A x on its output (built on demand): ticket
     // order of tiles (>= 0) and SpMV blocks of rpc rows (-(1 + block))
     std::vector<int32_t> fused;
+    // Tile groups (group > 1): the member tiles of a group run as the
+    // wavefronts of one workgroup and share its LDS (TileGroups).  Codes of
+    // rows in any member tile are local; chunk_wait[c*kGroupMax + m] is the
+    // number of chunks member m must have finished before chunk c reads LDS.
+    int group = 1;
+    int group_req = 1;                     // the group size asked of build_tiled
+    int gstride = 1;
+    int ngroups = 0;
+    std::vector<int32_t> group_tiles;      // [ngroups*group], -1 past the last tile
+    std::vector<int32_t> chunk_wait;       // [nchunks*kGroupMax], group > 1 only
 };
+
+constexpr int kGroupMax = 4;
+
+// Tiles in sweep order, cut into blocks of G*D consecutive tiles; inside a
+// block, tiles t0 + m*D (m = 0..G-1) form one group (member m).  On a grid
+// whose planes hold D tiles, a group is a stack of G tiles in consecutive
+// planes.  Groups are numbered block by block; only the last block can hold
+// groups without member 0, and those are dropped, so 0..count()-1 are used.
+struct TileGroups {
+    int G = 1, D = 1, ntiles = 0;
+    int member(int t) const { return (t % (G * D)) / D; }
+    int group(int t) const { return (t / (G * D)) * D + (t % (G * D)) % D; }
+    int tile(int g, int m) const
+    {
+        const int t = (g / D) * G * D + m * D + g % D;
+        return t < ntiles ? t : -1;
+    }
+    int count() const
+    {
+        const int full = ntiles / (G * D);
+        return full * D + std::min(D, ntiles - full * G * D);
+    }
+};
+
+// LDS bytes of one workgroup of the tiled sweep: the member tiles' rows, the
+// zero row, and (grouped) the members' progress counters.
+inline int64_t tiled_lds_bytes(int tile_rows, int group, int bs)
+{
+    return (static_cast<int64_t>(group) * tile_rows + 1) * bs * 8 + (group > 1 ? kGroupMax * 4 : 0);
+}
 
 // Dependency slots per row that the tiled sweep kernel loads ahead into
 // registers, from the widest chunk of the layout; wider rows finish their
@@ -93,6 +134,8 @@ struct DevSweep {
     int32_t* tile_lo = nullptr;
     int32_t* chunk_row = nullptr;  // tiled form: chunk_off / rpc (first slot row)
     int32_t* fused = nullptr;      // tiled U' form: fused sweep + SpMV ticket order
+    int32_t* group_tiles = nullptr;  // tiled form: member tiles of each group
+    int32_t* chunk_wait = nullptr;   // tiled form, grouped: waits of each chunk
     void* vals = nullptr;     // [nslots * bs*bs] FP64 or FP32, layout [k][c][r][q]
     void* dinv = nullptr;     // [nchunks*rpc * bs*bs] same layout, fused sweeps only
     int vals_precision = -1;  // precision the values were laid out in (-1: none)
@@ -123,14 +166,30 @@ int sweep_levels(int nb, const std::vector<int32_t>& Pp, const std::vector<int32
                  int which, std::vector<int32_t>& lvl);
 void build_sweep(const Host& h, int which, int rpc, HostSweep& out);
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags);
-void build_tiled(const Host& h, int which, int rpc, int tile_rows, HostTiled& out);
+// Tiled layout of one sweep with tiles of tile_rows rows in groups of up to
+// `group` tiles (falls back to smaller groups, down to 1, where a grouping
+// would break the ticket order or the group's LDS exceeds lds_limit bytes).
+void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, int64_t lds_limit, HostTiled& out);
 // Predicted duration (in units of `step`) of a tiled sweep with the given
-// tile size (forward sweeps may be restricted to their first row_limit rows;
-// 0 = all), and the tile size with the smallest prediction.
-double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, double hop_in_steps, int row_limit);
+// tile size and group size (forward sweeps may be restricted to their first
+// row_limit rows; 0 = all); +inf where the grouping is not usable.
+double simulate_tiled(const Host& h, int which, int rpc, int tile_rows, int group, double hop_in_steps,
+                      int row_limit);
 int choose_tile_rows(const Host& h, int rpc, int max_rows);
-// Every candidate tile size with its predicted duration, best first.
+// Every candidate tile size with its predicted duration, best first (one
+// wavefront per tile).
 std::vector<std::pair<double, int>> rank_tile_rows(const Host& h, int rpc, int max_rows);
+struct TileChoice {
+    double t;
+    int tile_rows;
+    int group;
+};
+// Layout choices, preferred first: groups of the tile size with the shortest
+// simulated single-tile schedule (the usable ones, whose workgroup LDS fits in
+// lds_limit bytes, in a fixed order of group sizes), then every candidate
+// tile size with one wavefront per tile, by simulated duration.  tile_req > 0
+// fixes the tile size; group_req 1 leaves groups out, > 1 asks for that size.
+std::vector<TileChoice> rank_tile_layouts(const Host& h, int rpc, int64_t lds_limit, int tile_req, int group_req);
 int validate_layout(const Host& h);
 // Ticket order of the backward U' tiled sweep fused with the SpMV on its
 // output: all tiles, then each block of rpc rows of A, ordered by the tile

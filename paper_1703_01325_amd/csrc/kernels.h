@@ -351,10 +351,17 @@ struct TiledArgs {
     unsigned int* done;
     int* status;
     int ntiles;
-    int tile_rows;                // LDS row tile_rows is kept at zero
+    int tile_rows;                // LDS row group*tile_rows is kept at zero
     int R;                        // right-hand sides (vectors are (n x R) row-major)
-    unsigned int total_waves;
+    unsigned int total_waves;     // grouped: workgroups
     unsigned int spin_limit;
+    // tile groups (k_sweep_grouped): member m of group g sweeps
+    // group_tiles[g*group + m]; chunk_wait[c*kGroupMax + m] chunks of member m
+    // must be finished before chunk c reads the group's LDS
+    const int32_t* group_tiles;
+    const int32_t* chunk_wait;
+    int group;
+    int ngroups;
 };
 
 // Byte offset of component c of a block row (row_byte = row * B * 8) in the
@@ -488,10 +495,37 @@ __device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)
     }
 }
 
-template <int B, typename T, int KMAX, bool FUSE, bool MULTI>
+// Tile groups: waits (bounded) until each earlier member of the workgroup has
+// finished the chunks this chunk reads from it.  A member publishes its count
+// of finished chunks in LDS after the chunk's rows; the LDS operations of one
+// wavefront take effect in issue order, so a count that is seen covers every
+// row written before it.
+__device__ __forceinline__ void await_members(const int* prog, const int (&need)[kGroupMax], unsigned int limit,
+                                              int* status)
+{
+    for (unsigned int spins = 0;;) {
+        bool behind = false;
+#pragma unroll
+        for (int m = 0; m < kGroupMax; ++m)
+            behind |= __hip_atomic_load(prog + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need[m];
+        if (!behind) break;
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    // the row reads that follow stay after the counts
+    asm volatile("" ::: "memory");
+}
+
+// lds: the workgroup's LDS (dependency codes are offsets into it);
+// tile_vals: this tile's rows in it.
+template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool GROUPED>
 __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
-                                             double* tile_vals, const TileData<B, T, KMAX, FUSE>& s,
-                                             const ColMap<MULTI>& cm)
+                                             const double* lds_base, double* tile_vals,
+                                             const TileData<B, T, KMAX, FUSE>& s, const int (&need)[kGroupMax],
+                                             const int* prog, const ColMap<MULTI>& cm)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
@@ -514,6 +548,7 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
 #pragma unroll
         for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
     await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
+    if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
     if (!active || s.row < 0) return;
     double acc;
     if (FUSE) {
@@ -528,7 +563,7 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     // to an empty asm statement once all are issued, so the compiler keeps
     // the reads unconditional (instead of turning each select into a branch
     // around its read) and waits for them once.
-    const char* lds = reinterpret_cast<const char*>(tile_vals);
+    const char* lds = reinterpret_cast<const char*>(lds_base);
     double lv[KMAX * B];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
@@ -585,8 +620,9 @@ struct TiledRing {
 
 // One tile of a tiled sweep by one wavefront (column cm of the vectors).
 // tile_vals: the wavefront's LDS, row a.tile_rows already zero.
-template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
-__device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap<MULTI>& cm, double* tile_vals)
+template <int B, typename T, bool FUSE, int KMAX, bool MULTI, bool GROUPED>
+__device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap<MULTI>& cm, const double* lds_base,
+                                         double* tile_vals, int* prog, int member)
 {
     constexpr int RPC = 64 / B;
     constexpr int NR = TiledRing<B, T, FUSE, KMAX>::value;   // register states in flight
@@ -599,6 +635,7 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
     const int qc = lane_ok ? q : RPC - 1;
     TileMeta<KMAX> mr[NR];
     TileData<B, T, KMAX, FUSE> dr[NR];
+    int wr[NR][kGroupMax];                                   // grouped: the chunks' waits
     const int lo = uniform_load(a.tile_lo, t);
     const int c0 = uniform_load(a.tile_chunk_ptr, t);
     const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
@@ -610,6 +647,11 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
         const int sr = uniform_load(a.chunk_row, ch);
         tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
     };
+    // waits of chunk i, read with its data (scalar loads)
+    auto wait_at = [&](int i, int (&w)[kGroupMax]) {
+#pragma unroll
+        for (int m = 0; m < kGroupMax; ++m) w[m] = GROUPED ? uniform_load(a.chunk_wait, chunk_at(i) * kGroupMax + m) : 0;
+    };
     // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
     // metadata of LD..LM-1 issued as their slots free up
 #pragma unroll
@@ -617,6 +659,7 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
 #pragma unroll
     for (int i = 0; i < LD; ++i) {
         tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
+        wait_at(i, wr[i % NR]);
         if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
     }
     // slot row range of the next chunk whose metadata is due, read a step
@@ -633,12 +676,16 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
             pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
             pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
             tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
-            tile_compute<B, T, KMAX, FUSE, MULTI>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p], cm);
+            wait_at(i + LD, wr[(p + LD) % NR]);
+            tile_compute<B, T, KMAX, FUSE, MULTI, GROUPED>(a, lo, qc, r, lane_ok && i < nch, lds_base, tile_vals,
+                                                           dr[p], wr[p], prog, cm);
             // one wavefront: its LDS accesses complete in issue order, so
             // only the compiler must keep this chunk's writes before the
-            // next chunk's reads
+            // next chunk's reads (and before the progress count)
             __builtin_amdgcn_wave_barrier();
             asm volatile("" ::: "memory");
+            if (GROUPED && i < nch && lane == 0)
+                __hip_atomic_store(prog + member, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
 }
@@ -659,9 +706,52 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
         ColMap<MULTI> cm;
         cm.R = static_cast<uint32_t>(a.R);
         cm.j8 = MULTI ? static_cast<uint32_t>(tk - t * a.R) * 8u : 0u;
-        run_tile<B, T, FUSE, KMAX, MULTI>(a, t, cm, tile_vals);
+        run_tile<B, T, FUSE, KMAX, MULTI, false>(a, t, cm, tile_vals, tile_vals, nullptr, 0);
     }
     finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
+// Tile groups: one workgroup of a.group wavefronts per ticket (a group, or
+// with MULTI a (group, column) pair); member m sweeps the group's m-th tile
+// into its part of the shared LDS and reads rows of earlier members there
+// once their progress counts cover them.  Tickets run in group order, and
+// every row a group reads from outside lies in a group with a smaller
+// ticket, so the persistent launch drains.
+template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
+__global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
+{
+    extern __shared__ double group_vals[];   // [group*tile_rows + 1][B], then kGroupMax progress counts
+    __shared__ int s_ticket;
+    const int G = a.group;
+    // wave-uniform (the compiler cannot see that on its own): the member's
+    // tile and chunk indices then stay scalar
+    const int member = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int zrow = G * a.tile_rows;
+    int* prog = reinterpret_cast<int*>(group_vals + static_cast<int64_t>(zrow + 1) * B);
+    if (static_cast<int>(threadIdx.x) < B) group_vals[zrow * B + threadIdx.x] = 0.0;
+    const int nticket = MULTI ? a.ngroups * a.R : a.ngroups;
+    for (;;) {
+        // the previous group is finished by every member (barrier below)
+        if (threadIdx.x < kGroupMax) prog[threadIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            const unsigned long long tk = atomicAdd(a.ticket, 1ULL);
+            s_ticket = tk > 0x3fffffffULL ? 0x3fffffff : static_cast<int>(tk);
+        }
+        __syncthreads();
+        const int tk = __builtin_amdgcn_readfirstlane(s_ticket);
+        if (tk >= nticket) break;
+        const int g = MULTI ? tk / a.R : tk;
+        const int t = member < G ? uniform_load(a.group_tiles, g * G + member) : -1;
+        ColMap<MULTI> cm;
+        cm.R = static_cast<uint32_t>(a.R);
+        cm.j8 = MULTI ? static_cast<uint32_t>(tk - g * a.R) * 8u : 0u;
+        if (t >= 0)
+            run_tile<B, T, FUSE, KMAX, MULTI, true>(a, t, cm, group_vals,
+                                                    group_vals + static_cast<int64_t>(member) * a.tile_rows * B, prog,
+                                                    member);
+        __syncthreads();
+    }
+    if (member == 0) finish_persistent(a.ticket, a.done, a.total_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,7 +826,7 @@ __global__ __launch_bounds__(64) void k_sweep_tiled_spmv(TiledArgs a, FusedSpmvA
             ColMap<false> cm;
             cm.R = 1;
             cm.j8 = 0;
-            run_tile<B, T, true, KMAX, false>(a, it, cm, tile_vals);
+            run_tile<B, T, true, KMAX, false, false>(a, it, cm, tile_vals, tile_vals, nullptr, 0);
         } else {
             spmv_block_ready<B>(m, static_cast<int64_t>(-1 - it) * (64 / B), a.out, a.spin_limit, a.status);
         }

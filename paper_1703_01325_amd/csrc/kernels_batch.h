@@ -117,7 +117,7 @@ __device__ __forceinline__ void batch_tile(const BatchSweepArgs& a, const BatchT
     ColMap<false> cm;
     cm.R = 1;
     cm.j8 = 0;
-    run_tile<B, T, FUSE, KMAX, false>(t, tile, cm, tile_vals);
+    run_tile<B, T, FUSE, KMAX, false, false>(t, tile, cm, tile_vals, tile_vals, nullptr, 0);
 }
 
 template <typename T, bool FUSE>

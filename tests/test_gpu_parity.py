@@ -410,7 +410,7 @@ def test_fused_sweep_spmv_identical(api, oracle_mod, name, make, k):
     b = cuda(c.rhs)
     M.tune(fuse_spmv=False)
     x0, st0, info0 = M.solve(c.Ax, b, rtol=1e-10)
-    M.tune(fuse_spmv=True)
+    M.tune(fuse_spmv=True, tile_group=1)      # the fused order takes single tiles
     M.timing(True)
     x1, st1, info1 = M.solve(c.Ax, b, rtol=1e-10)
     t = M.timing_read()
@@ -423,3 +423,65 @@ def test_fused_sweep_spmv_identical(api, oracle_mod, name, make, k):
     assert torch.equal(g0, g1)
     M.check()
     M.tune(fuse_spmv=False)
+
+
+# ---------------------------------------------------------------------------
+# tile groups: several tiles per workgroup, rows handed over through LDS
+# ---------------------------------------------------------------------------
+GROUPED = [
+    ("cube10_k0_t25", lambda: synth.small_10cube(), 0, 25),          # 4 tiles per plane
+    ("cube10_k0_t50", lambda: synth.small_10cube(), 0, 50),          # 2 tiles per plane
+    ("cube10_k0_t100", lambda: synth.small_10cube(), 0, 100),        # whole planes
+    ("cube10_k0_t30", lambda: synth.small_10cube(), 0, 30),          # tiles across planes
+    ("grid_b1_k0", lambda: synth.reservoir(8, 6, 10, 1, seed=81), 0, 24),
+    ("grid_b5_k0", lambda: synth.reservoir(8, 6, 10, 5, seed=82), 0, 16),
+    ("grid_b8_k0", lambda: synth.reservoir(8, 6, 10, 8, seed=83), 0, 48),
+    ("cube10_k1_t25", lambda: synth.small_10cube(), 1, 25),          # falls back where needed
+]
+
+
+@pytest.mark.parametrize("group", [2, 3, 4])
+@pytest.mark.parametrize("name,make,k,tile", GROUPED, ids=[g[0] for g in GROUPED])
+def test_grouped_tiles_parity(api, oracle_mod, name, make, k, tile, group):
+    """Grouped row tiles compute every row with the arithmetic of the single
+    tiles, so applications agree bit for bit with the ungrouped layout (one
+    and several right-hand sides, transposed too) and with the oracle to
+    1e-12."""
+    c = Case(oracle_mod, make(), k)
+    M = c.gpu(api, transpose=True, tile_rows=tile)
+    rng = np.random.default_rng(17)
+    r = cuda(rng.standard_normal(c.s.n))
+    B = cuda(rng.standard_normal((c.s.n, 3)))
+    M.tune(tile_group=1)
+    z1, zt1, Z1 = M.apply(r), M.apply(r, transpose=True), M.apply(B)
+    M.tune(tile_group=group)
+    used = M.info().tile_group
+    assert 1 <= used <= group
+    if k == 0 and tile in (25, 50, 16, 24, 48):
+        assert used == group                  # tiles stacked over consecutive planes
+    for _ in range(2):
+        z, zt, Z = M.apply(r), M.apply(r, transpose=True), M.apply(B)
+        assert torch.equal(z, z1) and torch.equal(zt, zt1) and torch.equal(Z, Z1)
+    assert rel(z.cpu().numpy(), c.O.apply(r.cpu().numpy())) <= 1e-12
+    assert rel(zt.cpu().numpy(), c.O.apply(r.cpu().numpy(), transpose=True)) <= 1e-12
+    M.check()
+
+
+def test_grouped_tiles_fp32_and_solve(api, oracle_mod):
+    """FP32 factors on grouped tiles (same rows as ungrouped, bit for bit),
+    and a solve with grouped tiles matches the oracle's."""
+    c = Case(oracle_mod, synth.small_10cube(), 0)
+    M = c.gpu(api, precision="fp32", tile_rows=25)
+    r = cuda(np.random.default_rng(5).standard_normal(c.s.n))
+    M.tune(tile_group=1)
+    z1 = M.apply(r)
+    M.tune(tile_group=4)
+    assert M.info().tile_group == 4
+    assert torch.equal(M.apply(r), z1)
+    M2 = c.gpu(api, tile_rows=25)
+    M2.tune(tile_group=4)
+    x, st, info = M2.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
+    xo, ito, rro, sto = c.O.solve(c.s.Ax, c.rhs, rtol=1e-8)
+    assert st == 0 and sto == 0 and abs(info[0][1] - ito) <= 1 and info[0][2] <= 1e-8
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-10
+    M2.check()

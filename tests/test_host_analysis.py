@@ -142,6 +142,30 @@ def test_tiled_layouts_validate(N, tile_rows):
         N.bilu_destroy(ctx)
 
 
+@pytest.mark.parametrize("group", [0, 2, 3, 4])
+@pytest.mark.parametrize("tile_rows", [0, 5, 16, 24, 40, 333])
+def test_grouped_tiled_layouts_validate(N, tile_rows, group):
+    """Tile groups pass the host self-check (codes into the group's LDS,
+    waits covering every row read from an earlier member, ticket order of
+    the groups) for every sweep, ragged tile counts included; on an ILU(0)
+    grid whose planes hold whole tiles the requested group is used."""
+    for grid, k in (((8, 6, 10), 0), ((8, 6, 10), 1), ((7, 5, 4), 2), ((5, 9, 11), 0)):
+        Ap, Aj = synth.stencil7_pattern(*grid)
+        nb = int(np.prod(grid))
+        ctx = N.bilu_analyze(nb, 3, Ap, Aj, k, N.WANT_TRANSPOSE)
+        try:
+            N.bilu_tune(ctx, N.TUNE_TILE_GROUP, group)
+            N.bilu_tune(ctx, N.TUNE_TILE_ROWS, tile_rows)
+            N.bilu_validate(ctx)
+            info = N.bilu_get_info(ctx)
+            assert 1 <= info.tile_group <= 4
+            if group and k == 0 and grid == (8, 6, 10) and tile_rows in (16, 24):
+                # 48-row planes of 3 or 2 tiles: stacks of `group` planes
+                assert info.tile_group == group
+        finally:
+            N.bilu_destroy(ctx)
+
+
 def test_batch_create_host(N):
     """Batch creation is host analysis only: offsets are the members' unknown
     counts laid end to end, members keep their own bit-exact analysis, and a
