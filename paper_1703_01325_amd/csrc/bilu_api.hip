@@ -1150,7 +1150,7 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, p, 0.0);
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, v, 0.0);
     hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, b, part, dev::SL_BB);
-    hipLaunchKernelGGL(dev::k_bicg_init, dim3(1), dim3(64), 0, s, R, part, S, o->rtol);
+    hipLaunchKernelGGL(dev::k_bicg_init, dim3(R), dim3(64), 0, s, R, part, S, o->rtol);
     CK(hipGetLastError());
 
     KState hs;
@@ -1164,20 +1164,20 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     while (any_active && it < o->maxit) {
         ++it;
         hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, r, part, dev::SL_RHO);
-        hipLaunchKernelGGL(dev::k_bicg_s_rho, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_s_rho, dim3(R), dim3(64), 0, s, R, part, S);
         hipLaunchKernelGGL(dev::k_bicg_p, dim3(eg), dim3(256), 0, s, n, R, r, v, p, S);
         if ((st = do_apply_spmv(c, Ax, p, ph, v, R, tr != 0, s))) return st;
         hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, v, part, dev::SL_RV);
-        hipLaunchKernelGGL(dev::k_bicg_s_alpha, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_s_alpha, dim3(R), dim3(64), 0, s, R, part, S);
         hipLaunchKernelGGL(dev::k_bicg_s, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, r, v, sv, S, part);
-        hipLaunchKernelGGL(dev::k_bicg_s_snorm, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_s_snorm, dim3(R), dim3(64), 0, s, R, part, S);
         if ((st = do_apply_spmv(c, Ax, sv, sh, t, R, tr != 0, s))) return st;
         hipLaunchKernelGGL(dev::k_dot2, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, t, sv, part,
                            dev::SL_TS, dev::SL_TT);
-        hipLaunchKernelGGL(dev::k_bicg_s_omega, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_s_omega, dim3(R), dim3(64), 0, s, R, part, S);
         hipLaunchKernelGGL(dev::k_bicg_xr, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, x, r, ph, sh, sv, t,
                            S, part);
-        hipLaunchKernelGGL(dev::k_bicg_s_end, dim3(1), dim3(64), 0, s, R, part, S);
+        hipLaunchKernelGGL(dev::k_bicg_s_end, dim3(R), dim3(64), 0, s, R, part, S);
         CK(hipGetLastError());
         CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
@@ -1195,7 +1195,7 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
             if ((st = spmv(x, w))) return st;
             hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part,
                                dev::SL_TRUE);
-            hipLaunchKernelGGL(dev::k_s_true, dim3(1), dim3(64), 0, s, R, part, S);
+            hipLaunchKernelGGL(dev::k_s_true, dim3(R), dim3(64), 0, s, R, part, S);
             CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
             CK(hipStreamSynchronize(s));
             bool restart = false;
@@ -1225,7 +1225,7 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     // final true residuals for every column
     if ((st = spmv(x, w))) return st;
     hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part, dev::SL_TRUE);
-    hipLaunchKernelGGL(dev::k_s_true, dim3(1), dim3(64), 0, s, R, part, S);
+    hipLaunchKernelGGL(dev::k_s_true, dim3(R), dim3(64), 0, s, R, part, S);
     CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
     int sweep_err = 0;
     CK(hipMemcpyAsync(&sweep_err, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -610,12 +610,16 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
 }
 
 // Ring depth: three register states where they fit in half the register
-// file (two wavefronts per SIMD), else two.
-template <int B, typename T, bool FUSE, int KMAX>
+// file (two wavefronts per SIMD), else two.  Tile groups take two: measured on
+// MI355X, the member wavefronts of a group (one compute unit, all near the
+// sweep front) run their sweeps faster with fewer loads in flight (60x220x85
+// ILU(0), groups of 3: U' sweep 528 -> 497 us), while a wavefront on its own
+// gains from the deeper ring.
+template <int B, typename T, bool FUSE, int KMAX, bool GROUPED>
 struct TiledRing {
     static constexpr int w = sizeof(T) == 8 ? 2 : 1;
     static constexpr int state = KMAX * B * (2 + w) + KMAX + (FUSE ? B * (2 + w) : 2) + 4 + KMAX + 3;
-    static constexpr int value = 3 * state + 40 <= 240 ? 3 : 2;
+    static constexpr int value = !GROUPED && 3 * state + 40 <= 240 ? 3 : 2;
 };
 
 // One tile of a tiled sweep by one wavefront (column cm of the vectors).
@@ -625,7 +629,7 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
                                          double* tile_vals, int* prog, int member)
 {
     constexpr int RPC = 64 / B;
-    constexpr int NR = TiledRing<B, T, FUSE, KMAX>::value;   // register states in flight
+    constexpr int NR = TiledRing<B, T, FUSE, KMAX, GROUPED>::value;   // register states in flight
     constexpr int LD = NR - 1;                               // data lookahead
     constexpr int LM = 2 * LD;                               // metadata lookahead
     const int lane = lane_id();
@@ -1274,13 +1278,22 @@ __global__ __launch_bounds__(kThreads) void k_dot2(int64_t n, int R, const doubl
     block_partial(tt, R, slot_ptr(part, slot_tt));
 }
 
+// Sum of the kRedBlocks partials of (slot, col), by one whole wavefront in a
+// fixed order (lane l adds partials l, l+64, ... in turn, then a fixed
+// butterfly over the lanes); lane 0's value, so every call on the same
+// partials gives the same bits.
 __device__ __forceinline__ double sum_partials(const double* part, int slot, int col)
 {
+    static_assert(kRedBlocks % 64 == 0, "partials per lane");
     const double* p = part + static_cast<int64_t>(slot) * kMaxRhs * kRedBlocks +
                       static_cast<int64_t>(col) * kRedBlocks;
+    const int lane = lane_id();
     double s = 0.0;
-    for (int k = 0; k < kRedBlocks; ++k) s += p[k];
-    return s;
+#pragma unroll
+    for (int k = 0; k < kRedBlocks / 64; ++k) s += p[lane + 64 * k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    return __shfl(s, 0);
 }
 
 enum { SL_RHO = 0, SL_RV = 1, SL_SS = 2, SL_TS = 3, SL_TT = 4, SL_RR = 5, SL_BB = 6, SL_TRUE = 7 };
@@ -1371,18 +1384,23 @@ __device__ __forceinline__ void bicg_end_one(S& st, int c, double r2)
 
 // BiCGSTAB setup: ||b||, tolerance, flags.  r = b, r^ = r, x = 0 are done
 // by copies on the host side.
-__global__ void k_bicg_init(int R, const double* part, KState* st, double rtol)
+// Scalar kernels: one wavefront (workgroup) per right-hand side c.
+__global__ __launch_bounds__(64) void k_bicg_init(int R, const double* part, KState* st, double rtol)
 {
-    const int c = threadIdx.x;
+    const int c = blockIdx.x;
     if (c >= R) return;
-    bicg_init_one(*st, c, sum_partials(part, SL_BB, c), rtol);
+    const double b2 = sum_partials(part, SL_BB, c);
+    if (lane_id() != 0) return;
+    bicg_init_one(*st, c, b2, rtol);
     if (c == 0) st->sweep_status = 0;
 }
 
-__global__ void k_bicg_s_rho(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_bicg_s_rho(int R, const double* part, KState* st)
 {
-    const int c = threadIdx.x;
-    if (c < R) bicg_rho_one(*st, c, sum_partials(part, SL_RHO, c));
+    const int c = blockIdx.x;
+    if (c >= R) return;
+    const double v = sum_partials(part, SL_RHO, c);
+    if (lane_id() == 0) bicg_rho_one(*st, c, v);
 }
 
 __global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const double* __restrict__ v,
@@ -1396,10 +1414,12 @@ __global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const d
     }
 }
 
-__global__ void k_bicg_s_alpha(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_bicg_s_alpha(int R, const double* part, KState* st)
 {
-    const int c = threadIdx.x;
-    if (c < R) bicg_alpha_one(*st, c, sum_partials(part, SL_RV, c));
+    const int c = blockIdx.x;
+    if (c >= R) return;
+    const double v = sum_partials(part, SL_RV, c);
+    if (lane_id() == 0) bicg_alpha_one(*st, c, v);
 }
 
 // s = r - alpha v, partial of s.s
@@ -1420,16 +1440,21 @@ __global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t n, int R, const dou
     block_partial(acc, R, slot_ptr(part, SL_SS));
 }
 
-__global__ void k_bicg_s_snorm(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_bicg_s_snorm(int R, const double* part, KState* st)
 {
-    const int c = threadIdx.x;
-    if (c < R) bicg_snorm_one(*st, c, sum_partials(part, SL_SS, c));
+    const int c = blockIdx.x;
+    if (c >= R) return;
+    const double v = sum_partials(part, SL_SS, c);
+    if (lane_id() == 0) bicg_snorm_one(*st, c, v);
 }
 
-__global__ void k_bicg_s_omega(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_bicg_s_omega(int R, const double* part, KState* st)
 {
-    const int c = threadIdx.x;
-    if (c < R) bicg_omega_one(*st, c, sum_partials(part, SL_TS, c), sum_partials(part, SL_TT, c));
+    const int c = blockIdx.x;
+    if (c >= R) return;
+    const double ts = sum_partials(part, SL_TS, c);
+    const double tt = sum_partials(part, SL_TT, c);
+    if (lane_id() == 0) bicg_omega_one(*st, c, ts, tt);
 }
 
 // x += alpha p^ (+ omega s^ unless the half step already converged),
@@ -1462,10 +1487,12 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t n, int R, double* 
     block_partial(acc, R, slot_ptr(part, SL_RR));
 }
 
-__global__ void k_bicg_s_end(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_bicg_s_end(int R, const double* part, KState* st)
 {
-    const int c = threadIdx.x;
-    if (c < R) bicg_end_one(*st, c, sum_partials(part, SL_RR, c));
+    const int c = blockIdx.x;
+    if (c >= R) return;
+    const double v = sum_partials(part, SL_RR, c);
+    if (lane_id() == 0) bicg_end_one(*st, c, v);
 }
 
 // w = b - w (w holds A x on entry), partial of w.w
@@ -1483,11 +1510,12 @@ __global__ __launch_bounds__(kThreads) void k_resid(int64_t n, int R, const doub
     block_partial(acc, R, slot_ptr(part, slot));
 }
 
-__global__ void k_s_true(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_s_true(int R, const double* part, KState* st)
 {
-    const int c = threadIdx.x;
+    const int c = blockIdx.x;
     if (c >= R) return;
-    st->tnorm2[c] = sum_partials(part, SL_TRUE, c);
+    const double v = sum_partials(part, SL_TRUE, c);
+    if (lane_id() == 0) st->tnorm2[c] = v;
 }
 
 // Restart of the columns flagged in st->restart: r = r^ = w (true residual).
@@ -1531,10 +1559,10 @@ __global__ __launch_bounds__(kThreads) void k_gm_mgs(int64_t n, double* __restri
 
 // h = sum of partials; mode 0: *hout = h, *coef = h (next projection);
 // mode 1: h = sqrt(sum), *hout = h, *coef = 1/h (normalisation, 0 if h == 0).
-__global__ void k_gm_h(const double* part, int slot, double* hout, double* coef, int mode)
+__global__ __launch_bounds__(64) void k_gm_h(const double* part, int slot, double* hout, double* coef, int mode)
 {
-    if (threadIdx.x != 0) return;
     double h = sum_partials(part, slot, 0);
+    if (threadIdx.x != 0) return;
     if (mode == 1) {
         h = sqrt(h);
         *coef = h != 0.0 ? 1.0 / h : 0.0;
