@@ -54,6 +54,10 @@ struct bilu_ctx {
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
     int32_t *d_Pp = nullptr, *d_Pj = nullptr, *d_Prow = nullptr, *d_Pdiag = nullptr, *d_PtoA = nullptr;
     int32_t* d_Lrows = nullptr;
+    // factorisation with rows in LDS: update lists and per L level the LDS
+    // bytes of its largest row (0: that level takes k_factor_rows)
+    int32_t *d_upd_ptr = nullptr, *d_upd_f = nullptr, *d_upd_g = nullptr;
+    std::vector<int32_t> fac_lds;
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
     int64_t* d_ATsrc = nullptr;
     double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
@@ -293,10 +297,67 @@ bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const i
     })
 }
 
-bool launch_factor(int bs, const int32_t* rows, int nrows, bilu_ctx* c, hipStream_t s)
+bool launch_factor(int bs, const int32_t* rows, int nrows, int lds, bilu_ctx* c, hipStream_t s)
 {
+    if (lds > 0) {
+        BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows_lds<B>), dim3(nrows), dim3(64), lds, s, rows, nrows,
+                                             c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_upd_ptr, c->d_upd_f, c->d_upd_g,
+                                             c->d_P, c->d_Dinv, c->d_bad))
+    }
     BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows,
                                          c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_P, c->d_Dinv, c->d_bad))
+}
+
+// Update lists of Algorithm 4 for k_factor_rows_lds: for each pivot entry
+// e = (i, p) of P (in entry order), the pairs (f, g) of entries (i, j), f > e,
+// and (p, j), g > diagonal of p, with the same column (f as a block index in
+// row i); and per L level the LDS bytes of its largest row.
+bilu_status factor_plan(bilu_ctx* c)
+{
+    constexpr int kCap = 48 * 1024;            // LDS per workgroup for the row
+    const Host& h = c->h;
+    const int nb = h.nb;
+    const int64_t nP = static_cast<int64_t>(h.Pj.size());
+    const int64_t bb8 = static_cast<int64_t>(h.bs) * h.bs * 8;
+    std::vector<int32_t> uptr(static_cast<size_t>(nP) + 1, 0), uf, ug;
+    std::vector<int64_t> row_bytes(static_cast<size_t>(nb), 0);
+    for (int32_t i = 0; i < nb; ++i) {
+        const int32_t e0 = h.Pp[i], e1 = h.Pp[i + 1], d = h.Pdiag[i];
+        for (int32_t e = e0; e < e1; ++e) {
+            if (e < d) {
+                const int32_t p = h.Pj[e];
+                int32_t f = e + 1, g = h.Pdiag[p] + 1;
+                const int32_t gEnd = h.Pp[p + 1];
+                while (f < e1 && g < gEnd) {
+                    if (h.Pj[f] == h.Pj[g]) {
+                        uf.push_back(f - e0);
+                        ug.push_back(g);
+                        ++f;
+                        ++g;
+                    } else if (h.Pj[f] < h.Pj[g]) {
+                        ++f;
+                    } else {
+                        ++g;
+                    }
+                }
+                if (uf.size() > static_cast<size_t>(INT32_MAX)) return BILU_OK;   // lists too long: no LDS path
+            }
+            uptr[e + 1] = static_cast<int32_t>(uf.size());
+        }
+        const int64_t nrow = e1 - e0, dk = d - e0, npair = uptr[d] - uptr[e0];
+        row_bytes[i] = (nrow + dk + npair) * bb8 + (2 * dk + 1 + 2 * npair) * 4;
+    }
+    const HostSweep& L = h.sweep[BILU_SWEEP_L];
+    c->fac_lds.assign(static_cast<size_t>(L.nlev), 0);
+    for (int l = 0; l < L.nlev; ++l) {
+        int64_t m = 0;
+        for (int32_t x = L.level_ptr[l]; x < L.level_ptr[l + 1]; ++x) m = std::max(m, row_bytes[L.level_rows[x]]);
+        c->fac_lds[l] = m <= kCap ? static_cast<int32_t>(m) : 0;
+    }
+    bilu_status st;
+    if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)))
+        return st;
+    return BILU_OK;
 }
 
 bool launch_split(bilu_ctx* c, hipStream_t s)
@@ -452,6 +513,7 @@ bilu_status ensure_device(bilu_ctx* c)
     CK(hipMemset(c->d_status, 0, sizeof(int)));
     CK(hipMemset(c->d_done, 0, sizeof(unsigned int)));
     CK(hipMemset(c->d_ticket, 0, sizeof(unsigned long long)));
+    if ((st = factor_plan(c))) return st;
     c->dev_ready = true;
     return BILU_OK;
 }
@@ -826,7 +888,8 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     const HostSweep& L = h.sweep[BILU_SWEEP_L];
     for (int l = 0; l < L.nlev; ++l) {
         const int n = L.level_ptr[l + 1] - L.level_ptr[l];
-        if (!launch_factor(h.bs, c->d_Lrows + L.level_ptr[l], n, c, s)) return BILU_ERR_ARG;
+        const int lds = l < static_cast<int>(c->fac_lds.size()) ? c->fac_lds[l] : 0;
+        if (!launch_factor(h.bs, c->d_Lrows + L.level_ptr[l], n, lds, c, s)) return BILU_ERR_ARG;
     }
     timing_end(c, tslot, s);
     CK(hipGetLastError());

@@ -1030,6 +1030,143 @@ __global__ __launch_bounds__(64) void k_factor_rows(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Block ILU(0) on P (Algorithm 4), the same arithmetic as k_factor_rows with
+// the row held in LDS: one workgroup per block row of an L level gathers the
+// row's blocks, the inverse pivot blocks D_p^{-1} of its pivots and every
+// block A_pj the row's updates read (host-built lists: upd[e] holds, for the
+// pivot entry e = (i, p), the pairs (f, g) of entries (i, j) and (p, j) with
+// the same column j > p, f as a block index inside row i), then eliminates in
+// LDS and writes the row and D_i^{-1} back.  Thread t = c*B + r owns element
+// (r, c) of a block.
+// LDS: [row blocks][pivot inverses][A_pj blocks] doubles, then the lists.
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(64) void k_factor_rows_lds(const int32_t* __restrict__ rows, int nrows,
+                                                        const int32_t* __restrict__ Pp,
+                                                        const int32_t* __restrict__ Pj,
+                                                        const int32_t* __restrict__ Pdiag,
+                                                        const int32_t* __restrict__ upd_ptr,
+                                                        const int32_t* __restrict__ upd_f,
+                                                        const int32_t* __restrict__ upd_g, double* __restrict__ P,
+                                                        double* __restrict__ Dinv, int* bad_row)
+{
+    constexpr int BB = B * B;
+    constexpr int W = 2 * B;
+    extern __shared__ double smem[];
+    __shared__ double sW[B * W];
+    __shared__ int sPiv;
+    __shared__ int sBad;
+    if (static_cast<int>(blockIdx.x) >= nrows) return;
+    const int i = rows[blockIdx.x];
+    const int t = threadIdx.x;
+    const int r = t % B;
+    const int c = t / B;
+    const int e0 = Pp[i];
+    const int nrow = Pp[i + 1] - e0;
+    const int dk = Pdiag[i] - e0;                 // pivots are blocks 0..dk-1 of the row
+    const int u0 = upd_ptr[e0];
+    const int npair = upd_ptr[e0 + dk] - u0;
+    double* sRow = smem;
+    double* sD = sRow + nrow * BB;
+    double* sU = sD + dk * BB;
+    int* sQ = reinterpret_cast<int*>(sU + npair * BB);    // [dk + 1] pair ranges
+    int* sF = sQ + dk + 1;                                 // [npair] target block in the row
+    int* sG = sF + npair;                                  // [npair] source entry (p, j)
+    int* sPv = sG + npair;                                 // [dk] pivot rows
+    if (t == 0) sBad = 0;
+    // the row, and the lists
+    for (int x = t; x < nrow * BB; x += 64) sRow[x] = P[static_cast<int64_t>(e0) * BB + x];
+    for (int x = t; x <= dk; x += 64) sQ[x] = upd_ptr[e0 + x] - u0;
+    for (int x = t; x < npair; x += 64) {
+        sF[x] = upd_f[u0 + x];
+        sG[x] = upd_g[u0 + x];
+    }
+    for (int x = t; x < dk; x += 64) sPv[x] = Pj[e0 + x];
+    __syncthreads();
+    // the finished blocks of earlier rows the row reads
+    for (int x = t; x < dk * BB; x += 64) {
+        const int k = x / BB;
+        sD[x] = Dinv[static_cast<int64_t>(sPv[k]) * BB + (x - k * BB)];
+    }
+    for (int x = t; x < npair * BB; x += 64) {
+        const int q = x / BB;
+        sU[x] = P[static_cast<int64_t>(sG[q]) * BB + (x - q * BB)];
+    }
+    __syncthreads();
+    for (int k = 0; k < dk; ++k) {
+        double tv = 0.0;
+        if (t < BB) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) tv += sRow[k * BB + u * B + r] * sD[k * BB + c * B + u];
+        }
+        __syncthreads();
+        if (t < BB) sRow[k * BB + t] = tv;
+        __syncthreads();
+        if (t < BB)
+            for (int q = sQ[k]; q < sQ[k + 1]; ++q) {
+                double acc = 0.0;
+#pragma unroll
+                for (int u = 0; u < B; ++u) acc += sRow[k * BB + u * B + r] * sU[q * BB + c * B + u];
+                sRow[sF[q] * BB + t] -= acc;
+            }
+        __syncthreads();
+    }
+    // Gauss-Jordan on [U_ii | I], row-major in LDS.
+    if (t < BB) {
+        sW[r * W + c] = sRow[dk * BB + t];
+        sW[r * W + B + c] = (r == c) ? 1.0 : 0.0;
+    }
+    for (int x = t; x < nrow * BB; x += 64) P[static_cast<int64_t>(e0) * BB + x] = sRow[x];
+    __syncthreads();
+    for (int col = 0; col < B; ++col) {
+        if (t == 0) {
+            int piv = col;
+            double best = fabs(sW[col * W + col]);
+            for (int rr = col + 1; rr < B; ++rr) {
+                const double v = fabs(sW[rr * W + col]);
+                if (v > best) {
+                    best = v;
+                    piv = rr;
+                }
+            }
+            if (!(best > 0.0) || !isfinite(best)) sBad = 1;
+            sPiv = piv;
+        }
+        __syncthreads();
+        const int piv = sPiv;
+        if (piv != col && t < W) {
+            const double tmp = sW[col * W + t];
+            sW[col * W + t] = sW[piv * W + t];
+            sW[piv * W + t] = tmp;
+        }
+        __syncthreads();
+        const double dd = sW[col * W + col];
+        __syncthreads();
+        if (t < W) sW[col * W + t] /= dd;
+        __syncthreads();
+        double fct[2];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int idx = t + 64 * s2;
+            fct[s2] = idx < B * W ? sW[(idx / W) * W + col] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int idx = t + 64 * s2;
+            if (idx < B * W) {
+                const int rr = idx / W;
+                const int cc = idx - rr * W;
+                if (rr != col) sW[idx] -= fct[s2] * sW[col * W + cc];
+            }
+        }
+        __syncthreads();
+    }
+    if (t < BB) Dinv[static_cast<int64_t>(i) * BB + t] = sW[r * W + B + c];
+    if (t == 0 && sBad) atomicMin(bad_row, i);
+}
+
+// ---------------------------------------------------------------------------
 // U = D U' (Eq 5): F = L below the diagonal, U'_ij = D_i^{-1} U_ij above
 // it, the identity on the diagonal.
 // ---------------------------------------------------------------------------
