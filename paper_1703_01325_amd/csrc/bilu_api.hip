@@ -542,15 +542,25 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots;
         const int nchunks = form == kFormLevel ? h.sweep[w].nchunks : h.tiled[w].nchunks;
         const int rpc = h.rpc;
-        dfree(c, d.vals);
-        dfree(c, d.dinv);
-        d.vals = d.dinv = nullptr;
-        char* p = nullptr;
-        if ((st = dalloc(c, &p, static_cast<size_t>(nslots) * bb * esz))) return st;
-        d.vals = p;
-        if (fused_sweep(w)) {
-            if ((st = dalloc(c, &p, static_cast<size_t>(nchunks) * rpc * bb * esz))) return st;
-            d.dinv = p;
+        // a new factorisation of the same layout reuses the arrays (no
+        // allocation on the factorisation path); another size or precision
+        // allocates them again
+        const size_t vbytes = static_cast<size_t>(nslots) * bb * esz;
+        const size_t dbytes = fused_sweep(w) ? static_cast<size_t>(nchunks) * rpc * bb * esz : 0;
+        if (!d.vals || d.vals_bytes != vbytes || d.dinv_bytes != dbytes) {
+            dfree(c, d.vals);
+            dfree(c, d.dinv);
+            d.vals = d.dinv = nullptr;
+            d.vals_bytes = d.dinv_bytes = 0;
+            char* p = nullptr;
+            if ((st = dalloc(c, &p, vbytes))) return st;
+            d.vals = p;
+            d.vals_bytes = vbytes;
+            if (dbytes) {
+                if ((st = dalloc(c, &p, dbytes))) return st;
+                d.dinv = p;
+                d.dinv_bytes = dbytes;
+            }
         }
         const int tr = transposed_sweep(w) ? 1 : 0;
         const int64_t nrs = static_cast<int64_t>(nchunks) * rpc;

@@ -139,6 +139,8 @@ struct DevSweep {
     void* vals = nullptr;     // [nslots * bs*bs] FP64 or FP32, layout [k][c][r][q]
     void* dinv = nullptr;     // [nchunks*rpc * bs*bs] same layout, fused sweeps only
     int vals_precision = -1;  // precision the values were laid out in (-1: none)
+    size_t vals_bytes = 0;    // allocated bytes of vals and dinv
+    size_t dinv_bytes = 0;
 };
 
 struct Host {
