@@ -76,6 +76,7 @@ struct bilu_ctx {
     size_t kv_cap = 0;
     double* d_part = nullptr;
     KState* d_state = nullptr;
+    KState* h_state = nullptr;  // pinned host copy read back every Krylov step
 
     // HIP-event timing of kernel classes (bilu_timing)
     bool timing = false;
@@ -1226,7 +1227,12 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     hipLaunchKernelGGL(dev::k_bicg_init, dim3(R), dim3(64), 0, s, R, part, S, o->rtol);
     CK(hipGetLastError());
 
-    KState hs;
+    if (!c->h_state) {
+        void* hp = nullptr;
+        if (hipHostMalloc(&hp, sizeof(KState), hipHostMallocDefault) != hipSuccess) return BILU_ERR_ALLOC;
+        c->h_state = static_cast<KState*>(hp);
+    }
+    KState& hs = *c->h_state;      // pinned: the per-step read-back is a plain DMA
     CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     std::vector<int> iters(R, 0), done(R, 0);
@@ -1470,6 +1476,7 @@ void bilu_destroy(bilu_ctx* c)
     if (!c) return;
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
+    if (c->h_state) (void)hipHostFree(c->h_state);
     delete c;
 }
 
