@@ -858,6 +858,9 @@ __device__ __forceinline__ void spmv_rows(int64_t row0, int nb, const int32_t* _
         double acc[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) acc[t] = 0.0;
+        // unrolled: the column-index and x loads of several blocks in flight
+        // (same accumulation order)
+#pragma unroll 4
         for (int e = e0; e < e1; ++e) {
             const int j = cj[e];
             const int64_t blk = TRANS ? srcpos[e] : e;
