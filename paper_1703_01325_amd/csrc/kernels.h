@@ -1354,6 +1354,8 @@ struct RedIdx {
     bool live;
 };
 
+// Grid-stride loops of the reductions below are unrolled by 4 (several
+// loads in flight per thread); the single accumulator keeps the order.
 __device__ __forceinline__ RedIdx red_index(int R)
 {
     const int64_t nthreads = static_cast<int64_t>(kRedBlocks) * kThreads;
@@ -1397,6 +1399,7 @@ __global__ __launch_bounds__(kThreads) void k_dot(int64_t n, int R, const double
     const RedIdx ri = red_index(R);
     double acc = 0.0;
     if (ri.live)
+#pragma unroll 4
         for (int64_t g = ri.start; g < n * R; g += ri.stride) acc += a[g] * b[g];
     block_partial(acc, R, slot_ptr(part, slot));
 }
@@ -1409,6 +1412,7 @@ __global__ __launch_bounds__(kThreads) void k_dot2(int64_t n, int R, const doubl
     const RedIdx ri = red_index(R);
     double ts = 0.0, tt = 0.0;
     if (ri.live)
+#pragma unroll 4
         for (int64_t g = ri.start; g < n * R; g += ri.stride) {
             const double tv = t[g];
             ts += tv * s[g];
@@ -1571,6 +1575,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t n, int R, const dou
     double acc = 0.0;
     if (ri.live && st->active[ri.col]) {
         const double al = st->alpha[ri.col];
+#pragma unroll 4
         for (int64_t g = ri.start; g < n * R; g += ri.stride) {
             const double sv = r[g] - al * v[g];
             s[g] = sv;
@@ -1613,9 +1618,11 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t n, int R, double* 
         const int c = ri.col;
         const double al = st->alpha[c];
         if (st->half[c]) {
+#pragma unroll 4
             for (int64_t g = ri.start; g < n * R; g += ri.stride) x[g] += al * ph[g];
         } else {
             const double om = st->omega[c];
+#pragma unroll 4
             for (int64_t g = ri.start; g < n * R; g += ri.stride) {
                 x[g] += al * ph[g] + om * sh[g];
                 const double rv = s[g] - om * t[g];
@@ -1642,6 +1649,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(int64_t n, int R, const doub
     const RedIdx ri = red_index(R);
     double acc = 0.0;
     if (ri.live)
+#pragma unroll 4
         for (int64_t g = ri.start; g < n * R; g += ri.stride) {
             const double v = b[g] - w[g];
             w[g] = v;
