@@ -166,6 +166,29 @@ def test_grouped_tiled_layouts_validate(N, tile_rows, group):
             N.bilu_destroy(ctx)
 
 
+def test_tune_arguments(N):
+    """Out-of-range launch knobs are refused; accepted ones keep valid
+    layouts (host self-check), and a requested tile size is reported."""
+    Ap, Aj = synth.stencil7_pattern(6, 5, 4)
+    ctx = N.bilu_analyze(120, 3, Ap, Aj, 0, 0)
+    try:
+        for param, bad in ((N.TUNE_SWEEP_MODE, 3), (N.TUNE_TILE_ROWS, -1), (N.TUNE_TILE_GROUP, 5),
+                           (N.TUNE_TILE_GROUP, -1), (N.TUNE_RHS_TILE, 3), (N.TUNE_FUSE_SPMV, 2), (99, 0)):
+            with pytest.raises(N.BiluError) as ei:
+                N.bilu_tune(ctx, param, bad)
+            assert ei.value.code == N.ERR_ARG
+        N.bilu_tune(ctx, N.TUNE_TILE_GROUP, 2)
+        N.bilu_tune(ctx, N.TUNE_TILE_ROWS, 30)       # one plane of 6x5 cells per tile
+        N.bilu_validate(ctx)
+        info = N.bilu_get_info(ctx)
+        assert info.tile_rows == 30 and info.tile_group == 2
+        N.bilu_tune(ctx, N.TUNE_TILE_GROUP, 1)
+        N.bilu_validate(ctx)
+        assert N.bilu_get_info(ctx).tile_group == 1
+    finally:
+        N.bilu_destroy(ctx)
+
+
 def test_batch_create_host(N):
     """Batch creation is host analysis only: offsets are the members' unknown
     counts laid end to end, members keep their own bit-exact analysis, and a
