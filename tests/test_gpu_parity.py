@@ -78,6 +78,29 @@ def test_factor_parity(api, oracle_mod, name, make, k):
     assert rel(D, c.O.Dinv) <= 1e-12
 
 
+def test_factor_long_rows(api, oracle_mod):
+    """Full fill (k = nb) of a random pattern with b = 8: the first level's
+    row fits the LDS budget of the LDS factorisation kernel, the longer rows
+    after it take the merge-walking kernel; factors and an application are
+    checked against the oracle."""
+    from types import SimpleNamespace
+    nb, bs, k = 48, 8, 48
+    Ap, Aj = synth.random_block_pattern(nb, 0.15, seed=91)
+    Ax = synth.random_block_values(Ap, Aj, bs, seed=92)
+    O = oracle_mod.OracleILU(nb, bs, Ap, Aj, k).factor(Ax)
+    M = api.BlockILU(nb, bs, Ap, Aj, k)
+    assert M.factor(cuda(Ax)) == -1
+    F, D = M.factors()
+    s = SimpleNamespace(nb=nb, bs=bs)
+    gL, gU = factor_parts(O, s, F.cpu().numpy())
+    oL, oU = factor_parts(O, s, O.F)
+    assert rel(gL, oL) <= 1e-12 and rel(gU, oU) <= 1e-12
+    assert rel(D.cpu().numpy(), O.Dinv) <= 1e-12
+    r = np.random.default_rng(93).standard_normal(nb * bs)
+    assert rel(M.apply(cuda(r)).cpu().numpy(), O.apply(r)) <= 1e-12
+    M.check()
+
+
 MODES = [(0, None), (1, None), (2, None), (2, 1), (2, 13), (2, 64)]
 
 
