@@ -318,7 +318,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 // drains.  Dependency codes are byte offsets: code >= 0 is row code/(8B) of
 // the vectors, code < 0 is byte (code & INT32_MAX) of the tile's LDS; a
 // padding slot points at LDS row tile_rows, kept at zero, and has zero
-// factor values.  Single right-hand side.
+// factor values.  A wavefront sweeps one right-hand side (MULTI: one per
+// (tile, column)); k_sweep_grouped runs several tiles per workgroup.
 //
 // The walk is software-pipelined over a ring of NR register states: at step
 // i the wavefront issues the metadata loads of chunk i + 2(NR-1) (row ids,
