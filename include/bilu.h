@@ -159,7 +159,10 @@ bilu_status bilu_factor_numeric(bilu_ctx* ctx, const double* Ax_dev, hipStream_t
  * Diagonal factorisation U = D U' (Eq 5): D^{-1} is the block diagonal of
  * pivot inverses, U'_ij = D_i^{-1} U_ij.  Lays L, D^{-1} and U' out for the
  * level-scheduled sweeps, stored as FP64 or rounded (nearest-even) to FP32
- * (precision = bilu_precision).  Must follow bilu_factor_numeric.
+ * (precision = bilu_precision).  Must follow bilu_factor_numeric.  The first
+ * call (and the first after a change of precision or layout) allocates the
+ * laid-out factors; later factorisations of the same matrix structure reuse
+ * them.
  */
 bilu_status bilu_factor_diag(bilu_ctx* ctx, int precision, hipStream_t stream);
 
