@@ -95,6 +95,9 @@ typedef struct {
     int tile_rows;        /* block rows per tile of the tiled sweeps (0: not chosen yet) */
     int tile_group;       /* tiles per workgroup of the tiled sweeps (1: one wavefront
                              per tile; see BILU_TUNE_TILE_GROUP)                         */
+    int lds_ring[4];      /* per tiled sweep: chunks whose rows a wavefront keeps in LDS
+                             (0: the whole tile; > 0 when every in-tile dependency is
+                             fewer than that many chunks back, single-tile layouts only) */
 } bilu_info;
 
 typedef struct {

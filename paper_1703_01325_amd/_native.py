@@ -43,7 +43,7 @@ class BiluInfo(ct.Structure):
                 ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
                 ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
                 ("sweep_slots", ct.c_int64 * 4), ("tile_rows", ct.c_int),
-                ("tile_group", ct.c_int)]
+                ("tile_group", ct.c_int), ("lds_ring", ct.c_int * 4)]
 
 
 class KernelTime(ct.Structure):

@@ -296,7 +296,64 @@ bool groups_ordered(int nb, int tile_rows, bool forward, const TileGroups& tg, c
 
 }  // namespace
 
-void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, int64_t lds_limit, HostTiled& s)
+namespace {
+
+// LDS ring: a wavefront sweeping a tile alone reads a row of its tile only a
+// few chunks after the chunk that formed it.  If every tile-local dependency
+// spans at most maxd chunks (maxd < kRingMax), the wavefront keeps just the
+// rows of its last maxd + 1 chunks: the row in lane slot q of the chunk at
+// position k of its tile lives in LDS row (k mod ring)*rpc + q, and the
+// codes are rewritten to those rows (the zero row moves to ring*rpc).
+constexpr int kRingMax = 16;
+
+void apply_ring(HostTiled& s, int nb, int bs)
+{
+    const int rpc = s.rpc;
+    const int32_t row_bytes = bs * 8;
+    std::vector<int32_t> chunk_of(static_cast<size_t>(nb), -1), q_of(static_cast<size_t>(nb), -1);
+    for (int c = 0; c < s.nchunks; ++c)
+        for (int q = 0; q < rpc; ++q) {
+            const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
+            if (r >= 0) {
+                chunk_of[r] = c;
+                q_of[r] = q;
+            }
+        }
+    const int32_t old_pad = tiled_local_code(s.tile_rows, bs);
+    int maxd = 0;
+    for (int t = 0; t < s.ntiles; ++t)
+        for (int c = s.tile_chunk_ptr[t]; c < s.tile_chunk_ptr[t + 1]; ++c)
+            for (int64_t x = s.chunk_off[c]; x < s.chunk_off[c + 1]; ++x) {
+                const int32_t code = s.deps[x];
+                if (code >= 0 || code == old_pad) continue;
+                const int32_t j = s.tile_lo[t] + (code & INT32_MAX) / row_bytes;
+                maxd = std::max(maxd, c - chunk_of[j]);
+            }
+    if (maxd < 1 || maxd >= kRingMax) return;
+    const int ring = maxd + 1;
+    if (static_cast<int64_t>(ring) * rpc >= s.tile_rows) return;     // no smaller than the tile
+    const int32_t new_pad = tiled_local_code(ring * rpc, bs);
+    for (int t = 0; t < s.ntiles; ++t) {
+        const int first = s.tile_chunk_ptr[t];
+        for (int c = first; c < s.tile_chunk_ptr[t + 1]; ++c)
+            for (int64_t x = s.chunk_off[c]; x < s.chunk_off[c + 1]; ++x) {
+                const int32_t code = s.deps[x];
+                if (code >= 0) continue;
+                if (code == old_pad) {
+                    s.deps[x] = new_pad;
+                    continue;
+                }
+                const int32_t j = s.tile_lo[t] + (code & INT32_MAX) / row_bytes;
+                s.deps[x] = tiled_local_code(((chunk_of[j] - first) % ring) * rpc + q_of[j], bs);
+            }
+    }
+    s.ring = ring;
+}
+
+}  // namespace
+
+void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, int64_t lds_limit, bool allow_ring,
+                 HostTiled& s)
 {
     const int nb = h.nb;
     const int bs = h.bs;
@@ -406,6 +463,7 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, in
     s.nchunks = static_cast<int>(s.chunk_off.size() - 1);
     s.tile_chunk_ptr[s.ntiles] = s.nchunks;
     s.nslots = s.chunk_off.back();
+    if (tg.G == 1 && allow_ring) apply_ring(s, nb, bs);
     s.built = true;
 }
 
@@ -707,8 +765,10 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
     const int64_t n_dinv = static_cast<int64_t>(s.nchunks) * RPC * BB;
     const int64_t vec_bytes = static_cast<int64_t>(h.nb) * B * 8;
     const int G = s.group;
-    // the member tiles' rows + the zero row (progress counters follow)
-    const int64_t lds_bytes = (static_cast<int64_t>(G) * s.tile_rows + 1) * B * 8;
+    if (s.ring > 0 && G != 1) return false;
+    // the member tiles' rows (or the ring's) + the zero row (progress counters follow)
+    const int64_t lds_rows = s.ring > 0 ? static_cast<int64_t>(s.ring) * RPC : static_cast<int64_t>(G) * s.tile_rows;
+    const int64_t lds_bytes = (lds_rows + 1) * B * 8;
     if (vec_bytes > INT32_MAX) return false;
     if (G < 1 || G > kGroupMax) return false;
     auto in = [](int64_t i, int64_t n) { return i >= 0 && i < n; };
@@ -774,7 +834,8 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                 }
                 if (!in8((static_cast<int64_t>(row) * B + r) * 8, vec_bytes)) return false;
                 if (row - lo < 0 || row - lo >= s.tile_rows) return false;
-                if (!in8(((own + row - lo) * B + r) * 8, lds_bytes - B * 8)) return false;
+                const int64_t wrow = s.ring > 0 ? ((c - s.tile_chunk_ptr[t]) % s.ring) * RPC + qc : own + row - lo;
+                if (!in8((wrow * B + r) * 8, lds_bytes - B * 8)) return false;
             }
         }
     }
@@ -887,7 +948,8 @@ int validate_layout(const Host& h)
                 if (!placed[t]) return BILU_ERR_STATE;
         }
         const int32_t row_bytes = h.bs * 8;
-        const int32_t pad_code = tiled_local_code(G * s.tile_rows, h.bs);
+        if (s.ring < 0 || s.ring >= kRingMax + 1 || (s.ring > 0 && G != 1)) return BILU_ERR_STATE;
+        const int32_t pad_code = tiled_local_code(s.ring > 0 ? s.ring * rpc : G * s.tile_rows, h.bs);
         std::vector<int32_t> tile_of(static_cast<size_t>(nb), -1), chunk_of(static_cast<size_t>(nb), -1);
         for (int t = 0; t < s.ntiles; ++t) {
             const int lo = s.tile_lo[t];
@@ -944,12 +1006,25 @@ int validate_layout(const Host& h)
                             const int32_t off = code & INT32_MAX;
                             if (off % row_bytes != 0) return BILU_ERR_STATE;
                             const int32_t lr = off / row_bytes;
-                            const int mj = lr / s.tile_rows;
-                            if (mj >= G) return BILU_ERR_STATE;
-                            const int tj = tg.tile(gt, mj);
-                            if (tj < 0) return BILU_ERR_STATE;
-                            j = s.tile_lo[tj] + lr % s.tile_rows;
+                            int tj;
+                            if (s.ring > 0) {
+                                // the row last written to LDS row lr before chunk c
+                                if (lr >= s.ring * rpc) return BILU_ERR_STATE;
+                                const int k = c - s.tile_chunk_ptr[t];
+                                const int sc = lr / rpc;
+                                const int kp = k - 1 - (((k - 1 - sc) % s.ring) + s.ring) % s.ring;
+                                if (kp < 0) return BILU_ERR_STATE;
+                                tj = t;
+                                j = s.rows[static_cast<size_t>(s.tile_chunk_ptr[t] + kp) * rpc + lr % rpc];
+                            } else {
+                                const int mj = lr / s.tile_rows;
+                                if (mj >= G) return BILU_ERR_STATE;
+                                tj = tg.tile(gt, mj);
+                                if (tj < 0) return BILU_ERR_STATE;
+                                j = s.tile_lo[tj] + lr % s.tile_rows;
+                            }
                             if (j < 0 || j >= nb || tile_of[j] != tj) return BILU_ERR_STATE;
+                            const int mj = tg.member(tj);
                             if (tj == t) {
                                 if (chunk_of[j] >= c) return BILU_ERR_STATE;
                             } else {             // an earlier member, covered by the chunk's wait

@@ -408,7 +408,7 @@ bilu_status set_layout(bilu_ctx* c, int tile_rows_req, int tile_group_req)
     free_form(c, kFormTiled);
     c->layouts_checked = false;
     for (int w = 0; w < 4; ++w)
-        if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->tile_group, c->lds_max, c->h.tiled[w]);
+        if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->tile_group, c->lds_max, true, c->h.tiled[w]);
     return BILU_OK;
 }
 
@@ -430,7 +430,7 @@ bilu_status upload_form(bilu_ctx* c, int form)
             if (c->tile_rows <= 0 || c->layout_lds != c->lds_max) choose_layout(c);
             HostTiled& ht = h.tiled[w];
             if (!ht.built || ht.tile_rows != c->tile_rows || ht.group_req != c->tile_group) {
-                build_tiled(h, w, h.rpc, c->tile_rows, c->tile_group, c->lds_max, ht);
+                build_tiled(h, w, h.rpc, c->tile_rows, c->tile_group, c->lds_max, true, ht);
                 c->layouts_checked = false;
             }
             std::vector<int32_t> crow(ht.chunk_off.size());
@@ -640,10 +640,11 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         const int blocks = ht.group > 1 ? persistent_blocks(c, ht.ngroups * R, 1, std::max(1, 8 / ht.group))
                                         : persistent_blocks(c, ht.ntiles * R, 1, 8);
         a.total_waves = static_cast<unsigned int>(blocks);
-        a.tile_rows = ht.tile_rows;
-        // the member tiles' rows, one row kept at zero (padding slots read
-        // it) and the members' progress counts
-        const size_t lds = static_cast<size_t>(tiled_lds_bytes(ht.tile_rows, ht.group, c->h.bs));
+        a.ring = ht.ring;
+        a.tile_rows = ht.ring > 0 ? ht.ring * c->h.rpc : ht.tile_rows;
+        // the member tiles' rows (or the ring's), one row kept at zero
+        // (padding slots read it) and the members' progress counts
+        const size_t lds = static_cast<size_t>(tiled_lds_bytes(a.tile_rows, ht.group, c->h.bs));
         if (static_cast<int64_t>(lds) > c->lds_max) return BILU_ERR_STATE;
         if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
@@ -776,7 +777,8 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
     a.done = c->d_done;
     a.status = c->d_status;
     a.ntiles = hu.ntiles;
-    a.tile_rows = hu.tile_rows;
+    a.ring = hu.ring;
+    a.tile_rows = hu.ring > 0 ? hu.ring * c->h.rpc : hu.tile_rows;
     a.R = 1;
     a.spin_limit = c->spin_limit;
     dev::FusedSpmvArgs m{};
@@ -791,7 +793,7 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
     // run on wavefronts whose tile is done, few wait and poll
     const int blocks = persistent_blocks(c, std::min(m.nsched, hu.ntiles + c->num_cu), 1, 8);
     a.total_waves = static_cast<unsigned int>(blocks);
-    const size_t lds = static_cast<size_t>(hu.tile_rows + 1) * c->h.bs * sizeof(double);
+    const size_t lds = static_cast<size_t>(a.tile_rows + 1) * c->h.bs * sizeof(double);
     const bool ok = c->precision == BILU_FACTORS_FP32 ? launch_fused_b<float>(c->h.bs, hu.kmax, blocks, lds, s, a, m)
                                                       : launch_fused_b<double>(c->h.bs, hu.kmax, blocks, lds, s, a, m);
     timing_end(c, tslot, s);
@@ -872,6 +874,7 @@ bilu_status bilu_get_info(const bilu_ctx* c, bilu_info* info)
     for (int w = 0; w < 4; ++w) {
         info->nlev[w] = h.sweep[w].built ? h.sweep[w].nlev : 0;
         info->sweep_slots[w] = h.sweep[w].built ? h.sweep[w].nslots : 0;
+        info->lds_ring[w] = h.tiled[w].built ? h.tiled[w].ring : 0;
     }
     return BILU_OK;
 }

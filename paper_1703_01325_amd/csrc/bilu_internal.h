@@ -66,6 +66,7 @@ struct HostTiled {
     // wavefronts of one workgroup and share its LDS (TileGroups).  Codes of
     // rows in any member tile are local; chunk_wait[c*kGroupMax + m] is the
     // number of chunks member m must have finished before chunk c reads LDS.
+    int ring = 0;                          // > 0: LDS ring of this many chunks (group 1 only)
     int group = 1;
     int group_req = 1;                     // the group size asked of build_tiled
     int gstride = 1;
@@ -171,7 +172,10 @@ int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, 
 // Tiled layout of one sweep with tiles of tile_rows rows in groups of up to
 // `group` tiles (falls back to smaller groups, down to 1, where a grouping
 // would break the ticket order or the group's LDS exceeds lds_limit bytes).
-void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, int64_t lds_limit, HostTiled& out);
+// allow_ring: a layout of single tiles may keep only a ring of recent chunks'
+// rows in LDS where the dependencies allow (HostTiled::ring).
+void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, int64_t lds_limit, bool allow_ring,
+                 HostTiled& out);
 // Predicted duration (in units of `step`) of a tiled sweep with the given
 // tile size and group size (forward sweeps may be restricted to their first
 // row_limit rows; 0 = all); +inf where the grouping is not usable.

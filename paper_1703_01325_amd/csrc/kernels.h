@@ -352,7 +352,8 @@ struct TiledArgs {
     unsigned int* done;
     int* status;
     int ntiles;
-    int tile_rows;                // LDS row group*tile_rows is kept at zero
+    int tile_rows;                // LDS row group*tile_rows is kept at zero (ring: ring*64/B)
+    int ring;                     // > 0: LDS keeps the rows of the last `ring` chunks only
     int R;                        // right-hand sides (vectors are (n x R) row-major)
     unsigned int total_waves;     // grouped: workgroups
     unsigned int spin_limit;
@@ -526,7 +527,7 @@ template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool GROUPED>
 __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
                                              const double* lds_base, double* tile_vals,
                                              const TileData<B, T, KMAX, FUSE>& s, const int (&need)[kGroupMax],
-                                             const int* prog, const ColMap<MULTI>& cm)
+                                             const int* prog, const ColMap<MULTI>& cm, int wbase)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
@@ -607,7 +608,8 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     const uint32_t ob = cm.at(static_cast<uint32_t>(s.row) * (B * 8u), r);
     if (a.reset) *reinterpret_cast<double*>(reinterpret_cast<char*>(a.reset) + ob) = not_ready();
     coherent_store(reinterpret_cast<double*>(reinterpret_cast<char*>(a.out) + ob), v);
-    tile_vals[(s.row - lo) * B + r] = v;
+    // the row's LDS slot: its place in the tile, or in the ring (wbase >= 0)
+    tile_vals[(wbase >= 0 ? wbase + qc : s.row - lo) * B + r] = v;
 }
 
 // Ring depth: three register states where they fit in half the register
@@ -671,6 +673,7 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
     // ahead so that no step waits on the scalar cache
     int pre_lo = uniform_load(a.chunk_row, chunk_at(LM));
     int pre_hi = uniform_load(a.chunk_row, chunk_at(LM) + 1);
+    int wchunk = 0;                                          // ring position of the chunk computed next
     // whole turns of the ring; steps past the tile's end load clamped
     // chunks and compute nothing
     for (int i0 = 0; i0 < nch; i0 += NR) {
@@ -683,7 +686,8 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
             tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
             wait_at(i + LD, wr[(p + LD) % NR]);
             tile_compute<B, T, KMAX, FUSE, MULTI, GROUPED>(a, lo, qc, r, lane_ok && i < nch, lds_base, tile_vals,
-                                                           dr[p], wr[p], prog, cm);
+                                                           dr[p], wr[p], prog, cm, a.ring > 0 ? wchunk * RPC : -1);
+            wchunk = wchunk + 1 == a.ring ? 0 : wchunk + 1;
             // one wavefront: its LDS accesses complete in issue order, so
             // only the compiler must keep this chunk's writes before the
             // next chunk's reads (and before the progress count)

@@ -108,6 +108,7 @@ __device__ __forceinline__ void batch_tile(const BatchSweepArgs& a, const BatchT
     t.reset = a.reset ? a.reset + M.voff : nullptr;
     t.status = a.status;
     t.tile_rows = M.tile_rows;
+    t.ring = 0;                      // member layouts keep whole tiles
     t.R = 1;
     t.spin_limit = a.spin_limit;
     // this member's zero row (an earlier item may have used that LDS)

@@ -468,7 +468,8 @@ GROUPED = [
 def test_grouped_tiles_parity(api, oracle_mod, name, make, k, tile, group):
     """Grouped row tiles compute every row with the arithmetic of the single
     tiles, so applications agree bit for bit with the ungrouped layout (one
-    and several right-hand sides, transposed too) and with the oracle to
+    and several right-hand sides, transposed too; single tiles keeping only
+    a ring of chunks in LDS where dependencies allow) and with the oracle to
     1e-12."""
     c = Case(oracle_mod, make(), k)
     M = c.gpu(api, transpose=True, tile_rows=tile)
@@ -476,7 +477,10 @@ def test_grouped_tiles_parity(api, oracle_mod, name, make, k, tile, group):
     r = cuda(rng.standard_normal(c.s.n))
     B = cuda(rng.standard_normal((c.s.n, 3)))
     M.tune(tile_group=1)
+    ring = list(M.info().lds_ring)
     z1, zt1, Z1 = M.apply(r), M.apply(r, transpose=True), M.apply(B)
+    if k == 0 and tile in (48, 50, 100):
+        assert min(ring) > 0                  # single tiles keep a ring of chunks in LDS
     M.tune(tile_group=group)
     used = M.info().tile_group
     assert 1 <= used <= group

@@ -166,6 +166,31 @@ def test_grouped_tiled_layouts_validate(N, tile_rows, group):
             N.bilu_destroy(ctx)
 
 
+def test_lds_ring_layouts_validate(N):
+    """Single-tile layouts keep only the last few chunks of a tile in LDS when
+    every in-tile dependency is that close: the host self-check decodes each
+    ring slot to the row it holds when read and checks it against the
+    pattern; the ring is used where planes are short, never for tile groups,
+    and is always smaller than the tile."""
+    seen = 0
+    for grid, k in (((8, 6, 10), 0), ((8, 6, 10), 1), ((7, 5, 4), 2), ((20, 20, 20), 0), ((13, 7, 9), 1)):
+        Ap, Aj = synth.stencil7_pattern(*grid)
+        nb = int(np.prod(grid))
+        ctx = N.bilu_analyze(nb, 3, Ap, Aj, k, N.WANT_TRANSPOSE)
+        try:
+            for group in (1, 0):
+                N.bilu_tune(ctx, N.TUNE_TILE_GROUP, group)
+                N.bilu_validate(ctx)
+                info = N.bilu_get_info(ctx)
+                for w in range(4):
+                    ring = info.lds_ring[w]
+                    assert ring == 0 or (info.tile_group == 1 and ring * info.rows_per_chunk < info.tile_rows)
+                    seen += ring > 0
+        finally:
+            N.bilu_destroy(ctx)
+    assert seen >= 8
+
+
 def test_tune_arguments(N):
     """Out-of-range launch knobs are refused; accepted ones keep valid
     layouts (host self-check), and a requested tile size is reported."""
