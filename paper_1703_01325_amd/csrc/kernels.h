@@ -845,11 +845,13 @@ __global__ __launch_bounds__(64) void k_sweep_tiled_spmv(TiledArgs a, FusedSpmvA
 
 // Rows [row0, row0 + 64/B) of y = A x (or A^T x through the transposed
 // structure), by one wavefront; lane (q, r) owns component r of row q.
+// Block values are read from Av at block (e - ebase): A itself (ebase 0), or
+// the wavefront's LDS copy of its rows' blocks (ebase the first of them).
 template <int B, int RT, bool TRANS>
 __device__ __forceinline__ void spmv_rows(int64_t row0, int nb, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ cj, const int64_t* __restrict__ srcpos,
-                                          const double* __restrict__ Ax, const double* __restrict__ x,
-                                          double* __restrict__ y, int R)
+                                          const double* __restrict__ Av, int64_t ebase,
+                                          const double* __restrict__ x, double* __restrict__ y, int R)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
@@ -868,10 +870,10 @@ __device__ __forceinline__ void spmv_rows(int64_t row0, int nb, const int32_t* _
 #pragma unroll 4
         for (int e = e0; e < e1; ++e) {
             const int j = cj[e];
-            const int64_t blk = TRANS ? srcpos[e] : e;
+            const int64_t blk = (TRANS ? srcpos[e] : e) - ebase;
 #pragma unroll
             for (int c = 0; c < B; ++c) {
-                const double v = TRANS ? Ax[blk * BB + r * B + c] : Ax[blk * BB + c * B + r];
+                const double v = TRANS ? Av[blk * BB + r * B + c] : Av[blk * BB + c * B + r];
                 const double* xj = x + (static_cast<int64_t>(j) * B + c) * R + c0;
 #pragma unroll
                 for (int t = 0; t < RT; ++t)
@@ -885,6 +887,17 @@ __device__ __forceinline__ void spmv_rows(int64_t row0, int nb, const int32_t* _
     }
 }
 
+// LDS per wavefront for its rows' blocks in k_spmv when each block serves a
+// tile of right-hand sides (RT > 1): eight blocks per row on average (a
+// 7-point stencil needs seven); 0 for block sizes whose rows already read
+// whole cache lines.  With one right-hand side the copy did not pay (156 ->
+// 159 us on 60x220x85, b = 3); with 8 and 32 it did (64^3 ILU(1) solves
+// 162 -> 172 and 219 -> 233 per second).
+template <int B>
+struct SpmvStage {
+    static constexpr int doubles = B <= 3 ? (64 / B) * 8 * B * B : 0;
+};
+
 template <int B, int RT, bool TRANS>
 __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ cj,
@@ -893,8 +906,40 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __rest
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y, int R)
 {
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int STAGE = TRANS || RT == 1 ? 0 : SpmvStage<B>::doubles;
     const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-    spmv_rows<B, RT, TRANS>(wave_global * (64 / B), nb, rp, cj, srcpos, Ax, x, y, R);
+    const int64_t row0 = wave_global * RPC;
+    if constexpr (STAGE > 0) {
+        // The wavefront's rows own one contiguous run of blocks: copied to
+        // LDS with whole-wavefront loads, then read as from A (same values,
+        // same accumulation order).
+        __shared__ double stage[kWavesPerBlock][STAGE];
+        if (row0 < nb) {
+            const int64_t rend = row0 + RPC < nb ? row0 + RPC : nb;
+            const int32_t E0 = uniform_load(rp, row0);
+            const int64_t n = static_cast<int64_t>(uniform_load(rp, rend) - E0) * BB;
+            if (n <= STAGE) {
+                constexpr int PER = (STAGE + 63) / 64;
+                double* st = stage[threadIdx.x >> 6];
+                const double* src = Ax + static_cast<int64_t>(E0) * BB;
+                const int lane = lane_id();
+                double v[PER];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) v[k] = lane + 64 * k < n ? src[lane + 64 * k] : 0.0;
+#pragma unroll
+                for (int k = 0; k < PER; ++k)
+                    if (lane + 64 * k < n) st[lane + 64 * k] = v[k];
+                // one wavefront: its LDS accesses complete in issue order
+                __builtin_amdgcn_wave_barrier();
+                asm volatile("" ::: "memory");
+                spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, st, E0, x, y, R);
+                return;
+            }
+        }
+    }
+    spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, Ax, 0, x, y, R);
 }
 
 // ---------------------------------------------------------------------------

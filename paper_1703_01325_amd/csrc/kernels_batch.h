@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_batch(BatchSpmvArgs a)
         const int2 it = uniform_record(a.items, w);
         if (a.active && !uniform_load(a.active, it.x)) continue;
         const BatchSys S = uniform_record(a.sys, it.x);
-        BILU_BATCH_SWITCH_B(S.bs, (spmv_rows<B, 1, false>(it.y, S.nb, S.Ap, S.Aj, nullptr, S.Ax, a.x + S.voff,
+        BILU_BATCH_SWITCH_B(S.bs, (spmv_rows<B, 1, false>(it.y, S.nb, S.Ap, S.Aj, nullptr, S.Ax, 0, a.x + S.voff,
                                                           a.y + S.voff, 1)))
     }
 }

@@ -208,6 +208,20 @@ def random_block_pattern(nb: int, density: float, seed: int, symmetric=False):
     return Ap, Aj
 
 
+def graded_block_pattern(nb: int, lo: float, hi: float, seed: int):
+    """Random block pattern whose row density rises linearly from lo (first
+    row) to hi (last row): short and long rows in one matrix.  Stored
+    diagonal, sorted unique columns."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dens = np.linspace(lo, hi, nb)[:, None]
+    M = rng.random((nb, nb)) < dens
+    np.fill_diagonal(M, True)
+    Ap = np.zeros(nb + 1, dtype=np.int32)
+    Ap[1:] = np.cumsum(M.sum(axis=1))
+    Aj = np.nonzero(M)[1].astype(np.int32)
+    return Ap, Aj
+
+
 def random_block_values(Ap, Aj, bs, seed, dominance=1.0):
     """Random block values; diagonal blocks made row diagonally dominant."""
     rng = np.random.Generator(np.random.PCG64(seed))
