@@ -57,6 +57,9 @@ struct bilu_ctx {
     // factorisation with rows in LDS: update lists and per L level the LDS
     // bytes of its largest row (0: that level takes k_factor_rows)
     int32_t *d_upd_ptr = nullptr, *d_upd_f = nullptr, *d_upd_g = nullptr;
+    // per row of the L levels, in level order: {row, first entry, entries,
+    // pivots, first update pair, update pairs, 0, 0}
+    int32_t* d_frec = nullptr;
     std::vector<int32_t> fac_lds;
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
     int64_t* d_ATsrc = nullptr;
@@ -298,12 +301,15 @@ bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const i
     })
 }
 
-bool launch_factor(int bs, const int32_t* rows, int nrows, int lds, bilu_ctx* c, hipStream_t s)
+// Rows [first, first + nrows) of the L level order.
+bool launch_factor(int bs, int64_t first, int nrows, int lds, bilu_ctx* c, hipStream_t s)
 {
+    const int32_t* rows = c->d_Lrows + first;
     if (lds > 0) {
-        BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows_lds<B>), dim3(nrows), dim3(64), lds, s, rows, nrows,
-                                             c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_upd_ptr, c->d_upd_f, c->d_upd_g,
-                                             c->d_P, c->d_Dinv, c->d_bad))
+        const int4* rec = reinterpret_cast<const int4*>(c->d_frec + 8 * first);
+        BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows_lds<B>), dim3(nrows), dim3(64), lds, s, rec, nrows,
+                                             c->d_Pj, c->d_upd_ptr, c->d_upd_f, c->d_upd_g, c->d_P, c->d_Dinv,
+                                             c->d_bad))
     }
     BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows,
                                          c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_P, c->d_Dinv, c->d_bad))
@@ -350,13 +356,26 @@ bilu_status factor_plan(bilu_ctx* c)
     }
     const HostSweep& L = h.sweep[BILU_SWEEP_L];
     c->fac_lds.assign(static_cast<size_t>(L.nlev), 0);
+    std::vector<int32_t> rec(static_cast<size_t>(L.level_ptr[L.nlev]) * 8, 0);
     for (int l = 0; l < L.nlev; ++l) {
         int64_t m = 0;
-        for (int32_t x = L.level_ptr[l]; x < L.level_ptr[l + 1]; ++x) m = std::max(m, row_bytes[L.level_rows[x]]);
+        for (int32_t x = L.level_ptr[l]; x < L.level_ptr[l + 1]; ++x) {
+            const int32_t i = L.level_rows[x];
+            m = std::max(m, row_bytes[i]);
+            const int32_t e0 = h.Pp[i], d = h.Pdiag[i];
+            int32_t* q = &rec[static_cast<size_t>(x) * 8];
+            q[0] = i;
+            q[1] = e0;
+            q[2] = h.Pp[i + 1] - e0;
+            q[3] = d - e0;
+            q[4] = uptr[e0];
+            q[5] = uptr[d] - uptr[e0];
+        }
         c->fac_lds[l] = m <= kCap ? static_cast<int32_t>(m) : 0;
     }
     bilu_status st;
-    if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)))
+    if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)) ||
+        (st = upload(c, &c->d_frec, rec)))
         return st;
     return BILU_OK;
 }
@@ -903,7 +922,7 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     for (int l = 0; l < L.nlev; ++l) {
         const int n = L.level_ptr[l + 1] - L.level_ptr[l];
         const int lds = l < static_cast<int>(c->fac_lds.size()) ? c->fac_lds[l] : 0;
-        if (!launch_factor(h.bs, c->d_Lrows + L.level_ptr[l], n, lds, c, s)) return BILU_ERR_ARG;
+        if (!launch_factor(h.bs, L.level_ptr[l], n, lds, c, s)) return BILU_ERR_ARG;
     }
     timing_end(c, tslot, s);
     CK(hipGetLastError());

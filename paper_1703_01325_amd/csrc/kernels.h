@@ -1094,10 +1094,8 @@ __global__ __launch_bounds__(64) void k_factor_rows(const int32_t* __restrict__ 
 // LDS: [row blocks][pivot inverses][A_pj blocks] doubles, then the lists.
 // ---------------------------------------------------------------------------
 template <int B>
-__global__ __launch_bounds__(64) void k_factor_rows_lds(const int32_t* __restrict__ rows, int nrows,
-                                                        const int32_t* __restrict__ Pp,
+__global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__ rec, int nrows,
                                                         const int32_t* __restrict__ Pj,
-                                                        const int32_t* __restrict__ Pdiag,
                                                         const int32_t* __restrict__ upd_ptr,
                                                         const int32_t* __restrict__ upd_f,
                                                         const int32_t* __restrict__ upd_g, double* __restrict__ P,
@@ -1110,15 +1108,19 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int32_t* __restric
     __shared__ int sPiv;
     __shared__ int sBad;
     if (static_cast<int>(blockIdx.x) >= nrows) return;
-    const int i = rows[blockIdx.x];
+    // the row's record: row, first entry, entries, pivots (blocks 0..dk-1 of
+    // the row), first update pair, update pairs
+    const int4 ra = rec[2 * blockIdx.x];
+    const int4 rb = rec[2 * blockIdx.x + 1];
+    const int i = ra.x;
+    const int e0 = ra.y;
+    const int nrow = ra.z;
+    const int dk = ra.w;
+    const int u0 = rb.x;
+    const int npair = rb.y;
     const int t = threadIdx.x;
     const int r = t % B;
     const int c = t / B;
-    const int e0 = Pp[i];
-    const int nrow = Pp[i + 1] - e0;
-    const int dk = Pdiag[i] - e0;                 // pivots are blocks 0..dk-1 of the row
-    const int u0 = upd_ptr[e0];
-    const int npair = upd_ptr[e0 + dk] - u0;
     double* sRow = smem;
     double* sD = sRow + nrow * BB;
     double* sU = sD + dk * BB;
