@@ -173,7 +173,9 @@ bilu_status bilu_factor_diag(bilu_ctx* ctx, int precision, hipStream_t stream);
  * Copies the FP64 factors in pattern order to caller device buffers:
  * F_dev[nnzb_P*bs*bs] holds L at strictly lower positions, U' at strictly
  * upper positions and the identity at diagonal positions; Dinv_dev[nb*bs*bs]
- * holds D^{-1}.  Either pointer may be NULL.
+ * holds D^{-1}.  Either pointer may be NULL.  The sweeps read their own
+ * layouts, so F is formed from the factorisation (on `stream`) the first time
+ * it is asked for after bilu_factor_diag.
  */
 bilu_status bilu_get_factors(const bilu_ctx* ctx, double* F_dev, double* Dinv_dev,
                              hipStream_t stream);

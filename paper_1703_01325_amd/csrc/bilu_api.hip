@@ -38,6 +38,7 @@ struct bilu_ctx {
     bool dev_ready = false;
     bool factored = false;
     bool split_done = false;
+    mutable bool f_ready = false; // d_F holds the split factors of the current factorisation
     int precision = BILU_FACTORS_FP64;
     int sweep_mode = 2;
     int tile_rows = 0;          // rows per tile of the tiled layouts (0: not chosen yet)
@@ -380,7 +381,7 @@ bilu_status factor_plan(bilu_ctx* c)
     return BILU_OK;
 }
 
-bool launch_split(bilu_ctx* c, hipStream_t s)
+bool launch_split(const bilu_ctx* c, hipStream_t s)
 {
     const int64_t nP = static_cast<int64_t>(c->h.Pj.size());
     BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_split<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP,
@@ -586,13 +587,13 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         const int64_t nrs = static_cast<int64_t>(nchunks) * rpc;
         if (c->precision == BILU_FACTORS_FP32) {
             hipLaunchKernelGGL(dev::k_layout<float>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs, rpc,
-                               d.src, c->d_F, tr, static_cast<float*>(d.vals));
+                               d.src, c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, tr, static_cast<float*>(d.vals));
             if (d.dinv)
                 hipLaunchKernelGGL(dev::k_layout_dinv<float>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
                                    rpc, d.rows, c->d_Dinv, tr, static_cast<float*>(d.dinv));
         } else {
             hipLaunchKernelGGL(dev::k_layout<double>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs,
-                               rpc, d.src, c->d_F, tr, static_cast<double*>(d.vals));
+                               rpc, d.src, c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, tr, static_cast<double*>(d.vals));
             if (d.dinv)
                 hipLaunchKernelGGL(dev::k_layout_dinv<double>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
                                    rpc, d.rows, c->d_Dinv, tr, static_cast<double*>(d.dinv));
@@ -915,6 +916,7 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     const int64_t nP = static_cast<int64_t>(h.Pj.size());
     c->factored = false;
     c->split_done = false;
+    c->f_ready = false;
     const long tslot = timing_begin(c, BILU_K_FACTOR, s);
     hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax, c->d_P);
     hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(1), c->d_bad, INT_MAX);
@@ -942,7 +944,7 @@ bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
     if (!c || (precision != BILU_FACTORS_FP64 && precision != BILU_FACTORS_FP32)) return BILU_ERR_ARG;
     if (!c->factored) return BILU_ERR_STATE;
     const long tslot = timing_begin(c, BILU_K_SPLIT, s);
-    if (!launch_split(c, s)) return BILU_ERR_ARG;
+    c->f_ready = false;                       // F is formed when a caller asks for it
     c->precision = precision;
     for (int f = 0; f < 2; ++f)
         for (int w = 0; w < 4; ++w) c->ds[f][w].vals_precision = -1;
@@ -959,6 +961,10 @@ bilu_status bilu_get_factors(const bilu_ctx* c, double* F, double* Dinv, hipStre
     if (!c) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
     const size_t bb = static_cast<size_t>(c->h.bs) * c->h.bs;
+    if (F && !c->f_ready) {
+        if (!launch_split(c, s)) return BILU_ERR_ARG;
+        c->f_ready = true;
+    }
     if (F) CK(hipMemcpyAsync(F, c->d_F, c->h.Pj.size() * bb * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (Dinv)
         CK(hipMemcpyAsync(Dinv, c->d_Dinv, static_cast<size_t>(c->h.nb) * bb * sizeof(double),

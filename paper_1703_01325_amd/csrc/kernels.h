@@ -1258,9 +1258,13 @@ __global__ void k_split(int64_t nP, const int32_t* __restrict__ Prow, const int3
 
 // Factor blocks gathered into a sweep layout ([k][c][r][q] per chunk),
 // transposed for the U'^T / L^T sweeps, converted to T (FP64 or FP32, RNE).
+// The blocks are formed from P and D^-1 as k_split forms them (same
+// operations in the same order), so the layouts need no split pass.
 template <typename T>
 __global__ void k_layout(int64_t nslots, int B, int rpc, const int64_t* __restrict__ src,
-                         const double* __restrict__ F, int transposed, T* __restrict__ vals)
+                         const int32_t* __restrict__ Prow, const int32_t* __restrict__ Pj,
+                         const double* __restrict__ P, const double* __restrict__ Dinv, int transposed,
+                         T* __restrict__ vals)
 {
     const int BB = B * B;
     const int64_t total = nslots * BB;
@@ -1273,7 +1277,22 @@ __global__ void k_layout(int64_t nslots, int B, int rpc, const int64_t* __restri
         const int q = static_cast<int>(s % rpc);
         const int64_t sp = src[s];
         double v = 0.0;
-        if (sp >= 0) v = transposed ? F[sp * BB + r * B + c] : F[sp * BB + c * B + r];
+        if (sp >= 0) {
+            // element (fr, fc) of the factor block
+            const int fr = transposed ? c : r;
+            const int fc = transposed ? r : c;
+            const int i = Prow[sp];
+            const int j = Pj[sp];
+            if (j < i) {
+                v = P[sp * BB + fc * B + fr];
+            } else if (j == i) {
+                v = (fr == fc) ? 1.0 : 0.0;
+            } else {
+                const double* Di = Dinv + static_cast<int64_t>(i) * BB;
+                const double* U = P + sp * BB;
+                for (int u = 0; u < B; ++u) v += Di[u * B + fr] * U[fc * B + u];
+            }
+        }
         vals[(s - q) * BB + static_cast<int64_t>(el) * rpc + q] = static_cast<T>(v);
     }
 }
