@@ -584,16 +584,17 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
             }
         }
         const int tr = transposed_sweep(w) ? 1 : 0;
+        const int up = (w == BILU_SWEEP_U || w == BILU_SWEEP_UT) ? 1 : 0;
         const int64_t nrs = static_cast<int64_t>(nchunks) * rpc;
         if (c->precision == BILU_FACTORS_FP32) {
             hipLaunchKernelGGL(dev::k_layout<float>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs, rpc,
-                               d.src, c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, tr, static_cast<float*>(d.vals));
+                               d.src, c->d_Prow, c->d_P, c->d_Dinv, up, tr, static_cast<float*>(d.vals));
             if (d.dinv)
                 hipLaunchKernelGGL(dev::k_layout_dinv<float>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
                                    rpc, d.rows, c->d_Dinv, tr, static_cast<float*>(d.dinv));
         } else {
             hipLaunchKernelGGL(dev::k_layout<double>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs,
-                               rpc, d.src, c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, tr, static_cast<double*>(d.vals));
+                               rpc, d.src, c->d_Prow, c->d_P, c->d_Dinv, up, tr, static_cast<double*>(d.vals));
             if (d.dinv)
                 hipLaunchKernelGGL(dev::k_layout_dinv<double>, dim3(grid_for(nrs * bb)), dim3(256), 0, s, nrs, h.bs,
                                    rpc, d.rows, c->d_Dinv, tr, static_cast<double*>(d.dinv));

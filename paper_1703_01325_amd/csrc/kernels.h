@@ -1259,12 +1259,13 @@ __global__ void k_split(int64_t nP, const int32_t* __restrict__ Prow, const int3
 // Factor blocks gathered into a sweep layout ([k][c][r][q] per chunk),
 // transposed for the U'^T / L^T sweeps, converted to T (FP64 or FP32, RNE).
 // The blocks are formed from P and D^-1 as k_split forms them (same
-// operations in the same order), so the layouts need no split pass.
+// operations in the same order), so the layouts need no split pass.  A
+// sweep reads blocks of one triangle only: upper (U', U'^T) = D_i^-1 U_ij,
+// else L_ij itself.
 template <typename T>
 __global__ void k_layout(int64_t nslots, int B, int rpc, const int64_t* __restrict__ src,
-                         const int32_t* __restrict__ Prow, const int32_t* __restrict__ Pj,
-                         const double* __restrict__ P, const double* __restrict__ Dinv, int transposed,
-                         T* __restrict__ vals)
+                         const int32_t* __restrict__ Prow, const double* __restrict__ P,
+                         const double* __restrict__ Dinv, int upper, int transposed, T* __restrict__ vals)
 {
     const int BB = B * B;
     const int64_t total = nslots * BB;
@@ -1281,14 +1282,10 @@ __global__ void k_layout(int64_t nslots, int B, int rpc, const int64_t* __restri
             // element (fr, fc) of the factor block
             const int fr = transposed ? c : r;
             const int fc = transposed ? r : c;
-            const int i = Prow[sp];
-            const int j = Pj[sp];
-            if (j < i) {
+            if (!upper) {
                 v = P[sp * BB + fc * B + fr];
-            } else if (j == i) {
-                v = (fr == fc) ? 1.0 : 0.0;
             } else {
-                const double* Di = Dinv + static_cast<int64_t>(i) * BB;
+                const double* Di = Dinv + static_cast<int64_t>(Prow[sp]) * BB;
                 const double* U = P + sp * BB;
                 for (int u = 0; u < B; ++u) v += Di[u * B + fr] * U[fc * B + u];
             }
