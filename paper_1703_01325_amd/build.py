@@ -1,7 +1,10 @@
 """Builds libbilu.so for gfx950 in-tree (paper_1703_01325_amd/_build/).
 
-hipcc compiles the HIP translation unit for the device (gfx950) and the
-host; g++ compiles the host-only analysis.  Every HIP compile carries
+hipcc compiles the HIP translation units for the device (gfx950) and the
+host -- the ABI and the non-sweep kernels (bilu_api.hip), the sweep and
+SpMV kernels once per block size (sweep_b.hip with -DBILU_B=1..8) and the
+batch sweep (batch_sweep.hip) -- in parallel; g++ compiles the host-only
+analysis.  Every HIP compile carries
 ``-Xclang -target-feature -Xclang -packed-fp32-ops`` (no packed FP32 ops).
 """
 from __future__ import annotations
@@ -38,20 +41,26 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
-    jobs = [
-        [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "bilu_api.hip"),
-         "-o", os.path.join(OUT_DIR, "bilu_api.o")],
-        ["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "analysis.cpp"),
-         "-o", os.path.join(OUT_DIR, "analysis.o")],
-    ]
-    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+    objs = []
+    jobs = []
+
+    def hip_job(src, obj, *defs):
+        objs.append(os.path.join(OUT_DIR, obj))
+        jobs.append([hipcc, *HIP_FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", objs[-1]])
+
+    hip_job("bilu_api.hip", "bilu_api.o")
+    for b in range(1, 9):
+        hip_job("sweep_b.hip", f"sweep_b{b}.o", f"-DBILU_B={b}")
+    hip_job("batch_sweep.hip", "batch_sweep.o")
+    objs.append(os.path.join(OUT_DIR, "analysis.o"))
+    jobs.append(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "analysis.cpp"), "-o", objs[-1]])
+    workers = max(1, min(len(jobs), int(os.environ.get("BILU_BUILD_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
         for r in ex.map(_run, jobs):
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout + r.stderr)
     tmp = LIB + f".tmp{os.getpid()}"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}",
-          os.path.join(OUT_DIR, "bilu_api.o"), os.path.join(OUT_DIR, "analysis.o"),
-          "-o", tmp, f"-Wl,-rpath,{ROCM}/lib"])
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, f"-Wl,-rpath,{ROCM}/lib"])
     os.replace(tmp, LIB)
     return LIB
 

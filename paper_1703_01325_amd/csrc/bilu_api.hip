@@ -14,6 +14,7 @@
 #include "bilu_internal.h"
 #include "kernels.h"
 #include "kernels_batch.h"
+#include "launch.h"
 
 using namespace bilu;
 using dev::KState;
@@ -183,123 +184,29 @@ bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; 
     }                               \
     return false;
 
-template <typename T, int RT>
-bool launch_sweep_b(int bs, int blocks, hipStream_t s, const SweepArgs& a)
-{
-    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_sweep<B, T, RT>), dim3(blocks), dim3(dev::kThreads), 0, s, a))
-}
-
 // rt: right-hand-side columns per pass (1, 4 or 8)
 bool launch_sweep(int bs, int prec, int rt, int blocks, hipStream_t s, const SweepArgs& a)
 {
-    if (prec == BILU_FACTORS_FP32) {
-        if (rt == 1) return launch_sweep_b<float, 1>(bs, blocks, s, a);
-        if (rt == 4) return launch_sweep_b<float, 4>(bs, blocks, s, a);
-        return rt == 8 && launch_sweep_b<float, 8>(bs, blocks, s, a);
-    }
-    if (rt == 1) return launch_sweep_b<double, 1>(bs, blocks, s, a);
-    if (rt == 4) return launch_sweep_b<double, 4>(bs, blocks, s, a);
-    return rt == 8 && launch_sweep_b<double, 8>(bs, blocks, s, a);
-}
-
-template <typename T, bool FUSE, int B, bool MULTI>
-bool launch_tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
-{
-    if constexpr (B >= 5) {
-        if (kmax != 3) return false;
-        hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a);
-        return true;
-    } else {
-        switch (kmax) {
-        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
-        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 6, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
-        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 9, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
-        }
-        return false;
-    }
-}
-
-// Tile groups: a.group wavefronts per workgroup.
-template <typename T, bool FUSE, int B, bool MULTI>
-bool launch_grouped_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
-{
-    const dim3 threads(64 * a.group);
-    if constexpr (B >= 5) {
-        if (kmax != 3) return false;
-        hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a);
-        return true;
-    } else {
-        switch (kmax) {
-        case 3: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a); return true;
-        case 6: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 6, MULTI>), dim3(blocks), threads, lds, s, a); return true;
-        case 9: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 9, MULTI>), dim3(blocks), threads, lds, s, a); return true;
-        }
-        return false;
-    }
-}
-
-template <typename T, bool FUSE>
-bool launch_tiled_b(int bs, int kmax, bool multi, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
-{
-    if (a.group > 1) {
-        if (a.group > kGroupMax) return false;
-        if (multi) {
-            BILU_SWITCH_B(bs, if (!(launch_grouped_k<T, FUSE, B, true>(kmax, blocks, lds, s, a))) return false)
-        }
-        BILU_SWITCH_B(bs, if (!(launch_grouped_k<T, FUSE, B, false>(kmax, blocks, lds, s, a))) return false)
-    }
-    if (multi) {
-        BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B, true>(kmax, blocks, lds, s, a))) return false)
-    }
-    BILU_SWITCH_B(bs, if (!(launch_tiled_k<T, FUSE, B, false>(kmax, blocks, lds, s, a))) return false)
+    BILU_SWITCH_B(bs, if (!launch::sweep<B>(prec, rt, blocks, s, a)) return false)
 }
 
 // One wavefront per tile (a.group == 1) or per member tile of a group.
 bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hipStream_t s,
                   const TiledArgs& a)
 {
-    if (prec == BILU_FACTORS_FP32)
-        return fuse ? launch_tiled_b<float, true>(bs, kmax, multi, blocks, lds, s, a)
-                    : launch_tiled_b<float, false>(bs, kmax, multi, blocks, lds, s, a);
-    return fuse ? launch_tiled_b<double, true>(bs, kmax, multi, blocks, lds, s, a)
-                : launch_tiled_b<double, false>(bs, kmax, multi, blocks, lds, s, a);
+    BILU_SWITCH_B(bs, if (!launch::tiled<B>(kmax, prec, fuse, multi, blocks, lds, s, a)) return false)
 }
 
-template <typename T, int B>
-bool launch_fused_k(int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a, const dev::FusedSpmvArgs& m)
+bool launch_fused(int bs, int kmax, int prec, int blocks, size_t lds, hipStream_t s, const TiledArgs& a,
+                  const dev::FusedSpmvArgs& m)
 {
-    if constexpr (B >= 5) {
-        if (kmax != 3) return false;
-        hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 3>), dim3(blocks), dim3(64), lds, s, a, m);
-        return true;
-    } else {
-        switch (kmax) {
-        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 3>), dim3(blocks), dim3(64), lds, s, a, m); return true;
-        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 6>), dim3(blocks), dim3(64), lds, s, a, m); return true;
-        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 9>), dim3(blocks), dim3(64), lds, s, a, m); return true;
-        }
-        return false;
-    }
+    BILU_SWITCH_B(bs, if (!launch::fused<B>(kmax, prec, blocks, lds, s, a, m)) return false)
 }
 
-template <typename T>
-bool launch_fused_b(int bs, int kmax, int blocks, size_t lds, hipStream_t s, const TiledArgs& a,
-                    const dev::FusedSpmvArgs& m)
+bool launch_spmv(int bs, int rt, bool tr, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src,
+                 const double* Ax, const double* x, double* y, int R, hipStream_t s)
 {
-    BILU_SWITCH_B(bs, if (!(launch_fused_k<T, B>(kmax, blocks, lds, s, a, m))) return false)
-}
-
-template <int RT, bool TR>
-bool launch_spmv_b(int bs, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
-                   const double* x, double* y, int R, hipStream_t s)
-{
-    BILU_SWITCH_B(bs, {
-        constexpr int RPC = 64 / B;
-        const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
-        const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
-        hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src,
-                           Ax, x, y, R);
-    })
+    BILU_SWITCH_B(bs, if (!launch::spmv<B>(rt, tr, nb, rp, cj, src, Ax, x, y, R, s)) return false)
 }
 
 // Rows [first, first + nrows) of the L level order.
@@ -736,17 +643,9 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
     const long tslot = timing_begin(c, BILU_K_SPMV, s);
     if (transpose) {
         if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
-        switch (rhs_tile(c, R)) {
-        case 1: ok = launch_spmv_b<1, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s); break;
-        case 4: ok = launch_spmv_b<4, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s); break;
-        default: ok = launch_spmv_b<8, true>(h.bs, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s); break;
-        }
+        ok = launch_spmv(h.bs, rhs_tile(c, R), true, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s);
     } else {
-        switch (rhs_tile(c, R)) {
-        case 1: ok = launch_spmv_b<1, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s); break;
-        case 4: ok = launch_spmv_b<4, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s); break;
-        default: ok = launch_spmv_b<8, false>(h.bs, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s); break;
-        }
+        ok = launch_spmv(h.bs, rhs_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s);
     }
     timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
@@ -815,8 +714,7 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
     const int blocks = persistent_blocks(c, std::min(m.nsched, hu.ntiles + c->num_cu), 1, 8);
     a.total_waves = static_cast<unsigned int>(blocks);
     const size_t lds = static_cast<size_t>(a.tile_rows + 1) * c->h.bs * sizeof(double);
-    const bool ok = c->precision == BILU_FACTORS_FP32 ? launch_fused_b<float>(c->h.bs, hu.kmax, blocks, lds, s, a, m)
-                                                      : launch_fused_b<double>(c->h.bs, hu.kmax, blocks, lds, s, a, m);
+    const bool ok = launch_fused(c->h.bs, hu.kmax, c->precision, blocks, lds, s, a, m);
     timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
     CK(hipGetLastError());

@@ -1,946 +1,12 @@
-// HIP kernels for gfx950 (CDNA4, wave64).  Included once, by bilu_api.hip.
-//
-// Block values are column-major b x b (Section 2.1).  Vectors are
-// (nb*b) x R row-major.  All floating-point accumulation is FP64; factor
-// values may be stored as FP32 and are widened before they are multiplied.
+// HIP kernels for gfx950 (CDNA4, wave64) other than the sweeps and the
+// SpMV: backfill, factorisation, split and layouts, Krylov vector and
+// scalar steps.  Included once, by bilu_api.hip.
 #pragma once
 
-#include <hip/hip_runtime.h>
-#include <cstdint>
+#include "sweep_kernels.h"
 
 namespace bilu {
 namespace dev {
-
-constexpr int kThreads = 256;          // 4 wavefronts per workgroup
-constexpr int kWavesPerBlock = kThreads / 64;
-constexpr int kRedBlocks = 512;        // fixed grid of the two-stage reductions
-constexpr int kMaxRhs = 32;
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-__device__ __forceinline__ double widen(double v) { return v; }
-__device__ __forceinline__ double widen(float v) { return static_cast<double>(v); }
-
-// ---------------------------------------------------------------------------
-// Readiness inside one persistent sweep is carried by the values themselves.
-// Before a sweep starts, every entry of its output vector holds kNotReady,
-// a signalling-NaN bit pattern that no arithmetic result can have (results
-// are quiet NaNs at worst, and a result that would copy the pattern is
-// replaced by the canonical quiet NaN).  A row is published by writing its
-// values with device-coherent stores; a reader polls each value it needs
-// with device-coherent loads until it differs from kNotReady.  No flags, no
-// fences, no cache maintenance: one memory round trip per dependency.
-// The invariant "output starts at kNotReady" is kept by the two sweeps of
-// an application: the first resets the second's output rows, the second
-// resets the first's output rows after it has read them.
-// ---------------------------------------------------------------------------
-constexpr unsigned long long kNotReadyBits = 0x7FF4DEADBEEF1234ULL;
-constexpr unsigned long long kQuietNaNBits = 0x7FF8000000000000ULL;
-
-__device__ __forceinline__ double not_ready() { return __longlong_as_double(static_cast<long long>(kNotReadyBits)); }
-
-__device__ __forceinline__ bool is_not_ready(double v)
-{
-    return static_cast<unsigned long long>(__double_as_longlong(v)) == kNotReadyBits;
-}
-
-__device__ __forceinline__ double publishable(double v)
-{
-    return is_not_ready(v) ? __longlong_as_double(static_cast<long long>(kQuietNaNBits)) : v;
-}
-
-__device__ __forceinline__ double coherent_load(const double* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void coherent_store(double* p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Waits (bounded) until *p is published; returns the value.  Past the limit
-// the timeout is recorded in *status and whatever was read is returned, so
-// the wavefront still finishes.
-__device__ __forceinline__ double await_value(const double* p, double v, unsigned int limit, int* status)
-{
-    unsigned int spins = 0;
-    while (is_not_ready(v)) {
-        if (++spins > limit) {
-            atomicOr(status, 1);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        v = coherent_load(p);
-    }
-    return v;
-}
-
-// Waits (bounded) until none of the values v[(g*B + c)*RT + t] shows
-// kNotReady, for the rows j[g] >= 0 (g < G), components c < B and columns
-// t < RT with c0 + t < R; the value lives at out[(j[g]*B + c)*R + c0 + t].
-// Each poll re-reads every value still missing with a device-coherent load,
-// all in one round trip.  Past the limit the timeout is recorded in *status
-// and whatever was read is kept, so the wavefront still finishes.
-template <int G, int B, int RT>
-__device__ __forceinline__ bool rows_missing(const double (&v)[G * B * RT], const int (&j)[G], int R, int c0)
-{
-    // bitwise, not short-circuit: no branches
-    bool pending = false;
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int c = 0; c < B; ++c)
-#pragma unroll
-            for (int t = 0; t < RT; ++t)
-                pending |= (j[g] >= 0) & (RT == 1 || c0 + t < R) & is_not_ready(v[(g * B + c) * RT + t]);
-    return pending;
-}
-
-template <int G, int B, int RT>
-__device__ __forceinline__ void await_rows(double (&v)[G * B * RT], const int (&j)[G], const double* out, int R,
-                                           int c0, unsigned int limit, int* status)
-{
-    // the first test reads only the values at hand, outside the loop, so
-    // the common case waits for nothing else
-    bool pending = rows_missing<G, B, RT>(v, j, R, c0);
-    for (unsigned int spins = 0; pending;) {
-        if (++spins > limit) {
-            atomicOr(status, 1);
-            return;
-        }
-        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int c = 0; c < B; ++c)
-#pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    const int i = (g * B + c) * RT + t;
-                    if (j[g] >= 0 && (RT == 1 || c0 + t < R) && is_not_ready(v[i]))
-                        v[i] = coherent_load(out + (static_cast<int64_t>(j[g]) * B + c) * R + c0 + t);
-                }
-        pending = rows_missing<G, B, RT>(v, j, R, c0);
-    }
-}
-
-// Read-only, wave-uniform load through the constant address space, which
-// the compiler turns into a scalar load (its own counter, so vector loads in
-// flight are not waited for).  Only for data no kernel writes while it runs.
-template <typename T>
-__device__ __forceinline__ T uniform_load(const T* p, int64_t i)
-{
-    return ((const __attribute__((address_space(4))) T*)p)[i];
-}
-
-// The same for a trivially copyable record, word by word.
-template <typename T>
-__device__ __forceinline__ T uniform_record(const T* p, int64_t i)
-{
-    static_assert(sizeof(T) % 4 == 0, "record of whole words");
-    constexpr int kWords = static_cast<int>(sizeof(T) / 4);
-    const int* w = reinterpret_cast<const int*>(p + i);
-    union {
-        int words[kWords];
-        T rec;
-    } u;
-#pragma unroll
-    for (int k = 0; k < kWords; ++k) u.words[k] = uniform_load(w, k);
-    return u.rec;
-}
-
-__device__ __forceinline__ int grab_ticket(unsigned long long* ticket)
-{
-    unsigned long long t = 0;
-    if (lane_id() == 0) t = atomicAdd(ticket, 1ULL);
-    t = __shfl(t, 0);
-    return t > 0x3fffffffULL ? 0x3fffffff : static_cast<int>(t);
-}
-
-// The last wavefront of a persistent launch to finish rewinds the ticket
-// for the next launch on the stream (every wavefront takes exactly one
-// ticket past the end, so all tickets have been taken by then).
-__device__ __forceinline__ void finish_persistent(unsigned long long* ticket, unsigned int* done,
-                                                  unsigned int total_waves)
-{
-    if (lane_id() == 0) {
-        const unsigned int prev = atomicAdd(done, 1u);
-        if (prev + 1 == total_waves) {
-            __hip_atomic_store(ticket, 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Level-scheduled sweep (Eq 4, Algorithm 6) of one unit-diagonal block
-// triangular factor, optionally with the block-diagonal D^{-1} product of
-// Algorithm 7 fused in front:
-//     out_i = (fuse ? Dv_i rhs_i : rhs_i) - sum_k F_ik out_{col(i,k)}
-// Level-chunk form: one wavefront per chunk of rpc = 64/B block rows of one
-// level; lane (q, r) = (lane / B, lane % B) owns component r of the
-// chunk's q-th row.  Values of a chunk are stored [k][c][r][q], so for a
-// fixed dependency k and block column c the wavefront reads B*rpc
-// consecutive values.
-//
-// persistent = 0: the launch covers the chunks [chunk_begin, chunk_end) of
-// one level, all of whose dependencies were written by earlier launches.
-// persistent = 1: one launch covers the whole sweep; wavefronts take chunks
-// in level order from an atomic ticket and poll the values they read.  A
-// chunk only reads rows of chunks with smaller tickets, held by wavefronts
-// that are already running, so the sweep always drains.
-// ---------------------------------------------------------------------------
-struct SweepArgs {
-    const int64_t* chunk_off;
-    const int32_t* rows;
-    const int32_t* cols;
-    const void* vals;
-    const void* dinv;
-    const double* rhs;
-    double* out;
-    double* reset;      // rows of this buffer are set to kNotReady (may be null)
-    unsigned long long* ticket;
-    unsigned int* done;
-    int* status;
-    int nchunks;
-    int chunk_begin;
-    int chunk_end;
-    int R;
-    int fuse;
-    int persistent;
-    unsigned int total_waves;
-    unsigned int spin_limit;
-};
-
-// One chunk of a level-chunk sweep, by one wavefront.
-template <int B, typename T, int RT>
-__device__ __forceinline__ void sweep_chunk(SweepArgs a, int chunk)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    const int lane = lane_id();
-    const int q = lane / B;
-    const int r = lane - q * B;
-    const bool lane_ok = q < RPC;
-    const T* __restrict__ vals = static_cast<const T*>(a.vals);
-    const T* __restrict__ dinv = static_cast<const T*>(a.dinv);
-    const int R = a.R;
-    const int row = lane_ok ? a.rows[static_cast<int64_t>(chunk) * RPC + q] : -1;
-    const int64_t off = a.chunk_off[chunk];
-    const int w = static_cast<int>((a.chunk_off[chunk + 1] - off) / RPC);
-    if (row < 0) return;
-    for (int c0 = 0; c0 < R; c0 += RT) {
-        double acc[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) acc[t] = 0.0;
-        if (a.fuse) {
-            const int64_t dbase = static_cast<int64_t>(chunk) * RPC * BB + r * RPC + q;
-#pragma unroll
-            for (int c = 0; c < B; ++c) {
-                const double d = widen(dinv[dbase + c * B * RPC]);
-                const double* src = a.rhs + (static_cast<int64_t>(row) * B + c) * R + c0;
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    if (RT == 1 || c0 + t < R) acc[t] += d * src[t];
-            }
-        } else {
-            const double* src = a.rhs + (static_cast<int64_t>(row) * B + r) * R + c0;
-#pragma unroll
-            for (int t = 0; t < RT; ++t)
-                if (RT == 1 || c0 + t < R) acc[t] = src[t];
-        }
-        // dependencies in groups of KG: all their values are requested
-        // together and missing ones polled together (one round trip each)
-        constexpr int KG = RT == 1 ? (B <= 4 ? 4 : 2) : 1;
-        for (int k0 = 0; k0 < w; k0 += KG) {
-            int j[KG];
-#pragma unroll
-            for (int g = 0; g < KG; ++g)
-                j[g] = k0 + g < w ? a.cols[off + static_cast<int64_t>(k0 + g) * RPC + q] : -1;
-            double xv[KG * B * RT];
-#pragma unroll
-            for (int g = 0; g < KG; ++g)
-#pragma unroll
-                for (int c = 0; c < B; ++c)
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const double* xp = a.out + (static_cast<int64_t>(j[g]) * B + c) * R + c0 + t;
-                        const bool want = j[g] >= 0 && (RT == 1 || c0 + t < R);
-                        xv[(g * B + c) * RT + t] = want ? (a.persistent ? coherent_load(xp) : *xp) : 0.0;
-                    }
-            if (a.persistent) await_rows<KG, B, RT>(xv, j, a.out, R, c0, a.spin_limit, a.status);
-#pragma unroll
-            for (int g = 0; g < KG; ++g) {
-                if (j[g] < 0) continue;
-                const int64_t vbase = (off + static_cast<int64_t>(k0 + g) * RPC) * BB + r * RPC + q;
-#pragma unroll
-                for (int c = 0; c < B; ++c) {
-                    const double v = widen(vals[vbase + c * B * RPC]);
-#pragma unroll
-                    for (int t = 0; t < RT; ++t)
-                        if (RT == 1 || c0 + t < R) acc[t] -= v * xv[(g * B + c) * RT + t];
-                }
-            }
-        }
-        const int64_t o = (static_cast<int64_t>(row) * B + r) * R + c0;
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            if (RT == 1 || c0 + t < R) {
-                if (a.reset) a.reset[o + t] = not_ready();
-                if (a.persistent) coherent_store(a.out + o + t, publishable(acc[t]));
-                else a.out[o + t] = publishable(acc[t]);
-            }
-        }
-    }
-}
-
-template <int B, typename T, int RT>
-__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
-{
-    if (a.persistent) {
-        for (int chunk = grab_ticket(a.ticket); chunk < a.nchunks; chunk = grab_ticket(a.ticket))
-            sweep_chunk<B, T, RT>(a, chunk);
-        finish_persistent(a.ticket, a.done, a.total_waves);
-    } else {
-        const int chunk = a.chunk_begin + static_cast<int>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-        if (chunk < a.chunk_end) sweep_chunk<B, T, RT>(a, chunk);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Tiled sweep: one wavefront owns a contiguous range of block rows (a tile)
-// and walks it in its own level order (levels of Eq 4 restricted to the
-// dependencies inside the tile), one chunk of up to 64/B rows at a time.
-// A dependency inside the tile is read from LDS, where the wavefront keeps
-// every row it has finished; a dependency on another tile is read from
-// global memory.  Tiles are taken from a ticket in sweep order, and every
-// row a tile reads from outside lies in an earlier tile, so the sweep
-// drains.  Dependency codes are byte offsets: code >= 0 is row code/(8B) of
-// the vectors, code < 0 is byte (code & INT32_MAX) of the tile's LDS; a
-// padding slot points at LDS row tile_rows, kept at zero, and has zero
-// factor values.  A wavefront sweeps one right-hand side (MULTI: one per
-// (tile, column)); k_sweep_grouped runs several tiles per workgroup.
-//
-// The walk is software-pipelined over a ring of NR register states: at step
-// i the wavefront issues the metadata loads of chunk i + 2(NR-1) (row ids,
-// dependency codes), the data loads of chunk i + NR - 1 (factor values,
-// right-hand side, D^{-1} row, values read from other tiles, addressed by
-// metadata that arrived NR - 1 steps earlier) and computes chunk i.  Every
-// batch is branch-free with a fixed instruction count: chunk indices past
-// the tile clamp to its last chunk, and the first KMAX slot rows of a chunk
-// are always read (every chunk has at least KMAX).  Chunk-wide addresses
-// are scalar; a lane adds a fixed offset, so the per-slot loads need no
-// vector address arithmetic.  Values from other tiles are prefetched with plain,
-// cacheable loads: during a sweep an output location only ever holds
-// kNotReady or its final value, so a stale cached copy can only show
-// kNotReady, and the values still showing it are then polled together with
-// device-coherent loads.  Dependencies past the first KMAX of a row take an
-// unpipelined path.
-// ---------------------------------------------------------------------------
-struct TiledArgs {
-    const int32_t* tile_chunk_ptr;
-    const int32_t* tile_lo;
-    const int32_t* chunk_row;     // first slot row of each chunk (slot offset / (64/B))
-    const int32_t* rows;
-    const int32_t* deps;
-    const void* vals;
-    const void* dinv;
-    const double* rhs;
-    double* out;
-    double* reset;
-    unsigned long long* ticket;
-    unsigned int* done;
-    int* status;
-    int ntiles;
-    int tile_rows;                // LDS row group*tile_rows is kept at zero (ring: ring*64/B)
-    int ring;                     // > 0: LDS keeps the rows of the last `ring` chunks only
-    int R;                        // right-hand sides (vectors are (n x R) row-major)
-    unsigned int total_waves;     // grouped: workgroups
-    unsigned int spin_limit;
-    // tile groups (k_sweep_grouped): member m of group g sweeps
-    // group_tiles[g*group + m]; chunk_wait[c*kGroupMax + m] chunks of member m
-    // must be finished before chunk c reads the group's LDS
-    const int32_t* group_tiles;
-    const int32_t* chunk_wait;
-    int group;
-    int ngroups;
-};
-
-// Byte offset of component c of a block row (row_byte = row * B * 8) in the
-// column this wavefront sweeps.  One right-hand side: row_byte + 8c.
-// Several (MULTI): the vectors are (n x R) row-major, element (i, j) at
-// i*R + j.
-template <bool MULTI>
-struct ColMap {
-    uint32_t R;
-    uint32_t j8;      // 8 * column
-    __device__ __forceinline__ uint32_t at(uint32_t row_byte, int c) const
-    {
-        return MULTI ? row_byte * R + static_cast<uint32_t>(c) * 8u * R + j8 : row_byte + static_cast<uint32_t>(c) * 8u;
-    }
-};
-
-// Load at a 32-bit byte offset from a (wave-uniform) base: the address is
-// formed by the load itself.  Vectors of the tiled sweep are below 2 GiB.
-template <typename T>
-__device__ __forceinline__ T load_at(const T* base, uint32_t byte_off)
-{
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
-template <int KMAX>
-struct TileMeta {
-    int64_t off;         // first slot of the chunk (wave-uniform)
-    int w;               // slots per row (wave-uniform)
-    int row;             // as loaded (unused row slots hold -1)
-    int code[KMAX];      // dependency codes of slot rows 0..KMAX-1
-};
-
-template <int B, typename T, int KMAX, bool FUSE>
-struct TileData {
-    int64_t off;
-    int w;
-    int row;
-    int code[KMAX];
-    T f[KMAX][B];        // factor values as stored
-    double x[KMAX][B];   // values read from other tiles (may show kNotReady)
-    double h[FUSE ? B : 1];
-    T d[FUSE ? B : 1];
-};
-
-// `chunk` is wave-uniform; its first slot row and width (srow, w) were
-// read through the scalar cache a step earlier, and every address below is
-// a scalar base plus a per-lane constant.
-template <int B, int KMAX>
-__device__ __forceinline__ void tile_meta(const TiledArgs& a, int chunk, int srow, int w, int qc,
-                                          TileMeta<KMAX>& m)
-{
-    constexpr int RPC = 64 / B;
-    m.off = static_cast<int64_t>(srow) * RPC;
-    m.w = w;
-    const int32_t* rp = a.rows + static_cast<int64_t>(chunk) * RPC;
-    const int32_t* dp = a.deps + m.off;
-    m.row = rp[qc];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) m.code[k] = dp[k * RPC + qc];
-}
-
-template <int B, typename T, int KMAX, bool FUSE, bool MULTI>
-__device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc, int r, const TileMeta<KMAX>& m,
-                                          TileData<B, T, KMAX, FUSE>& s, const ColMap<MULTI>& cm)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    const int lane_off = r * RPC + qc;
-    s.off = m.off;
-    s.w = m.w;
-    s.row = m.row;
-    const T* vp = static_cast<const T*>(a.vals) + m.off * BB;
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        s.code[k] = m.code[k];
-#pragma unroll
-        for (int c = 0; c < B; ++c) s.f[k][c] = vp[k * RPC * BB + c * B * RPC + lane_off];
-    }
-    // unused row slots of a partly filled chunk hold -1: read row 0 instead
-    const uint32_t rowc_b = static_cast<uint32_t>(m.row >= 0 ? m.row : 0) * (B * 8u);
-    if (FUSE) {
-        const T* dp = static_cast<const T*>(a.dinv) + static_cast<int64_t>(chunk) * RPC * BB;
-#pragma unroll
-        for (int c = 0; c < B; ++c) {
-            s.h[c] = load_at(a.rhs, cm.at(rowc_b, c));
-            s.d[c] = dp[c * B * RPC + lane_off];
-        }
-    } else {
-        s.h[0] = load_at(a.rhs, cm.at(rowc_b, r));
-    }
-    // tile-local and padding slots do not use the value: every such lane
-    // reads row 0, so the wavefront touches one cache line for them
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : 0u;
-#pragma unroll
-        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), cm.at(xb, c));
-    }
-}
-
-// Waits (bounded) until no value of another tile that a lane needs shows
-// kNotReady; every value still missing is re-read with a device-coherent
-// load, all in one round trip per poll.
-template <int K, int B, bool MULTI>
-__device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)[K], const double* out,
-                                           const ColMap<MULTI>& cm, unsigned int limit, int* status)
-{
-    bool pending = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & is_not_ready(v[k * B + c]);
-    for (unsigned int spins = 0; pending;) {
-        if (++spins > limit) {
-            atomicOr(status, 1);
-            return;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        pending = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int c = 0; c < B; ++c)
-                if (code[k] >= 0 && is_not_ready(v[k * B + c]))
-                    v[k * B + c] = coherent_load(reinterpret_cast<const double*>(
-                        reinterpret_cast<const char*>(out) + cm.at(static_cast<uint32_t>(code[k]), c)));
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & is_not_ready(v[k * B + c]);
-    }
-}
-
-// Tile groups: waits (bounded) until each earlier member of the workgroup has
-// finished the chunks this chunk reads from it.  A member publishes its count
-// of finished chunks in LDS after the chunk's rows; the LDS operations of one
-// wavefront take effect in issue order, so a count that is seen covers every
-// row written before it.
-__device__ __forceinline__ void await_members(const int* prog, const int (&need)[kGroupMax], unsigned int limit,
-                                              int* status)
-{
-    for (unsigned int spins = 0;;) {
-        bool behind = false;
-#pragma unroll
-        for (int m = 0; m < kGroupMax; ++m)
-            behind |= __hip_atomic_load(prog + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need[m];
-        if (!behind) break;
-        if (++spins > limit) {
-            atomicOr(status, 1);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    // the row reads that follow stay after the counts
-    asm volatile("" ::: "memory");
-}
-
-// lds: the workgroup's LDS (dependency codes are offsets into it);
-// tile_vals: this tile's rows in it.
-template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool GROUPED>
-__device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
-                                             const double* lds_base, double* tile_vals,
-                                             const TileData<B, T, KMAX, FUSE>& s, const int (&need)[kGroupMax],
-                                             const int* prog, const ColMap<MULTI>& cm, int wbase)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    // Every lane takes delivery of the whole batch here, also lanes that
-    // compute nothing: the compiler then never finds a load of this batch
-    // still in flight when it reuses its registers, which would cost a wait
-    // for all later loads.
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-#pragma unroll
-        for (int c = 0; c < B; ++c) asm volatile("" ::"v"(s.f[k][c]), "v"(s.x[k][c]));
-    }
-#pragma unroll
-    for (int c = 0; c < (FUSE ? B : 1); ++c) asm volatile("" ::"v"(s.h[c]), "v"(s.d[c]));
-    // values from other tiles: the prefetched copies, the ones still showing
-    // kNotReady polled together
-    double xg[KMAX * B];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-        for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
-    await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
-    if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
-    if (!active || s.row < 0) return;
-    double acc;
-    if (FUSE) {
-        acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < B; ++c) acc += widen(s.d[c]) * s.h[c];
-    } else {
-        acc = s.h[0];
-    }
-    // branch-free: every slot reads LDS (its own row for tile-local and
-    // padding slots, row 0 otherwise) and selects.  Each LDS value is handed
-    // to an empty asm statement once all are issued, so the compiler keeps
-    // the reads unconditional (instead of turning each select into a branch
-    // around its read) and waits for them once.
-    const char* lds = reinterpret_cast<const char*>(lds_base);
-    double lv[KMAX * B];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const uint32_t lb = s.code[k] < 0 ? static_cast<uint32_t>(s.code[k]) & 0x7fffffffu : 0u;
-#pragma unroll
-        for (int c = 0; c < B; ++c) lv[k * B + c] = *reinterpret_cast<const double*>(lds + lb + c * 8u);
-    }
-#pragma unroll
-    for (int i = 0; i < KMAX * B; ++i) asm volatile("" : "+v"(lv[i]));
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const bool local = s.code[k] < 0;
-#pragma unroll
-        for (int c = 0; c < B; ++c) acc -= widen(s.f[k][c]) * (local ? lv[k * B + c] : xg[k * B + c]);
-    }
-    if (s.w > KMAX) {
-        const T* __restrict__ vals = static_cast<const T*>(a.vals);
-        for (int k = KMAX; k < s.w; ++k) {
-            const int64_t sl = s.off + static_cast<int64_t>(k) * RPC;
-            const int code = a.deps[sl + qc];
-            double xv[B];
-            if (code < 0) {
-#pragma unroll
-                for (int c = 0; c < B; ++c)
-                    xv[c] = *reinterpret_cast<const double*>(lds + (static_cast<uint32_t>(code) & 0x7fffffffu) + c * 8u);
-            } else {
-                const char* ob = reinterpret_cast<const char*>(a.out);
-#pragma unroll
-                for (int c = 0; c < B; ++c)
-                    xv[c] = coherent_load(reinterpret_cast<const double*>(ob + cm.at(static_cast<uint32_t>(code), c)));
-                const int one[1] = {code};
-                await_tile<1, B, MULTI>(xv, one, a.out, cm, a.spin_limit, a.status);
-            }
-            const int64_t vbase = sl * BB + r * RPC + qc;
-#pragma unroll
-            for (int c = 0; c < B; ++c) acc -= widen(vals[vbase + c * B * RPC]) * xv[c];
-        }
-    }
-    const double v = publishable(acc);
-    const uint32_t ob = cm.at(static_cast<uint32_t>(s.row) * (B * 8u), r);
-    if (a.reset) *reinterpret_cast<double*>(reinterpret_cast<char*>(a.reset) + ob) = not_ready();
-    coherent_store(reinterpret_cast<double*>(reinterpret_cast<char*>(a.out) + ob), v);
-    // the row's LDS slot: its place in the tile, or in the ring (wbase >= 0)
-    tile_vals[(wbase >= 0 ? wbase + qc : s.row - lo) * B + r] = v;
-}
-
-// Ring depth: three register states where they fit in half the register
-// file (two wavefronts per SIMD), else two.  Tile groups take two: measured on
-// MI355X, the member wavefronts of a group (one compute unit, all near the
-// sweep front) run their sweeps faster with fewer loads in flight (60x220x85
-// ILU(0), groups of 3: U' sweep 528 -> 497 us), while a wavefront on its own
-// gains from the deeper ring.
-template <int B, typename T, bool FUSE, int KMAX, bool GROUPED>
-struct TiledRing {
-    static constexpr int w = sizeof(T) == 8 ? 2 : 1;
-    static constexpr int state = KMAX * B * (2 + w) + KMAX + (FUSE ? B * (2 + w) : 2) + 4 + KMAX + 3;
-    static constexpr int value = !GROUPED && 3 * state + 40 <= 240 ? 3 : 2;
-};
-
-// One tile of a tiled sweep by one wavefront (column cm of the vectors).
-// tile_vals: the wavefront's LDS, row a.tile_rows already zero.
-template <int B, typename T, bool FUSE, int KMAX, bool MULTI, bool GROUPED>
-__device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap<MULTI>& cm, const double* lds_base,
-                                         double* tile_vals, int* prog, int member)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int NR = TiledRing<B, T, FUSE, KMAX, GROUPED>::value;   // register states in flight
-    constexpr int LD = NR - 1;                               // data lookahead
-    constexpr int LM = 2 * LD;                               // metadata lookahead
-    const int lane = lane_id();
-    const int q = lane / B;
-    const int r = lane - q * B;
-    const bool lane_ok = q < RPC;
-    const int qc = lane_ok ? q : RPC - 1;
-    TileMeta<KMAX> mr[NR];
-    TileData<B, T, KMAX, FUSE> dr[NR];
-    int wr[NR][kGroupMax];                                   // grouped: the chunks' waits
-    const int lo = uniform_load(a.tile_lo, t);
-    const int c0 = uniform_load(a.tile_chunk_ptr, t);
-    const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
-    if (nch <= 0) return;
-    const int clast = c0 + nch - 1;
-    auto chunk_at = [&](int i) { return min(c0 + i, clast); };
-    auto meta_at = [&](int i, TileMeta<KMAX>& m) {
-        const int ch = chunk_at(i);
-        const int sr = uniform_load(a.chunk_row, ch);
-        tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
-    };
-    // waits of chunk i, read with its data (scalar loads)
-    auto wait_at = [&](int i, int (&w)[kGroupMax]) {
-#pragma unroll
-        for (int m = 0; m < kGroupMax; ++m) w[m] = GROUPED ? uniform_load(a.chunk_wait, chunk_at(i) * kGroupMax + m) : 0;
-    };
-    // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
-    // metadata of LD..LM-1 issued as their slots free up
-#pragma unroll
-    for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
-#pragma unroll
-    for (int i = 0; i < LD; ++i) {
-        tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
-        wait_at(i, wr[i % NR]);
-        if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
-    }
-    // slot row range of the next chunk whose metadata is due, read a step
-    // ahead so that no step waits on the scalar cache
-    int pre_lo = uniform_load(a.chunk_row, chunk_at(LM));
-    int pre_hi = uniform_load(a.chunk_row, chunk_at(LM) + 1);
-    int wchunk = 0;                                          // ring position of the chunk computed next
-    // whole turns of the ring; steps past the tile's end load clamped
-    // chunks and compute nothing
-    for (int i0 = 0; i0 < nch; i0 += NR) {
-#pragma unroll
-        for (int p = 0; p < NR; ++p) {
-            const int i = i0 + p;
-            tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
-            pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
-            pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
-            tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
-            wait_at(i + LD, wr[(p + LD) % NR]);
-            tile_compute<B, T, KMAX, FUSE, MULTI, GROUPED>(a, lo, qc, r, lane_ok && i < nch, lds_base, tile_vals,
-                                                           dr[p], wr[p], prog, cm, a.ring > 0 ? wchunk * RPC : -1);
-            wchunk = wchunk + 1 == a.ring ? 0 : wchunk + 1;
-            // one wavefront: its LDS accesses complete in issue order, so
-            // only the compiler must keep this chunk's writes before the
-            // next chunk's reads (and before the progress count)
-            __builtin_amdgcn_wave_barrier();
-            asm volatile("" ::: "memory");
-            if (GROUPED && i < nch && lane == 0)
-                __hip_atomic_store(prog + member, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    }
-}
-
-// MULTI: R right-hand sides swept side by side, one wavefront per (tile,
-// column); tickets run tile by tile, the columns of a tile together, so
-// every dependency of a ticket (same column, earlier tile) has a smaller one.
-template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
-__global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
-{
-    extern __shared__ double tile_vals[];                    // [tile rows + 1][B]
-    // LDS row tile_rows stays zero: padding slots read it
-    if (lane_id() < B) tile_vals[a.tile_rows * B + lane_id()] = 0.0;
-    const int nticket = MULTI ? a.ntiles * a.R : a.ntiles;
-    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < nticket;
-         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
-        const int t = MULTI ? tk / a.R : tk;
-        ColMap<MULTI> cm;
-        cm.R = static_cast<uint32_t>(a.R);
-        cm.j8 = MULTI ? static_cast<uint32_t>(tk - t * a.R) * 8u : 0u;
-        run_tile<B, T, FUSE, KMAX, MULTI, false>(a, t, cm, tile_vals, tile_vals, nullptr, 0);
-    }
-    finish_persistent(a.ticket, a.done, a.total_waves);
-}
-
-// Tile groups: one workgroup of a.group wavefronts per ticket (a group, or
-// with MULTI a (group, column) pair); member m sweeps the group's m-th tile
-// into its part of the shared LDS and reads rows of earlier members there
-// once their progress counts cover them.  Tickets run in group order, and
-// every row a group reads from outside lies in a group with a smaller
-// ticket, so the persistent launch drains.
-template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
-__global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
-{
-    extern __shared__ double group_vals[];   // [group*tile_rows + 1][B], then kGroupMax progress counts
-    __shared__ int s_ticket;
-    const int G = a.group;
-    // wave-uniform (the compiler cannot see that on its own): the member's
-    // tile and chunk indices then stay scalar
-    const int member = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
-    const int zrow = G * a.tile_rows;
-    int* prog = reinterpret_cast<int*>(group_vals + static_cast<int64_t>(zrow + 1) * B);
-    if (static_cast<int>(threadIdx.x) < B) group_vals[zrow * B + threadIdx.x] = 0.0;
-    const int nticket = MULTI ? a.ngroups * a.R : a.ngroups;
-    for (;;) {
-        // the previous group is finished by every member (barrier below)
-        if (threadIdx.x < kGroupMax) prog[threadIdx.x] = 0;
-        if (threadIdx.x == 0) {
-            const unsigned long long tk = atomicAdd(a.ticket, 1ULL);
-            s_ticket = tk > 0x3fffffffULL ? 0x3fffffff : static_cast<int>(tk);
-        }
-        __syncthreads();
-        const int tk = __builtin_amdgcn_readfirstlane(s_ticket);
-        if (tk >= nticket) break;
-        const int g = MULTI ? tk / a.R : tk;
-        const int t = member < G ? uniform_load(a.group_tiles, g * G + member) : -1;
-        ColMap<MULTI> cm;
-        cm.R = static_cast<uint32_t>(a.R);
-        cm.j8 = MULTI ? static_cast<uint32_t>(tk - g * a.R) * 8u : 0u;
-        if (t >= 0)
-            run_tile<B, T, FUSE, KMAX, MULTI, true>(a, t, cm, group_vals,
-                                                    group_vals + static_cast<int64_t>(member) * a.tile_rows * B, prog,
-                                                    member);
-        __syncthreads();
-    }
-    if (member == 0) finish_persistent(a.ticket, a.done, a.total_waves);
-}
-
-// ---------------------------------------------------------------------------
-// U' sweep fused with y = A x on its output x: one persistent launch whose
-// tickets are the sweep's tiles and then the blocks of 64/B rows of A,
-// ordered by the tile that finishes the lowest row each reads (host-built
-// order, so every item depends only on earlier tickets, and every tile has
-// a wavefront before any wavefront waits in an SpMV block).  An SpMV block
-// requests A's values and the x values (device-coherent) of a group of
-// blocks of a row together, polls any x value still showing kNotReady, then
-// forms its rows exactly as k_spmv does (same operations, same order).
-// ---------------------------------------------------------------------------
-struct FusedSpmvArgs {
-    const int32_t* sched;        // >= 0 tile, < 0 SpMV block -(1 + b)
-    int nsched;
-    int nb;
-    const int32_t* Ap;
-    const int32_t* Aj;
-    const double* Ax;
-    double* y;
-};
-
-template <int B>
-__device__ __forceinline__ void spmv_block_ready(const FusedSpmvArgs& m, int64_t row0, const double* x,
-                                                 unsigned int limit, int* status)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    constexpr int EG = B <= 4 ? 8 : 4;          // blocks of a row read together
-    const int lane = lane_id();
-    const int q = lane / B;
-    const int r = lane - q * B;
-    const int64_t row = row0 + q;
-    if (q >= RPC || row >= m.nb) return;
-    const int e0 = m.Ap[row], e1 = m.Ap[row + 1];
-    double acc = 0.0;
-    for (int g = e0; g < e1; g += EG) {
-        int j[EG];
-#pragma unroll
-        for (int k = 0; k < EG; ++k) j[k] = g + k < e1 ? m.Aj[g + k] : -1;
-        // A's values and x's values requested together (the x values with
-        // device-coherent loads: cached copies would be stale)
-        double av[EG * B], xv[EG * B];
-#pragma unroll
-        for (int k = 0; k < EG; ++k)
-#pragma unroll
-            for (int c = 0; c < B; ++c) {
-                const int64_t blk = g + k;
-                av[k * B + c] = j[k] >= 0 ? m.Ax[blk * BB + c * B + r] : 0.0;
-                xv[k * B + c] = j[k] >= 0 ? coherent_load(x + static_cast<int64_t>(j[k]) * B + c) : 0.0;
-            }
-        await_rows<EG, B, 1>(xv, j, x, 1, 0, limit, status);
-#pragma unroll
-        for (int k = 0; k < EG; ++k) {
-            if (j[k] < 0) continue;
-#pragma unroll
-            for (int c = 0; c < B; ++c) acc += av[k * B + c] * xv[k * B + c];
-        }
-    }
-    m.y[row * B + r] = acc;
-}
-
-template <int B, typename T, int KMAX>
-__global__ __launch_bounds__(64) void k_sweep_tiled_spmv(TiledArgs a, FusedSpmvArgs m)
-{
-    extern __shared__ double tile_vals[];                    // [tile rows + 1][B]
-    if (lane_id() < B) tile_vals[a.tile_rows * B + lane_id()] = 0.0;
-    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < m.nsched;
-         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
-        const int it = uniform_load(m.sched, tk);
-        if (it >= 0) {
-            ColMap<false> cm;
-            cm.R = 1;
-            cm.j8 = 0;
-            run_tile<B, T, true, KMAX, false, false>(a, it, cm, tile_vals, tile_vals, nullptr, 0);
-        } else {
-            spmv_block_ready<B>(m, static_cast<int64_t>(-1 - it) * (64 / B), a.out, a.spin_limit, a.status);
-        }
-    }
-    finish_persistent(a.ticket, a.done, a.total_waves);
-}
-
-// Rows [row0, row0 + 64/B) of y = A x (or A^T x through the transposed
-// structure), by one wavefront; lane (q, r) owns component r of row q.
-// Block values are read from Av at block (e - ebase): A itself (ebase 0), or
-// the wavefront's LDS copy of its rows' blocks (ebase the first of them).
-template <int B, int RT, bool TRANS>
-__device__ __forceinline__ void spmv_rows(int64_t row0, int nb, const int32_t* __restrict__ rp,
-                                          const int32_t* __restrict__ cj, const int64_t* __restrict__ srcpos,
-                                          const double* __restrict__ Av, int64_t ebase,
-                                          const double* __restrict__ x, double* __restrict__ y, int R)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    const int lane = lane_id();
-    const int q = lane / B;
-    const int r = lane - q * B;
-    const int64_t row = row0 + q;
-    if (q >= RPC || row >= nb) return;
-    const int e0 = rp[row], e1 = rp[row + 1];
-    for (int c0 = 0; c0 < R; c0 += RT) {
-        double acc[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) acc[t] = 0.0;
-        // unrolled: the column-index and x loads of several blocks in flight
-        // (same accumulation order)
-#pragma unroll 4
-        for (int e = e0; e < e1; ++e) {
-            const int j = cj[e];
-            const int64_t blk = (TRANS ? srcpos[e] : e) - ebase;
-#pragma unroll
-            for (int c = 0; c < B; ++c) {
-                const double v = TRANS ? Av[blk * BB + r * B + c] : Av[blk * BB + c * B + r];
-                const double* xj = x + (static_cast<int64_t>(j) * B + c) * R + c0;
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    if (RT == 1 || c0 + t < R) acc[t] += v * xj[t];
-            }
-        }
-        double* dst = y + (row * B + r) * R + c0;
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-            if (RT == 1 || c0 + t < R) dst[t] = acc[t];
-    }
-}
-
-// LDS per wavefront for its rows' blocks in k_spmv when each block serves a
-// tile of right-hand sides (RT > 1): eight blocks per row on average (a
-// 7-point stencil needs seven); 0 for block sizes whose rows already read
-// whole cache lines.  With one right-hand side the copy did not pay (156 ->
-// 159 us on 60x220x85, b = 3); with 8 and 32 it did (64^3 ILU(1) solves
-// 162 -> 172 and 219 -> 233 per second).
-template <int B>
-struct SpmvStage {
-    static constexpr int doubles = B <= 3 ? (64 / B) * 8 * B * B : 0;
-};
-
-template <int B, int RT, bool TRANS>
-__global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ cj,
-                                                   const int64_t* __restrict__ srcpos,
-                                                   const double* __restrict__ Ax,
-                                                   const double* __restrict__ x,
-                                                   double* __restrict__ y, int R)
-{
-    constexpr int RPC = 64 / B;
-    constexpr int BB = B * B;
-    constexpr int STAGE = TRANS || RT == 1 ? 0 : SpmvStage<B>::doubles;
-    const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-    const int64_t row0 = wave_global * RPC;
-    if constexpr (STAGE > 0) {
-        // The wavefront's rows own one contiguous run of blocks: copied to
-        // LDS with whole-wavefront loads, then read as from A (same values,
-        // same accumulation order).
-        __shared__ double stage[kWavesPerBlock][STAGE];
-        if (row0 < nb) {
-            const int64_t rend = row0 + RPC < nb ? row0 + RPC : nb;
-            const int32_t E0 = uniform_load(rp, row0);
-            const int64_t n = static_cast<int64_t>(uniform_load(rp, rend) - E0) * BB;
-            if (n <= STAGE) {
-                constexpr int PER = (STAGE + 63) / 64;
-                double* st = stage[threadIdx.x >> 6];
-                const double* src = Ax + static_cast<int64_t>(E0) * BB;
-                const int lane = lane_id();
-                double v[PER];
-#pragma unroll
-                for (int k = 0; k < PER; ++k) v[k] = lane + 64 * k < n ? src[lane + 64 * k] : 0.0;
-#pragma unroll
-                for (int k = 0; k < PER; ++k)
-                    if (lane + 64 * k < n) st[lane + 64 * k] = v[k];
-                // one wavefront: its LDS accesses complete in issue order
-                __builtin_amdgcn_wave_barrier();
-                asm volatile("" ::: "memory");
-                spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, st, E0, x, y, R);
-                return;
-            }
-        }
-    }
-    spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, Ax, 0, x, y, R);
-}
 
 // ---------------------------------------------------------------------------
 // Backfill (Algorithm 5 steps 3-4): P takes A's block where A stores one

@@ -54,97 +54,6 @@ constexpr int kPieceLen = 16384;
     }
 
 // ---------------------------------------------------------------------------
-// Sweeps over the batch: one persistent launch per sweep on the members'
-// row-tile layouts.  Items are (member, tile), merged tile index by tile
-// index (tile t of every member before tile t + 1 of any), so each item
-// depends only on items with smaller tickets, as in the single-system tiled
-// sweep.  Members whose Krylov recurrence is frozen are skipped by both
-// sweeps of an application alike, which keeps the kNotReady invariant of
-// their buffers.
-// ---------------------------------------------------------------------------
-struct BatchTiled {               // one member's tiled layout of one sweep
-    const int32_t* tile_chunk_ptr;
-    const int32_t* tile_lo;
-    const int32_t* chunk_row;
-    const int32_t* rows;
-    const int32_t* deps;
-    const void* vals;
-    const void* dinv;
-    int64_t voff;                 // first unknown of the member in the batch vectors
-    int tile_rows;
-    int kmax;
-    int bs;
-    int pad;
-};
-
-struct BatchSweepArgs {
-    const BatchTiled* mem;        // per member, this sweep
-    const int2* items;            // (member, tile)
-    int nitems;
-    const double* rhs;
-    double* out;
-    double* reset;
-    const int* active;            // per member, or null: every member
-    unsigned long long* ticket;
-    unsigned int* done;
-    int* status;
-    unsigned int total_waves;
-    unsigned int spin_limit;
-};
-
-template <int B, typename T, bool FUSE, int KMAX>
-__device__ __forceinline__ void batch_tile(const BatchSweepArgs& a, const BatchTiled& M, int tile, double* tile_vals)
-{
-    TiledArgs t{};
-    t.tile_chunk_ptr = M.tile_chunk_ptr;
-    t.tile_lo = M.tile_lo;
-    t.chunk_row = M.chunk_row;
-    t.rows = M.rows;
-    t.deps = M.deps;
-    t.vals = M.vals;
-    t.dinv = M.dinv;
-    t.rhs = a.rhs + M.voff;
-    t.out = a.out + M.voff;
-    t.reset = a.reset ? a.reset + M.voff : nullptr;
-    t.status = a.status;
-    t.tile_rows = M.tile_rows;
-    t.ring = 0;                      // member layouts keep whole tiles
-    t.R = 1;
-    t.spin_limit = a.spin_limit;
-    // this member's zero row (an earlier item may have used that LDS)
-    if (lane_id() < B) tile_vals[M.tile_rows * B + lane_id()] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    asm volatile("" ::: "memory");
-    ColMap<false> cm;
-    cm.R = 1;
-    cm.j8 = 0;
-    run_tile<B, T, FUSE, KMAX, false, false>(t, tile, cm, tile_vals, tile_vals, nullptr, 0);
-}
-
-template <typename T, bool FUSE>
-__global__ __launch_bounds__(64) void k_sweep_batch(BatchSweepArgs a)
-{
-    extern __shared__ double tile_vals[];
-    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < a.nitems;
-         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
-        const int2 it = uniform_record(a.items, tk);
-        if (a.active && !uniform_load(a.active, it.x)) continue;
-        const BatchTiled M = uniform_record(a.mem, it.x);
-        switch (M.bs * 16 + M.kmax) {
-#define BILU_BATCH_TILE(BS, K) \
-    case BS * 16 + K: batch_tile<BS, T, FUSE, K>(a, M, it.y, tile_vals); break;
-        BILU_BATCH_TILE(1, 3) BILU_BATCH_TILE(2, 3) BILU_BATCH_TILE(3, 3) BILU_BATCH_TILE(4, 3)
-        BILU_BATCH_TILE(5, 3) BILU_BATCH_TILE(6, 3) BILU_BATCH_TILE(7, 3) BILU_BATCH_TILE(8, 3)
-        BILU_BATCH_TILE(1, 6) BILU_BATCH_TILE(2, 6) BILU_BATCH_TILE(3, 6) BILU_BATCH_TILE(4, 6)
-        BILU_BATCH_TILE(1, 9) BILU_BATCH_TILE(2, 9) BILU_BATCH_TILE(3, 9) BILU_BATCH_TILE(4, 9)
-#undef BILU_BATCH_TILE
-        default: break;
-        }
-    }
-    finish_persistent(a.ticket, a.done, a.total_waves);
-}
-
-// ---------------------------------------------------------------------------
 // y = A x over the batch: items are (system, first block row of a
 // wavefront's 64/b rows); wavefronts take items grid-stride.
 // ---------------------------------------------------------------------------

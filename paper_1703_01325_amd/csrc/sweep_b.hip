@@ -1,0 +1,140 @@
+// Sweep and SpMV launchers for one block size, BILU_B (set by the build,
+// 1..8): every kernel template of sweep_kernels.h that this block size uses
+// is instantiated here and nowhere else.
+#include <hip/hip_runtime.h>
+
+#include "bilu.h"
+#include "launch.h"
+
+#ifndef BILU_B
+#error "BILU_B (the block size of this translation unit) must be defined"
+#endif
+
+namespace bilu {
+namespace launch {
+
+namespace {
+
+template <int B, typename T, int RT>
+void sweep_k(int blocks, hipStream_t s, const dev::SweepArgs& a)
+{
+    hipLaunchKernelGGL((dev::k_sweep<B, T, RT>), dim3(blocks), dim3(dev::kThreads), 0, s, a);
+}
+
+template <int B, typename T, bool FUSE, bool MULTI>
+bool tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (a.group > 1) {
+        if (a.group > kGroupMax) return false;
+        const dim3 threads(64 * a.group);
+        if constexpr (B >= 5) {
+            if (kmax != 3) return false;
+            hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a);
+            return true;
+        } else {
+            switch (kmax) {
+            case 3: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+            case 6: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 6, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+            case 9: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 9, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+            }
+            return false;
+        }
+    }
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 6, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 9, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
+        }
+        return false;
+    }
+}
+
+template <int B, typename T>
+bool tiled_t(int kmax, bool fuse, bool multi, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (fuse) return multi ? tiled_k<B, T, true, true>(kmax, blocks, lds, s, a) : tiled_k<B, T, true, false>(kmax, blocks, lds, s, a);
+    return multi ? tiled_k<B, T, false, true>(kmax, blocks, lds, s, a) : tiled_k<B, T, false, false>(kmax, blocks, lds, s, a);
+}
+
+template <int B, typename T>
+bool fused_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a, const dev::FusedSpmvArgs& m)
+{
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 3>), dim3(blocks), dim3(64), lds, s, a, m);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 3>), dim3(blocks), dim3(64), lds, s, a, m); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 6>), dim3(blocks), dim3(64), lds, s, a, m); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_tiled_spmv<B, T, 9>), dim3(blocks), dim3(64), lds, s, a, m); return true;
+        }
+        return false;
+    }
+}
+
+template <int B, int RT, bool TR>
+void spmv_k(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax, const double* x,
+            double* y, int R, hipStream_t s)
+{
+    constexpr int RPC = 64 / B;
+    const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
+    const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+    hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src, Ax, x,
+                       y, R);
+}
+
+}  // namespace
+
+template <int B>
+bool sweep(int prec, int rt, int blocks, hipStream_t s, const dev::SweepArgs& a)
+{
+    const bool f32 = prec == BILU_FACTORS_FP32;
+    switch (rt) {
+    case 1: f32 ? sweep_k<B, float, 1>(blocks, s, a) : sweep_k<B, double, 1>(blocks, s, a); return true;
+    case 4: f32 ? sweep_k<B, float, 4>(blocks, s, a) : sweep_k<B, double, 4>(blocks, s, a); return true;
+    case 8: f32 ? sweep_k<B, float, 8>(blocks, s, a) : sweep_k<B, double, 8>(blocks, s, a); return true;
+    }
+    return false;
+}
+
+template <int B>
+bool tiled(int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (prec == BILU_FACTORS_FP32) return tiled_t<B, float>(kmax, fuse, multi, blocks, lds, s, a);
+    return tiled_t<B, double>(kmax, fuse, multi, blocks, lds, s, a);
+}
+
+template <int B>
+bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a,
+           const dev::FusedSpmvArgs& m)
+{
+    if (prec == BILU_FACTORS_FP32) return fused_k<B, float>(kmax, blocks, lds, s, a, m);
+    return fused_k<B, double>(kmax, blocks, lds, s, a, m);
+}
+
+template <int B>
+bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
+          const double* x, double* y, int R, hipStream_t s)
+{
+    switch (rt) {
+    case 1: trans ? spmv_k<B, 1, true>(nb, rp, cj, src, Ax, x, y, R, s) : spmv_k<B, 1, false>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 4: trans ? spmv_k<B, 4, true>(nb, rp, cj, src, Ax, x, y, R, s) : spmv_k<B, 4, false>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 8: trans ? spmv_k<B, 8, true>(nb, rp, cj, src, Ax, x, y, R, s) : spmv_k<B, 8, false>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    }
+    return false;
+}
+
+template bool sweep<BILU_B>(int, int, int, hipStream_t, const dev::SweepArgs&);
+template bool tiled<BILU_B>(int, int, bool, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
+template bool fused<BILU_B>(int, int, int, size_t, hipStream_t, const dev::TiledArgs&, const dev::FusedSpmvArgs&);
+template bool spmv<BILU_B>(int, bool, int, const int32_t*, const int32_t*, const int64_t*, const double*,
+                           const double*, double*, int, hipStream_t);
+
+}  // namespace launch
+}  // namespace bilu
