@@ -634,6 +634,11 @@ static double true_residual(const orc_system *S, const double *bvec, const doubl
  * Returns 0, ORC_NOT_CONVERGED or ORC_BREAKDOWN (rho = 0, <r^,v> = 0, or
  * omega = 0).
  */
+/* Number of true-residual restarts taken by the last BiCGSTAB solve (a
+ * counter for the tests; it does not enter the arithmetic). */
+static int last_restarts = 0;
+int orc_last_restarts(void) { return last_restarts; }
+
 static int bicgstab(const orc_system *S, const double *bvec, double *x, double rtol,
                     int maxit, int *iters, double *relres)
 {
@@ -649,6 +654,7 @@ static int bicgstab(const orc_system *S, const double *bvec, double *x, double r
     memcpy(rh, r, sz);
     double rho_old = 1.0, alpha = 1.0, omega = 1.0, rres = bnorm;
     int fresh = 1;
+    last_restarts = 0;
     if (bnorm == 0.0) { status = ORC_OK; rres = 0.0; goto done; }
     for (it = 1; it <= maxit; it++) {
         double rho = dot(N, rh, r);
@@ -674,6 +680,7 @@ static int bicgstab(const orc_system *S, const double *bvec, double *x, double r
             memcpy(r, w, sz);
             memcpy(rh, r, sz);
             fresh = 1;
+            last_restarts++;
             rho_old = rho;
             continue;
         }
@@ -695,6 +702,7 @@ static int bicgstab(const orc_system *S, const double *bvec, double *x, double r
             memcpy(r, w, sz);
             memcpy(rh, r, sz);
             fresh = 1;
+            last_restarts++;
         }
     }
     if (it > maxit) it = maxit;

@@ -61,6 +61,7 @@ def lib():
         L.orc_solve.argtypes = [I, I, P, P, P, P, P, P, P, P, P, P, P,
                                 I, I, D, I, I, ct.POINTER(I), ct.POINTER(D)]
         L.orc_grad_A.argtypes = [I, I, P, P, P, P, P]
+        L.orc_last_restarts.restype = I
         _lib = L
     return _lib
 
@@ -198,6 +199,11 @@ def solve(nb, bs, Ap, Aj, Ax, Pp, Pj, F, Dinv, b, method=0, restart=30, rtol=1e-
                          float(rtol), int(maxit), int(bool(transpose)),
                          ct.byref(it), ct.byref(rr))
     return x, it.value, rr.value, st
+
+
+def last_restarts():
+    """True-residual restarts taken by the last BiCGSTAB solve (a counter)."""
+    return int(lib().orc_last_restarts())
 
 
 def grad_A(nb, bs, Ap, Aj, lam, x):

@@ -94,7 +94,7 @@ def test_batch_solve(api, oracle_mod):
     rs = split(B, rhs)
     for s, m in enumerate(members):
         xo, ito, rro, sto = O[s].solve(m.Ax, rs[s], rtol=1e-8)
-        stg, itg, rrg = info[s]
+        stg, itg, rrg = info[s][:3]
         assert sto == 0 and stg == 0 and rrg <= 1e-8, (s, info[s])
         assert abs(itg - ito) <= 1, (s, itg, ito)
         assert np.linalg.norm(xs[s] - xo) / np.linalg.norm(xo) <= 1e-10, s

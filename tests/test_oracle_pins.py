@@ -514,6 +514,40 @@ def test_transposed_solve(oracle_mod):
     assert np.linalg.norm(A.T @ lam - g) <= 1e-11 * np.linalg.norm(g)
 
 
+def test_bicgstab_true_residual_restart(oracle_mod):
+    """At rtol 5e-16 the BiCGSTAB recurrence residual of this system passes
+    the test at step 9 while the true residual b - A x does not (5.4e-16):
+    the iteration must restart from the true residual and exit only when
+    that passes.  Pinned against numpy: the reported residual is the true
+    one, and x is the dense solution."""
+    s = synth.reservoir(5, 4, 3, 3, seed=8, sigma=1.0)
+    O = oracle_mod.OracleILU(s.nb, s.bs, s.Ap, s.Aj, 0).factor(s.Ax)
+    A = dense_blocks(s.nb, s.bs, s.Ap, s.Aj, s.Ax)
+    rhs = A @ s.xstar
+    bn = np.linalg.norm(rhs)
+    rtol = 5e-16
+    # stopped right after the restart: not converged, true residual above rtol
+    x, it, rr, st = O.solve(s.Ax, rhs, rtol=rtol, maxit=9)
+    assert oracle_mod.last_restarts() == 1 and st == oracle_mod.NOT_CONVERGED and it == 9
+    assert rr > rtol and abs(rr - np.linalg.norm(rhs - A @ x) / bn) <= 2e-16
+    x, it, rr, st = O.solve(s.Ax, rhs, rtol=rtol, maxit=200)
+    assert oracle_mod.last_restarts() >= 1 and st == 0 and it > 9
+    assert rr <= rtol and abs(rr - np.linalg.norm(rhs - A @ x) / bn) <= 2e-16
+    xd = np.linalg.solve(A, rhs)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-14
+    # with a loose tolerance the same system takes no restart
+    O.solve(s.Ax, rhs, rtol=1e-8)
+    assert oracle_mod.last_restarts() == 0
+
+
+def test_solver_zero_rhs(oracle_mod):
+    s = synth.reservoir(5, 4, 3, 3, seed=8)
+    O = oracle_mod.OracleILU(s.nb, s.bs, s.Ap, s.Aj, 0).factor(s.Ax)
+    for method in (0, 1):
+        x, it, rr, st = O.solve(s.Ax, np.zeros(s.n), method=method, rtol=1e-8)
+        assert st == 0 and it == 0 and rr == 0.0 and not x.any()
+
+
 def test_solver_reports_not_converged(oracle_mod):
     s = synth.small_10cube()
     O = oracle_mod.OracleILU(s.nb, s.bs, s.Ap, s.Aj, 0).factor(s.Ax)
