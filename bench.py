@@ -96,6 +96,9 @@ def run_gpu(args, sysm, k, precision, R=1, steps=None, warmup=None, method="bicg
     times = M.timing_read()
     M.timing(False)
     st, inf = last
+    bad = [i for i in inf if i[0] != 0 or not (i[2] <= 1e-8)]
+    if st != 0 or bad:
+        raise RuntimeError(f"solve did not reach the 1e-8 true residual: status {st}, per column {bad[:4]}")
     err = float((x - xs).norm() / xs.norm())
     fb = 4 if precision == "fp32" else 8
     ab = algorithmic_bytes(info, sysm.bs, R, fb)
@@ -112,6 +115,19 @@ def run_gpu(args, sysm, k, precision, R=1, steps=None, warmup=None, method="bicg
         "x_err": err, "per_kernel": per, "bytes": ab,
         "pair_us": pair_us, "pair_GBps": pair_bytes / pair_us / 1e3,
     }
+
+
+def variant_line(res, R=1):
+    """Summary of one timed configuration: solve time, convergence, the
+    apply + SpMV pair and the roofline of its dominant kernel."""
+    rf = roofline_of(res)
+    return {"ms_per_solve": 1e3 * res["elapsed"] / res["steps"],
+            "solves_per_s": R * res["steps"] / res["elapsed"],
+            "status": res["status"], "iters": max(res["iters"]), "relres": max(res["relres"]),
+            "pair_us": res["pair_us"], "apply_spmv_GBps": res["pair_GBps"],
+            "frac_of_hbm_peak": res["pair_GBps"] / HBM_PEAK_GBPS,
+            "kernels_us": {kk: round(v["avg_us"], 2) for kk, v in res["per_kernel"].items()},
+            "roofline": {kk: rf[kk] for kk in ("kernel", "achieved", "frac", "avg_launch_us") if kk in rf}}
 
 
 def roofline_of(res):
@@ -164,6 +180,9 @@ def run_batch(nsys=256, reps=5):
     x, st, info = B.solve(b, rtol=1e-8, out=x)
     torch.cuda.synchronize()
     solve_s = time.perf_counter() - t0
+    bad = [i for i in info if i[0] != 0 or not (i[2] <= 1e-8)]
+    if st != 0 or bad:
+        raise RuntimeError(f"batch solve did not reach the 1e-8 true residual: status {st}, members {bad[:4]}")
     z = torch.empty_like(b)
     y = torch.empty_like(b)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -186,25 +205,56 @@ def run_batch(nsys=256, reps=5):
     return out
 
 
-def cpu_baseline(sysm, k):
-    """The oracle (plain C, one thread) on the same workload: one full
-    factorisation + split + BiCGSTAB solve."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sysm, k, reps=5):
+    """The oracle (plain C, one thread) on the same workload: the median of
+    `reps` runs of each phase that is cheap enough (symbolic phase, numeric
+    factorisation, split, one application, one SpMV) and one full
+    factorisation + split + BiCGSTAB solve, which sets `value`."""
+    import statistics
     from oracle import oracle as O
     import numpy as np
 
+    def med(fn):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
     rhs = O.spmv(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, sysm.Ax, sysm.xstar)
-    t0 = time.perf_counter()
     ref = O.OracleILU(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, k)
-    t_sym = time.perf_counter() - t0
+    phases = {"symbolic_s": med(lambda: O.symbolic(sysm.nb, sysm.Ap, sysm.Aj, k))}
+    box = {}
+    phases["factor_s"] = med(lambda: box.update(zip(("LU", "Dinv"), O.factor(
+        sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, sysm.Ax, ref.Pp, ref.Pj))))
+    phases["split_s"] = med(lambda: box.update(F=O.split(sysm.nb, sysm.bs, ref.Pp, ref.Pj, box["LU"], box["Dinv"])))
+    ref.F, ref.Dinv = box["F"], box["Dinv"]
+    r = np.random.default_rng(0).standard_normal(sysm.n)
+    phases["apply_s"] = med(lambda: ref.apply(r))
+    phases["spmv_s"] = med(lambda: O.spmv(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, sysm.Ax, r))
     t0 = time.perf_counter()
     ref.factor(sysm.Ax)
     x, it, rr, st = ref.solve(sysm.Ax, rhs, rtol=1e-8)
     t_solve = time.perf_counter() - t0
+    phases["factor_split_solve_s"] = t_solve
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"one full numeric factorisation + split + BiCGSTAB solve of the same workload "
-                      f"(ILU({k}), {it} iterations, relres {rr:.2e}), {t_solve:.1f} s; symbolic phase "
-                      f"{t_sym:.1f} s not included, as on the GPU side",
-            "iters": it}
+                      f"(ILU({k}), {it} iterations, relres {rr:.2e}, status {st}), {t_solve:.1f} s; symbolic "
+                      f"phase not included, as on the GPU side; per-phase figures are medians of {reps} runs",
+            "iters": it, "nproc": os.cpu_count(), "cpu_model": _cpu_model(), "threads_used": 1,
+            "phases": phases}
 
 
 def main():
@@ -264,6 +314,7 @@ def main():
                    "grid": list(sysm.grid), "block_size": sysm.bs, "k": args.k, "nrhs": 1,
                    "block_rows": sysm.nb, "unknowns": sysm.n, "nnzb_A": int(info.nnzb_A),
                    "nnzb_L": int(info.nnzb_L), "levels": int(info.nlev[0])},
+        "status": res["status"],
         "iters": res["iters"][0],
         "relres": res["relres"][0],
         "x_rel_err_vs_xstar": res["x_err"],
@@ -278,19 +329,20 @@ def main():
     res["M"].close()
     if not args.no_variants:
         variants = {}
-        r32 = run_gpu(args, sysm, args.k, "fp32", steps=2, warmup=1)
-        variants["fp32_factors"] = {"ms_per_solve": 1e3 * r32["elapsed"] / r32["steps"],
-                                    "iters": r32["iters"][0], "relres": r32["relres"][0],
-                                    "apply_spmv_GBps": r32["pair_GBps"],
-                                    "final_error_ratio_vs_fp64": r32["x_err"] / max(res["x_err"], 1e-300)}
+        r32 = run_gpu(args, sysm, args.k, "fp32", steps=3, warmup=1)
+        v = variant_line(r32)
+        v["final_error_ratio_vs_fp64"] = r32["x_err"] / max(res["x_err"], 1e-300)
+        variants[f"layered_ilu{args.k}_fp32"] = v
         r32["M"].close()
+        if args.workload == "layered":
+            for prec in ("fp64", "fp32"):
+                r1 = run_gpu(args, sysm, 1, prec, steps=3, warmup=1)
+                variants[f"layered_ilu1_{prec}"] = variant_line(r1)
+                r1["M"].close()
         mid = synth.mid_64cube()
         for R in (1, 8, 32):
-            rr = run_gpu(args, mid, 1, "fp64", R=R, steps=1, warmup=1)
-            variants[f"mid64_ilu1_nrhs{R}"] = {"ms_per_solve": 1e3 * rr["elapsed"] / rr["steps"],
-                                             "solves_per_s": R * rr["steps"] / rr["elapsed"],
-                                             "max_iters": max(rr["iters"]), "max_relres": max(rr["relres"]),
-                                             "apply_spmv_GBps": rr["pair_GBps"]}
+            rr = run_gpu(args, mid, 1, "fp64", R=R, steps=2, warmup=1)
+            variants[f"mid64_ilu1_nrhs{R}"] = variant_line(rr, R)
             rr["M"].close()
         variants["uneven_batch_256_ilu0"] = run_batch()
         line["variants"] = variants

@@ -98,6 +98,8 @@ typedef struct {
     int lds_ring[4];      /* per tiled sweep: chunks whose rows a wavefront keeps in LDS
                              (0: the whole tile; > 0 when every in-tile dependency is
                              fewer than that many chunks back, single-tile layouts only) */
+    int tile_block[4];    /* per tiled sweep: ny + 256*nz when its tiles are blocks of
+                             ny x nz grid lines (BILU_TUNE_TILE_BLOCK), else 0       */
 } bilu_info;
 
 typedef struct {
@@ -111,6 +113,10 @@ typedef struct {
     int status;      /* bilu_status of this right-hand side              */
     int iters;       /* BiCGSTAB steps or GMRES Arnoldi steps taken        */
     double relres;   /* true relative residual ||b - A x|| / ||b|| at exit */
+    int restarts;    /* BiCGSTAB: restarts from the true residual, taken when
+                        the recurrence residual passed the test but the
+                        true one did not; GMRES: restart cycles completed   */
+    int reserved;
 } bilu_rhs_info;
 
 /*
@@ -238,6 +244,14 @@ enum {
                                  SpMV in one launch (row tiles, one right-hand side,
                                  not transposed, tiles not grouped); 0 (default):
                                  separate launches                                   */
+    BILU_TUNE_TILE_BLOCK = 7, /* mode 2 on a pattern in natural grid order (block rows
+                                 in lines of nx, lines in planes): value ny + 256*nz
+                                 makes every tile a block of ny x nz grid lines (all
+                                 of their block rows), one wavefront per tile, so
+                                 dependencies between neighbouring lines and planes
+                                 stay inside a tile; 0 (default): row-range tiles.
+                                 Falls back to row-range tiles where the pattern has
+                                 no grid lines or the blocks cannot be ordered        */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

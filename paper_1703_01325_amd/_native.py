@@ -43,7 +43,7 @@ class BiluInfo(ct.Structure):
                 ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
                 ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
                 ("sweep_slots", ct.c_int64 * 4), ("tile_rows", ct.c_int),
-                ("tile_group", ct.c_int), ("lds_ring", ct.c_int * 4)]
+                ("tile_group", ct.c_int), ("lds_ring", ct.c_int * 4), ("tile_block", ct.c_int * 4)]
 
 
 class KernelTime(ct.Structure):
@@ -56,7 +56,8 @@ class SolveOpts(ct.Structure):
 
 
 class RhsInfo(ct.Structure):
-    _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("relres", ct.c_double)]
+    _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("relres", ct.c_double),
+                ("restarts", ct.c_int), ("reserved", ct.c_int)]
 
 
 class TuneResult(ct.Structure):
@@ -227,7 +228,7 @@ def bilu_solve(ctx, Ax_ptr, b_ptr, x_ptr, nrhs, method, restart, rtol, maxit, tr
     st = _check(lib.bilu_solve(ctx, ct.c_void_p(Ax_ptr), ct.c_void_p(b_ptr), ct.c_void_p(x_ptr), int(nrhs),
                                ct.byref(opts), info, int(transpose), ct.c_void_p(stream)),
                 "bilu_solve", allow_positive=True)
-    return st, [(i.status, i.iters, i.relres) for i in info]
+    return st, [(i.status, i.iters, i.relres, i.restarts) for i in info]
 
 
 def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
@@ -236,6 +237,7 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
 
 
 TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV, TUNE_TILE_GROUP = 0, 1, 3, 4, 5, 6
+TUNE_TILE_BLOCK = 7
 
 
 def bilu_tune(ctx, param, value):
@@ -312,7 +314,7 @@ def bilu_batch_solve(batch, nsys, b_ptr, x_ptr, rtol, maxit, stream):
     info = (RhsInfo * int(nsys))()
     st = _check(lib.bilu_batch_solve(batch, ct.c_void_p(b_ptr), ct.c_void_p(x_ptr), ct.byref(opts), info,
                                      ct.c_void_p(stream)), "bilu_batch_solve", allow_positive=True)
-    return st, [(i.status, i.iters, i.relres) for i in info]
+    return st, [(i.status, i.iters, i.relres, i.restarts) for i in info]
 
 
 def bilu_batch_member(batch, s):

@@ -53,10 +53,13 @@ class BlockILU:
     def set_sweep_mode(self, mode):
         N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
 
-    def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None):
+    def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None,
+             tile_block=None):
         """Launch knobs of the sweeps (results are bit-identical for all)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
                          (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
+                         (N.TUNE_TILE_BLOCK, None if tile_block is None else
+                          (0 if not tile_block else tile_block[0] + 256 * tile_block[1])),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)
@@ -101,7 +104,7 @@ class BlockILU:
 
     def solve(self, Ax, b, method="bicgstab", restart=30, rtol=1e-8, maxit=2000, transpose=False,
               out=None):
-        """x = A^{-1} b (or A^{-T} b); returns (x, status, [(status, iters, relres)] per RHS)."""
+        """x = A^{-1} b (or A^{-T} b); returns (x, status, [(status, iters, relres, restarts)] per RHS)."""
         _dev_f64(Ax, "Ax")
         _dev_f64(b, "b")
         x = torch.empty_like(b) if out is None else out

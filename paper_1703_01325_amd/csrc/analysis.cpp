@@ -467,6 +467,166 @@ void build_tiled(const Host& h, int which, int rpc, int tile_rows, int group, in
     s.built = true;
 }
 
+bool grid_lines(const Host& h, int& nx, int& nxy)
+{
+    const int nb = h.nb;
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, BILU_SWEEP_L, dptr, deps);
+    auto has = [&](int32_t i, int32_t d) {
+        for (int32_t e = dptr[i]; e < dptr[i + 1]; ++e)
+            if (deps[e].col == i - d) return true;
+        return false;
+    };
+    // line starts: rows without a dependency on the previous row
+    nx = 0;
+    for (int32_t i = 1; i < nb && !nx; ++i)
+        if (!has(i, 1)) nx = i;
+    if (nx < 2 || nb % nx != 0) return false;
+    for (int32_t i = 1; i < nb; ++i)
+        if (has(i, 1) == (i % nx == 0)) return false;
+    // plane starts: line starts without a dependency on the line before
+    nxy = 0;
+    for (int32_t i = nx; i < nb && !nxy; i += nx)
+        if (!has(i, nx)) nxy = i;
+    if (nxy == 0) nxy = nb;                 // a single plane
+    if (nxy % nx != 0 || nb % nxy != 0) return false;
+    for (int32_t i = nx; i < nb; i += nx)
+        if (has(i, nx) == (i % nxy == 0)) return false;
+    return true;
+}
+
+void build_tiled_blocks(const Host& h, int which, int rpc, int ny_b, int nz_b, HostTiled& s)
+{
+    const int nb = h.nb;
+    const int bs = h.bs;
+    const bool forward = (which == BILU_SWEEP_L || which == BILU_SWEEP_UT);
+    s = HostTiled{};
+    int nx = 0, nxy = 0;
+    if (ny_b < 1 || nz_b < 1 || !grid_lines(h, nx, nxy)) return;
+    if (static_cast<int64_t>(nb) * bs * 8 > INT32_MAX) return;
+    const int ny = nxy / nx, nz = nb / nxy;
+    const int NYb = (ny + ny_b - 1) / ny_b, NZb = (nz + nz_b - 1) / nz_b;
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, which, dptr, deps);
+    int max_ndep = 0;
+    for (int i = 0; i < nb; ++i) max_ndep = std::max(max_ndep, dptr[i + 1] - dptr[i]);
+    s.kmax = tiled_kmax(bs, max_ndep);
+    s.which = which;
+    s.rpc = rpc;
+    s.block_ny = ny_b;
+    s.block_nz = nz_b;
+    s.ntiles = NYb * NZb;
+    // tile of a row: blocks numbered plane-block by plane-block in the
+    // forward sweep, the reverse for backward sweeps
+    auto tile_of = [&](int32_t i) {
+        const int line = i / nx;
+        const int t = (line / ny / nz_b) * NYb + (line % ny) / ny_b;
+        return forward ? t : s.ntiles - 1 - t;
+    };
+    std::vector<int32_t> tile_ptr(static_cast<size_t>(s.ntiles) + 1, 0), trow(static_cast<size_t>(nb));
+    for (int32_t i = 0; i < nb; ++i) tile_ptr[tile_of(i) + 1]++;
+    for (int t = 0; t < s.ntiles; ++t) tile_ptr[t + 1] += tile_ptr[t];
+    {
+        std::vector<int32_t> fill(tile_ptr.begin(), tile_ptr.end() - 1);
+        for (int step = 0; step < nb; ++step) {        // rows of a tile in sweep order
+            const int32_t i = forward ? step : nb - 1 - step;
+            trow[fill[tile_of(i)]++] = i;
+        }
+    }
+    // every dependency on another tile must be on an earlier one
+    for (int32_t i = 0; i < nb; ++i)
+        for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d)
+            if (tile_of(deps[d].col) > tile_of(i)) return;
+    s.group = 1;
+    s.gstride = 1;
+    s.ngroups = s.ntiles;
+    s.group_tiles.resize(static_cast<size_t>(s.ntiles));
+    std::iota(s.group_tiles.begin(), s.group_tiles.end(), 0);
+    s.tile_chunk_ptr.assign(static_cast<size_t>(s.ntiles) + 1, 0);
+    s.tile_lo.assign(static_cast<size_t>(s.ntiles), 0);
+    s.chunk_off.assign(1, 0);
+    std::vector<int32_t> lev(static_cast<size_t>(nb), 0), chunk_of(static_cast<size_t>(nb), -1),
+        q_of(static_cast<size_t>(nb), -1);
+    // chunks: rows of a tile by level inside the tile, at most rpc per chunk
+    std::vector<int32_t> order;
+    std::vector<int32_t> chunk_tile;
+    for (int t = 0; t < s.ntiles; ++t) {
+        const int32_t b0 = tile_ptr[t], b1 = tile_ptr[t + 1];
+        s.tile_lo[t] = trow[b0];
+        s.tile_chunk_ptr[t] = static_cast<int32_t>(chunk_tile.size());
+        for (int32_t p = b0; p < b1; ++p) {
+            const int32_t i = trow[p];
+            int32_t l = 0;
+            for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+                const int32_t j = deps[d].col;
+                if (tile_of(j) == t) l = std::max(l, lev[j] + 1);
+            }
+            lev[i] = l;
+        }
+        order.assign(trow.begin() + b0, trow.begin() + b1);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            if (lev[a] != lev[b]) return lev[a] < lev[b];
+            return (dptr[a + 1] - dptr[a]) > (dptr[b + 1] - dptr[b]);
+        });
+        size_t pos = 0;
+        while (pos < order.size()) {
+            size_t cn = 0;
+            while (pos + cn < order.size() && cn < static_cast<size_t>(rpc) && lev[order[pos + cn]] == lev[order[pos]])
+                ++cn;
+            const int32_t c = static_cast<int32_t>(chunk_tile.size());
+            chunk_tile.push_back(t);
+            for (size_t q = 0; q < static_cast<size_t>(rpc); ++q) {
+                const int32_t i = q < cn ? order[pos + q] : -1;
+                s.rows.push_back(i);
+                if (i >= 0) {
+                    chunk_of[i] = c;
+                    q_of[i] = static_cast<int32_t>(q);
+                }
+            }
+            pos += cn;
+        }
+    }
+    s.nchunks = static_cast<int>(chunk_tile.size());
+    s.tile_chunk_ptr[s.ntiles] = s.nchunks;
+    // ring depth: the farthest in-tile dependency, in chunks
+    int maxd = 0;
+    for (int32_t i = 0; i < nb; ++i)
+        for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+            const int32_t j = deps[d].col;
+            if (tile_of(j) == tile_of(i)) maxd = std::max(maxd, chunk_of[i] - chunk_of[j]);
+        }
+    if (maxd >= kRingMax) return;
+    s.ring = std::max(1, maxd + 1);
+    s.tile_rows = s.ring * rpc;
+    const int32_t pad_code = tiled_local_code(s.ring * rpc, bs);        // the zero row
+    for (int c = 0; c < s.nchunks; ++c) {
+        const int t = chunk_tile[c];
+        const int32_t first = s.tile_chunk_ptr[t];
+        const int32_t* rowc = &s.rows[static_cast<size_t>(c) * rpc];
+        const int32_t w = std::max(dptr[rowc[0] + 1] - dptr[rowc[0]], s.kmax);
+        const int64_t base = s.chunk_off.back();
+        s.chunk_off.push_back(base + static_cast<int64_t>(w) * rpc);
+        s.deps.resize(static_cast<size_t>(base) + static_cast<size_t>(w) * rpc, pad_code);
+        s.src.resize(s.deps.size(), -1);
+        for (int q = 0; q < rpc; ++q) {
+            const int32_t i = rowc[q];
+            if (i < 0) continue;
+            for (int32_t d = dptr[i]; d < dptr[i + 1]; ++d) {
+                const size_t slot = static_cast<size_t>(base) + static_cast<size_t>(d - dptr[i]) * rpc + q;
+                const int32_t j = deps[d].col;
+                s.deps[slot] = tile_of(j) == t
+                                   ? tiled_local_code(((chunk_of[j] - first) % s.ring) * rpc + q_of[j], bs)
+                                   : tiled_global_code(j, bs);
+                s.src[slot] = deps[d].src;
+            }
+        }
+    }
+    s.nslots = s.chunk_off.back();
+    s.built = true;
+}
+
 // Event simulation of the tiled schedule: tiles run concurrently, a tile
 // walks its chunks in order, a chunk costs one step and may start once the
 // previous chunk of its tile is done and every row it reads from another
@@ -833,7 +993,8 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
                     if (!in(vb + static_cast<int64_t>(B - 1) * B * RPC, n_vals)) return false;
                 }
                 if (!in8((static_cast<int64_t>(row) * B + r) * 8, vec_bytes)) return false;
-                if (row - lo < 0 || row - lo >= s.tile_rows) return false;
+                if (!s.block_ny && (row - lo < 0 || row - lo >= s.tile_rows)) return false;
+                if (s.block_ny && s.ring < 1) return false;
                 const int64_t wrow = s.ring > 0 ? ((c - s.tile_chunk_ptr[t]) % s.ring) * RPC + qc : own + row - lo;
                 if (!in8((wrow * B + r) * 8, lds_bytes - B * 8)) return false;
             }
@@ -962,7 +1123,8 @@ int validate_layout(const Host& h)
                     const int32_t r = s.rows[static_cast<size_t>(c) * rpc + q];
                     if (r < -1 || r >= nb) return BILU_ERR_STATE;
                     if (r < 0) continue;
-                    if (r < lo || r - lo >= s.tile_rows || tile_of[r] != -1) return BILU_ERR_STATE;
+                    if (tile_of[r] != -1) return BILU_ERR_STATE;
+                    if (!s.block_ny && (r < lo || r - lo >= s.tile_rows)) return BILU_ERR_STATE;
                     tile_of[r] = t;
                     chunk_of[r] = c;
                 }
@@ -1049,7 +1211,8 @@ int validate_layout(const Host& h)
         for (int i = 0; i < nb; ++i)
             if (seen[i] != ndep[i]) return BILU_ERR_STATE;
         if (!tiled_accesses_in_bounds(h, s, w)) return BILU_ERR_STATE;
-        if (w == BILU_SWEEP_U && G == 1) {   // the order of the U' sweep fused with the SpMV
+        if (s.block_ny && s.ring < 1) return BILU_ERR_STATE;
+        if (w == BILU_SWEEP_U && G == 1 && !s.block_ny) {   // the order of the U' sweep fused with the SpMV
             std::vector<int32_t> sched;
             if (build_fused_schedule(h, s, sched) != BILU_OK) return BILU_ERR_STATE;
         }

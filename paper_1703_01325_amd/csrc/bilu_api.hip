@@ -1,6 +1,7 @@
 // C ABI of the block ILU(k) library: context, device storage, launches and
 // the Krylov drivers.  See include/bilu.h for the contract of each call.
 #include <hip/hip_runtime.h>
+#include <cstdio>
 
 #include <algorithm>
 #include <climits>
@@ -21,10 +22,21 @@ using dev::KState;
 using dev::SweepArgs;
 using dev::TiledArgs;
 
+#ifdef BILU_TRACE
+#define CK(call)                                                                                   \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            fprintf(stderr, "HIP error %s at %s:%d\n", hipGetErrorString(e_), __FILE__, __LINE__); \
+            return BILU_ERR_HIP;                                                                   \
+        }                                                                                          \
+    } while (0)
+#else
 #define CK(call)                                       \
     do {                                               \
         if ((call) != hipSuccess) return BILU_ERR_HIP; \
     } while (0)
+#endif
 
 namespace {
 constexpr int kFormLevel = 0;   // level-chunk layout (sweep modes 0 and 1)
@@ -46,6 +58,7 @@ struct bilu_ctx {
     int tile_group = 1;         // tiles per workgroup of the tiled layouts
     int tile_rows_req = 0;      // requested rows per tile (0: by schedule simulation)
     int tile_group_req = 0;     // requested tiles per group (0: by schedule simulation)
+    int tile_block = 0;         // line-block tiles: ny + 256*nz (0: row-range tiles)
     int64_t lds_max = 65536;    // LDS bytes a workgroup may use (the device's, once known)
     int64_t layout_lds = 0;     // lds_max the tiled layouts were chosen for
     int blocks_override = 0;
@@ -80,8 +93,13 @@ struct bilu_ctx {
     double* d_kv = nullptr;
     size_t kv_cap = 0;
     double* d_part = nullptr;
+    double* d_gmh = nullptr;    // GMRES Hessenberg matrix, coefficient and y
+    size_t gm_cap = 0;
     KState* d_state = nullptr;
-    KState* h_state = nullptr;  // pinned host copy read back every Krylov step
+    KState* h_state = nullptr;  // pinned host copy of the Krylov state, read at the end of a solve
+    int* h_flags = nullptr;     // mapped pinned host flags written by the decide kernel (2 slots)
+    int* d_flags = nullptr;     // their device address
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
 
     // HIP-event timing of kernel classes (bilu_timing)
     bool timing = false;
@@ -204,9 +222,9 @@ bool launch_fused(int bs, int kmax, int prec, int blocks, size_t lds, hipStream_
 }
 
 bool launch_spmv(int bs, int rt, bool tr, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src,
-                 const double* Ax, const double* x, double* y, int R, hipStream_t s)
+                 const double* Ax, const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr)
 {
-    BILU_SWITCH_B(bs, if (!launch::spmv<B>(rt, tr, nb, rp, cj, src, Ax, x, y, R, s)) return false)
+    BILU_SWITCH_B(bs, if (!launch::spmv<B>(rt, tr, nb, rp, cj, src, Ax, x, y, R, s, gate)) return false)
 }
 
 // Rows [first, first + nrows) of the L level order.
@@ -315,6 +333,16 @@ void choose_layout(bilu_ctx* c)
     c->layout_lds = c->lds_max;
 }
 
+// Tiled layout of sweep w as requested: line blocks where asked for and
+// possible, else row-range tiles of the chosen size and group.
+void build_tiled_layout(bilu_ctx* c, int w)
+{
+    HostTiled& ht = c->h.tiled[w];
+    ht.built = false;
+    if (c->tile_block > 0) build_tiled_blocks(c->h, w, c->h.rpc, c->tile_block & 255, c->tile_block >> 8, ht);
+    if (!ht.built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->tile_group, c->lds_max, true, ht);
+}
+
 // Group size the tiled layouts were built with (they fall back to smaller
 // groups where a larger one cannot be used).
 int built_group(const bilu_ctx* c)
@@ -335,7 +363,7 @@ bilu_status set_layout(bilu_ctx* c, int tile_rows_req, int tile_group_req)
     free_form(c, kFormTiled);
     c->layouts_checked = false;
     for (int w = 0; w < 4; ++w)
-        if (c->h.sweep[w].built) build_tiled(c->h, w, c->h.rpc, c->tile_rows, c->tile_group, c->lds_max, true, c->h.tiled[w]);
+        if (c->h.sweep[w].built) build_tiled_layout(c, w);
     return BILU_OK;
 }
 
@@ -356,8 +384,8 @@ bilu_status upload_form(bilu_ctx* c, int form)
             if (!h.sweep[w].built) continue;
             if (c->tile_rows <= 0 || c->layout_lds != c->lds_max) choose_layout(c);
             HostTiled& ht = h.tiled[w];
-            if (!ht.built || ht.tile_rows != c->tile_rows || ht.group_req != c->tile_group) {
-                build_tiled(h, w, h.rpc, c->tile_rows, c->tile_group, c->lds_max, true, ht);
+            if (!ht.built || (!ht.block_ny && (ht.tile_rows != c->tile_rows || ht.group_req != c->tile_group))) {
+                build_tiled_layout(c, w);
                 c->layouts_checked = false;
             }
             std::vector<int32_t> crow(ht.chunk_off.size());
@@ -535,7 +563,13 @@ int persistent_blocks(bilu_ctx* c, int units, int units_per_block, int per_cu)
     return std::max(1, std::min(want, cap));
 }
 
-bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, double* reset, int R, hipStream_t s)
+#ifdef BILU_TRACE
+long long* g_trace_buf[4] = {nullptr, nullptr, nullptr, nullptr};
+size_t g_trace_n[4] = {0, 0, 0, 0};
+#endif
+
+bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, double* reset, int R, hipStream_t s,
+                      const int* gate = nullptr)
 {
     const int form = sweep_form(c, R);
     const long tslot = timing_begin(c, BILU_K_SWEEP_L + which, s);
@@ -564,6 +598,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.ngroups = ht.ngroups;
         a.group_tiles = d.group_tiles;
         a.chunk_wait = d.chunk_wait;
+        a.gate = gate;
         // tickets: tiles (or groups of tiles) times right-hand sides
         const int blocks = ht.group > 1 ? persistent_blocks(c, ht.ngroups * R, 1, std::max(1, 8 / ht.group))
                                         : persistent_blocks(c, ht.ntiles * R, 1, 8);
@@ -574,6 +609,22 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         // (padding slots read it) and the members' progress counts
         const size_t lds = static_cast<size_t>(tiled_lds_bytes(a.tile_rows, ht.group, c->h.bs));
         if (static_cast<int64_t>(lds) > c->lds_max) return BILU_ERR_STATE;
+#ifdef BILU_TRACE
+        {
+            static long long* tbuf[4] = {nullptr, nullptr, nullptr, nullptr};
+            static size_t tcap[4] = {0, 0, 0, 0};
+            const size_t need = 4 * static_cast<size_t>(ht.nchunks) + ht.ntiles;
+            if (tcap[which] < need) {
+                if (tbuf[which]) (void)hipFree(tbuf[which]);
+                if (hipMalloc(&tbuf[which], need * sizeof(long long)) != hipSuccess) return BILU_ERR_ALLOC;
+                tcap[which] = need;
+            }
+            a.trace = tbuf[which];
+            a.trace_nchunks = ht.nchunks;
+            g_trace_buf[which] = tbuf[which];
+            g_trace_n[which] = need;
+        }
+#endif
         if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) return BILU_ERR_ARG;
     } else {
         const HostSweep& hs = c->h.sweep[which];
@@ -594,6 +645,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.R = R;
         a.fuse = fuse;
         a.spin_limit = c->spin_limit;
+        a.gate = gate;
         if (c->sweep_mode != 0) {
             a.persistent = 1;
             const int blocks = persistent_blocks(c, hs.nchunks, dev::kWavesPerBlock, 1);
@@ -617,7 +669,8 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
 }
 
 // z = M^{-1} r: first sweep r -> y (resets z), second y -> z (resets y).
-bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transpose, hipStream_t s)
+bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transpose, hipStream_t s,
+                     const int* gate = nullptr)
 {
     if (!c || !r || !z || R < 1 || R > dev::kMaxRhs || r == z) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
@@ -628,24 +681,26 @@ bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transp
     const int form = sweep_form(c, R);
     if ((st = layout_form(c, form, s))) return st;
     if ((st = ensure_y(c, R, s))) return st;
-    if ((st = run_sweep(c, first, r, c->d_y, z, R, s))) return st;
-    return run_sweep(c, second, c->d_y, z, c->d_y, R, s);
+    if ((st = run_sweep(c, first, r, c->d_y, z, R, s, gate))) return st;
+    return run_sweep(c, second, c->d_y, z, c->d_y, R, s, gate);
 }
 
+// timed: counted in the SpMV class of bilu_timing (the solvers' gated
+// true-residual SpMV, mostly gated off, is not)
 bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, int R, int transpose,
-                    hipStream_t s)
+                    hipStream_t s, const int* gate = nullptr, bool timed = true)
 {
     if (!c || !Ax || !x || !y || R < 1 || R > dev::kMaxRhs || x == y) return BILU_ERR_ARG;
     bilu_status st = ensure_device(c);
     if (st) return st;
     const Host& h = c->h;
     bool ok;
-    const long tslot = timing_begin(c, BILU_K_SPMV, s);
+    const long tslot = timed ? timing_begin(c, BILU_K_SPMV, s) : -1;
     if (transpose) {
         if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
-        ok = launch_spmv(h.bs, rhs_tile(c, R), true, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s);
+        ok = launch_spmv(h.bs, rhs_tile(c, R), true, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s, gate);
     } else {
-        ok = launch_spmv(h.bs, rhs_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s);
+        ok = launch_spmv(h.bs, rhs_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s, gate);
     }
     timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
@@ -658,19 +713,20 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
 // ticket order).  Falls back to the separate calls where the fused launch
 // does not apply (other sweep forms, transposes, several columns).
 bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double* z, double* y, int R,
-                          bool transpose, hipStream_t s)
+                          bool transpose, hipStream_t s, const int* gate = nullptr)
 {
     if (transpose || R != 1 || sweep_form(c, 1) != kFormTiled || !c->fuse_spmv) {
-        bilu_status st = do_apply(c, r, z, R, transpose, s);
-        return st ? st : do_spmv(c, Ax, z, y, R, transpose ? 1 : 0, s);
+        bilu_status st = do_apply(c, r, z, R, transpose, s, gate);
+        return st ? st : do_spmv(c, Ax, z, y, R, transpose ? 1 : 0, s, gate);
     }
     if (!c || !Ax || !r || !z || !y || r == z || y == z) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
     bilu_status st;
     if ((st = layout_form(c, kFormTiled, s))) return st;
-    if (c->h.tiled[BILU_SWEEP_U].group > 1) {      // the fused ticket order is for single tiles
-        st = do_apply(c, r, z, R, false, s);
-        return st ? st : do_spmv(c, Ax, z, y, R, 0, s);
+    if (c->h.tiled[BILU_SWEEP_U].group > 1 || c->h.tiled[BILU_SWEEP_U].block_ny) {
+        // the fused ticket order is for single row-range tiles
+        st = do_apply(c, r, z, R, false, s, gate);
+        return st ? st : do_spmv(c, Ax, z, y, R, 0, s, gate);
     }
     if ((st = ensure_y(c, 1, s))) return st;
     HostTiled& hu = c->h.tiled[BILU_SWEEP_U];
@@ -679,7 +735,7 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
         if (build_fused_schedule(c->h, hu, hu.fused) != BILU_OK) return BILU_ERR_STATE;
         if ((st = upload(c, &du.fused, hu.fused))) return st;
     }
-    if ((st = run_sweep(c, BILU_SWEEP_L, r, c->d_y, z, 1, s))) return st;
+    if ((st = run_sweep(c, BILU_SWEEP_L, r, c->d_y, z, 1, s, gate))) return st;
     // U' sweep + SpMV
     const long tslot = timing_begin(c, BILU_K_SWEEP_U_SPMV, s);
     TiledArgs a{};
@@ -701,6 +757,7 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
     a.tile_rows = hu.ring > 0 ? hu.ring * c->h.rpc : hu.tile_rows;
     a.R = 1;
     a.spin_limit = c->spin_limit;
+    a.gate = gate;
     dev::FusedSpmvArgs m{};
     m.sched = du.fused;
     m.nsched = static_cast<int>(hu.fused.size());
@@ -727,6 +784,23 @@ bilu_status do_apply_spmv(bilu_ctx* c, const double* Ax, const double* r, double
 // ABI
 // ===========================================================================
 extern "C" {
+
+#ifdef BILU_TRACE
+// trace of the last tiled launch of sweep `which`: chunk finish times, then
+// tile start times (device wall clock); also the tile -> chunk map
+int64_t bilu_trace_get(bilu_ctx* c, int which, long long* host, int64_t cap, int32_t* tile_ptr, int32_t* group_tiles,
+                       int64_t cap2)
+{
+    if (!g_trace_buf[which]) return -1;
+    (void)hipDeviceSynchronize();
+    const int64_t n = std::min<int64_t>(cap, g_trace_n[which]);
+    (void)hipMemcpy(host, g_trace_buf[which], n * sizeof(long long), hipMemcpyDeviceToHost);
+    const HostTiled& ht = c->h.tiled[which];
+    for (int64_t i = 0; i < std::min<int64_t>(cap2, ht.tile_chunk_ptr.size()); ++i) tile_ptr[i] = ht.tile_chunk_ptr[i];
+    for (int64_t i = 0; i < std::min<int64_t>(cap2, ht.group_tiles.size()); ++i) group_tiles[i] = ht.group_tiles[i];
+    return n;
+}
+#endif
 
 bilu_status bilu_analyze(int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags,
                          bilu_ctx** out)
@@ -794,6 +868,7 @@ bilu_status bilu_get_info(const bilu_ctx* c, bilu_info* info)
         info->nlev[w] = h.sweep[w].built ? h.sweep[w].nlev : 0;
         info->sweep_slots[w] = h.sweep[w].built ? h.sweep[w].nslots : 0;
         info->lds_ring[w] = h.tiled[w].built ? h.tiled[w].ring : 0;
+        info->tile_block[w] = h.tiled[w].built && h.tiled[w].block_ny ? h.tiled[w].block_ny + 256 * h.tiled[w].block_nz : 0;
     }
     return BILU_OK;
 }
@@ -955,6 +1030,18 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (value != 0 && value != 1) return BILU_ERR_ARG;
         c->fuse_spmv = value != 0;
         return BILU_OK;
+    case BILU_TUNE_TILE_BLOCK: {
+        const int ny = value & 255, nz = value >> 8;
+        if (value < 0 || (value != 0 && (ny < 1 || nz < 1 || nz > 255))) return BILU_ERR_ARG;
+        if (value == c->tile_block) return BILU_OK;
+        c->tile_block = value;
+        free_form(c, kFormTiled);
+        c->layouts_checked = false;
+        if (c->tile_rows <= 0) choose_layout(c);
+        for (int w = 0; w < 4; ++w)
+            if (c->h.sweep[w].built) build_tiled_layout(c, w);
+        return BILU_OK;
+    }
     }
     return BILU_ERR_ARG;
 }
@@ -1129,6 +1216,38 @@ static bilu_status ensure_krylov(bilu_ctx* c, int R, int nvec)
     return BILU_OK;
 }
 
+// Host side of the solvers' step loop: pinned state, mapped flags and the
+// two events of the one-step-behind exit test.
+static bilu_status ensure_step_host(bilu_ctx* c)
+{
+    if (!c->h_state) {
+        void* hp = nullptr;
+        if (hipHostMalloc(&hp, sizeof(KState), hipHostMallocDefault) != hipSuccess) return BILU_ERR_ALLOC;
+        c->h_state = static_cast<KState*>(hp);
+    }
+    if (!c->h_flags) {
+        void* hp = nullptr;
+        if (hipHostMalloc(&hp, 2 * sizeof(int), hipHostMallocMapped) != hipSuccess) return BILU_ERR_ALLOC;
+        c->h_flags = static_cast<int*>(hp);
+        void* dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) return BILU_ERR_HIP;
+        c->d_flags = static_cast<int*>(dp);
+    }
+    for (hipEvent_t& e : c->step_ev)
+        if (!e) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return BILU_OK;
+}
+
+// Right-preconditioned BiCGSTAB on R columns at once, each with its own
+// recurrence.  Every decision is taken on the device: the scalar kernels
+// freeze a column that breaks down, k_bicg_s_end marks a column whose
+// recurrence residual passes for the true-residual test, a gated SpMV
+// computes b - A x only when some column is marked, and k_bicg_decide
+// either stops the column (true residual passes) or restarts it from the
+// true residual.  The host queues steps without waiting: after queuing step
+// it, it waits only for step it - 1 and reads the flag that step wrote to
+// mapped host memory, so one step is always queued ahead; a step queued
+// after every column had stopped is gated off and costs only its launches.
 static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, double* x, int R,
                             const bilu_solve_opts* o, bilu_rhs_info* info, int tr, hipStream_t s)
 {
@@ -1136,114 +1255,75 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
     const size_t vb = static_cast<size_t>(n) * R * sizeof(double);
     bilu_status st = ensure_krylov(c, R, 9);
     if (st) return st;
+    if ((st = ensure_step_host(c))) return st;
     double* kv = c->d_kv;
     const size_t stride = static_cast<size_t>(n) * R;
     double *r = kv, *rh = kv + stride, *p = kv + 2 * stride, *v = kv + 3 * stride, *ph = kv + 4 * stride;
     double *sv = kv + 5 * stride, *sh = kv + 6 * stride, *t = kv + 7 * stride, *w = kv + 8 * stride;
     double* part = c->d_part;
     KState* S = c->d_state;
+    const int* g_active = &S->any_active;
+    const int* g_check = &S->any_check;
     const int eg = grid_for(n * R);
-    auto spmv = [&](const double* in, double* out) { return do_spmv(c, Ax, in, out, R, tr, s); };
+    const dim3 rb(dev::kRedBlocks), rt(dev::kThreads);
 
     CK(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, s));
     CK(hipMemcpyAsync(rh, b, vb, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, x, 0.0);
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, p, 0.0);
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n * R, v, 0.0);
-    hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, b, part, dev::SL_BB);
+    hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, R, b, b, part, dev::SL_BB, nullptr);
     hipLaunchKernelGGL(dev::k_bicg_init, dim3(R), dim3(64), 0, s, R, part, S, o->rtol);
+    hipLaunchKernelGGL(dev::k_bicg_decide, dim3(1), dim3(64), 0, s, R, S, 0, c->d_flags);
     CK(hipGetLastError());
+    CK(hipEventRecord(c->step_ev[0], s));
 
-    if (!c->h_state) {
-        void* hp = nullptr;
-        if (hipHostMalloc(&hp, sizeof(KState), hipHostMallocDefault) != hipSuccess) return BILU_ERR_ALLOC;
-        c->h_state = static_cast<KState*>(hp);
-    }
-    KState& hs = *c->h_state;      // pinned: the per-step read-back is a plain DMA
-    CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
-    std::vector<int> iters(R, 0), done(R, 0);
-    for (int j = 0; j < R; ++j)
-        if (!hs.active[j]) done[j] = 1;
     int it = 0;
-    bool any_active = std::find(done.begin(), done.end(), 0) != done.end();
-    while (any_active && it < o->maxit) {
+    while (it < o->maxit) {
         ++it;
-        hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, r, part, dev::SL_RHO);
+        hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, R, rh, r, part, dev::SL_RHO, g_active);
         hipLaunchKernelGGL(dev::k_bicg_s_rho, dim3(R), dim3(64), 0, s, R, part, S);
         hipLaunchKernelGGL(dev::k_bicg_p, dim3(eg), dim3(256), 0, s, n, R, r, v, p, S);
-        if ((st = do_apply_spmv(c, Ax, p, ph, v, R, tr != 0, s))) return st;
-        hipLaunchKernelGGL(dev::k_dot, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, rh, v, part, dev::SL_RV);
+        if ((st = do_apply_spmv(c, Ax, p, ph, v, R, tr != 0, s, g_active))) return st;
+        hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, R, rh, v, part, dev::SL_RV, g_active);
         hipLaunchKernelGGL(dev::k_bicg_s_alpha, dim3(R), dim3(64), 0, s, R, part, S);
-        hipLaunchKernelGGL(dev::k_bicg_s, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, r, v, sv, S, part);
+        hipLaunchKernelGGL(dev::k_bicg_s, rb, rt, 0, s, n, R, r, v, sv, S, part);
         hipLaunchKernelGGL(dev::k_bicg_s_snorm, dim3(R), dim3(64), 0, s, R, part, S);
-        if ((st = do_apply_spmv(c, Ax, sv, sh, t, R, tr != 0, s))) return st;
-        hipLaunchKernelGGL(dev::k_dot2, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, t, sv, part,
-                           dev::SL_TS, dev::SL_TT);
+        if ((st = do_apply_spmv(c, Ax, sv, sh, t, R, tr != 0, s, g_active))) return st;
+        hipLaunchKernelGGL(dev::k_dot2, rb, rt, 0, s, n, R, t, sv, part, dev::SL_TS, dev::SL_TT, g_active);
         hipLaunchKernelGGL(dev::k_bicg_s_omega, dim3(R), dim3(64), 0, s, R, part, S);
-        hipLaunchKernelGGL(dev::k_bicg_xr, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, x, r, ph, sh, sv, t,
-                           S, part);
+        hipLaunchKernelGGL(dev::k_bicg_xr, rb, rt, 0, s, n, R, x, r, ph, sh, sv, t, S, part);
         hipLaunchKernelGGL(dev::k_bicg_s_end, dim3(R), dim3(64), 0, s, R, part, S);
+        // true residual of the marked columns, then their verdict
+        if ((st = do_spmv(c, Ax, x, w, R, tr, s, g_check, false))) return st;
+        hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, R, b, w, part, dev::SL_TRUE, g_check);
+        hipLaunchKernelGGL(dev::k_s_true, dim3(R), dim3(64), 0, s, R, part, S, g_check);
+        hipLaunchKernelGGL(dev::k_bicg_decide, dim3(1), dim3(64), 0, s, R, S, it, c->d_flags + (it & 1));
+        hipLaunchKernelGGL(dev::k_bicg_restart, dim3(eg), dim3(256), 0, s, n, R, w, r, rh, S);
         CK(hipGetLastError());
-        CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
-        CK(hipStreamSynchronize(s));
-        bool candidate = false;
-        for (int j = 0; j < R; ++j) {
-            if (done[j]) continue;
-            if (!hs.active[j]) {       // breakdown / non-finite
-                done[j] = 1;
-                iters[j] = it;
-                continue;
-            }
-            if (hs.half[j] || hs.rnorm2[j] <= hs.tol2[j]) candidate = true;
-        }
-        if (candidate) {
-            if ((st = spmv(x, w))) return st;
-            hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part,
-                               dev::SL_TRUE);
-            hipLaunchKernelGGL(dev::k_s_true, dim3(R), dim3(64), 0, s, R, part, S);
-            CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
-            CK(hipStreamSynchronize(s));
-            bool restart = false;
-            for (int j = 0; j < R; ++j) {
-                hs.restart[j] = 0;
-                if (done[j] || !hs.active[j]) continue;
-                if (!(hs.half[j] || hs.rnorm2[j] <= hs.tol2[j])) continue;
-                if (hs.tnorm2[j] <= hs.tol2[j]) {
-                    hs.active[j] = 0;
-                    hs.status[j] = dev::ST_OK;
-                    done[j] = 1;
-                    iters[j] = it;
-                } else {
-                    hs.restart[j] = 1;
-                    hs.fresh[j] = 1;
-                    hs.half[j] = 0;
-                    restart = true;
-                }
-            }
-            CK(hipMemcpyAsync(S, &hs, sizeof(KState), hipMemcpyHostToDevice, s));
-            CK(hipStreamSynchronize(s));
-            if (restart)
-                hipLaunchKernelGGL(dev::k_bicg_restart, dim3(eg), dim3(256), 0, s, n, R, w, r, rh, S);
-        }
-        any_active = std::find(done.begin(), done.end(), 0) != done.end();
+        CK(hipEventRecord(c->step_ev[it & 1], s));
+        // step it - 1 has written its flag once its event has completed
+        CK(hipEventSynchronize(c->step_ev[(it - 1) & 1]));
+        if (__hip_atomic_load(c->h_flags + ((it - 1) & 1), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == 0) break;
     }
     // final true residuals for every column
-    if ((st = spmv(x, w))) return st;
-    hipLaunchKernelGGL(dev::k_resid, dim3(dev::kRedBlocks), dim3(dev::kThreads), 0, s, n, R, b, w, part, dev::SL_TRUE);
-    hipLaunchKernelGGL(dev::k_s_true, dim3(R), dim3(64), 0, s, R, part, S);
+    if ((st = do_spmv(c, Ax, x, w, R, tr, s))) return st;
+    hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, R, b, w, part, dev::SL_TRUE, nullptr);
+    hipLaunchKernelGGL(dev::k_s_true, dim3(R), dim3(64), 0, s, R, part, S, nullptr);
+    KState& hs = *c->h_state;
     CK(hipMemcpyAsync(&hs, S, sizeof(KState), hipMemcpyDeviceToHost, s));
     int sweep_err = 0;
     CK(hipMemcpyAsync(&sweep_err, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     int worst = BILU_OK;
     for (int j = 0; j < R; ++j) {
-        if (!done[j]) iters[j] = it;
         int stj = hs.status[j];
-        if (!done[j]) stj = BILU_NOT_CONVERGED;
+        if (hs.active[j]) stj = BILU_NOT_CONVERGED;
         info[j].status = stj;
-        info[j].iters = iters[j];
+        info[j].iters = hs.done_it[j] >= 0 ? hs.done_it[j] : it;
         info[j].relres = hs.bnorm2[j] > 0 ? std::sqrt(hs.tnorm2[j] / hs.bnorm2[j]) : 0.0;
+        info[j].restarts = hs.nrestart[j];
+        info[j].reserved = 0;
         if (stj > worst) worst = stj;
     }
     if (sweep_err) {
@@ -1270,8 +1350,17 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
     double* w = V + static_cast<size_t>(m + 1) * n;
     double* z = w + n;
     double* u = z + n;
-    double* dH = nullptr;                                  // (m+1) x m, column j contiguous, + coef + y
-    if ((st = dalloc(c, &dH, static_cast<size_t>(m + 1) * m + 1 + m))) return st;
+    // (m+1) x m Hessenberg matrix, column j contiguous, + coef + y; kept in
+    // the context across solves
+    const size_t hneed = static_cast<size_t>(m + 1) * m + 1 + m;
+    if (c->gm_cap < hneed) {
+        dfree(c, c->d_gmh);
+        c->d_gmh = nullptr;
+        c->gm_cap = 0;
+        if ((st = dalloc(c, &c->d_gmh, hneed))) return st;
+        c->gm_cap = hneed;
+    }
+    double* dH = c->d_gmh;
     double* coef = dH + static_cast<size_t>(m + 1) * m;
     double* dy = coef + 1;
     double* part = c->d_part;
@@ -1286,17 +1375,17 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
     };
 
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n, x, 0.0);
-    hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, 1, b, b, part, dev::SL_BB);
+    hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, 1, b, b, part, dev::SL_BB, nullptr);
     hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_BB, dH, coef, 1);
     double bnorm = 0.0;
-    if ((st = fetch(&bnorm, dH, 1))) { dfree(c, dH); return st; }
+    if ((st = fetch(&bnorm, dH, 1))) return st;
     std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 1);
-    int total = 0, status = BILU_NOT_CONVERGED;
+    int total = 0, cycles = 0, status = BILU_NOT_CONVERGED;
     double rres = bnorm;
     if (bnorm == 0.0) status = BILU_OK;
     while (status == BILU_NOT_CONVERGED) {
         if ((st = spmv(x, w))) break;
-        hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE);
+        hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE, nullptr);
         hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1);
         double beta = 0.0;
         if ((st = fetch(&beta, dH, 1))) break;
@@ -1355,11 +1444,11 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
         hipLaunchKernelGGL(dev::k_gm_combine, dim3(eg), dim3(256), 0, s, n, jend, V, dy, u);
         if ((st = apply(u, z))) break;
         hipLaunchKernelGGL(dev::k_axpy1, dim3(eg), dim3(256), 0, s, n, x, z);
-        if (hipStreamSynchronize(s) != hipSuccess) { st = BILU_ERR_HIP; break; }
+        ++cycles;
     }
     if (!st && status == BILU_BREAKDOWN) {
         if ((st = spmv(x, w)) == BILU_OK) {
-            hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE);
+            hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE, nullptr);
             hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1);
             st = fetch(&rres, dH, 1);
         }
@@ -1370,11 +1459,12 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
             hipStreamSynchronize(s) != hipSuccess)
             st = BILU_ERR_HIP;
     }
-    dfree(c, dH);
     if (st) return st;
     info[0].status = status;
     info[0].iters = total;
     info[0].relres = bnorm > 0.0 ? rres / bnorm : 0.0;
+    info[0].restarts = cycles;
+    info[0].reserved = 0;
     if (sweep_err) {
         CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
         CK(hipStreamSynchronize(s));
@@ -1404,6 +1494,9 @@ void bilu_destroy(bilu_ctx* c)
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
+    for (hipEvent_t e : c->step_ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 

@@ -67,6 +67,11 @@ struct HostTiled {
     // rows in any member tile are local; chunk_wait[c*kGroupMax + m] is the
     // number of chunks member m must have finished before chunk c reads LDS.
     int ring = 0;                          // > 0: LDS ring of this many chunks (group 1 only)
+    // line blocks (block_ny > 0): a tile is a block of block_ny x block_nz
+    // grid lines (rows of nx consecutive block rows), not a contiguous row
+    // range; tile-local rows are always addressed through the LDS ring, and
+    // tile_lo holds the tile's first row only
+    int block_ny = 0, block_nz = 0;
     int group = 1;
     int group_req = 1;                     // the group size asked of build_tiled
     int gstride = 1;
@@ -197,6 +202,17 @@ struct TileChoice {
 // fixes the tile size; group_req 1 leaves groups out, > 1 asks for that size.
 std::vector<TileChoice> rank_tile_layouts(const Host& h, int rpc, int64_t lds_limit, int tile_req, int group_req);
 int validate_layout(const Host& h);
+// Grid lines of a pattern in natural order: nx (block rows per line) and
+// nxy (per plane) when the rows without an L dependency on the previous row
+// are exactly the multiples of nx, and those without one on the row nx back
+// exactly the multiples of nxy; false otherwise.
+bool grid_lines(const Host& h, int& nx, int& nxy);
+// Tiled layout of one sweep whose tiles are blocks of ny_b x nz_b grid lines
+// (tickets in sweep order of the blocks, plane by plane), one wavefront per
+// tile, tile-local rows in an LDS ring.  Leaves out.built false where the
+// pattern has no grid lines, a dependency crosses to a later block, or the
+// in-tile dependencies span more chunks than the ring can hold.
+void build_tiled_blocks(const Host& h, int which, int rpc, int ny_b, int nz_b, HostTiled& out);
 // Ticket order of the backward U' tiled sweep fused with the SpMV on its
 // output: all tiles, then each block of rpc rows of A, ordered by the tile
 // that finishes the lowest row the block reads.  Checked before it is

@@ -476,6 +476,12 @@ struct KState {
     double rho[kMaxRhs], rho_old[kMaxRhs], alpha[kMaxRhs], omega[kMaxRhs], beta[kMaxRhs];
     double bnorm2[kMaxRhs], tol2[kMaxRhs], snorm2[kMaxRhs], rnorm2[kMaxRhs], tnorm2[kMaxRhs];
     int active[kMaxRhs], fresh[kMaxRhs], half[kMaxRhs], status[kMaxRhs], restart[kMaxRhs];
+    int check[kMaxRhs];      // the recurrence passed the test this step: compute the true residual
+    int nrestart[kMaxRhs];   // restarts from the true residual so far
+    int done_it[kMaxRhs];    // step at which the column stopped (-1: still running)
+    int any_check;           // some column has check set (gates the true-residual pass)
+    int any_restart;         // some column restarts (gates the restart pass)
+    int any_active;          // some column still iterates (gates every kernel of a step)
     int sweep_status;
 };
 
@@ -549,8 +555,10 @@ __device__ __forceinline__ double* slot_ptr(double* part, int slot)
 }
 
 __global__ __launch_bounds__(kThreads) void k_dot(int64_t n, int R, const double* __restrict__ a,
-                                                  const double* __restrict__ b, double* part, int slot)
+                                                  const double* __restrict__ b, double* part, int slot,
+                                                  const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     const RedIdx ri = red_index(R);
     double acc = 0.0;
     if (ri.live)
@@ -562,8 +570,9 @@ __global__ __launch_bounds__(kThreads) void k_dot(int64_t n, int R, const double
 // t.s and t.t in one pass
 __global__ __launch_bounds__(kThreads) void k_dot2(int64_t n, int R, const double* __restrict__ t,
                                                    const double* __restrict__ s, double* part,
-                                                   int slot_ts, int slot_tt)
+                                                   int slot_ts, int slot_tt, const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     const RedIdx ri = red_index(R);
     double ts = 0.0, tt = 0.0;
     if (ri.live)
@@ -682,7 +691,8 @@ __device__ __forceinline__ void bicg_end_one(S& st, int c, double r2)
 }
 
 // BiCGSTAB setup: ||b||, tolerance, flags.  r = b, r^ = r, x = 0 are done
-// by copies on the host side.
+// by copies on the host side; k_bicg_decide(it = 0) follows and sets the
+// flags that gate the first step.
 // Scalar kernels: one wavefront (workgroup) per right-hand side c.
 __global__ __launch_bounds__(64) void k_bicg_init(int R, const double* part, KState* st, double rtol)
 {
@@ -691,11 +701,15 @@ __global__ __launch_bounds__(64) void k_bicg_init(int R, const double* part, KSt
     const double b2 = sum_partials(part, SL_BB, c);
     if (lane_id() != 0) return;
     bicg_init_one(*st, c, b2, rtol);
+    st->check[c] = 0;
+    st->nrestart[c] = 0;
+    st->done_it[c] = -1;
     if (c == 0) st->sweep_status = 0;
 }
 
 __global__ __launch_bounds__(64) void k_bicg_s_rho(int R, const double* part, KState* st)
 {
+    if (!st->any_active) return;
     const int c = blockIdx.x;
     if (c >= R) return;
     const double v = sum_partials(part, SL_RHO, c);
@@ -705,6 +719,7 @@ __global__ __launch_bounds__(64) void k_bicg_s_rho(int R, const double* part, KS
 __global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const double* __restrict__ v,
                          double* __restrict__ p, const KState* st)
 {
+    if (!st->any_active) return;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n * R;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int c = static_cast<int>(g % R);
@@ -715,6 +730,7 @@ __global__ void k_bicg_p(int64_t n, int R, const double* __restrict__ r, const d
 
 __global__ __launch_bounds__(64) void k_bicg_s_alpha(int R, const double* part, KState* st)
 {
+    if (!st->any_active) return;
     const int c = blockIdx.x;
     if (c >= R) return;
     const double v = sum_partials(part, SL_RV, c);
@@ -726,6 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t n, int R, const dou
                                                      const double* __restrict__ v, double* __restrict__ s,
                                                      const KState* st, double* part)
 {
+    if (!st->any_active) return;
     const RedIdx ri = red_index(R);
     double acc = 0.0;
     if (ri.live && st->active[ri.col]) {
@@ -742,6 +759,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_s(int64_t n, int R, const dou
 
 __global__ __launch_bounds__(64) void k_bicg_s_snorm(int R, const double* part, KState* st)
 {
+    if (!st->any_active) return;
     const int c = blockIdx.x;
     if (c >= R) return;
     const double v = sum_partials(part, SL_SS, c);
@@ -750,6 +768,7 @@ __global__ __launch_bounds__(64) void k_bicg_s_snorm(int R, const double* part, 
 
 __global__ __launch_bounds__(64) void k_bicg_s_omega(int R, const double* part, KState* st)
 {
+    if (!st->any_active) return;
     const int c = blockIdx.x;
     if (c >= R) return;
     const double ts = sum_partials(part, SL_TS, c);
@@ -767,6 +786,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t n, int R, double* 
                                                       const double* __restrict__ t, const KState* st,
                                                       double* part)
 {
+    if (!st->any_active) return;
     const RedIdx ri = red_index(R);
     double acc = 0.0;
     if (ri.live && st->active[ri.col]) {
@@ -789,18 +809,64 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(int64_t n, int R, double* 
     block_partial(acc, R, slot_ptr(part, SL_RR));
 }
 
+// End of a step: ||r||^2; a column whose recurrence residual (or the half
+// step) meets the tolerance is marked for the true-residual test.
 __global__ __launch_bounds__(64) void k_bicg_s_end(int R, const double* part, KState* st)
 {
+    if (!st->any_active) return;
     const int c = blockIdx.x;
     if (c >= R) return;
     const double v = sum_partials(part, SL_RR, c);
-    if (lane_id() == 0) bicg_end_one(*st, c, v);
+    if (lane_id() != 0) return;
+    bicg_end_one(*st, c, v);
+    const int chk = st->active[c] && (st->half[c] || st->rnorm2[c] <= st->tol2[c]);
+    st->check[c] = chk;
+    if (chk) atomicOr(&st->any_check, 1);
+}
+
+// After step `it` (0: after the setup), one wavefront, lane c for column c:
+// a column marked for the test converges if its true residual meets the
+// tolerance, else it restarts from it (r = r^ = b - A x).  Records the step
+// at which each column stopped, sets the flags that gate the next step and
+// copies any_active to *host_flag (mapped host memory, may be null), which
+// the host reads a step later to stop queueing steps.
+__global__ __launch_bounds__(64) void k_bicg_decide(int R, KState* st, int it, int* host_flag)
+{
+    const int c = lane_id();
+    int restart = 0, active = 0;
+    if (c < R) {
+        if (st->check[c] && st->active[c]) {
+            if (st->tnorm2[c] <= st->tol2[c]) {
+                st->active[c] = 0;
+                st->status[c] = ST_OK;
+            } else {
+                restart = 1;
+                st->fresh[c] = 1;
+                st->half[c] = 0;
+                st->nrestart[c] += 1;
+            }
+        }
+        st->check[c] = 0;
+        st->restart[c] = restart;
+        active = st->active[c];
+        if (!active && st->done_it[c] < 0) st->done_it[c] = it;
+    }
+    const bool any_restart = __any(restart);
+    const bool any_active = __any(active);
+    if (c == 0) {
+        st->any_check = 0;
+        st->any_restart = any_restart ? 1 : 0;
+        st->any_active = any_active ? 1 : 0;
+        if (host_flag) __hip_atomic_store(host_flag, any_active ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // w = b - w (w holds A x on entry), partial of w.w
 __global__ __launch_bounds__(kThreads) void k_resid(int64_t n, int R, const double* __restrict__ b,
-                                                    double* __restrict__ w, double* part, int slot)
+                                                    double* __restrict__ w, double* part, int slot,
+                                                    const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     const RedIdx ri = red_index(R);
     double acc = 0.0;
     if (ri.live)
@@ -813,8 +879,9 @@ __global__ __launch_bounds__(kThreads) void k_resid(int64_t n, int R, const doub
     block_partial(acc, R, slot_ptr(part, slot));
 }
 
-__global__ __launch_bounds__(64) void k_s_true(int R, const double* part, KState* st)
+__global__ __launch_bounds__(64) void k_s_true(int R, const double* part, KState* st, const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     const int c = blockIdx.x;
     if (c >= R) return;
     const double v = sum_partials(part, SL_TRUE, c);
@@ -825,6 +892,7 @@ __global__ __launch_bounds__(64) void k_s_true(int R, const double* part, KState
 __global__ void k_bicg_restart(int64_t n, int R, const double* __restrict__ w, double* __restrict__ r,
                                double* __restrict__ rh, KState* st)
 {
+    if (!st->any_restart) return;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n * R;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int c = static_cast<int>(g % R);

@@ -31,10 +31,11 @@ template <int B>
 bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a,
            const dev::FusedSpmvArgs& m);
 
-// y = A x (trans = false) or A^T x, rt columns per pass (1, 4 or 8).
+// y = A x (trans = false) or A^T x, rt columns per pass (1, 4 or 8); nothing
+// runs when gate is given and *gate == 0.
 template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
-          const double* x, double* y, int R, hipStream_t s);
+          const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr);
 
 // Batch sweep over the members' tiled layouts (every block size in one
 // kernel); fuse: the second sweep of an application (D^{-1} fused).

@@ -80,13 +80,13 @@ bool fused_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledAr
 
 template <int B, int RT, bool TR>
 void spmv_k(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax, const double* x,
-            double* y, int R, hipStream_t s)
+            double* y, int R, hipStream_t s, const int* gate)
 {
     constexpr int RPC = 64 / B;
     const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
     const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
     hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src, Ax, x,
-                       y, R);
+                       y, R, gate);
 }
 
 }  // namespace
@@ -120,12 +120,12 @@ bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev:
 
 template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
-          const double* x, double* y, int R, hipStream_t s)
+          const double* x, double* y, int R, hipStream_t s, const int* gate)
 {
     switch (rt) {
-    case 1: trans ? spmv_k<B, 1, true>(nb, rp, cj, src, Ax, x, y, R, s) : spmv_k<B, 1, false>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 4: trans ? spmv_k<B, 4, true>(nb, rp, cj, src, Ax, x, y, R, s) : spmv_k<B, 4, false>(nb, rp, cj, src, Ax, x, y, R, s); return true;
-    case 8: trans ? spmv_k<B, 8, true>(nb, rp, cj, src, Ax, x, y, R, s) : spmv_k<B, 8, false>(nb, rp, cj, src, Ax, x, y, R, s); return true;
+    case 1: trans ? spmv_k<B, 1, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 1, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
+    case 4: trans ? spmv_k<B, 4, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 4, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
+    case 8: trans ? spmv_k<B, 8, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 8, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
     }
     return false;
 }
@@ -134,7 +134,7 @@ template bool sweep<BILU_B>(int, int, int, hipStream_t, const dev::SweepArgs&);
 template bool tiled<BILU_B>(int, int, bool, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
 template bool fused<BILU_B>(int, int, int, size_t, hipStream_t, const dev::TiledArgs&, const dev::FusedSpmvArgs&);
 template bool spmv<BILU_B>(int, bool, int, const int32_t*, const int32_t*, const int64_t*, const double*,
-                           const double*, double*, int, hipStream_t);
+                           const double*, double*, int, hipStream_t, const int*);
 
 }  // namespace launch
 }  // namespace bilu

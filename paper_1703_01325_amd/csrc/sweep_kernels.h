@@ -154,6 +154,14 @@ __device__ __forceinline__ T uniform_record(const T* p, int64_t i)
     return u.rec;
 }
 
+// A launch whose gate (a device flag written by an earlier kernel on the
+// stream, or null) reads 0 does nothing: the solvers gate the work of an
+// iteration that was queued after every right-hand side had finished.
+__device__ __forceinline__ bool gated_off(const int* gate)
+{
+    return gate != nullptr && uniform_load(gate, 0) == 0;
+}
+
 __device__ __forceinline__ int grab_ticket(unsigned long long* ticket)
 {
     unsigned long long t = 0;
@@ -215,6 +223,7 @@ struct SweepArgs {
     int persistent;
     unsigned int total_waves;
     unsigned int spin_limit;
+    const int* gate;    // nothing runs when *gate == 0 (may be null)
 };
 
 // One chunk of a level-chunk sweep, by one wavefront.
@@ -302,6 +311,7 @@ __device__ __forceinline__ void sweep_chunk(SweepArgs a, int chunk)
 template <int B, typename T, int RT>
 __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a)
 {
+    if (gated_off(a.gate)) return;
     if (a.persistent) {
         for (int chunk = grab_ticket(a.ticket); chunk < a.nchunks; chunk = grab_ticket(a.ticket))
             sweep_chunk<B, T, RT>(a, chunk);
@@ -369,6 +379,11 @@ struct TiledArgs {
     const int32_t* chunk_wait;
     int group;
     int ngroups;
+    const int* gate;              // nothing runs when *gate == 0 (may be null)
+#ifdef BILU_TRACE
+    long long* trace;             // [nchunks] finish time of each chunk, then [ntiles] start of each tile
+    int trace_nchunks;
+#endif
 };
 
 // Byte offset of component c of a block row (row_byte = row * B * 8) in the
@@ -473,18 +488,19 @@ __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc,
 // kNotReady; every value still missing is re-read with a device-coherent
 // load, all in one round trip per poll.
 template <int K, int B, bool MULTI>
-__device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)[K], const double* out,
-                                           const ColMap<MULTI>& cm, unsigned int limit, int* status)
+__device__ __forceinline__ unsigned int await_tile(double (&v)[K * B], const int (&code)[K], const double* out,
+                                                   const ColMap<MULTI>& cm, unsigned int limit, int* status)
 {
     bool pending = false;
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & is_not_ready(v[k * B + c]);
-    for (unsigned int spins = 0; pending;) {
+    unsigned int spins = 0;
+    while (pending) {
         if (++spins > limit) {
             atomicOr(status, 1);
-            return;
+            return spins;
         }
         __builtin_amdgcn_s_sleep(1);
         pending = false;
@@ -500,6 +516,7 @@ __device__ __forceinline__ void await_tile(double (&v)[K * B], const int (&code)
 #pragma unroll
             for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & is_not_ready(v[k * B + c]);
     }
+    return spins;
 }
 
 // Tile groups: waits (bounded) until each earlier member of the workgroup has
@@ -532,7 +549,11 @@ template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool GROUPED>
 __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
                                              const double* lds_base, double* tile_vals,
                                              const TileData<B, T, KMAX, FUSE>& s, const int (&need)[kGroupMax],
-                                             const int* prog, const ColMap<MULTI>& cm, int wbase)
+                                             const int* prog, const ColMap<MULTI>& cm, int wbase
+#ifdef BILU_TRACE
+                                             , long long* trc
+#endif
+)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
@@ -554,8 +575,15 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
     for (int k = 0; k < KMAX; ++k)
 #pragma unroll
         for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
+#ifdef BILU_TRACE
+    if (trc && lane_id() == 0) trc[1] = wall_clock64();
+    const unsigned int spins_ = await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
+    if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
+    if (trc && lane_id() == 0) { trc[2] = wall_clock64(); trc[3] = spins_; }
+#else
     await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
     if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
+#endif
     if (!active || s.row < 0) return;
     double acc;
     if (FUSE) {
@@ -652,6 +680,9 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
     const int c0 = uniform_load(a.tile_chunk_ptr, t);
     const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
     if (nch <= 0) return;
+#ifdef BILU_TRACE
+    if (a.trace && lane == 0) a.trace[4 * a.trace_nchunks + t] = wall_clock64();
+#endif
     const int clast = c0 + nch - 1;
     auto chunk_at = [&](int i) { return min(c0 + i, clast); };
     auto meta_at = [&](int i, TileMeta<KMAX>& m) {
@@ -691,8 +722,15 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
             tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
             wait_at(i + LD, wr[(p + LD) % NR]);
             tile_compute<B, T, KMAX, FUSE, MULTI, GROUPED>(a, lo, qc, r, lane_ok && i < nch, lds_base, tile_vals,
-                                                           dr[p], wr[p], prog, cm, a.ring > 0 ? wchunk * RPC : -1);
+                                                           dr[p], wr[p], prog, cm, a.ring > 0 ? wchunk * RPC : -1
+#ifdef BILU_TRACE
+                                                           , (a.trace && i < nch) ? a.trace + 4 * (c0 + i) : nullptr
+#endif
+            );
             wchunk = wchunk + 1 == a.ring ? 0 : wchunk + 1;
+#ifdef BILU_TRACE
+            if (a.trace && lane == 0 && i < nch) a.trace[4 * (c0 + i)] = wall_clock64();
+#endif
             // one wavefront: its LDS accesses complete in issue order, so
             // only the compiler must keep this chunk's writes before the
             // next chunk's reads (and before the progress count)
@@ -711,6 +749,7 @@ template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
 __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 {
     extern __shared__ double tile_vals[];                    // [tile rows + 1][B]
+    if (gated_off(a.gate)) return;
     // LDS row tile_rows stays zero: padding slots read it
     if (lane_id() < B) tile_vals[a.tile_rows * B + lane_id()] = 0.0;
     const int nticket = MULTI ? a.ntiles * a.R : a.ntiles;
@@ -736,6 +775,7 @@ __global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
 {
     extern __shared__ double group_vals[];   // [group*tile_rows + 1][B], then kGroupMax progress counts
     __shared__ int s_ticket;
+    if (gated_off(a.gate)) return;
     const int G = a.group;
     // wave-uniform (the compiler cannot see that on its own): the member's
     // tile and chunk indices then stay scalar
@@ -832,6 +872,7 @@ template <int B, typename T, int KMAX>
 __global__ __launch_bounds__(64) void k_sweep_tiled_spmv(TiledArgs a, FusedSpmvArgs m)
 {
     extern __shared__ double tile_vals[];                    // [tile rows + 1][B]
+    if (gated_off(a.gate)) return;
     if (lane_id() < B) tile_vals[a.tile_rows * B + lane_id()] = 0.0;
     for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < m.nsched;
          tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
@@ -909,11 +950,12 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __rest
                                                    const int64_t* __restrict__ srcpos,
                                                    const double* __restrict__ Ax,
                                                    const double* __restrict__ x,
-                                                   double* __restrict__ y, int R)
+                                                   double* __restrict__ y, int R, const int* gate)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
     constexpr int STAGE = TRANS || RT == 1 ? 0 : SpmvStage<B>::doubles;
+    if (gated_off(gate)) return;
     const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t row0 = wave_global * RPC;
     if constexpr (STAGE > 0) {

@@ -160,7 +160,7 @@ def test_solve_parity_small(api, oracle_mod, k):
     x, st, info = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
     xo, ito, rro, sto = c.O.solve(c.s.Ax, c.rhs, rtol=1e-8)
     assert st == 0 and sto == 0
-    (s1, it1, rr1), = info
+    (s1, it1, rr1, _), = info
     assert abs(it1 - ito) <= 1 and rr1 <= 1e-8
     x = x.cpu().numpy()
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-10
@@ -534,3 +534,41 @@ def test_grouped_tiles_fp32_and_solve(api, oracle_mod):
     assert st == 0 and sto == 0 and abs(info[0][1] - ito) <= 1 and info[0][2] <= 1e-8
     assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-10
     M2.check()
+
+
+# ---------------------------------------------------------------------------
+# tiles made of blocks of grid lines
+# ---------------------------------------------------------------------------
+BLOCKS = [("cube10_k0", lambda: synth.small_10cube(), 0, (3, 2)),
+          ("cube10_k0_b7x3", lambda: synth.small_10cube(), 0, (7, 3)),
+          ("cube10_k1_b5x1", lambda: synth.small_10cube(), 1, (5, 1)),
+          ("grid_b4_k0", lambda: synth.reservoir(9, 8, 7, 4, seed=61), 0, (4, 4)),
+          ("grid_b2_k0", lambda: synth.reservoir(11, 5, 6, 2, seed=62), 0, (2, 3))]
+
+
+@pytest.mark.parametrize("name,make,k,blk", BLOCKS, ids=[b[0] for b in BLOCKS])
+def test_line_block_tiles_parity(api, oracle_mod, name, make, k, blk):
+    """Line-block tiles compute every row with the same operations in the
+    same order as row-range tiles: applications (both directions) match the
+    oracle and the row-range result bit for bit, also in FP32."""
+    c = Case(oracle_mod, make(), k)
+    M = c.gpu(api, transpose=True)
+    r = cuda(np.random.default_rng(71).standard_normal(c.s.n))
+    z0, zt0 = M.apply(r), M.apply(r, transpose=True)
+    M.tune(tile_block=blk)
+    info = M.info()
+    assert list(info.tile_block) == [blk[0] + 256 * blk[1]] * 4
+    for _ in range(2):
+        z, zt = M.apply(r), M.apply(r, transpose=True)
+        assert torch.equal(z, z0) and torch.equal(zt, zt0)
+    assert rel(z.cpu().numpy(), c.O.apply(r.cpu().numpy())) <= 1e-12
+    x, st, inf = M.solve(c.Ax, cuda(c.rhs), rtol=1e-8)
+    xo, ito, rro, sto = c.O.solve(c.s.Ax, c.rhs, rtol=1e-8)
+    assert st == 0 and abs(inf[0][1] - ito) <= 1
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-10
+    M.check()
+    M.factor(c.Ax, precision="fp32")
+    F32, D32 = M.factors_f32()
+    z32 = M.apply(r).cpu().numpy()
+    zo32 = oracle_mod.apply(c.s.nb, c.s.bs, c.O.Pp, c.O.Pj, F32.cpu().numpy(), D32.cpu().numpy(), r.cpu().numpy())
+    assert rel(z32, zo32) <= 1e-12

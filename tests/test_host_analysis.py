@@ -191,6 +191,43 @@ def test_lds_ring_layouts_validate(N):
     assert seen >= 8
 
 
+@pytest.mark.parametrize("blk", [(1, 1), (7, 3), (3, 7), (4, 5), (2, 2), (40, 40)])
+def test_line_block_layouts_validate(N, blk):
+    """Tiles made of blocks of grid lines pass the host self-check (ring codes
+    decoded to the row they hold when read, every other tile earlier in the
+    ticket order) for all four sweeps.  ILU(0) grids use them; patterns whose
+    blocks cannot be ordered (ILU(1) with blocks over several planes), or
+    without grid lines (a random pattern), fall back to row-range tiles."""
+    cases = (((8, 6, 10), 0, True), ((13, 7, 9), 0, True), ((9, 11, 4), 1, blk[1] == 1),
+             ((5, 4, 3), 2, blk[1] == 1))
+    for grid, k, expect in cases:
+        Ap, Aj = synth.stencil7_pattern(*grid)
+        nb = int(np.prod(grid))
+        ctx = N.bilu_analyze(nb, 3, Ap, Aj, k, N.WANT_TRANSPOSE)
+        try:
+            N.bilu_tune(ctx, N.TUNE_TILE_BLOCK, blk[0] + 256 * blk[1])
+            N.bilu_validate(ctx)
+            info = N.bilu_get_info(ctx)
+            used = [info.tile_block[w] for w in range(4)]
+            if expect:
+                assert used == [blk[0] + 256 * blk[1]] * 4, (grid, k, used)
+            assert all(u in (0, blk[0] + 256 * blk[1]) for u in used)
+            assert all(info.lds_ring[w] >= 1 for w in range(4) if used[w])
+            N.bilu_tune(ctx, N.TUNE_TILE_BLOCK, 0)
+            N.bilu_validate(ctx)
+            assert list(N.bilu_get_info(ctx).tile_block) == [0, 0, 0, 0]
+        finally:
+            N.bilu_destroy(ctx)
+    Ap, Aj = synth.random_block_pattern(90, 0.05, 3)
+    ctx = N.bilu_analyze(90, 5, Ap, Aj, 1, N.WANT_TRANSPOSE)
+    try:
+        N.bilu_tune(ctx, N.TUNE_TILE_BLOCK, blk[0] + 256 * blk[1])
+        N.bilu_validate(ctx)
+        assert list(N.bilu_get_info(ctx).tile_block) == [0, 0, 0, 0]
+    finally:
+        N.bilu_destroy(ctx)
+
+
 def test_tune_arguments(N):
     """Out-of-range launch knobs are refused; accepted ones keep valid
     layouts (host self-check), and a requested tile size is reported."""
