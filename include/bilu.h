@@ -199,6 +199,24 @@ bilu_status bilu_get_factors_f32(bilu_ctx* ctx, float* F_dev, float* Dinv_dev,
 bilu_status bilu_apply(bilu_ctx* ctx, const double* r, double* z, int nrhs,
                        hipStream_t stream);
 
+/*
+ * bilu_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result bits as bilu_apply, with the
+ * intermediate vector and the sweeps' counters in a fixed 32 MiB scratch
+ * array of the library (one per device, held until the process ends); calls
+ * no hipMalloc, hipFree or allocating routine.  nb*bs*nrhs doubles must fit
+ * in 32 MiB - 256 bytes, else BILU_ERR_ARG.  The layouts must already hold
+ * the current factors (they do after bilu_factor_diag for nrhs = 1, or after
+ * one bilu_apply with the same nrhs), else BILU_ERR_STATE, as when the
+ * current device is not the context's.  Every call on a device shares its
+ * scratch: calls that overlap on one device (other streams, other contexts)
+ * race.  An expired bounded wait is reported as for bilu_apply (bilu_check,
+ * the solvers).
+ */
+bilu_status bilu_apply_noalloc(bilu_ctx* ctx, const double* r, double* z, int nrhs,
+                               hipStream_t stream);
+
 /* z = M^{-T} r = L^{-T} D^{-T} U'^{-T} r (needs BILU_WANT_TRANSPOSE). */
 bilu_status bilu_apply_transpose(bilu_ctx* ctx, const double* r, double* z, int nrhs,
                                  hipStream_t stream);

@@ -1,6 +1,7 @@
 // C ABI of the block ILU(k) library: context, device storage, launches and
 // the Krylov drivers.  See include/bilu.h for the contract of each call.
 #include <hip/hip_runtime.h>
+#include <mutex>
 #include <cstdio>
 
 #include <algorithm>
@@ -42,6 +43,36 @@ namespace {
 constexpr int kFormLevel = 0;   // level-chunk layout (sweep modes 0 and 1)
 constexpr int kFormTiled = 1;   // tiled layout (sweep mode 2)
 constexpr int kMaxTileDoubles = 8192;   // LDS of one tiled wavefront: 64 KiB
+}  // namespace
+
+// Scratch of bilu_apply_noalloc, one copy per device for the life of the
+// process: bytes [0, 8) ticket, [8, 12) done count and [12, 16) status of the
+// persistent sweeps, from byte kScratchHeader the intermediate vector y of
+// the application.  Host code uses the address hipGetSymbolAddress gives for
+// the current device, never the symbol itself.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr size_t kScratchHeader = 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_addr[kScratchDevices] = {};
+
+// Device address of the scratch on `device` (the current device), looked up
+// once per device.
+bilu_status scratch_of_device(int device, unsigned char** out)
+{
+    if (device < 0 || device >= kScratchDevices) return BILU_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BILU_ERR_HIP;
+        g_scratch_addr[device] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_addr[device];
+    return BILU_OK;
+}
 }  // namespace
 
 struct bilu_ctx {
@@ -568,11 +599,22 @@ long long* g_trace_buf[4] = {nullptr, nullptr, nullptr, nullptr};
 size_t g_trace_n[4] = {0, 0, 0, 0};
 #endif
 
+// Ticket, done count and status of a persistent sweep launch.
+struct SweepSync {
+    unsigned long long* ticket;
+    unsigned int* done;
+    int* status;
+};
+
+// sync: counters to use instead of the context's (may be null); timed:
+// recorded in bilu_timing's sweep classes.
 bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, double* reset, int R, hipStream_t s,
-                      const int* gate = nullptr)
+                      const int* gate = nullptr, const SweepSync* sync = nullptr, bool timed = true)
 {
     const int form = sweep_form(c, R);
-    const long tslot = timing_begin(c, BILU_K_SWEEP_L + which, s);
+    const long tslot = timed ? timing_begin(c, BILU_K_SWEEP_L + which, s) : -1;
+    const SweepSync own{c->d_ticket, c->d_done, c->d_status};
+    const SweepSync& sy = sync ? *sync : own;
     const int fuse = fused_sweep(which) ? 1 : 0;
     if (form == kFormTiled) {
         const HostTiled& ht = c->h.tiled[which];
@@ -588,9 +630,9 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.rhs = rhs;
         a.out = out;
         a.reset = reset;
-        a.ticket = c->d_ticket;
-        a.done = c->d_done;
-        a.status = c->d_status;
+        a.ticket = sy.ticket;
+        a.done = sy.done;
+        a.status = sy.status;
         a.ntiles = ht.ntiles;
         a.R = R;
         a.spin_limit = c->spin_limit;
@@ -638,9 +680,9 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         a.rhs = rhs;
         a.out = out;
         a.reset = reset;
-        a.ticket = c->d_ticket;
-        a.done = c->d_done;
-        a.status = c->d_status;
+        a.ticket = sy.ticket;
+        a.done = sy.done;
+        a.status = sy.status;
         a.nchunks = hs.nchunks;
         a.R = R;
         a.fuse = fuse;
@@ -978,6 +1020,41 @@ bilu_status bilu_get_factors_f32(bilu_ctx* c, float* F, float* Dinv, hipStream_t
 bilu_status bilu_apply(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
 {
     return do_apply(c, r, z, nrhs, false, s);
+}
+
+bilu_status bilu_apply_noalloc(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
+{
+    if (!c || !r || !z || nrhs < 1 || nrhs > dev::kMaxRhs || r == z) return BILU_ERR_ARG;
+    const int64_t ny = static_cast<int64_t>(c->h.nb) * c->h.bs * nrhs;
+    if (static_cast<size_t>(ny) * sizeof(double) > kScratchBytes - kScratchHeader) return BILU_ERR_ARG;
+    if (!c->dev_ready || !c->split_done) return BILU_ERR_STATE;
+    // the layouts of this form must already hold the current factors: laying
+    // them out would allocate
+    const int form = sweep_form(c, nrhs);
+    if (!c->form_uploaded[form]) return BILU_ERR_STATE;
+    for (int w : {static_cast<int>(BILU_SWEEP_L), static_cast<int>(BILU_SWEEP_U)})
+        if (!c->h.sweep[w].built || c->ds[form][w].vals_precision != c->precision) return BILU_ERR_STATE;
+    int device = -1;
+    CK(hipGetDevice(&device));
+    if (device != c->device) return BILU_ERR_STATE;
+    unsigned char* base = nullptr;
+    bilu_status st = scratch_of_device(device, &base);
+    if (st) return st;
+    const SweepSync sync{reinterpret_cast<unsigned long long*>(base), reinterpret_cast<unsigned int*>(base + 8),
+                         reinterpret_cast<int*>(base + 12)};
+    double* y = reinterpret_cast<double*>(base + kScratchHeader);
+    // the scratch keeps the last call's contents: counters cleared and y set
+    // to kNotReady by fill kernels on every call
+    hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(4), reinterpret_cast<int32_t*>(base), 0);
+    hipLaunchKernelGGL(dev::k_fill_not_ready, dim3(grid_for(ny)), dim3(256), 0, s, ny, y);
+    CK(hipGetLastError());
+    if ((st = run_sweep(c, BILU_SWEEP_L, r, y, z, nrhs, s, nullptr, &sync, false))) return st;
+    if ((st = run_sweep(c, BILU_SWEEP_U, y, z, y, nrhs, s, nullptr, &sync, false))) return st;
+    // a bounded wait that expired shows in bilu_check and the solvers, as for
+    // bilu_apply
+    hipLaunchKernelGGL(dev::k_merge_status, dim3(1), dim3(64), 0, s, sync.status, c->d_status);
+    CK(hipGetLastError());
+    return BILU_OK;
 }
 
 bilu_status bilu_apply_transpose(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)

@@ -450,6 +450,12 @@ __global__ void k_fill_i32(int64_t n, int32_t* p, int32_t v)
         p[g] = v;
 }
 
+// *dst |= *src (one thread): a sweep status kept elsewhere joins the context's.
+__global__ void k_merge_status(const int* src, int* dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *src) atomicOr(dst, *src);
+}
+
 __global__ void k_fill_not_ready(int64_t n, double* p)
 {
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
