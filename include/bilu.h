@@ -100,6 +100,8 @@ typedef struct {
                              fewer than that many chunks back, single-tile layouts only) */
     int tile_block[4];    /* per tiled sweep: ny + 256*nz when its tiles are blocks of
                              ny x nz grid lines (BILU_TUNE_TILE_BLOCK), else 0       */
+    int line_sweep[2];    /* L, U' sweeps: ny + 256*nz when they run as line sweeps
+                             (BILU_TUNE_LINE_SWEEP), else 0                          */
 } bilu_info;
 
 typedef struct {
@@ -270,6 +272,12 @@ enum {
                                  stay inside a tile; 0 (default): row-range tiles.
                                  Falls back to row-range tiles where the pattern has
                                  no grid lines or the blocks cannot be ordered        */
+    BILU_TUNE_LINE_SWEEP = 8, /* mode 2, one right-hand side, on a 7-point ILU(0)
+                                 pattern in natural grid order: value ny + 256*nz runs
+                                 the L and U' sweeps as line sweeps, one wavefront per
+                                 block of ny x nz grid lines (ny*nz <= 64/bs) computing
+                                 one diagonal of its block per step; 0 (default): off.
+                                 Other patterns keep the tiled sweeps               */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

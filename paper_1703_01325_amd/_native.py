@@ -43,7 +43,8 @@ class BiluInfo(ct.Structure):
                 ("nnzb_A", ct.c_int64), ("nnzb_P", ct.c_int64), ("nnzb_L", ct.c_int64),
                 ("nnzb_U", ct.c_int64), ("nlev", ct.c_int * 4), ("rows_per_chunk", ct.c_int),
                 ("sweep_slots", ct.c_int64 * 4), ("tile_rows", ct.c_int),
-                ("tile_group", ct.c_int), ("lds_ring", ct.c_int * 4), ("tile_block", ct.c_int * 4)]
+                ("tile_group", ct.c_int), ("lds_ring", ct.c_int * 4), ("tile_block", ct.c_int * 4),
+                ("line_sweep", ct.c_int * 2)]
 
 
 class KernelTime(ct.Structure):
@@ -244,6 +245,7 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
 
 TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV, TUNE_TILE_GROUP = 0, 1, 3, 4, 5, 6
 TUNE_TILE_BLOCK = 7
+TUNE_LINE_SWEEP = 8
 
 
 def bilu_tune(ctx, param, value):

@@ -627,6 +627,212 @@ void build_tiled_blocks(const Host& h, int which, int rpc, int ny_b, int nz_b, H
     s.built = true;
 }
 
+namespace {
+// Grid coordinates of the sweep: a forward sweep (L, U'^T) walks rows
+// ascending, a backward one (U', L^T) descending; sweep coordinates mirror
+// the grid for backward sweeps.
+struct LineGeom {
+    int nx = 0, ny = 0, nz = 0;
+    bool forward = true;
+    int32_t row(int xs, int ys, int zs) const
+    {
+        const int x = forward ? xs : nx - 1 - xs, y = forward ? ys : ny - 1 - ys, z = forward ? zs : nz - 1 - zs;
+        return x + nx * (y + ny * z);
+    }
+    void coords(int32_t i, int& xs, int& ys, int& zs) const
+    {
+        int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+        xs = forward ? x : nx - 1 - x;
+        ys = forward ? y : ny - 1 - y;
+        zs = forward ? z : nz - 1 - z;
+    }
+};
+}  // namespace
+
+void build_line_layout(const Host& h, int which, int rpc, int ny_b, int nz_b, HostTiled& s)
+{
+    s = HostTiled{};
+    if (which != BILU_SWEEP_L && which != BILU_SWEEP_U) return;
+    if (ny_b < 1 || nz_b < 1 || ny_b * nz_b > rpc) return;
+    const int nb = h.nb;
+    if (static_cast<int64_t>(nb) * h.bs * 8 > INT32_MAX) return;
+    int nx = 0, nxy = 0;
+    if (!grid_lines(h, nx, nxy)) return;
+    LineGeom g;
+    g.nx = nx;
+    g.ny = nxy / nx;
+    g.nz = nb / nxy;
+    g.forward = which == BILU_SWEEP_L;
+    std::vector<int32_t> dptr;
+    std::vector<Dep> deps;
+    sweep_deps(h, which, dptr, deps);
+    // slot order: the dependencies in ascending column order, as every sweep
+    // forms a row (L: z-1, y-1, x-1; U': x+1, y+1, z+1)
+    const int dims[3] = {g.forward ? 2 : 0, 1, g.forward ? 0 : 2};
+    // eligibility: each row depends on exactly its grid neighbours before it,
+    // listed in that order
+    for (int32_t i = 0; i < nb; ++i) {
+        int xs, ys, zs;
+        g.coords(i, xs, ys, zs);
+        int32_t want[3];
+        int n = 0;
+        for (int k = 0; k < 3; ++k) {
+            const int d = dims[k];
+            const int cx = xs - (d == 0), cy = ys - (d == 1), cz = zs - (d == 2);
+            if (cx >= 0 && cy >= 0 && cz >= 0) want[n++] = g.row(cx, cy, cz);
+        }
+        if (dptr[i + 1] - dptr[i] != n) return;
+        for (int k = 0; k < n; ++k)
+            if (deps[dptr[i] + k].col != want[k]) return;
+    }
+    const int NYb = (g.ny + ny_b - 1) / ny_b, NZb = (g.nz + nz_b - 1) / nz_b;
+    const int nsteps = nx + ny_b + nz_b - 2;
+    s.which = which;
+    s.rpc = rpc;
+    s.kmax = 3;
+    s.lines = true;
+    s.block_ny = ny_b;
+    s.block_nz = nz_b;
+    s.line_nx = nx;
+    s.line_ny = g.ny;
+    s.line_nz = g.nz;
+    s.line_steps = nsteps;
+    s.line_NYb = NYb;
+    for (int k = 0; k < 3; ++k) s.line_dim[k] = dims[k];
+    s.ntiles = NYb * NZb;
+    s.nchunks = s.ntiles * nsteps;
+    s.tile_rows = 1;
+    s.group = 1;
+    s.gstride = 1;
+    s.ngroups = s.ntiles;
+    s.group_tiles.resize(static_cast<size_t>(s.ntiles));
+    std::iota(s.group_tiles.begin(), s.group_tiles.end(), 0);
+    s.tile_chunk_ptr.resize(static_cast<size_t>(s.ntiles) + 1);
+    s.tile_lo.assign(static_cast<size_t>(s.ntiles), 0);
+    for (int t = 0; t <= s.ntiles; ++t) s.tile_chunk_ptr[t] = t * nsteps;
+    s.chunk_off.resize(static_cast<size_t>(s.nchunks) + 1);
+    for (int c = 0; c <= s.nchunks; ++c) s.chunk_off[c] = static_cast<int64_t>(c) * 3 * rpc;
+    s.nslots = s.chunk_off.back();
+    s.rows.assign(static_cast<size_t>(s.nchunks) * rpc, -1);
+    s.deps.assign(static_cast<size_t>(s.nslots), tiled_local_code(0, h.bs));
+    s.src.assign(static_cast<size_t>(s.nslots), -1);
+    for (int t = 0; t < s.ntiles; ++t) {
+        const int Yb = t % NYb, Zb = t / NYb;
+        s.tile_lo[t] = g.row(0, std::min(Yb * ny_b, g.ny - 1), std::min(Zb * nz_b, g.nz - 1));
+        for (int q = 0; q < ny_b * nz_b; ++q) {
+            const int yl = q % ny_b, zl = q / ny_b;
+            const int ys = Yb * ny_b + yl, zs = Zb * nz_b + zl;
+            if (ys >= g.ny || zs >= g.nz) continue;
+            for (int xs = 0; xs < nx; ++xs) {
+                const int step = xs + yl + zl;
+                const int64_t c = static_cast<int64_t>(t) * nsteps + step;
+                const int32_t i = g.row(xs, ys, zs);
+                s.rows[static_cast<size_t>(c) * rpc + q] = i;
+                int n = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const int d = dims[k];
+                    const int cx = xs - (d == 0), cy = ys - (d == 1), cz = zs - (d == 2);
+                    if (cx < 0 || cy < 0 || cz < 0) continue;
+                    const int64_t slot = s.chunk_off[c] + static_cast<int64_t>(k) * rpc + q;
+                    const Dep& dp = deps[dptr[i] + n++];
+                    s.src[static_cast<size_t>(slot)] = dp.src;
+                    s.deps[static_cast<size_t>(slot)] = tiled_global_code(dp.col, h.bs);
+                }
+            }
+        }
+    }
+    s.built = true;
+}
+
+int validate_line_layout(const Host& h, const HostTiled& s)
+{
+    if (!s.lines || !s.built) return BILU_ERR_STATE;
+    const int nb = h.nb, rpc = s.rpc;
+    const int WY = s.block_ny, WZ = s.block_nz;
+    if (WY < 1 || WZ < 1 || WY * WZ > rpc || rpc * h.bs > kWave) return BILU_ERR_STATE;
+    LineGeom g;
+    g.nx = s.line_nx;
+    g.ny = s.line_ny;
+    g.nz = s.line_nz;
+    g.forward = s.which == BILU_SWEEP_L;
+    if (s.which != BILU_SWEEP_L && s.which != BILU_SWEEP_U) return BILU_ERR_STATE;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || static_cast<int64_t>(g.nx) * g.ny * g.nz != nb) return BILU_ERR_STATE;
+    if (static_cast<int64_t>(nb) * h.bs * 8 > INT32_MAX) return BILU_ERR_STATE;
+    const int NYb = (g.ny + WY - 1) / WY, NZb = (g.nz + WZ - 1) / WZ;
+    if (s.line_NYb != NYb || s.ntiles != NYb * NZb || s.line_steps != g.nx + WY + WZ - 2) return BILU_ERR_STATE;
+    if (s.nchunks != s.ntiles * s.line_steps || static_cast<int64_t>(s.rows.size()) != static_cast<int64_t>(s.nchunks) * rpc ||
+        s.nslots != static_cast<int64_t>(s.nchunks) * 3 * rpc || static_cast<int64_t>(s.src.size()) != s.nslots ||
+        static_cast<int>(s.chunk_off.size()) != s.nchunks + 1)
+        return BILU_ERR_STATE;
+    for (int c = 0; c <= s.nchunks; ++c)
+        if (s.chunk_off[c] != static_cast<int64_t>(c) * 3 * rpc) return BILU_ERR_STATE;
+    int dims_seen = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (s.line_dim[k] < 0 || s.line_dim[k] > 2) return BILU_ERR_STATE;
+        dims_seen |= 1 << s.line_dim[k];
+    }
+    if (dims_seen != 7) return BILU_ERR_STATE;
+    std::vector<int32_t> seen(static_cast<size_t>(nb), 0);
+    const int64_t nP = static_cast<int64_t>(h.Pj.size());
+    const bool rowwise = true;   // L and U': the entry of row i, column j
+    std::vector<int32_t> ndep(static_cast<size_t>(nb), 0), used(static_cast<size_t>(nb), 0);
+    for (int32_t i = 0; i < nb; ++i)
+        for (int32_t e = h.Pp[i]; e < h.Pp[i + 1]; ++e) {
+            const int32_t j = h.Pj[e];
+            if (g.forward ? j < i : j > i) ndep[i]++;
+        }
+    for (int t = 0; t < s.ntiles; ++t) {
+        const int Yb = t % NYb, Zb = t / NYb;
+        for (int st = 0; st < s.line_steps; ++st) {
+            const int64_t c = static_cast<int64_t>(t) * s.line_steps + st;
+            for (int q = 0; q < rpc; ++q) {
+                const int32_t i = s.rows[static_cast<size_t>(c) * rpc + q];
+                // the row the kernel computes for this lane, if any
+                const bool lane_line = q < WY * WZ;
+                const int yl = lane_line ? q % WY : 0, zl = lane_line ? q / WY : 0;
+                const int ys = Yb * WY + yl, zs = Zb * WZ + zl, xs = st - yl - zl;
+                const bool act = lane_line && ys < g.ny && zs < g.nz && xs >= 0 && xs < g.nx;
+                if (act != (i >= 0)) return BILU_ERR_STATE;
+                if (!act) {
+                    for (int k = 0; k < 3; ++k)
+                        if (s.src[static_cast<size_t>(s.chunk_off[c] + k * rpc + q)] != -1) return BILU_ERR_STATE;
+                    continue;
+                }
+                if (i != g.row(xs, ys, zs) || seen[i]++) return BILU_ERR_STATE;
+                for (int k = 0; k < 3; ++k) {
+                    const int d = s.line_dim[k];
+                    const int cx = xs - (d == 0), cy = ys - (d == 1), cz = zs - (d == 2);
+                    const int64_t e = s.src[static_cast<size_t>(s.chunk_off[c] + k * rpc + q)];
+                    const bool exists = cx >= 0 && cy >= 0 && cz >= 0;
+                    if (!exists) {
+                        // the kernel reads zero for a neighbour outside the grid
+                        if (e != -1) return BILU_ERR_STATE;
+                        continue;
+                    }
+                    // every grid neighbour before the row is a dependency
+                    if (e < 0 || e >= nP) return BILU_ERR_STATE;
+                    const int32_t j = g.row(cx, cy, cz);
+                    if (!rowwise || h.Prow[e] != i || h.Pj[e] != j) return BILU_ERR_STATE;
+                    used[i]++;
+                    // where the kernel reads it: the same block one step
+                    // earlier, or a block with a smaller ticket
+                    const bool inside = (d == 0) || (d == 1 && yl > 0) || (d == 2 && zl > 0);
+                    if (inside) {
+                        const int qq = d == 0 ? q : (d == 1 ? q - 1 : q - WY);
+                        if (st < 1 || s.rows[static_cast<size_t>(c - 1) * rpc + qq] != j) return BILU_ERR_STATE;
+                    } else {
+                        const int tb = (cz / WZ) * NYb + cy / WY;
+                        if (tb >= t) return BILU_ERR_STATE;
+                    }
+                }
+            }
+        }
+    }
+    for (int32_t i = 0; i < nb; ++i)
+        if (seen[i] != 1 || used[i] != ndep[i]) return BILU_ERR_STATE;
+    return BILU_OK;
+}
+
 // Event simulation of the tiled schedule: tiles run concurrently, a tile
 // walks its chunks in order, a chunk costs one step and may start once the
 // previous chunk of its tile is done and every row it reads from another
@@ -1006,6 +1212,8 @@ bool tiled_accesses_in_bounds(const Host& h, const HostTiled& s, int which)
 
 int validate_layout(const Host& h)
 {
+    for (int w = 0; w < 4; ++w)
+        if (h.lines[w].built && validate_line_layout(h, h.lines[w]) != BILU_OK) return BILU_ERR_STATE;
     const int nb = h.nb;
     const int64_t nP = static_cast<int64_t>(h.Pj.size());
     for (int w = 0; w < 4; ++w) {

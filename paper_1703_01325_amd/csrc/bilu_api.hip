@@ -42,6 +42,8 @@ using dev::TiledArgs;
 namespace {
 constexpr int kFormLevel = 0;   // level-chunk layout (sweep modes 0 and 1)
 constexpr int kFormTiled = 1;   // tiled layout (sweep mode 2)
+constexpr int kFormLines = 2;   // line-sweep layout of L and U' (BILU_TUNE_LINE_SWEEP)
+constexpr int kForms = 3;
 constexpr int kMaxTileDoubles = 8192;   // LDS of one tiled wavefront: 64 KiB
 }  // namespace
 
@@ -110,8 +112,9 @@ struct bilu_ctx {
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
     int64_t* d_ATsrc = nullptr;
     double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
-    DevSweep ds[2][4];          // [form][sweep]
-    bool form_uploaded[2] = {false, false};
+    DevSweep ds[kForms][4];     // [form][sweep]
+    bool form_uploaded[kForms] = {false, false, false};
+    int line_block = 0;         // line sweep of L and U' with blocks ny + 256*nz (0: off)
     bool layouts_checked = false;   // validate_layout passed on the layouts as built
 
     double* d_y = nullptr;      // intermediate of an application, kept at kNotReady
@@ -244,6 +247,11 @@ bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks,
                   const TiledArgs& a)
 {
     BILU_SWITCH_B(bs, if (!launch::tiled<B>(kmax, prec, fuse, multi, blocks, lds, s, a)) return false)
+}
+
+bool launch_lines(int bs, int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& a)
+{
+    BILU_SWITCH_B(bs, if (!launch::lines<B>(prec, fuse, blocks, s, a)) return false)
 }
 
 bool launch_fused(int bs, int kmax, int prec, int blocks, size_t lds, hipStream_t s, const TiledArgs& a,
@@ -411,6 +419,10 @@ bilu_status upload_form(bilu_ctx* c, int form)
             if ((st = upload(c, &d.chunk_off, hs.chunk_off)) || (st = upload(c, &d.rows, hs.rows)) ||
                 (st = upload(c, &d.cols, hs.cols)) || (st = upload(c, &d.src, hs.src)))
                 return st;
+        } else if (form == kFormLines) {
+            const HostTiled& hl = h.lines[w];
+            if (!hl.built) continue;
+            if ((st = upload(c, &d.rows, hl.rows)) || (st = upload(c, &d.src, hl.src))) return st;
         } else {
             if (!h.sweep[w].built) continue;
             if (c->tile_rows <= 0 || c->layout_lds != c->lds_max) choose_layout(c);
@@ -508,6 +520,12 @@ bilu_status ensure_device(bilu_ctx* c)
 // Layout form the sweeps use: row tiles in mode 2 (their vector accesses are
 // 31-bit byte offsets, so the (n x R) vectors must stay below 2 GiB), level
 // chunks otherwise.
+// Sweep `which` of R columns runs as a line sweep.
+bool use_lines(const bilu_ctx* c, int which, int R)
+{
+    return c->line_block > 0 && R == 1 && c->sweep_mode == 2 && c->h.lines[which].built;
+}
+
 int sweep_form(const bilu_ctx* c, int R)
 {
     const bool fits = static_cast<int64_t>(c->h.nb) * c->h.bs * 8 * R <= static_cast<int64_t>(INT32_MAX);
@@ -526,8 +544,11 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         if (!h.sweep[w].built) continue;
         DevSweep& d = c->ds[form][w];
         if (d.vals_precision == c->precision) continue;
-        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots : h.tiled[w].nslots;
-        const int nchunks = form == kFormLevel ? h.sweep[w].nchunks : h.tiled[w].nchunks;
+        if (form == kFormLines && !h.lines[w].built) continue;
+        const int64_t nslots = form == kFormLevel ? h.sweep[w].nslots
+                               : form == kFormTiled ? h.tiled[w].nslots : h.lines[w].nslots;
+        const int nchunks = form == kFormLevel ? h.sweep[w].nchunks
+                            : form == kFormTiled ? h.tiled[w].nchunks : h.lines[w].nchunks;
         const int rpc = h.rpc;
         // a new factorisation of the same layout reuses the arrays (no
         // allocation on the factorisation path); another size or precision
@@ -615,6 +636,55 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
     const long tslot = timed ? timing_begin(c, BILU_K_SWEEP_L + which, s) : -1;
     const SweepSync own{c->d_ticket, c->d_done, c->d_status};
     const SweepSync& sy = sync ? *sync : own;
+    if (use_lines(c, which, R)) {
+        const HostTiled& hl = c->h.lines[which];
+        // the kernel's slot order: L z~, y~, x~ (forward); U' x~, y~, z~
+        if (hl.line_dim[0] != (which == BILU_SWEEP_L ? 2 : 0) || hl.line_dim[1] != 1 ||
+            hl.line_dim[2] != (which == BILU_SWEEP_L ? 0 : 2) || fused_sweep(which) != (which == BILU_SWEEP_U))
+            return BILU_ERR_STATE;
+        const DevSweep& d = c->ds[kFormLines][which];
+        dev::LineArgs a{};
+        a.vals = d.vals;
+        a.dinv = d.dinv;
+        a.rhs = rhs;
+        a.out = out;
+        a.reset = reset;
+        a.ticket = sy.ticket;
+        a.done = sy.done;
+        a.status = sy.status;
+        a.gate = gate;
+        a.nx = hl.line_nx;
+        a.ny = hl.line_ny;
+        a.nz = hl.line_nz;
+        a.WY = hl.block_ny;
+        a.WZ = hl.block_nz;
+        a.NYb = hl.line_NYb;
+        a.nblocks = hl.ntiles;
+        a.nsteps = hl.line_steps;
+        a.forward = which == BILU_SWEEP_L ? 1 : 0;
+        a.spin_limit = c->spin_limit;
+        const int blocks = persistent_blocks(c, hl.ntiles, 1, 8);
+        a.total_waves = static_cast<unsigned int>(blocks);
+#ifdef BILU_TRACE
+        {
+            static long long* lbuf[4] = {nullptr, nullptr, nullptr, nullptr};
+            static size_t lcap[4] = {0, 0, 0, 0};
+            const size_t need = 4 * static_cast<size_t>(hl.nchunks) + hl.ntiles;
+            if (lcap[which] < need) {
+                if (lbuf[which]) (void)hipFree(lbuf[which]);
+                if (hipMalloc(&lbuf[which], need * sizeof(long long)) != hipSuccess) return BILU_ERR_ALLOC;
+                lcap[which] = need;
+            }
+            a.trace = lbuf[which];
+            g_trace_buf[which] = lbuf[which];
+            g_trace_n[which] = need;
+        }
+#endif
+        if (!launch_lines(c->h.bs, c->precision, fused_sweep(which), blocks, s, a)) return BILU_ERR_ARG;
+        timing_end(c, tslot, s);
+        CK(hipGetLastError());
+        return BILU_OK;
+    }
     const int fuse = fused_sweep(which) ? 1 : 0;
     if (form == kFormTiled) {
         const HostTiled& ht = c->h.tiled[which];
@@ -722,6 +792,7 @@ bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transp
     bilu_status st;
     const int form = sweep_form(c, R);
     if ((st = layout_form(c, form, s))) return st;
+    if ((use_lines(c, first, R) || use_lines(c, second, R)) && (st = layout_form(c, kFormLines, s))) return st;
     if ((st = ensure_y(c, R, s))) return st;
     if ((st = run_sweep(c, first, r, c->d_y, z, R, s, gate))) return st;
     return run_sweep(c, second, c->d_y, z, c->d_y, R, s, gate);
@@ -837,7 +908,7 @@ int64_t bilu_trace_get(bilu_ctx* c, int which, long long* host, int64_t cap, int
     (void)hipDeviceSynchronize();
     const int64_t n = std::min<int64_t>(cap, g_trace_n[which]);
     (void)hipMemcpy(host, g_trace_buf[which], n * sizeof(long long), hipMemcpyDeviceToHost);
-    const HostTiled& ht = c->h.tiled[which];
+    const HostTiled& ht = use_lines(c, which, 1) ? c->h.lines[which] : c->h.tiled[which];
     for (int64_t i = 0; i < std::min<int64_t>(cap2, ht.tile_chunk_ptr.size()); ++i) tile_ptr[i] = ht.tile_chunk_ptr[i];
     for (int64_t i = 0; i < std::min<int64_t>(cap2, ht.group_tiles.size()); ++i) group_tiles[i] = ht.group_tiles[i];
     return n;
@@ -912,6 +983,8 @@ bilu_status bilu_get_info(const bilu_ctx* c, bilu_info* info)
         info->lds_ring[w] = h.tiled[w].built ? h.tiled[w].ring : 0;
         info->tile_block[w] = h.tiled[w].built && h.tiled[w].block_ny ? h.tiled[w].block_ny + 256 * h.tiled[w].block_nz : 0;
     }
+    for (int w = 0; w < 2; ++w)
+        info->line_sweep[w] = use_lines(c, w, 1) ? h.lines[w].block_ny + 256 * h.lines[w].block_nz : 0;
     return BILU_OK;
 }
 
@@ -962,10 +1035,13 @@ bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
     const long tslot = timing_begin(c, BILU_K_SPLIT, s);
     c->f_ready = false;                       // F is formed when a caller asks for it
     c->precision = precision;
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < kForms; ++f)
         for (int w = 0; w < 4; ++w) c->ds[f][w].vals_precision = -1;
     bilu_status st = layout_form(c, sweep_form(c, 1), s);
     if (st) return st;
+    if (use_lines(c, BILU_SWEEP_L, 1) || use_lines(c, BILU_SWEEP_U, 1)) {
+        if ((st = layout_form(c, kFormLines, s))) return st;
+    }
     timing_end(c, tslot, s);
     CK(hipGetLastError());
     c->split_done = true;
@@ -1031,9 +1107,11 @@ bilu_status bilu_apply_noalloc(bilu_ctx* c, const double* r, double* z, int nrhs
     // the layouts of this form must already hold the current factors: laying
     // them out would allocate
     const int form = sweep_form(c, nrhs);
-    if (!c->form_uploaded[form]) return BILU_ERR_STATE;
-    for (int w : {static_cast<int>(BILU_SWEEP_L), static_cast<int>(BILU_SWEEP_U)})
-        if (!c->h.sweep[w].built || c->ds[form][w].vals_precision != c->precision) return BILU_ERR_STATE;
+    for (int w : {static_cast<int>(BILU_SWEEP_L), static_cast<int>(BILU_SWEEP_U)}) {
+        const int f = use_lines(c, w, nrhs) ? kFormLines : form;
+        if (!c->form_uploaded[f] || !c->h.sweep[w].built || c->ds[f][w].vals_precision != c->precision)
+            return BILU_ERR_STATE;
+    }
     int device = -1;
     CK(hipGetDevice(&device));
     if (device != c->device) return BILU_ERR_STATE;
@@ -1107,6 +1185,19 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (value != 0 && value != 1) return BILU_ERR_ARG;
         c->fuse_spmv = value != 0;
         return BILU_OK;
+    case BILU_TUNE_LINE_SWEEP: {
+        const int ny = value & 255, nz = value >> 8;
+        if (value < 0 || (value != 0 && (ny < 1 || nz < 1 || nz > 255))) return BILU_ERR_ARG;
+        if (value == c->line_block) return BILU_OK;
+        c->line_block = value;
+        free_form(c, kFormLines);
+        c->layouts_checked = false;
+        for (int w : {static_cast<int>(BILU_SWEEP_L), static_cast<int>(BILU_SWEEP_U)}) {
+            if (value > 0 && c->h.sweep[w].built) build_line_layout(c->h, w, c->h.rpc, ny, nz, c->h.lines[w]);
+            else c->h.lines[w] = HostTiled{};
+        }
+        return BILU_OK;
+    }
     case BILU_TUNE_TILE_BLOCK: {
         const int ny = value & 255, nz = value >> 8;
         if (value < 0 || (value != 0 && (ny < 1 || nz < 1 || nz > 255))) return BILU_ERR_ARG;

@@ -72,6 +72,13 @@ struct HostTiled {
     // range; tile-local rows are always addressed through the LDS ring, and
     // tile_lo holds the tile's first row only
     int block_ny = 0, block_nz = 0;
+    // line sweep (lines = true): tiles are blocks of block_ny x block_nz grid
+    // lines swept one diagonal per step by k_sweep_lines; chunk
+    // b*line_steps + s holds step s of block b, row slot q = line, slot k =
+    // the neighbour along dimension line_dim[k] of the sweep coordinates
+    bool lines = false;
+    int line_nx = 0, line_ny = 0, line_nz = 0, line_steps = 0, line_NYb = 0;
+    int line_dim[3] = {0, 0, 0};
     int group = 1;
     int group_req = 1;                     // the group size asked of build_tiled
     int gstride = 1;
@@ -164,6 +171,7 @@ struct Host {
     std::vector<int64_t> ATsrc;
     HostSweep sweep[4];
     HostTiled tiled[4];
+    HostTiled lines[4];     // line-sweep layouts (L and U' only; see build_line_layout)
 };
 
 // Host analysis entry points (analysis.cpp).
@@ -213,6 +221,16 @@ bool grid_lines(const Host& h, int& nx, int& nxy);
 // pattern has no grid lines, a dependency crosses to a later block, or the
 // in-tile dependencies span more chunks than the ring can hold.
 void build_tiled_blocks(const Host& h, int which, int rpc, int ny_b, int nz_b, HostTiled& out);
+// Line-sweep layout of sweep `which` (L or U') with blocks of ny_b x nz_b
+// grid lines (ny_b*nz_b <= rpc): built only where the pattern is a 7-point
+// ILU(0) pattern in natural grid order (every row depends on exactly the
+// grid neighbours before it in the sweep); out.built stays false otherwise.
+void build_line_layout(const Host& h, int which, int rpc, int ny_b, int nz_b, HostTiled& out);
+// Host self-check of a line-sweep layout: every row once, at the chunk and
+// slot the kernel computes, each slot's factor entry the neighbour the
+// kernel reads, every neighbour either one step earlier in the block or in
+// an earlier block.
+int validate_line_layout(const Host& h, const HostTiled& s);
 // Ticket order of the backward U' tiled sweep fused with the SpMV on its
 // output: all tiles, then each block of rpc rows of A, ordered by the tile
 // that finishes the lowest row the block reads.  Checked before it is

@@ -31,6 +31,10 @@ template <int B>
 bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a,
            const dev::FusedSpmvArgs& m);
 
+// Line sweep (k_sweep_lines) of L (fuse = false) or U' (fuse = true).
+template <int B>
+bool lines(int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& a);
+
 // y = A x (trans = false) or A^T x, rt columns per pass (1, 4 or 8); nothing
 // runs when gate is given and *gate == 0.
 template <int B>

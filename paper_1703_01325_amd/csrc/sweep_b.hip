@@ -119,6 +119,20 @@ bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev:
 }
 
 template <int B>
+bool lines(int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& a)
+{
+    const dim3 g(blocks), t(64);
+    if (prec == BILU_FACTORS_FP32) {
+        if (fuse) hipLaunchKernelGGL((dev::k_sweep_lines<B, float, true>), g, t, 0, s, a);
+        else hipLaunchKernelGGL((dev::k_sweep_lines<B, float, false>), g, t, 0, s, a);
+    } else {
+        if (fuse) hipLaunchKernelGGL((dev::k_sweep_lines<B, double, true>), g, t, 0, s, a);
+        else hipLaunchKernelGGL((dev::k_sweep_lines<B, double, false>), g, t, 0, s, a);
+    }
+    return true;
+}
+
+template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
           const double* x, double* y, int R, hipStream_t s, const int* gate)
 {
@@ -133,6 +147,7 @@ bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, cons
 template bool sweep<BILU_B>(int, int, int, hipStream_t, const dev::SweepArgs&);
 template bool tiled<BILU_B>(int, int, bool, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
 template bool fused<BILU_B>(int, int, int, size_t, hipStream_t, const dev::TiledArgs&, const dev::FusedSpmvArgs&);
+template bool lines<BILU_B>(int, bool, int, hipStream_t, const dev::LineArgs&);
 template bool spmv<BILU_B>(int, bool, int, const int32_t*, const int32_t*, const int64_t*, const double*,
                            const double*, double*, int, hipStream_t, const int*);
 

@@ -809,6 +809,233 @@ __global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Line sweep: the sweep of a pattern in natural grid order (block rows in
+// lines of nx along x, ny lines per plane, nz planes) whose rows depend only
+// on their x-, y- and z-neighbour before them in the sweep (ILU(0) on a
+// 7-point stencil).  In sweep coordinates (x~, y~, z~: the grid coordinates
+// for a forward sweep, mirrored for a backward one) a row depends on
+// (x~-1), (y~-1) and (z~-1).  A wavefront owns a block of WY x WZ lines
+// (lane (q, r): component r of line q = yl + WY*zl) and at step s computes
+// the row x~ = s - yl - zl of every line: the rows of one step are
+// independent, the x~- and in-block y~/z~-neighbours were computed by the
+// wavefront one step earlier and are exchanged through a small LDS area,
+// and neighbours in the blocks before (y~ or z~ side) are read from the
+// output vector, prefetched and polled with the data-carried readiness of
+// the tiled sweeps.  Factor values arrive in the chunk format of the tiled
+// layouts (chunk = block*nsteps + step, row slot q = line, slot k = the
+// neighbour in the k-th dimension of the ascending column order: z~, y~, x~
+// for L, x~, y~, z~ for U' with D^{-1} fused); row indices are computed, not
+// loaded.  Every row is formed with the same operations in the same order as
+// by the other sweeps.
+// ---------------------------------------------------------------------------
+struct LineArgs {
+    const void* vals;
+    const void* dinv;
+    const double* rhs;
+    double* out;
+    double* reset;
+    unsigned long long* ticket;
+    unsigned int* done;
+    int* status;
+    const int* gate;
+    int nx, ny, nz;
+    int WY, WZ;               // lines per block along y~ and z~
+    int NYb, nblocks;         // blocks along y~, blocks in all (ticket t: block t)
+    int nsteps;               // nx + WY + WZ - 2
+    int forward;
+    unsigned int total_waves;
+    unsigned int spin_limit;
+#ifdef BILU_TRACE
+    long long* trace;         // [nblocks*nsteps][4]: finish, wait begin, wait end, polls
+#endif
+};
+
+template <int B, typename T, bool FUSE>
+struct LineStage {
+    T f[3][B];               // factor row r of the three neighbour blocks, as stored
+    double h[FUSE ? B : 1];  // right-hand side (the whole row when D^{-1} is fused)
+    T d[FUSE ? B : 1];       // row r of D^{-1}
+    double ext[2][B];        // neighbour rows in earlier blocks (y~ side, z~ side)
+};
+
+template <int B, typename T, bool FUSE>
+__device__ __forceinline__ void line_stage_load(const LineArgs& a, int chunk, int lane_off, int64_t rowc_b,
+                                                int64_t ext_y_b, int64_t ext_z_b, LineStage<B, T, FUSE>& g)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    const T* vp = static_cast<const T*>(a.vals) + static_cast<int64_t>(chunk) * 3 * RPC * BB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < B; ++c) g.f[k][c] = vp[k * RPC * BB + c * B * RPC + lane_off];
+    const char* rb = reinterpret_cast<const char*>(a.rhs);
+    if (FUSE) {
+        const T* dp = static_cast<const T*>(a.dinv) + static_cast<int64_t>(chunk) * RPC * BB;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            g.h[c] = *reinterpret_cast<const double*>(rb + rowc_b + 8 * c);
+            g.d[c] = dp[c * B * RPC + lane_off];
+        }
+    } else {
+        g.h[0] = *reinterpret_cast<const double*>(rb + rowc_b + 8 * (lane_off / RPC));
+    }
+    const char* ob = reinterpret_cast<const char*>(a.out);
+    // device-coherent: a cached copy of a line read before its neighbours
+    // were published would show kNotReady for them
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+        g.ext[0][c] = coherent_load(reinterpret_cast<const double*>(ob + ext_y_b + 8 * c));
+        g.ext[1][c] = coherent_load(reinterpret_cast<const double*>(ob + ext_z_b + 8 * c));
+    }
+}
+
+template <int B, typename T, bool FUSE>
+__global__ __launch_bounds__(64) void k_sweep_lines(LineArgs a)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int NR = 3;                   // stages in flight
+    __shared__ double xch[2][64];           // outputs of the last step, by lane
+    if (gated_off(a.gate)) return;
+    const int lane = lane_id();
+    const int q = lane / B;
+    const int r = lane - q * B;
+    const int nlines = a.WY * a.WZ;
+    const bool lane_ok = q < nlines && q < RPC;
+    const int qc = lane_ok ? q : 0;
+    const int yl = qc % a.WY;
+    const int zl = qc / a.WY;
+    const int lane_off = r * RPC + qc;
+    const int nxy = a.nx * a.ny;
+    const int sgn = a.forward ? 1 : -1;
+    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < a.nblocks;
+         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int Yb = tk % a.NYb, Zb = tk / a.NYb;
+        const int ys = Yb * a.WY + yl, zs = Zb * a.WZ + zl;    // sweep coordinates
+        const bool line_ok = lane_ok && ys < a.ny && zs < a.nz;
+        const int y = a.forward ? ys : a.ny - 1 - ys;
+        const int z = a.forward ? zs : a.nz - 1 - zs;
+        const int64_t line_row0 = a.forward ? static_cast<int64_t>(a.nx) * (y + static_cast<int64_t>(a.ny) * z)
+                                            : static_cast<int64_t>(a.nx) * (y + static_cast<int64_t>(a.ny) * z) + a.nx - 1;
+        // neighbours outside the block read from the output vector
+        const bool ext_y = line_ok && yl == 0 && ys > 0;
+        const bool ext_z = line_ok && zl == 0 && zs > 0;
+        const int c0 = static_cast<int>(tk) * a.nsteps;
+#ifdef BILU_TRACE
+        if (a.trace && lane == 0) a.trace[4 * static_cast<int64_t>(a.nblocks) * a.nsteps + tk] = wall_clock64();
+#endif
+        auto row_at = [&](int s) -> int64_t {   // row of this line at step s (any x~, clamped)
+            int xs = s - yl - zl;
+            xs = xs < 0 ? 0 : (xs >= a.nx ? a.nx - 1 : xs);
+            return line_row0 + sgn * static_cast<int64_t>(xs);
+        };
+        auto stage = [&](int s, LineStage<B, T, FUSE>& g) {
+            const int sc = s < a.nsteps ? s : a.nsteps - 1;
+            const int64_t row = line_ok ? row_at(sc) : 0;
+            const int64_t rowc_b = row * (B * 8);
+            const int64_t ey = ext_y ? (row - sgn * static_cast<int64_t>(a.nx)) * (B * 8) : 0;
+            const int64_t ez = ext_z ? (row - sgn * static_cast<int64_t>(nxy)) * (B * 8) : 0;
+            line_stage_load<B, T, FUSE>(a, c0 + sc, lane_off, rowc_b, ey, ez, g);
+        };
+        LineStage<B, T, FUSE> ring[NR];
+#pragma unroll
+        for (int i = 0; i < NR - 1; ++i) stage(i, ring[i]);
+        double cur = 0.0;                   // this lane's output of the previous step
+        xch[1][lane] = 0.0;
+        for (int s0 = 0; s0 < a.nsteps; s0 += NR) {
+#pragma unroll
+            for (int p = 0; p < NR; ++p) {
+                const int s = s0 + p;
+                LineStage<B, T, FUSE>& g = ring[p];
+                // every lane takes delivery of the stage (see tile_compute)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int c = 0; c < B; ++c) asm volatile("" ::"v"(g.f[k][c]));
+                const int xs = s - yl - zl;
+                const bool act = line_ok && s < a.nsteps && xs >= 0 && xs < a.nx;
+                // neighbours in earlier blocks: polled until published
+                double ev[2 * B];
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    ev[c] = g.ext[0][c];
+                    ev[B + c] = g.ext[1][c];
+                }
+                {
+                    const int64_t row = line_ok ? row_at(s < a.nsteps ? s : a.nsteps - 1) : 0;
+                    const int code_y = act && ext_y ? static_cast<int>((row - sgn * static_cast<int64_t>(a.nx)) * (B * 8)) : -1;
+                    const int code_z = act && ext_z ? static_cast<int>((row - sgn * static_cast<int64_t>(nxy)) * (B * 8)) : -1;
+                    const int codes[2] = {code_y, code_z};
+                    ColMap<false> cm;
+                    cm.R = 1;
+                    cm.j8 = 0;
+#ifdef BILU_TRACE
+                    long long* trc = (a.trace && s < a.nsteps) ? a.trace + 4 * (static_cast<int64_t>(c0) + s) : nullptr;
+                    if (trc && lane == 0) trc[1] = wall_clock64();
+                    const unsigned int sp_ = await_tile<2, B, false>(ev, codes, a.out, cm, a.spin_limit, a.status);
+                    if (trc && lane == 0) { trc[2] = wall_clock64(); trc[3] = sp_; }
+#else
+                    await_tile<2, B, false>(ev, codes, a.out, cm, a.spin_limit, a.status);
+#endif
+                }
+                // values of the last step: this line (x~), the line before
+                // along y~ and along z~ inside the block
+                const double* xb = xch[(s + 1) & 1];
+                double nv[3][B];
+                const int qy = qc - 1, qz = qc - a.WY;
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    nv[0][c] = xb[qc * B + c];
+                    nv[1][c] = xb[(qy >= 0 ? qy : 0) * B + c];
+                    nv[2][c] = xb[(qz >= 0 ? qz : 0) * B + c];
+                }
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    if (yl == 0) nv[1][c] = ext_y ? ev[c] : 0.0;
+                    if (zl == 0) nv[2][c] = ext_z ? ev[B + c] : 0.0;
+                    if (xs <= 0) nv[0][c] = 0.0;
+                }
+                double acc;
+                if (FUSE) {
+                    acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < B; ++c) acc += widen(g.d[c]) * g.h[c];
+                } else {
+                    acc = g.h[0];
+                }
+                // slots in ascending column order: L (forward) z~, y~, x~;
+                // U' (backward, D^{-1} fused) x~, y~, z~
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    constexpr int kDimL[3] = {2, 1, 0}, kDimU[3] = {0, 1, 2};
+                    const int d = FUSE ? kDimU[k] : kDimL[k];
+#pragma unroll
+                    for (int c = 0; c < B; ++c) acc -= widen(g.f[k][c]) * nv[d][c];
+                }
+                const double v = publishable(acc);
+                cur = act ? v : 0.0;
+                if (act) {
+                    const int64_t o = row_at(s) * B + r;
+                    if (a.reset) a.reset[o] = not_ready();
+                    coherent_store(a.out + o, v);
+                }
+                xch[s & 1][lane] = cur;
+                // one wavefront: its LDS accesses complete in issue order
+                __builtin_amdgcn_wave_barrier();
+                asm volatile("" ::: "memory");
+#ifdef BILU_TRACE
+                if (a.trace && s < a.nsteps && lane == 0) a.trace[4 * (static_cast<int64_t>(c0) + s)] = wall_clock64();
+#endif
+                // the next stage is requested only now, so a poll above
+                // never waits behind it (vector loads complete in order)
+                stage(s + NR - 1, ring[(p + NR - 1) % NR]);
+            }
+        }
+    }
+    finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
+// ---------------------------------------------------------------------------
 // U' sweep fused with y = A x on its output x: one persistent launch whose
 // tickets are the sweep's tiles and then the blocks of 64/B rows of A,
 // ordered by the tile that finishes the lowest row each reads (host-built

@@ -282,3 +282,35 @@ def test_batch_create_host(N):
     with pytest.raises(N.BiluError) as ei:
         N.bilu_batch_create([(0, 3, np.zeros(1, np.int32), np.zeros(0, np.int32))], 0)
     assert ei.value.code == N.ERR_ARG
+
+
+@pytest.mark.parametrize("blk", [(1, 1), (7, 3), (3, 7), (4, 5), (21, 1), (2, 2)])
+def test_line_sweep_layouts_validate(N, blk):
+    """Line-sweep layouts pass their host self-check (every row once at the
+    chunk and lane the kernel computes it, each factor slot the neighbour the
+    kernel reads, neighbours one step earlier in the block or in an earlier
+    block) on 7-point ILU(0) grids, ragged ones included; other patterns keep
+    the tiled sweeps."""
+    v = blk[0] + 256 * blk[1]
+    for grid, bs, k, expect in (((8, 6, 10), 3, 0, True), ((13, 7, 9), 3, 0, True), ((5, 11, 4), 2, 0, True),
+                                ((9, 11, 4), 3, 1, False), ((6, 5, 4), 8, 0, blk[0] * blk[1] <= 8)):
+        Ap, Aj = synth.stencil7_pattern(*grid)
+        nb = int(np.prod(grid))
+        ctx = N.bilu_analyze(nb, bs, Ap, Aj, k, N.WANT_TRANSPOSE)
+        try:
+            N.bilu_tune(ctx, N.TUNE_LINE_SWEEP, v)
+            N.bilu_validate(ctx)
+            used = list(N.bilu_get_info(ctx).line_sweep)
+            assert used == ([v, v] if expect else [0, 0]), (grid, bs, k, used)
+            N.bilu_tune(ctx, N.TUNE_LINE_SWEEP, 0)
+            assert list(N.bilu_get_info(ctx).line_sweep) == [0, 0]
+        finally:
+            N.bilu_destroy(ctx)
+    Ap, Aj = synth.random_block_pattern(90, 0.05, 3)
+    ctx = N.bilu_analyze(90, 3, Ap, Aj, 0, 0)
+    try:
+        N.bilu_tune(ctx, N.TUNE_LINE_SWEEP, v)
+        N.bilu_validate(ctx)
+        assert list(N.bilu_get_info(ctx).line_sweep) == [0, 0]
+    finally:
+        N.bilu_destroy(ctx)
