@@ -258,7 +258,8 @@ enum {
     BILU_TUNE_BLOCKS = 3,     /* persistent grid in workgroups, 0 = automatic        */
     BILU_TUNE_RHS_TILE = 4,   /* right-hand-side columns per pass of the level-chunk
                                  sweeps and the SpMV when nrhs > 1: 1, 4 or 8;
-                                 0 = 8 (default)                                     */
+                                 0 (default): 8 for the sweeps, and one SpMV pass
+                                 with lanes over all columns                         */
     BILU_TUNE_FUSE_SPMV = 5,  /* 1: inside bilu_solve, each U' sweep of an application
                                  followed by an SpMV of its output runs with that
                                  SpMV in one launch (row tiles, one right-hand side,
@@ -278,6 +279,11 @@ enum {
                                  block of ny x nz grid lines (ny*nz <= 64/bs) computing
                                  one diagonal of its block per step; 0 (default): off.
                                  Other patterns keep the tiled sweeps               */
+    BILU_TUNE_HELPER = 9,     /* mode 2, one right-hand side: 1 runs every tile (or
+                                 tile group member) with a helper wavefront in its
+                                 workgroup that reads the values of other tiles and
+                                 hands them over through LDS, so the tile's own
+                                 loads are prefetches only; 0 (default): off         */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

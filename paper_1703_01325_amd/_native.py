@@ -246,6 +246,7 @@ def bilu_grad_A(ctx, lam_ptr, x_ptr, dA_ptr, stream):
 TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV, TUNE_TILE_GROUP = 0, 1, 3, 4, 5, 6
 TUNE_TILE_BLOCK = 7
 TUNE_LINE_SWEEP = 8
+TUNE_HELPER = 9
 
 
 def bilu_tune(ctx, param, value):

@@ -54,7 +54,7 @@ class BlockILU:
         N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
 
     def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None,
-             tile_block=None, line_sweep=None):
+             tile_block=None, line_sweep=None, helper=None):
         """Launch knobs of the sweeps (results are bit-identical for all)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
                          (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
@@ -62,6 +62,7 @@ class BlockILU:
                           (0 if not tile_block else tile_block[0] + 256 * tile_block[1])),
                          (N.TUNE_LINE_SWEEP, None if line_sweep is None else
                           (0 if not line_sweep else line_sweep[0] + 256 * line_sweep[1])),
+                         (N.TUNE_HELPER, None if helper is None else int(bool(helper))),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

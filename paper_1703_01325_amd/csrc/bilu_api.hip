@@ -97,6 +97,7 @@ struct bilu_ctx {
     int blocks_override = 0;
     int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
     bool fuse_spmv = false;     // solvers run U' sweep + SpMV as one launch
+    bool helper = false;        // tiled sweeps of one column: a helper wavefront per tile
     unsigned int spin_limit = 1u << 24;
 
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
@@ -220,6 +221,13 @@ int rhs_tile(const bilu_ctx* c, int R)
     if (R == 1) return 1;
     return c->rhs_tile > 0 ? c->rhs_tile : 8;
 }
+// The SpMV's columns per pass: by default (rhs_tile 0) one pass with lanes
+// over all columns (0); an explicit rhs_tile keeps the per-row kernel.
+int spmv_tile(const bilu_ctx* c, int R)
+{
+    if (R == 1) return 1;
+    return c->rhs_tile > 0 ? c->rhs_tile : 8;
+}
 bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; }
 
 // ----- templated launch helpers ---------------------------------------------
@@ -247,6 +255,11 @@ bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks,
                   const TiledArgs& a)
 {
     BILU_SWITCH_B(bs, if (!launch::tiled<B>(kmax, prec, fuse, multi, blocks, lds, s, a)) return false)
+}
+
+bool launch_helped(int bs, int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+{
+    BILU_SWITCH_B(bs, if (!launch::helped<B>(kmax, prec, fuse, blocks, lds, s, a)) return false)
 }
 
 bool launch_lines(int bs, int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& a)
@@ -737,7 +750,16 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
             g_trace_n[which] = need;
         }
 #endif
-        if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) return BILU_ERR_ARG;
+        const size_t hlds = static_cast<size_t>(helped_lds_bytes(a.tile_rows, ht.group, c->h.bs, ht.kmax));
+        if (c->helper && R == 1 && static_cast<int64_t>(hlds) <= c->lds_max) {
+            // one workgroup of 2 * group wavefronts per group (or tile)
+            a.ngroups = ht.group > 1 ? ht.ngroups : ht.ntiles;
+            const int hblocks = persistent_blocks(c, a.ngroups, 1, std::max(1, 4 / ht.group));
+            a.total_waves = static_cast<unsigned int>(hblocks);
+            if (!launch_helped(c->h.bs, ht.kmax, c->precision, fuse != 0, hblocks, hlds, s, a)) return BILU_ERR_ARG;
+        } else if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) {
+            return BILU_ERR_ARG;
+        }
     } else {
         const HostSweep& hs = c->h.sweep[which];
         const DevSweep& d = c->ds[kFormLevel][which];
@@ -811,9 +833,9 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
     const long tslot = timed ? timing_begin(c, BILU_K_SPMV, s) : -1;
     if (transpose) {
         if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
-        ok = launch_spmv(h.bs, rhs_tile(c, R), true, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s, gate);
+        ok = launch_spmv(h.bs, spmv_tile(c, R), true, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s, gate);
     } else {
-        ok = launch_spmv(h.bs, rhs_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s, gate);
+        ok = launch_spmv(h.bs, spmv_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s, gate);
     }
     timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
@@ -1184,6 +1206,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
     case BILU_TUNE_FUSE_SPMV:
         if (value != 0 && value != 1) return BILU_ERR_ARG;
         c->fuse_spmv = value != 0;
+        return BILU_OK;
+    case BILU_TUNE_HELPER:
+        if (value != 0 && value != 1) return BILU_ERR_ARG;
+        c->helper = value != 0;
         return BILU_OK;
     case BILU_TUNE_LINE_SWEEP: {
         const int ny = value & 255, nz = value >> 8;

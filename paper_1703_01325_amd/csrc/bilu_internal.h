@@ -117,6 +117,19 @@ inline int64_t tiled_lds_bytes(int tile_rows, int group, int bs)
     return (static_cast<int64_t>(group) * tile_rows + 1) * bs * 8 + (group > 1 ? kGroupMax * 4 : 0);
 }
 
+// Chunks held by the LDS ring through which a helper wavefront hands its
+// member the values of other tiles.
+constexpr int kHelpRing = 4;
+
+// LDS bytes of a tile-group workgroup with helper wavefronts: the member
+// tiles' rows, the zero row, progress and delivered counts, and each
+// member's ring of kHelpRing chunks of kmax * bs values per lane.
+inline int64_t helped_lds_bytes(int tile_rows, int group, int bs, int kmax)
+{
+    return (static_cast<int64_t>(group) * tile_rows + 1) * bs * 8 + 2 * kGroupMax * 4 +
+           static_cast<int64_t>(group) * kHelpRing * kmax * bs * 64 * 8;
+}
+
 // Dependency slots per row that the tiled sweep kernel loads ahead into
 // registers, from the widest chunk of the layout; wider rows finish their
 // remaining slots unpipelined.  Register budget: 3 for blocks of 5..8,

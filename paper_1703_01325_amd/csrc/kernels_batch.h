@@ -23,10 +23,16 @@ struct BatchSys {
     int bs;
 };
 
-// Krylov scalars of every system (arrays of length nsys, device memory).
+// Krylov scalars of every system (arrays of length nsys, device memory),
+// the per-system bookkeeping of the true-residual test (check: marked for
+// it this step; nrestart: restarts so far; done_it: step at which the
+// system stopped, -1 while it runs) and three batch-wide flags that gate
+// the kernels of a step: flags[0] some system is active, flags[1] some
+// system is marked for the test, flags[2] some system restarts.
 struct BatchState {
     double *rho, *rho_old, *alpha, *omega, *beta, *bnorm2, *tol2, *snorm2, *rnorm2, *tnorm2;
-    int *active, *fresh, *half, *status, *restart;
+    int *active, *fresh, *half, *status, *restart, *check, *nrestart, *done_it;
+    int* flags;
 };
 
 // A piece of the batch vectors: a range of unknowns inside one system.
@@ -64,11 +70,13 @@ struct BatchSpmvArgs {
     const double* x;
     double* y;
     const int* active;        // per system, or null
+    const int* gate;          // nothing runs when given and *gate == 0
 };
 
 __global__ __launch_bounds__(kThreads) void k_spmv_batch(BatchSpmvArgs a)
 {
     const int waves = static_cast<int>(gridDim.x) * kWavesPerBlock;
+    if (gated_off(a.gate)) return;
     const int first = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * kWavesPerBlock +
                                                      static_cast<int>(threadIdx.x >> 6));
     for (int w = first; w < a.nitems; w += waves) {
@@ -103,11 +111,13 @@ __device__ __forceinline__ bool piece_live(const Piece& pc, const int* active)
     return !active || active[pc.sys];
 }
 
-// part[slot] = <a, b> per piece (0 for frozen systems when active is given)
+// part[slot] = <a, b> per piece (0 for frozen systems when active is given);
+// nothing runs when gate is given and *gate == 0
 __global__ __launch_bounds__(kThreads) void kb_dot(const Piece* pieces, int npieces, const double* __restrict__ a,
                                                    const double* __restrict__ b, const int* active, double* part,
-                                                   int slot)
+                                                   int slot, const int* gate)
 {
+    if (gated_off(gate)) return;
     const Piece pc = pieces[blockIdx.x];
     double acc = 0.0;
     if (piece_live(pc, active))
@@ -119,8 +129,9 @@ __global__ __launch_bounds__(kThreads) void kb_dot(const Piece* pieces, int npie
 // <t, s> and <t, t>
 __global__ __launch_bounds__(kThreads) void kb_dot2(const Piece* pieces, int npieces, const double* __restrict__ t,
                                                     const double* __restrict__ s, const int* active, double* part,
-                                                    int slot_ts, int slot_tt)
+                                                    int slot_ts, int slot_tt, const int* gate)
 {
+    if (gated_off(gate)) return;
     const Piece pc = pieces[blockIdx.x];
     double ts = 0.0, tt = 0.0;
     if (piece_live(pc, active))
@@ -146,24 +157,43 @@ __device__ __forceinline__ double sum_pieces(const double* part, int slot, int n
 }
 
 // The scalar steps of BiCGSTAB for every system (one thread per system).
-enum { KB_INIT = 0, KB_RHO, KB_ALPHA, KB_SNORM, KB_OMEGA, KB_END, KB_TRUE };
+// KB_END also marks a system whose recurrence residual (or half step) meets
+// the tolerance for the true-residual test; KB_TRUE_CHECKED takes the true
+// residual of the marked systems only, KB_TRUE of every system.  Nothing
+// runs when gate is given and *gate == 0.
+enum { KB_INIT = 0, KB_RHO, KB_ALPHA, KB_SNORM, KB_OMEGA, KB_END, KB_TRUE, KB_TRUE_CHECKED };
 
 __global__ void kb_scalar(int nsys, const int32_t* __restrict__ piece_ptr, int npieces, const double* part,
-                          BatchState st, int op, double rtol)
+                          BatchState st, int op, double rtol, const int* gate)
 {
+    if (gated_off(gate)) return;
     const int c = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= nsys) return;
     const int p0 = piece_ptr[c], p1 = piece_ptr[c + 1];
     switch (op) {
-    case KB_INIT: bicg_init_one(st, c, sum_pieces(part, SL_BB, npieces, p0, p1), rtol); break;
+    case KB_INIT:
+        bicg_init_one(st, c, sum_pieces(part, SL_BB, npieces, p0, p1), rtol);
+        st.check[c] = 0;
+        st.nrestart[c] = 0;
+        st.done_it[c] = -1;
+        break;
     case KB_RHO: bicg_rho_one(st, c, sum_pieces(part, SL_RHO, npieces, p0, p1)); break;
     case KB_ALPHA: bicg_alpha_one(st, c, sum_pieces(part, SL_RV, npieces, p0, p1)); break;
     case KB_SNORM: bicg_snorm_one(st, c, sum_pieces(part, SL_SS, npieces, p0, p1)); break;
     case KB_OMEGA:
         bicg_omega_one(st, c, sum_pieces(part, SL_TS, npieces, p0, p1), sum_pieces(part, SL_TT, npieces, p0, p1));
         break;
-    case KB_END: bicg_end_one(st, c, sum_pieces(part, SL_RR, npieces, p0, p1)); break;
+    case KB_END: {
+        bicg_end_one(st, c, sum_pieces(part, SL_RR, npieces, p0, p1));
+        const int chk = st.active[c] && (st.half[c] || st.rnorm2[c] <= st.tol2[c]);
+        st.check[c] = chk;
+        if (chk) atomicOr(st.flags + 1, 1);
+        break;
+    }
     case KB_TRUE: st.tnorm2[c] = sum_pieces(part, SL_TRUE, npieces, p0, p1); break;
+    case KB_TRUE_CHECKED:
+        if (st.check[c]) st.tnorm2[c] = sum_pieces(part, SL_TRUE, npieces, p0, p1);
+        break;
     default: break;
     }
 }
@@ -172,6 +202,7 @@ __global__ void kb_scalar(int nsys, const int32_t* __restrict__ piece_ptr, int n
 __global__ __launch_bounds__(kThreads) void kb_p(const Piece* pieces, const double* __restrict__ r,
                                                  const double* __restrict__ v, double* __restrict__ p, BatchState st)
 {
+    if (!st.flags[0]) return;
     const Piece pc = pieces[blockIdx.x];
     const int c = pc.sys;
     if (!st.active[c]) return;
@@ -186,6 +217,7 @@ __global__ __launch_bounds__(kThreads) void kb_s(const Piece* pieces, int npiece
                                                  const double* __restrict__ v, double* __restrict__ s, BatchState st,
                                                  double* part)
 {
+    if (!st.flags[0]) return;
     const Piece pc = pieces[blockIdx.x];
     const int c = pc.sys;
     double acc = 0.0;
@@ -208,6 +240,7 @@ __global__ __launch_bounds__(kThreads) void kb_xr(const Piece* pieces, int npiec
                                                   const double* __restrict__ sh, const double* __restrict__ s,
                                                   const double* __restrict__ t, BatchState st, double* part)
 {
+    if (!st.flags[0]) return;
     const Piece pc = pieces[blockIdx.x];
     const int c = pc.sys;
     double acc = 0.0;
@@ -229,17 +262,22 @@ __global__ __launch_bounds__(kThreads) void kb_xr(const Piece* pieces, int npiec
     if (threadIdx.x == 0) part[static_cast<int64_t>(SL_RR) * npieces + blockIdx.x] = tot;
 }
 
-// w = b - w (w holds A x on entry), partial of <w, w>
+// w = b - w (w holds A x on entry), partial of <w, w>, for the systems
+// marked in `active` (all if null); nothing runs when gate is given and
+// *gate == 0
 __global__ __launch_bounds__(kThreads) void kb_resid(const Piece* pieces, int npieces, const double* __restrict__ b,
-                                                     double* __restrict__ w, double* part, int slot)
+                                                     double* __restrict__ w, double* part, int slot,
+                                                     const int* active, const int* gate)
 {
+    if (gated_off(gate)) return;
     const Piece pc = pieces[blockIdx.x];
     double acc = 0.0;
-    for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
-        const double v = b[g] - w[g];
-        w[g] = v;
-        acc += v * v;
-    }
+    if (piece_live(pc, active))
+        for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
+            const double v = b[g] - w[g];
+            w[g] = v;
+            acc += v * v;
+        }
     const double tot = block_sum(acc);
     if (threadIdx.x == 0) part[static_cast<int64_t>(slot) * npieces + blockIdx.x] = tot;
 }
@@ -248,11 +286,51 @@ __global__ __launch_bounds__(kThreads) void kb_resid(const Piece* pieces, int np
 __global__ __launch_bounds__(kThreads) void kb_restart(const Piece* pieces, const double* __restrict__ w,
                                                        double* __restrict__ r, double* __restrict__ rh, BatchState st)
 {
+    if (!st.flags[2]) return;
     const Piece pc = pieces[blockIdx.x];
     if (!st.restart[pc.sys]) return;
     for (int64_t g = pc.begin + threadIdx.x; g < pc.end; g += kThreads) {
         r[g] = w[g];
         rh[g] = w[g];
+    }
+}
+
+// After step `it` (0: after the setup), one workgroup over every system: a
+// system marked for the test stops if its true residual meets the
+// tolerance, else it restarts from it (r = r^ = b - A x).  Records the step
+// at which each system stopped, sets the batch-wide flags that gate the
+// next step and copies flags[0] to *host_flag (mapped host memory), which
+// the host reads a step later to stop queueing steps.
+__global__ __launch_bounds__(256) void kb_decide(int nsys, BatchState st, int it, int* host_flag)
+{
+    int any_restart = 0, any_active = 0;
+    for (int c = static_cast<int>(threadIdx.x); c < nsys; c += static_cast<int>(blockDim.x)) {
+        int restart = 0;
+        if (st.check[c] && st.active[c]) {
+            if (st.tnorm2[c] <= st.tol2[c]) {
+                st.active[c] = 0;
+                st.status[c] = ST_OK;
+            } else {
+                restart = 1;
+                st.fresh[c] = 1;
+                st.half[c] = 0;
+                st.nrestart[c] += 1;
+            }
+        }
+        st.check[c] = 0;
+        st.restart[c] = restart;
+        const int active = st.active[c];
+        if (!active && st.done_it[c] < 0) st.done_it[c] = it;
+        any_restart |= restart;
+        any_active |= active;
+    }
+    any_restart = __syncthreads_or(any_restart);
+    any_active = __syncthreads_or(any_active);
+    if (threadIdx.x == 0) {
+        st.flags[0] = any_active ? 1 : 0;
+        st.flags[1] = 0;
+        st.flags[2] = any_restart ? 1 : 0;
+        if (host_flag) __hip_atomic_store(host_flag, any_active ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -26,6 +26,11 @@ template <int B>
 bool tiled(int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hipStream_t s,
            const dev::TiledArgs& a);
 
+// Tile groups of a.group >= 1 tiles, each member with a helper wavefront
+// that hands it the values of other tiles through LDS (one right-hand side).
+template <int B>
+bool helped(int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a);
+
 // U' sweep fused with the SpMV of its output (single tiles, one column).
 template <int B>
 bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a,
@@ -35,8 +40,9 @@ bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev:
 template <int B>
 bool lines(int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& a);
 
-// y = A x (trans = false) or A^T x, rt columns per pass (1, 4 or 8); nothing
-// runs when gate is given and *gate == 0.
+// y = A x (trans = false) or A^T x, rt columns per pass (1, 4 or 8), or
+// rt = 0: lanes over the R columns (2 <= R <= 32); nothing runs when gate
+// is given and *gate == 0.
 template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
           const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr);

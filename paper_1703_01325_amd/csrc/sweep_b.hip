@@ -29,13 +29,13 @@ bool tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledAr
         const dim3 threads(64 * a.group);
         if constexpr (B >= 5) {
             if (kmax != 3) return false;
-            hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a);
+            hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI, false>), dim3(blocks), threads, lds, s, a);
             return true;
         } else {
             switch (kmax) {
-            case 3: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI>), dim3(blocks), threads, lds, s, a); return true;
-            case 6: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 6, MULTI>), dim3(blocks), threads, lds, s, a); return true;
-            case 9: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 9, MULTI>), dim3(blocks), threads, lds, s, a); return true;
+            case 3: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, MULTI, false>), dim3(blocks), threads, lds, s, a); return true;
+            case 6: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 6, MULTI, false>), dim3(blocks), threads, lds, s, a); return true;
+            case 9: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 9, MULTI, false>), dim3(blocks), threads, lds, s, a); return true;
             }
             return false;
         }
@@ -49,6 +49,27 @@ bool tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledAr
         case 3: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 3, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
         case 6: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 6, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
         case 9: hipLaunchKernelGGL((dev::k_sweep_tiled<B, T, FUSE, 9, MULTI>), dim3(blocks), dim3(64), lds, s, a); return true;
+        }
+        return false;
+    }
+}
+
+// Tile groups (a.group >= 1) with a helper wavefront per member; one
+// right-hand side.
+template <int B, typename T, bool FUSE>
+bool helped_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (a.group < 1 || a.group > kGroupMax) return false;
+    const dim3 threads(128 * a.group);
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, false, true>), dim3(blocks), threads, lds, s, a);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 3, false, true>), dim3(blocks), threads, lds, s, a); return true;
+        case 6: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 6, false, true>), dim3(blocks), threads, lds, s, a); return true;
+        case 9: hipLaunchKernelGGL((dev::k_sweep_grouped<B, T, FUSE, 9, false, true>), dim3(blocks), threads, lds, s, a); return true;
         }
         return false;
     }
@@ -89,6 +110,25 @@ void spmv_k(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, co
                        y, R, gate);
 }
 
+template <int B, int CW, bool TR>
+void spmv_cols_k(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
+                 const double* x, double* y, int R, hipStream_t s, const int* gate)
+{
+    constexpr int RPW = 64 / CW;
+    const int64_t waves = (static_cast<int64_t>(nb) + RPW - 1) / RPW;
+    const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+    hipLaunchKernelGGL((dev::k_spmv_cols<B, CW, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src, Ax,
+                       x, y, R, gate);
+}
+
+template <int B, int CW>
+void spmv_cols_t(bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
+                 const double* x, double* y, int R, hipStream_t s, const int* gate)
+{
+    if (trans) spmv_cols_k<B, CW, true>(nb, rp, cj, src, Ax, x, y, R, s, gate);
+    else spmv_cols_k<B, CW, false>(nb, rp, cj, src, Ax, x, y, R, s, gate);
+}
+
 }  // namespace
 
 template <int B>
@@ -108,6 +148,14 @@ bool tiled(int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hi
 {
     if (prec == BILU_FACTORS_FP32) return tiled_t<B, float>(kmax, fuse, multi, blocks, lds, s, a);
     return tiled_t<B, double>(kmax, fuse, multi, blocks, lds, s, a);
+}
+
+template <int B>
+bool helped(int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (prec == BILU_FACTORS_FP32)
+        return fuse ? helped_k<B, float, true>(kmax, blocks, lds, s, a) : helped_k<B, float, false>(kmax, blocks, lds, s, a);
+    return fuse ? helped_k<B, double, true>(kmax, blocks, lds, s, a) : helped_k<B, double, false>(kmax, blocks, lds, s, a);
 }
 
 template <int B>
@@ -136,6 +184,16 @@ template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
           const double* x, double* y, int R, hipStream_t s, const int* gate)
 {
+    if (rt == 0) {
+        // lanes over columns
+        if (R < 2 || R > 32) return false;
+        if (R <= 2) spmv_cols_t<B, 2>(trans, nb, rp, cj, src, Ax, x, y, R, s, gate);
+        else if (R <= 4) spmv_cols_t<B, 4>(trans, nb, rp, cj, src, Ax, x, y, R, s, gate);
+        else if (R <= 8) spmv_cols_t<B, 8>(trans, nb, rp, cj, src, Ax, x, y, R, s, gate);
+        else if (R <= 16) spmv_cols_t<B, 16>(trans, nb, rp, cj, src, Ax, x, y, R, s, gate);
+        else spmv_cols_t<B, 32>(trans, nb, rp, cj, src, Ax, x, y, R, s, gate);
+        return true;
+    }
     switch (rt) {
     case 1: trans ? spmv_k<B, 1, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 1, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
     case 4: trans ? spmv_k<B, 4, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 4, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
@@ -146,6 +204,7 @@ bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, cons
 
 template bool sweep<BILU_B>(int, int, int, hipStream_t, const dev::SweepArgs&);
 template bool tiled<BILU_B>(int, int, bool, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
+template bool helped<BILU_B>(int, int, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
 template bool fused<BILU_B>(int, int, int, size_t, hipStream_t, const dev::TiledArgs&, const dev::FusedSpmvArgs&);
 template bool lines<BILU_B>(int, bool, int, hipStream_t, const dev::LineArgs&);
 template bool spmv<BILU_B>(int, bool, int, const int32_t*, const int32_t*, const int64_t*, const double*,

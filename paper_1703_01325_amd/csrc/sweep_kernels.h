@@ -445,7 +445,7 @@ __device__ __forceinline__ void tile_meta(const TiledArgs& a, int chunk, int sro
     for (int k = 0; k < KMAX; ++k) m.code[k] = dp[k * RPC + qc];
 }
 
-template <int B, typename T, int KMAX, bool FUSE, bool MULTI>
+template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool HELP = false>
 __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc, int r, const TileMeta<KMAX>& m,
                                           TileData<B, T, KMAX, FUSE>& s, const ColMap<MULTI>& cm)
 {
@@ -475,12 +475,15 @@ __device__ __forceinline__ void tile_data(const TiledArgs& a, int chunk, int qc,
         s.h[0] = load_at(a.rhs, cm.at(rowc_b, r));
     }
     // tile-local and padding slots do not use the value: every such lane
-    // reads row 0, so the wavefront touches one cache line for them
+    // reads row 0, so the wavefront touches one cache line for them.  With a
+    // helper wavefront the values of other tiles come through LDS instead.
+    if constexpr (!HELP) {
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : 0u;
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : 0u;
 #pragma unroll
-        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), cm.at(xb, c));
+            for (int c = 0; c < B; ++c) s.x[k][c] = load_at(static_cast<const double*>(a.out), cm.at(xb, c));
+        }
     }
 }
 
@@ -543,13 +546,47 @@ __device__ __forceinline__ void await_members(const int* prog, const int (&need)
     asm volatile("" ::: "memory");
 }
 
+// Helper wavefronts (k_sweep_grouped<..., HELP>): next to each member
+// wavefront of a tile group runs a helper wavefront that reads the member's
+// values from other tiles, chunk by chunk in the member's order, polls those
+// still showing kNotReady, and hands them over through an LDS ring of
+// kHelpRing chunks ([chunk % kHelpRing][slot value][lane]), publishing its
+// count of delivered chunks after them.  The member then issues no load of
+// another tile's values: its vector loads are prefetches only, which
+// complete in issue order, so no poll waits behind them, and it can keep a
+// deeper prefetch ring.  The helper refills a ring entry once the member's
+// progress count shows that the member has finished the chunk held there
+// (kHelpRing: bilu_internal.h, shared with the host's LDS sizing).
+
+// Waits (bounded) until the LDS count *cnt reaches need.
+__device__ __forceinline__ void await_count(const int* cnt, int need, unsigned int limit, int* status)
+{
+    for (unsigned int spins = 0;
+         __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need;) {
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    asm volatile("" ::: "memory");
+}
+
+// The member side of a helper's ring: count of chunks delivered, the
+// member's ring and the index of the chunk in the member's tile.
+struct HelpView {
+    const int* hprog;
+    const double* ring;
+    int idx;
+};
+
 // lds: the workgroup's LDS (dependency codes are offsets into it);
 // tile_vals: this tile's rows in it.
-template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool GROUPED>
+template <int B, typename T, int KMAX, bool FUSE, bool MULTI, bool GROUPED, bool HELP = false>
 __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc, int r, bool active,
                                              const double* lds_base, double* tile_vals,
                                              const TileData<B, T, KMAX, FUSE>& s, const int (&need)[kGroupMax],
-                                             const int* prog, const ColMap<MULTI>& cm, int wbase
+                                             const int* prog, const ColMap<MULTI>& cm, int wbase, const HelpView& hv
 #ifdef BILU_TRACE
                                              , long long* trc
 #endif
@@ -564,26 +601,38 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
 #pragma unroll
-        for (int c = 0; c < B; ++c) asm volatile("" ::"v"(s.f[k][c]), "v"(s.x[k][c]));
+        for (int c = 0; c < B; ++c) {
+            asm volatile("" ::"v"(s.f[k][c]));
+            if constexpr (!HELP) asm volatile("" ::"v"(s.x[k][c]));
+        }
     }
 #pragma unroll
     for (int c = 0; c < (FUSE ? B : 1); ++c) asm volatile("" ::"v"(s.h[c]), "v"(s.d[c]));
     // values from other tiles: the prefetched copies, the ones still showing
-    // kNotReady polled together
+    // kNotReady polled together; with a helper, its ring entry once the
+    // helper has delivered this chunk
     double xg[KMAX * B];
+    if constexpr (HELP) {
+        await_count(hv.hprog, hv.idx + 1, a.spin_limit, a.status);
+        const double* rs = hv.ring + (hv.idx % kHelpRing) * (KMAX * B * 64) + lane_id();
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
+        for (int j = 0; j < KMAX * B; ++j) xg[j] = rs[j * 64];
+        if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
+    } else {
 #pragma unroll
-        for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
+        for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+            for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
 #ifdef BILU_TRACE
-    if (trc && lane_id() == 0) trc[1] = wall_clock64();
-    const unsigned int spins_ = await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
-    if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
-    if (trc && lane_id() == 0) { trc[2] = wall_clock64(); trc[3] = spins_; }
+        if (trc && lane_id() == 0) trc[1] = wall_clock64();
+        const unsigned int spins_ = await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
+        if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
+        if (trc && lane_id() == 0) { trc[2] = wall_clock64(); trc[3] = spins_; }
 #else
-    await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
-    if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
+        await_tile<KMAX, B, MULTI>(xg, s.code, a.out, cm, a.spin_limit, a.status);
+        if (GROUPED) await_members(prog, need, a.spin_limit, a.status);
 #endif
+    }
     if (!active || s.row < 0) return;
     double acc;
     if (FUSE) {
@@ -651,21 +700,24 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
 // sweep front) run their sweeps faster with fewer loads in flight (60x220x85
 // ILU(0), groups of 3: U' sweep 528 -> 497 us), while a wavefront on its own
 // gains from the deeper ring.
-template <int B, typename T, bool FUSE, int KMAX, bool GROUPED>
+template <int B, typename T, bool FUSE, int KMAX, bool GROUPED, bool HELP = false>
 struct TiledRing {
     static constexpr int w = sizeof(T) == 8 ? 2 : 1;
-    static constexpr int state = KMAX * B * (2 + w) + KMAX + (FUSE ? B * (2 + w) : 2) + 4 + KMAX + 3;
-    static constexpr int value = !GROUPED && 3 * state + 40 <= 240 ? 3 : 2;
+    static constexpr int state = KMAX * B * ((HELP ? 0 : 2) + w) + KMAX + (FUSE ? B * (2 + w) : 2) + 4 + KMAX + 3;
+    // with a helper the member's loads are prefetches only: a deeper ring
+    static constexpr int value = HELP ? (4 * state + 40 <= 200 ? 4 : 3 * state + 40 <= 220 ? 3 : 2)
+                                      : (!GROUPED && 3 * state + 40 <= 240 ? 3 : 2);
 };
 
 // One tile of a tiled sweep by one wavefront (column cm of the vectors).
 // tile_vals: the wavefront's LDS, row a.tile_rows already zero.
-template <int B, typename T, bool FUSE, int KMAX, bool MULTI, bool GROUPED>
+template <int B, typename T, bool FUSE, int KMAX, bool MULTI, bool GROUPED, bool HELP = false>
 __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap<MULTI>& cm, const double* lds_base,
-                                         double* tile_vals, int* prog, int member)
+                                         double* tile_vals, int* prog, int member, const int* hprog = nullptr,
+                                         const double* ring = nullptr)
 {
     constexpr int RPC = 64 / B;
-    constexpr int NR = TiledRing<B, T, FUSE, KMAX, GROUPED>::value;   // register states in flight
+    constexpr int NR = TiledRing<B, T, FUSE, KMAX, GROUPED, HELP>::value;   // register states in flight
     constexpr int LD = NR - 1;                               // data lookahead
     constexpr int LM = 2 * LD;                               // metadata lookahead
     const int lane = lane_id();
@@ -693,7 +745,8 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
     // waits of chunk i, read with its data (scalar loads)
     auto wait_at = [&](int i, int (&w)[kGroupMax]) {
 #pragma unroll
-        for (int m = 0; m < kGroupMax; ++m) w[m] = GROUPED ? uniform_load(a.chunk_wait, chunk_at(i) * kGroupMax + m) : 0;
+        for (int m = 0; m < kGroupMax; ++m)
+            w[m] = GROUPED && a.group > 1 ? uniform_load(a.chunk_wait, chunk_at(i) * kGroupMax + m) : 0;
     };
     // prologue: metadata of chunks 0..NR-1, then data of 0..LD-1 with the
     // metadata of LD..LM-1 issued as their slots free up
@@ -701,7 +754,7 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
     for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
 #pragma unroll
     for (int i = 0; i < LD; ++i) {
-        tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
+        tile_data<B, T, KMAX, FUSE, MULTI, HELP>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
         wait_at(i, wr[i % NR]);
         if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
     }
@@ -719,10 +772,13 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
             tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
             pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
             pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
-            tile_data<B, T, KMAX, FUSE, MULTI>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
+            tile_data<B, T, KMAX, FUSE, MULTI, HELP>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR],
+                                                     cm);
             wait_at(i + LD, wr[(p + LD) % NR]);
-            tile_compute<B, T, KMAX, FUSE, MULTI, GROUPED>(a, lo, qc, r, lane_ok && i < nch, lds_base, tile_vals,
-                                                           dr[p], wr[p], prog, cm, a.ring > 0 ? wchunk * RPC : -1
+            const HelpView hv{hprog, ring, i < nch ? i : nch - 1};
+            tile_compute<B, T, KMAX, FUSE, MULTI, GROUPED, HELP>(a, lo, qc, r, lane_ok && i < nch, lds_base, tile_vals,
+                                                                 dr[p], wr[p], prog, cm,
+                                                                 a.ring > 0 ? wchunk * RPC : -1, hv
 #ifdef BILU_TRACE
                                                            , (a.trace && i < nch) ? a.trace + 4 * (c0 + i) : nullptr
 #endif
@@ -739,6 +795,56 @@ __device__ __forceinline__ void run_tile(const TiledArgs& a, int t, const ColMap
             if (GROUPED && i < nch && lane == 0)
                 __hip_atomic_store(prog + member, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+    }
+}
+
+// The helper wavefront of one member tile: for each chunk in the member's
+// order, the values of other tiles its lanes need (the same slots, lanes and
+// columns as the member's), read with device-coherent loads and polled until
+// none shows kNotReady, then written to the member's LDS ring once the
+// member has finished the chunk that entry held, and the delivered count
+// published after them (one wavefront: its LDS operations take effect in
+// issue order).  The dependency codes of the next chunk are loaded while
+// the current chunk's values are awaited.
+template <int B, int KMAX, bool MULTI>
+__device__ __forceinline__ void run_helper(const TiledArgs& a, int t, const ColMap<MULTI>& cm, double* ring,
+                                           int* hprog, const int* prog)
+{
+    constexpr int RPC = 64 / B;
+    const int lane = lane_id();
+    const int q = lane / B;
+    const int qc = q < RPC ? q : RPC - 1;
+    const int c0 = uniform_load(a.tile_chunk_ptr, t);
+    const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
+    if (nch <= 0) return;
+    auto meta_at = [&](int i, TileMeta<KMAX>& m) {
+        const int ch = c0 + (i < nch ? i : nch - 1);
+        const int sr = uniform_load(a.chunk_row, ch);
+        tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
+    };
+    TileMeta<KMAX> cur, nxt;
+    meta_at(0, cur);
+    for (int i = 0; i < nch; ++i) {
+        double v[KMAX * B];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t xb = cur.code[k] >= 0 ? static_cast<uint32_t>(cur.code[k]) : 0u;
+#pragma unroll
+            for (int c = 0; c < B; ++c)
+                v[k * B + c] = coherent_load(reinterpret_cast<const double*>(
+                    reinterpret_cast<const char*>(a.out) + cm.at(xb, c)));
+        }
+        meta_at(i + 1, nxt);
+        await_tile<KMAX, B, MULTI>(v, cur.code, a.out, cm, a.spin_limit, a.status);
+        // the entry's previous chunk, i - kHelpRing, is finished
+        await_count(prog, i - kHelpRing + 1, a.spin_limit, a.status);
+        double* dst = ring + (i % kHelpRing) * (KMAX * B * 64) + lane;
+#pragma unroll
+        for (int j = 0; j < KMAX * B; ++j) dst[j * 64] = v[j];
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+        if (lane == 0) __hip_atomic_store(hprog, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        cur = nxt;
     }
 }
 
@@ -770,8 +876,12 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 // once their progress counts cover them.  Tickets run in group order, and
 // every row a group reads from outside lies in a group with a smaller
 // ticket, so the persistent launch drains.
-template <int B, typename T, bool FUSE, int KMAX, bool MULTI>
-__global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
+// HELP: a.group helper wavefronts follow the a.group members (workgroup of
+// 2 * a.group wavefronts; a.group may then be 1, with a.ngroups the number
+// of tiles); LDS after the progress counts: kGroupMax delivered counts, then
+// the members' rings.
+template <int B, typename T, bool FUSE, int KMAX, bool MULTI, bool HELP>
+__global__ __launch_bounds__(64 * kGroupMax * (HELP ? 2 : 1)) void k_sweep_grouped(TiledArgs a)
 {
     extern __shared__ double group_vals[];   // [group*tile_rows + 1][B], then kGroupMax progress counts
     __shared__ int s_ticket;
@@ -779,14 +889,19 @@ __global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
     const int G = a.group;
     // wave-uniform (the compiler cannot see that on its own): the member's
     // tile and chunk indices then stay scalar
-    const int member = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const bool helper = HELP && wave >= G;
+    const int member = helper ? wave - G : wave;
     const int zrow = G * a.tile_rows;
     int* prog = reinterpret_cast<int*>(group_vals + static_cast<int64_t>(zrow + 1) * B);
+    int* hprog = prog + kGroupMax;
+    double* rings = reinterpret_cast<double*>(hprog + kGroupMax);
+    double* ring = rings + static_cast<int64_t>(member) * (kHelpRing * KMAX * B * 64);
     if (static_cast<int>(threadIdx.x) < B) group_vals[zrow * B + threadIdx.x] = 0.0;
     const int nticket = MULTI ? a.ngroups * a.R : a.ngroups;
     for (;;) {
         // the previous group is finished by every member (barrier below)
-        if (threadIdx.x < kGroupMax) prog[threadIdx.x] = 0;
+        if (threadIdx.x < (HELP ? 2 : 1) * kGroupMax) prog[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             const unsigned long long tk = atomicAdd(a.ticket, 1ULL);
             s_ticket = tk > 0x3fffffffULL ? 0x3fffffff : static_cast<int>(tk);
@@ -795,17 +910,21 @@ __global__ __launch_bounds__(64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
         const int tk = __builtin_amdgcn_readfirstlane(s_ticket);
         if (tk >= nticket) break;
         const int g = MULTI ? tk / a.R : tk;
-        const int t = member < G ? uniform_load(a.group_tiles, g * G + member) : -1;
+        const int t = member >= G ? -1 : G == 1 ? g : uniform_load(a.group_tiles, g * G + member);
         ColMap<MULTI> cm;
         cm.R = static_cast<uint32_t>(a.R);
         cm.j8 = MULTI ? static_cast<uint32_t>(tk - g * a.R) * 8u : 0u;
-        if (t >= 0)
-            run_tile<B, T, FUSE, KMAX, MULTI, true>(a, t, cm, group_vals,
-                                                    group_vals + static_cast<int64_t>(member) * a.tile_rows * B, prog,
-                                                    member);
+        if (t >= 0) {
+            if (helper)
+                run_helper<B, KMAX, MULTI>(a, t, cm, ring, hprog + member, prog + member);
+            else
+                run_tile<B, T, FUSE, KMAX, MULTI, true, HELP>(a, t, cm, group_vals,
+                                                              group_vals + static_cast<int64_t>(member) * a.tile_rows * B,
+                                                              prog, member, hprog + member, ring);
+        }
         __syncthreads();
     }
-    if (member == 0) finish_persistent(a.ticket, a.done, a.total_waves);
+    if (wave == 0) finish_persistent(a.ticket, a.done, a.total_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -1216,8 +1335,56 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __rest
     spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, Ax, 0, x, y, R);
 }
 
+// y = A x (or A^T x) for R >= 2 right-hand sides, lanes over columns: lane
+// (s, j) of a wavefront computes column j of block row row0 + s, all B
+// components of it in registers, with CW >= R lanes per row (a power of
+// two) and 64/CW rows per wavefront.  A block's values are read by all CW
+// lanes of its row at once (one cache line per row and load), and the x
+// values of a block column (B unknowns, R columns each, row-major) by the
+// row's lanes together, contiguous.  Per column, the products are summed in
+// the order of spmv_rows (blocks in order, components in order), so each
+// column equals the one-column result bit for bit.
+template <int B, int CW, bool TRANS>
+__global__ __launch_bounds__(kThreads) void k_spmv_cols(int nb, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ cj,
+                                                        const int64_t* __restrict__ srcpos,
+                                                        const double* __restrict__ Ax,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ y, int R, const int* gate)
+{
+    constexpr int RPW = 64 / CW;
+    constexpr int BB = B * B;
+    if (gated_off(gate)) return;
+    const int lane = lane_id();
+    const int s = lane / CW;
+    const int j = lane - s * CW;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t row = wave * RPW + s;
+    if (row >= nb || j >= R) return;
+    const int e0 = rp[row], e1 = rp[row + 1];
+    double acc[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) acc[r] = 0.0;
+#pragma unroll 2
+    for (int e = e0; e < e1; ++e) {
+        const int64_t col = cj[e];
+        const double* av = Ax + (TRANS ? srcpos[e] : static_cast<int64_t>(e)) * BB;
+        const double* xj = x + col * B * R + j;
+        double xv[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) xv[c] = xj[c * R];
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+#pragma unroll
+            for (int r = 0; r < B; ++r) acc[r] += (TRANS ? av[r * B + c] : av[c * B + r]) * xv[c];
+    }
+    double* dst = y + row * B * R + j;
+#pragma unroll
+    for (int r = 0; r < B; ++r) dst[r * R] = acc[r];
+}
+
 // ---------------------------------------------------------------------------
-// Sweeps over the batch: one persistent launch per sweep on the members'
+// Sweeps over the batch: one persistent launch per sweep on the members''
 // row-tile layouts.  Items are (member, tile), merged tile index by tile
 // index (tile t of every member before tile t + 1 of any), so each item
 // depends only on items with smaller tickets, as in the single-system tiled
@@ -1248,6 +1415,7 @@ struct BatchSweepArgs {
     double* out;
     double* reset;
     const int* active;            // per member, or null: every member
+    const int* gate;              // nothing runs when given and *gate == 0
     unsigned long long* ticket;
     unsigned int* done;
     int* status;
@@ -1288,6 +1456,9 @@ template <typename T, bool FUSE>
 __global__ __launch_bounds__(64) void k_sweep_batch(BatchSweepArgs a)
 {
     extern __shared__ double tile_vals[];
+    // the gate is uniform over the grid: either every wavefront leaves here
+    // (the ticket and done counters stay untouched) or none does
+    if (gated_off(a.gate)) return;
     for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < a.nitems;
          tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
         const int2 it = uniform_record(a.items, tk);

@@ -152,6 +152,56 @@ def layered_60x220x85(seed: int = 3) -> BlockSystem:
     return reservoir(60, 220, 85, 3, seed, sigma=1.5, layer_mu=(-2.0, 3.0))
 
 
+def poisson7(n: int, bs: int, seed: int = 6, nx: int | None = None, ny: int | None = None) -> BlockSystem:
+    """Scalar 7-point Poisson matrix on an ``nx x ny x n`` grid (``nx``,
+    ``ny`` default to ``n``), unknowns in natural order ``u = x + nx*(y +
+    ny*z)``, regrouped into block rows of ``bs`` consecutive unknowns (the
+    block-size study of Section 3, Table 1).
+
+    Scalar entries: 6 on the diagonal, -1 for each grid neighbour inside the
+    domain (homogeneous Dirichlet boundary eliminated, so boundary rows keep
+    the 6).  ``bs`` must divide ``nx``: block row ``I`` then holds the ``bs``
+    x-consecutive unknowns of one grid line segment, and the block pattern is
+    the 7-point stencil of the ``nx/bs x ny x n`` block grid.  The diagonal
+    block is tridiagonal (-1, 6, -1); the block of the x-neighbour segment
+    before holds a single -1 at (0, bs-1), the one after at (bs-1, 0), and
+    the y and z neighbour blocks are -I.  The explicit zeros of the
+    x-neighbour blocks are stored, as the block format does.
+
+    The exact solution ``x*`` is drawn ``U[-1, 1]`` from ``PCG64(seed)``.
+    """
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    if bs < 1 or nx % bs:
+        raise ValueError(f"block size {bs} must divide the x extent {nx}")
+    gx = nx // bs
+    Ap, Aj = stencil7_pattern(gx, ny, n)
+    nb = gx * ny * n
+    bb = bs * bs
+    rows = np.repeat(np.arange(nb, dtype=np.int64), np.diff(Ap).astype(np.int64))
+    d = Aj.astype(np.int64) - rows
+    vals = np.zeros((int(Ap[-1]), bs, bs), dtype=np.float64)   # [blk][c][r]
+    idx = np.arange(bs)
+    diag = np.zeros((bs, bs))
+    diag[idx, idx] = 6.0
+    diag[idx[:-1], idx[1:]] = -1.0
+    diag[idx[1:], idx[:-1]] = -1.0
+    vals[d == 0] = diag                      # symmetric: layout-independent
+    vals[d == -1, bs - 1, 0] = -1.0          # (r=0, c=bs-1), column-major
+    vals[d == 1, 0, bs - 1] = -1.0           # (r=bs-1, c=0)
+    far = np.nonzero(np.abs(d) > 1)[0]
+    vals[far[:, None], idx[None, :], idx[None, :]] = -1.0
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xstar = rng.uniform(-1.0, 1.0, size=nb * bs)
+    return BlockSystem(nb=nb, bs=bs, Ap=Ap, Aj=Aj, Ax=vals.reshape(-1), xstar=xstar,
+                       grid=(gx, ny, n), seed=seed)
+
+
+def poisson_120cube(bs: int, seed: int = 6) -> BlockSystem:
+    """The 120^3 Poisson matrix (n = 1,728,000) with blocks of ``bs``."""
+    return poisson7(120, bs, seed)
+
+
 def multi_rhs(n: int, nrhs: int, seed: int = 41) -> np.ndarray:
     """(n, nrhs) right-hand sides, entries U[-1,1], row-major."""
     rng = np.random.Generator(np.random.PCG64(seed))

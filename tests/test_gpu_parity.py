@@ -403,6 +403,29 @@ def test_spmv_short_and_long_rows(api, oracle_mod, bs):
         assert rel(yc[:, j], oracle_mod.spmv(nb, bs, Ap, Aj, Ax, X[:, j].copy())) <= 1e-13
 
 
+@pytest.mark.parametrize("bs", [1, 3, 8])
+@pytest.mark.parametrize("R", [2, 3, 5, 8, 16, 17, 32])
+def test_spmv_column_lanes(api, oracle_mod, bs, R):
+    """The default several-column SpMV (lanes over columns) gives, column by
+    column, the bits of the one-column-per-pass kernel, for A and A^T, with
+    column counts below, at and above each lane width."""
+    nb = 157
+    Ap, Aj = synth.graded_block_pattern(nb, 0.005, 0.08, seed=81 + bs)
+    Ax = synth.random_block_values(Ap, Aj, bs, seed=82 + bs)
+    M = api.BlockILU(nb, bs, Ap, Aj, 0, transpose=True)
+    X = synth.multi_rhs(nb * bs, R, seed=83 + R)
+    A, Xd = cuda(Ax), cuda(X)
+    M.tune(rhs_tile=1)
+    y1 = M.spmv(A, Xd)
+    t1 = M.spmv(A, Xd, transpose=True)
+    M.tune(rhs_tile=0)
+    assert torch.equal(M.spmv(A, Xd), y1)
+    assert torch.equal(M.spmv(A, Xd, transpose=True), t1)
+    yc = y1.cpu().numpy()
+    for j in (0, R - 1):
+        assert rel(yc[:, j], oracle_mod.spmv(nb, bs, Ap, Aj, Ax, X[:, j].copy())) <= 1e-13
+
+
 @pytest.mark.parametrize("rt", [1, 4, 8])
 def test_rhs_tile_parity(api, oracle_mod, rt):
     """Columns per pass change only how the columns are grouped: every
