@@ -279,11 +279,14 @@ enum {
                                  block of ny x nz grid lines (ny*nz <= 64/bs) computing
                                  one diagonal of its block per step; 0 (default): off.
                                  Other patterns keep the tiled sweeps               */
-    BILU_TUNE_HELPER = 9,     /* mode 2, one right-hand side: 1 runs every tile (or
-                                 tile group member) with a helper wavefront in its
+    BILU_TUNE_HELPER = 9,     /* mode 2, one right-hand side: run each tile (or tile
+                                 group member) with a helper wavefront in its
                                  workgroup that reads the values of other tiles and
                                  hands them over through LDS, so the tile's own
-                                 loads are prefetches only; 0 (default): off         */
+                                 loads are prefetches only.  0 (default): automatic,
+                                 helpers for ungrouped tiles whose rows load six or
+                                 more dependency slots ahead; 1: always; 2: never.
+                                 bilu_autotune times both                           */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

@@ -62,7 +62,8 @@ class BlockILU:
                           (0 if not tile_block else tile_block[0] + 256 * tile_block[1])),
                          (N.TUNE_LINE_SWEEP, None if line_sweep is None else
                           (0 if not line_sweep else line_sweep[0] + 256 * line_sweep[1])),
-                         (N.TUNE_HELPER, None if helper is None else int(bool(helper))),
+                         (N.TUNE_HELPER, None if helper is None else
+                          (0 if helper == "auto" else 1 if helper else 2)),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

@@ -97,7 +97,7 @@ struct bilu_ctx {
     int blocks_override = 0;
     int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
     bool fuse_spmv = false;     // solvers run U' sweep + SpMV as one launch
-    bool helper = false;        // tiled sweeps of one column: a helper wavefront per tile
+    int helper = 0;             // helper wavefronts: 0 automatic, 1 always, 2 never
     unsigned int spin_limit = 1u << 24;
 
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
@@ -226,9 +226,23 @@ int rhs_tile(const bilu_ctx* c, int R)
 int spmv_tile(const bilu_ctx* c, int R)
 {
     if (R == 1) return 1;
-    return c->rhs_tile > 0 ? c->rhs_tile : 8;
+    return c->rhs_tile > 0 ? c->rhs_tile : 0;
 }
 bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; }
+
+// Helper wavefronts for a tiled sweep of R columns.  Automatic: for single
+// tiles whose rows load six or more dependency slots ahead (ILU(1) and
+// beyond on a 7-point grid), where the member's deeper prefetch ring pays:
+// measured on MI355X, 64^3 ILU(1) L/U' sweeps 682/707 -> 517/532 us and
+// 60x220x85 ILU(1) U' 1587 -> 1491 us, while ILU(0) tiles (three slots,
+// already a three-state ring) and tile groups ran slower with helpers
+// (60x220x85 ILU(0), groups of 3: 483/499 -> 505/550 us).
+bool use_helper(const bilu_ctx* c, const HostTiled& ht, int R)
+{
+    if (R != 1 || c->helper == 2) return false;
+    if (c->helper == 1) return true;
+    return ht.group == 1 && ht.kmax >= 6;
+}
 
 // ----- templated launch helpers ---------------------------------------------
 #define BILU_SWITCH_B(bs, CALL)     \
@@ -290,10 +304,11 @@ bool launch_factor(int bs, int64_t first, int nrows, int lds, bilu_ctx* c, hipSt
                                              c->d_bad))
     }
     BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows,
-                                         c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_P, c->d_Dinv, c->d_bad))
+                                         c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_upd_ptr, c->d_upd_f, c->d_upd_g, c->d_P,
+                                         c->d_Dinv, c->d_bad))
 }
 
-// Update lists of Algorithm 4 for k_factor_rows_lds: for each pivot entry
+// Update lists of Algorithm 4 for k_factor_rows_lds and k_factor_rows: for each pivot entry
 // e = (i, p) of P (in entry order), the pairs (f, g) of entries (i, j), f > e,
 // and (p, j), g > diagonal of p, with the same column (f as a block index in
 // row i); and per L level the LDS bytes of its largest row.
@@ -325,7 +340,7 @@ bilu_status factor_plan(bilu_ctx* c)
                         ++g;
                     }
                 }
-                if (uf.size() > static_cast<size_t>(INT32_MAX)) return BILU_OK;   // lists too long: no LDS path
+                if (uf.size() > static_cast<size_t>(INT32_MAX)) return BILU_ERR_ALLOC;   // lists beyond int32 indices
             }
             uptr[e + 1] = static_cast<int32_t>(uf.size());
         }
@@ -751,7 +766,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         }
 #endif
         const size_t hlds = static_cast<size_t>(helped_lds_bytes(a.tile_rows, ht.group, c->h.bs, ht.kmax));
-        if (c->helper && R == 1 && static_cast<int64_t>(hlds) <= c->lds_max) {
+        if (use_helper(c, ht, R) && static_cast<int64_t>(hlds) <= c->lds_max) {
             // one workgroup of 2 * group wavefronts per group (or tile)
             a.ngroups = ht.group > 1 ? ht.ngroups : ht.ntiles;
             const int hblocks = persistent_blocks(c, a.ngroups, 1, std::max(1, 4 / ht.group));
@@ -1208,8 +1223,8 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         c->fuse_spmv = value != 0;
         return BILU_OK;
     case BILU_TUNE_HELPER:
-        if (value != 0 && value != 1) return BILU_ERR_ARG;
-        c->helper = value != 0;
+        if (value < 0 || value > 2) return BILU_ERR_ARG;
+        c->helper = value;
         return BILU_OK;
     case BILU_TUNE_LINE_SWEEP: {
         const int ny = value & 255, nz = value >> 8;
@@ -1279,28 +1294,30 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
     std::memset(out, 0, sizeof(*out));
     // tile_rows / group: the layout requests (0: by schedule simulation)
     struct Cand {
-        int mode, tile_rows, group, rhs_tile;
+        int mode, tile_rows, group, rhs_tile, helper;
     };
     std::vector<Cand> cands;
-    const Cand before{c->sweep_mode, c->tile_rows_req, c->tile_group_req, c->rhs_tile};
+    const Cand before{c->sweep_mode, c->tile_rows_req, c->tile_group_req, c->rhs_tile, c->helper};
     if (nrhs == 1) {
         // the preferred layouts, every group size of the best tile size, and
-        // the next single-tile sizes
+        // the next single-tile sizes, each with and without helper
+        // wavefronts
         auto add = [&](int rows, int group) {
             for (const Cand& k : cands)
                 if (k.mode == 2 && k.tile_rows == rows && k.group == group) return;
-            cands.push_back({2, rows, group, 0});
+            cands.push_back({2, rows, group, 0, 2});
+            cands.push_back({2, rows, group, 0, 1});
         };
         const auto ranked = rank_tile_layouts(c->h, c->h.rpc, c->lds_max, 0, 0);
         for (size_t i = 0; i < ranked.size() && i < 4; ++i) add(ranked[i].tile_rows, ranked[i].group);
         const int best_rows = ranked.front().tile_rows;
         for (int g = 1; g <= kGroupMax; ++g)
             if (tiled_lds_bytes(best_rows, g, c->h.bs) <= c->lds_max) add(best_rows, g);
-        cands.push_back({1, before.tile_rows, before.group, 0});
+        cands.push_back({1, before.tile_rows, before.group, 0, before.helper});
     } else {
-        cands.push_back({2, 0, 0, 0});
-        cands.push_back({2, 0, 1, 0});
-        for (int rt : {1, 4, 8}) cands.push_back({1, before.tile_rows, before.group, rt});
+        cands.push_back({2, 0, 0, 0, before.helper});
+        cands.push_back({2, 0, 1, 0, before.helper});
+        for (int rt : {1, 4, 8}) cands.push_back({1, before.tile_rows, before.group, rt, before.helper});
     }
     const size_t n = static_cast<size_t>(c->h.nb) * c->h.bs * nrhs;
     double* r = nullptr;
@@ -1314,7 +1331,8 @@ bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result
                        static_cast<int64_t>(n), r, 1.0);
     auto set = [&](const Cand& k) -> bilu_status {
         bilu_status e;
-        if ((e = bilu_tune(c, BILU_TUNE_SWEEP_MODE, k.mode)) || (e = bilu_tune(c, BILU_TUNE_RHS_TILE, k.rhs_tile)))
+        if ((e = bilu_tune(c, BILU_TUNE_SWEEP_MODE, k.mode)) || (e = bilu_tune(c, BILU_TUNE_RHS_TILE, k.rhs_tile)) ||
+            (e = bilu_tune(c, BILU_TUNE_HELPER, k.helper)))
             return e;
         return k.mode == 2 ? set_layout(c, k.tile_rows, k.group) : BILU_OK;
     };

@@ -32,17 +32,24 @@ __global__ void k_backfill(int64_t nP, int bb, const int32_t* __restrict__ PtoA,
 //   for p < i in row i, ascending:  A_ip <- A_ip * inv(A_pp)
 //       for j > p in row i with (p, j) in P:  A_ij <- A_ij - A_ip * A_pj
 //   then inv(A_ii) by Gauss-Jordan with partial pivoting inside the block.
+// The pairs (i, j), (p, j) of each pivot come from the host-built update
+// lists (as in k_factor_rows_lds); this kernel serves the rows whose blocks
+// do not fit the LDS budget and works on P in global memory.
 // ---------------------------------------------------------------------------
 template <int B>
 __global__ __launch_bounds__(64) void k_factor_rows(const int32_t* __restrict__ rows, int nrows,
                                                     const int32_t* __restrict__ Pp,
                                                     const int32_t* __restrict__ Pj,
                                                     const int32_t* __restrict__ Pdiag,
+                                                    const int32_t* __restrict__ upd_ptr,
+                                                    const int32_t* __restrict__ upd_f,
+                                                    const int32_t* __restrict__ upd_g,
                                                     double* __restrict__ P,
                                                     double* __restrict__ Dinv, int* bad_row)
 {
     constexpr int BB = B * B;
     constexpr int W = 2 * B;
+    constexpr int kPairs = 64 / BB > 0 ? 64 / BB : 1;
     __shared__ double sL[BB];
     __shared__ double sW[B * W];
     __shared__ int sPiv;
@@ -52,7 +59,11 @@ __global__ __launch_bounds__(64) void k_factor_rows(const int32_t* __restrict__ 
     const int t = threadIdx.x;
     const int r = t % B;
     const int c = t / B;
-    const int eEnd = Pp[i + 1];
+    const int sub = t / BB;
+    const int el = t - sub * BB;
+    const int er = el % B;
+    const int ec = el / B;
+    const int e0 = Pp[i];
     const int d = Pdiag[i];
     if (t == 0) sBad = 0;
     for (int e = Pp[i]; e < d; ++e) {
@@ -70,28 +81,17 @@ __global__ __launch_bounds__(64) void k_factor_rows(const int32_t* __restrict__ 
             sL[t] = tv;
         }
         __syncthreads();
-        int f = e + 1;
-        int g = Pdiag[p] + 1;
-        const int gEnd = Pp[p + 1];
-        while (f < eEnd && g < gEnd) {
-            const int cf = Pj[f];
-            const int cg = Pj[g];
-            if (cf == cg) {
-                if (t < BB) {
-                    const double* Apj = P + static_cast<int64_t>(g) * BB;
-                    double s = 0.0;
+        // the update pairs of pivot entry e (host-built lists, one target
+        // block per column j), 64 / BB of them at a time; each element is
+        // summed in the same order as one pair at a time
+        if (sub < kPairs)
+            for (int q = upd_ptr[e] + sub; q < upd_ptr[e + 1]; q += kPairs) {
+                const double* Apj = P + static_cast<int64_t>(upd_g[q]) * BB;
+                double sacc = 0.0;
 #pragma unroll
-                    for (int u = 0; u < B; ++u) s += sL[u * B + r] * Apj[c * B + u];
-                    P[static_cast<int64_t>(f) * BB + t] -= s;
-                }
-                ++f;
-                ++g;
-            } else if (cf < cg) {
-                ++f;
-            } else {
-                ++g;
+                for (int u = 0; u < B; ++u) sacc += sL[u * B + er] * Apj[ec * B + u];
+                P[static_cast<int64_t>(e0 + upd_f[q]) * BB + el] -= sacc;
             }
-        }
         __syncthreads();
     }
     // Gauss-Jordan on [U_ii | I], row-major in LDS.
@@ -187,6 +187,11 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
     const int t = threadIdx.x;
     const int r = t % B;
     const int c = t / B;
+    constexpr int kPairs = 64 / BB > 0 ? 64 / BB : 1;
+    const int sub = t / BB;
+    const int el = t - sub * BB;
+    const int er = el % B;
+    const int ec = el / B;
     double* sRow = smem;
     double* sD = sRow + nrow * BB;
     double* sU = sD + dk * BB;
@@ -223,12 +228,15 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
         __syncthreads();
         if (t < BB) sRow[k * BB + t] = tv;
         __syncthreads();
-        if (t < BB)
-            for (int q = sQ[k]; q < sQ[k + 1]; ++q) {
+        // the pairs of pivot k update distinct blocks of the row (one per
+        // column j): 64 / BB pairs at a time, thread (sub, el) on element el
+        // of pair sub, each element summed in the same order as one at a time
+        if (sub < kPairs)
+            for (int q = sQ[k] + sub; q < sQ[k + 1]; q += kPairs) {
                 double acc = 0.0;
 #pragma unroll
-                for (int u = 0; u < B; ++u) acc += sRow[k * BB + u * B + r] * sU[q * BB + c * B + u];
-                sRow[sF[q] * BB + t] -= acc;
+                for (int u = 0; u < B; ++u) acc += sRow[k * BB + u * B + er] * sU[q * BB + ec * B + u];
+                sRow[sF[q] * BB + el] -= acc;
             }
         __syncthreads();
     }

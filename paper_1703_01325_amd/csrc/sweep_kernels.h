@@ -9,6 +9,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <climits>
 #include <cstdint>
 
 #include "bilu_internal.h"
@@ -664,26 +665,40 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
         for (int c = 0; c < B; ++c) acc -= widen(s.f[k][c]) * (local ? lv[k * B + c] : xg[k * B + c]);
     }
     if (s.w > KMAX) {
+        // slots past the first KMAX, XB at a time: their codes in one round
+        // trip, then factor values and dependency values (LDS, or other
+        // tiles' values polled together) in the next; products subtracted
+        // in slot order, as for the first KMAX
+        constexpr int XB = B <= 2 ? 8 : (16 / B > 2 ? 16 / B : 2);
         const T* __restrict__ vals = static_cast<const T*>(a.vals);
-        for (int k = KMAX; k < s.w; ++k) {
-            const int64_t sl = s.off + static_cast<int64_t>(k) * RPC;
-            const int code = a.deps[sl + qc];
-            double xv[B];
-            if (code < 0) {
+        const char* ob = reinterpret_cast<const char*>(a.out);
+        for (int k0 = KMAX; k0 < s.w; k0 += XB) {
+            int code[XB];
 #pragma unroll
-                for (int c = 0; c < B; ++c)
-                    xv[c] = *reinterpret_cast<const double*>(lds + (static_cast<uint32_t>(code) & 0x7fffffffu) + c * 8u);
-            } else {
-                const char* ob = reinterpret_cast<const char*>(a.out);
+            for (int j = 0; j < XB; ++j)
+                code[j] = k0 + j < s.w ? a.deps[s.off + static_cast<int64_t>(k0 + j) * RPC + qc] : INT_MIN;
+            double xv[XB * B];
+            T fv[XB][B];
 #pragma unroll
-                for (int c = 0; c < B; ++c)
-                    xv[c] = coherent_load(reinterpret_cast<const double*>(ob + cm.at(static_cast<uint32_t>(code), c)));
-                const int one[1] = {code};
-                await_tile<1, B, MULTI>(xv, one, a.out, cm, a.spin_limit, a.status);
+            for (int j = 0; j < XB; ++j) {
+                const int k = k0 + j < s.w ? k0 + j : k0;
+                const int64_t vbase = (s.off + static_cast<int64_t>(k) * RPC) * BB + r * RPC + qc;
+                const uint32_t lb = code[j] < 0 ? static_cast<uint32_t>(code[j]) & 0x7fffffffu : 0u;
+                const uint32_t gb = code[j] >= 0 ? static_cast<uint32_t>(code[j]) : 0u;
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    fv[j][c] = vals[vbase + c * B * RPC];
+                    const double lx = *reinterpret_cast<const double*>(lds + lb + c * 8u);
+                    const double gx = *reinterpret_cast<const double*>(ob + cm.at(gb, c));
+                    xv[j * B + c] = code[j] < 0 ? lx : gx;
+                }
             }
-            const int64_t vbase = sl * BB + r * RPC + qc;
+            await_tile<XB, B, MULTI>(xv, code, a.out, cm, a.spin_limit, a.status);
 #pragma unroll
-            for (int c = 0; c < B; ++c) acc -= widen(vals[vbase + c * B * RPC]) * xv[c];
+            for (int j = 0; j < XB; ++j)
+                if (k0 + j < s.w)
+#pragma unroll
+                    for (int c = 0; c < B; ++c) acc -= widen(fv[j][c]) * xv[j * B + c];
         }
     }
     const double v = publishable(acc);
@@ -826,16 +841,26 @@ __device__ __forceinline__ void run_helper(const TiledArgs& a, int t, const ColM
     meta_at(0, cur);
     for (int i = 0; i < nch; ++i) {
         double v[KMAX * B];
+        // a chunk whose dependencies all lie in the group needs no load
+        bool any = false;
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const uint32_t xb = cur.code[k] >= 0 ? static_cast<uint32_t>(cur.code[k]) : 0u;
+        for (int k = 0; k < KMAX; ++k) any |= cur.code[k] >= 0;
+        const bool wave_any = __any(any ? 1 : 0) != 0;
+        if (wave_any) {
 #pragma unroll
-            for (int c = 0; c < B; ++c)
-                v[k * B + c] = coherent_load(reinterpret_cast<const double*>(
-                    reinterpret_cast<const char*>(a.out) + cm.at(xb, c)));
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t xb = cur.code[k] >= 0 ? static_cast<uint32_t>(cur.code[k]) : 0u;
+#pragma unroll
+                for (int c = 0; c < B; ++c)
+                    v[k * B + c] = coherent_load(reinterpret_cast<const double*>(
+                        reinterpret_cast<const char*>(a.out) + cm.at(xb, c)));
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < KMAX * B; ++j) v[j] = 0.0;
         }
         meta_at(i + 1, nxt);
-        await_tile<KMAX, B, MULTI>(v, cur.code, a.out, cm, a.spin_limit, a.status);
+        if (wave_any) await_tile<KMAX, B, MULTI>(v, cur.code, a.out, cm, a.spin_limit, a.status);
         // the entry's previous chunk, i - kHelpRing, is finished
         await_count(prog, i - kHelpRing + 1, a.spin_limit, a.status);
         double* dst = ring + (i % kHelpRing) * (KMAX * B * 64) + lane;
