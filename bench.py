@@ -25,12 +25,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ILU(k) apply+SpMV HBM GB/s & solves/s to 1e-8 res; FP64 vs FP32-factor vs multi-RHS"
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1703_01325_amd", "csrc", "kernels.h")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1703_01325_amd", "csrc", f)
+               for f in ("kernels.h", "sweep_kernels.h", "kernels_batch.h")]
 
 
 def kernels_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the device kernel sources: a stored traffic figure is used only
+    while the kernels it was measured on are unchanged."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 WORKLOADS = {

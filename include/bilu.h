@@ -285,7 +285,9 @@ enum {
                                  hands them over through LDS, so the tile's own
                                  loads are prefetches only.  0 (default): automatic,
                                  helpers for ungrouped tiles whose rows load six or
-                                 more dependency slots ahead; 1: always; 2: never.
+                                 more dependency slots ahead; 1: always (tile groups
+                                 of at most 2 tiles; larger groups run without);
+                                 2: never.
                                  bilu_autotune times both                           */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each

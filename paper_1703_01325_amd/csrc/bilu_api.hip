@@ -239,7 +239,7 @@ bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; 
 // (60x220x85 ILU(0), groups of 3: 483/499 -> 505/550 us).
 bool use_helper(const bilu_ctx* c, const HostTiled& ht, int R)
 {
-    if (R != 1 || c->helper == 2) return false;
+    if (R != 1 || c->helper == 2 || ht.group > kHelpGroupMax) return false;
     if (c->helper == 1) return true;
     return ht.group == 1 && ht.kmax >= 6;
 }
@@ -1547,10 +1547,14 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
 }
 
 // Restarted right-preconditioned GMRES(m), one right-hand side: Arnoldi with
-// modified Gram-Schmidt on the device, Givens rotations and the small
-// triangular solve on the host (one readback of a Hessenberg column per
-// Arnoldi step), x += M^{-1} V y at the end of each cycle, exit on the true
-// residual at the start of a cycle.  maxit bounds the Arnoldi steps.
+// modified Gram-Schmidt, the Givens rotations and the small triangular
+// solve all on the device, x += M^{-1} V y at the end of each cycle, exit on
+// the true residual at the start of a cycle.  Inside a cycle the host
+// queues Arnoldi step j and then waits only for step j - 1, whose flag
+// (mapped host memory) says whether the cycle goes on; a step queued after
+// the cycle stopped is gated off.  One host read per cycle (the true
+// residual norm and the cycle's step count).  maxit bounds the Arnoldi
+// steps.
 static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double* x, const bilu_solve_opts* o,
                          bilu_rhs_info* info, int tr, hipStream_t s)
 {
@@ -1558,13 +1562,14 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
     const int m = o->restart;
     bilu_status st = ensure_krylov(c, 1, m + 4);
     if (st) return st;
+    if ((st = ensure_step_host(c))) return st;
     double* V = c->d_kv;                                   // (m+1) x n basis
     double* w = V + static_cast<size_t>(m + 1) * n;
     double* z = w + n;
     double* u = z + n;
-    // (m+1) x m Hessenberg matrix, column j contiguous, + coef + y; kept in
-    // the context across solves
-    const size_t hneed = static_cast<size_t>(m + 1) * m + 1 + m;
+    // kept in the context across solves: the (m+1) x m Hessenberg matrix
+    // (column j contiguous), coef, y, the rotations, g and the cycle flags
+    const size_t hneed = static_cast<size_t>(m + 1) * m + 1 + 3 * static_cast<size_t>(m) + (m + 1) + 2;
     if (c->gm_cap < hneed) {
         dfree(c, c->d_gmh);
         c->d_gmh = nullptr;
@@ -1574,96 +1579,90 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
     }
     double* dH = c->d_gmh;
     double* coef = dH + static_cast<size_t>(m + 1) * m;
-    double* dy = coef + 1;
+    dev::GmView gv;
+    gv.H = dH;
+    gv.y = coef + 1;
+    gv.cs = gv.y + m;
+    gv.sn = gv.cs + m;
+    gv.g = gv.sn + m;
+    gv.flags = reinterpret_cast<int*>(gv.g + m + 1);
+    gv.m = m;
+    const int* g_active = gv.flags + dev::GM_ACTIVE;
     double* part = c->d_part;
     const int eg = grid_for(n);
     const dim3 rb(dev::kRedBlocks), rt(dev::kThreads);
-    auto apply = [&](const double* in, double* out) { return do_apply(c, in, out, 1, tr != 0, s); };
-    auto spmv = [&](const double* in, double* out) { return do_spmv(c, Ax, in, out, 1, tr, s); };
-    auto fetch = [&](double* host, const double* devp, size_t count) -> bilu_status {
-        CK(hipMemcpyAsync(host, devp, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    const double tol_abs_factor = o->rtol;
+    struct Cycle {
+        double beta;
+        int flags[dev::GM_NFLAGS];
+    };
+    Cycle* hc = reinterpret_cast<Cycle*>(c->h_state);      // pinned host memory (KState-sized)
+    static_assert(sizeof(Cycle) <= sizeof(KState), "cycle readback fits the pinned state");
+    auto fetch_cycle = [&]() -> bilu_status {
+        CK(hipMemcpyAsync(&hc->beta, dH, sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(hc->flags, gv.flags, sizeof(hc->flags), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         return BILU_OK;
     };
 
     hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n, x, 0.0);
+    hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(dev::GM_NFLAGS), gv.flags, 0);
     hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, 1, b, b, part, dev::SL_BB, nullptr);
-    hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_BB, dH, coef, 1);
-    double bnorm = 0.0;
-    if ((st = fetch(&bnorm, dH, 1))) return st;
-    std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 1);
+    hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_BB, dH, coef, 1, nullptr);
+    if ((st = fetch_cycle())) return st;
+    const double bnorm = hc->beta;
+    const double tol = tol_abs_factor * bnorm;
     int total = 0, cycles = 0, status = BILU_NOT_CONVERGED;
     double rres = bnorm;
     if (bnorm == 0.0) status = BILU_OK;
     while (status == BILU_NOT_CONVERGED) {
-        if ((st = spmv(x, w))) break;
+        if ((st = do_spmv(c, Ax, x, w, 1, tr, s))) break;
         hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE, nullptr);
-        hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1);
-        double beta = 0.0;
-        if ((st = fetch(&beta, dH, 1))) break;
+        hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1, nullptr);
+        if ((st = fetch_cycle())) break;
+        const double beta = hc->beta;
+        if (cycles > 0) total += hc->flags[dev::GM_STEPS];
         rres = beta;
+        if (cycles > 0 && hc->flags[dev::GM_BREAKDOWN]) { status = BILU_BREAKDOWN; break; }
         if (!std::isfinite(beta)) { status = BILU_NONFINITE; break; }
-        if (beta <= o->rtol * bnorm) { status = BILU_OK; break; }
+        if (beta <= tol) { status = BILU_OK; break; }
         if (total >= o->maxit) break;
-        hipLaunchKernelGGL(dev::k_gm_scale, dim3(eg), dim3(256), 0, s, n, w, coef, V);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int jend = 0;
-        for (int j = 0; j < m; ++j) {
+        const int steps = std::min(m, o->maxit - total);
+        hipLaunchKernelGGL(dev::k_gm_scale, dim3(eg), dim3(256), 0, s, n, w, coef, V, nullptr);
+        hipLaunchKernelGGL(dev::k_gm_begin, dim3(1), dim3(64), 0, s, gv, steps);
+        for (int j = 0; j < steps; ++j) {
             double* vj = V + static_cast<size_t>(j) * n;
             double* hcol = dH + static_cast<size_t>(j) * (m + 1);
-            if ((st = do_apply_spmv(c, Ax, vj, z, w, 1, tr != 0, s))) break;
-            hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, nullptr, coef, V, part, dev::SL_RHO);
-            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol, coef, 0);
+            if ((st = do_apply_spmv(c, Ax, vj, z, w, 1, tr != 0, s, g_active))) break;
+            hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, nullptr, coef, V, part, dev::SL_RHO, g_active);
+            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol, coef, 0, g_active);
             for (int i = 1; i <= j; ++i) {
                 hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, V + static_cast<size_t>(i - 1) * n, coef,
-                                   V + static_cast<size_t>(i) * n, part, dev::SL_RHO);
-                hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol + i, coef, 0);
+                                   V + static_cast<size_t>(i) * n, part, dev::SL_RHO, g_active);
+                hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol + i, coef, 0,
+                                   g_active);
             }
-            hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, vj, coef, nullptr, part, dev::SL_RHO);
-            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol + j + 1, coef, 1);
-            hipLaunchKernelGGL(dev::k_gm_scale, dim3(eg), dim3(256), 0, s, n, w, coef, vj + n);
+            hipLaunchKernelGGL(dev::k_gm_mgs, rb, rt, 0, s, n, w, vj, coef, nullptr, part, dev::SL_RHO, g_active);
+            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_RHO, hcol + j + 1, coef, 1,
+                               g_active);
+            hipLaunchKernelGGL(dev::k_gm_scale, dim3(eg), dim3(256), 0, s, n, w, coef, vj + n, g_active);
+            hipLaunchKernelGGL(dev::k_gm_givens, dim3(1), dim3(64), 0, s, gv, j, steps, tol, c->d_flags + (j & 1));
             if (hipGetLastError() != hipSuccess) { st = BILU_ERR_HIP; break; }
-            if ((st = fetch(col.data(), hcol, static_cast<size_t>(j) + 2))) break;
-            for (int i = 0; i <= j + 1; ++i) H[static_cast<size_t>(i) * m + j] = col[i];
-            for (int i = 0; i < j; ++i) {
-                const double a1 = H[static_cast<size_t>(i) * m + j], a2 = H[static_cast<size_t>(i + 1) * m + j];
-                H[static_cast<size_t>(i) * m + j] = cs[i] * a1 + sn[i] * a2;
-                H[static_cast<size_t>(i + 1) * m + j] = -sn[i] * a1 + cs[i] * a2;
+            if (hipEventRecord(c->step_ev[j & 1], s) != hipSuccess) { st = BILU_ERR_HIP; break; }
+            if (j >= 1) {
+                // step j - 1 has written its flag once its event has completed
+                if (hipEventSynchronize(c->step_ev[(j - 1) & 1]) != hipSuccess) { st = BILU_ERR_HIP; break; }
+                if (__hip_atomic_load(c->h_flags + ((j - 1) & 1), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == 0)
+                    break;
             }
-            const double a1 = H[static_cast<size_t>(j) * m + j], a2 = H[static_cast<size_t>(j + 1) * m + j];
-            const double rr = std::hypot(a1, a2);
-            if (rr == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-            else { cs[j] = a1 / rr; sn[j] = a2 / rr; }
-            H[static_cast<size_t>(j) * m + j] = cs[j] * a1 + sn[j] * a2;
-            H[static_cast<size_t>(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++total;
-            jend = j + 1;
-            if (std::fabs(g[j + 1]) <= o->rtol * bnorm || total >= o->maxit || col[j + 1] == 0.0) break;
         }
         if (st) break;
-        for (int i = jend - 1; i >= 0; --i) {
-            double sum = g[i];
-            for (int k = i + 1; k < jend; ++k) sum -= H[static_cast<size_t>(i) * m + k] * y[k];
-            if (H[static_cast<size_t>(i) * m + i] == 0.0) { status = BILU_BREAKDOWN; break; }
-            y[i] = sum / H[static_cast<size_t>(i) * m + i];
-        }
-        if (status == BILU_BREAKDOWN) break;
-        if (hipMemcpyAsync(dy, y.data(), static_cast<size_t>(jend) * sizeof(double), hipMemcpyHostToDevice, s) !=
-            hipSuccess) { st = BILU_ERR_HIP; break; }
-        hipLaunchKernelGGL(dev::k_gm_combine, dim3(eg), dim3(256), 0, s, n, jend, V, dy, u);
-        if ((st = apply(u, z))) break;
+        hipLaunchKernelGGL(dev::k_gm_solve_y, dim3(1), dim3(64), 0, s, gv);
+        hipLaunchKernelGGL(dev::k_gm_combine, dim3(eg), dim3(256), 0, s, n, m, V, gv.y, u,
+                           gv.flags + dev::GM_JEND);
+        if ((st = do_apply(c, u, z, 1, tr != 0, s))) break;
         hipLaunchKernelGGL(dev::k_axpy1, dim3(eg), dim3(256), 0, s, n, x, z);
         ++cycles;
-    }
-    if (!st && status == BILU_BREAKDOWN) {
-        if ((st = spmv(x, w)) == BILU_OK) {
-            hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE, nullptr);
-            hipLaunchKernelGGL(dev::k_gm_h, dim3(1), dim3(64), 0, s, part, dev::SL_TRUE, dH, coef, 1);
-            st = fetch(&rres, dH, 1);
-        }
     }
     int sweep_err = 0;
     if (!st) {

@@ -118,8 +118,10 @@ inline int64_t tiled_lds_bytes(int tile_rows, int group, int bs)
 }
 
 // Chunks held by the LDS ring through which a helper wavefront hands its
-// member the values of other tiles.
+// member the values of other tiles, and the largest tile group that runs
+// with helpers.
 constexpr int kHelpRing = 4;
+constexpr int kHelpGroupMax = 2;
 
 // LDS bytes of a tile-group workgroup with helper wavefronts: the member
 // tiles' rows, the zero row, progress and delivered counts, and each

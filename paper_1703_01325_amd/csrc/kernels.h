@@ -925,8 +925,10 @@ __global__ void k_bicg_restart(int64_t n, int R, const double* __restrict__ w, d
 __global__ __launch_bounds__(kThreads) void k_gm_mgs(int64_t n, double* __restrict__ w,
                                                      const double* __restrict__ vprev,
                                                      const double* __restrict__ coef,
-                                                     const double* __restrict__ vnext, double* part, int slot)
+                                                     const double* __restrict__ vnext, double* part, int slot,
+                                                     const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     const RedIdx ri = red_index(1);
     double acc = 0.0;
     const double h = vprev ? *coef : 0.0;
@@ -944,8 +946,10 @@ __global__ __launch_bounds__(kThreads) void k_gm_mgs(int64_t n, double* __restri
 
 // h = sum of partials; mode 0: *hout = h, *coef = h (next projection);
 // mode 1: h = sqrt(sum), *hout = h, *coef = 1/h (normalisation, 0 if h == 0).
-__global__ __launch_bounds__(64) void k_gm_h(const double* part, int slot, double* hout, double* coef, int mode)
+__global__ __launch_bounds__(64) void k_gm_h(const double* part, int slot, double* hout, double* coef, int mode,
+                                             const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     double h = sum_partials(part, slot, 0);
     if (threadIdx.x != 0) return;
     if (mode == 1) {
@@ -958,23 +962,113 @@ __global__ __launch_bounds__(64) void k_gm_h(const double* part, int slot, doubl
 }
 
 __global__ void k_gm_scale(int64_t n, const double* __restrict__ w, const double* __restrict__ coef,
-                           double* __restrict__ v)
+                           double* __restrict__ v, const int* gate = nullptr)
 {
+    if (gated_off(gate)) return;
     const double s = *coef;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x)
         v[g] = w[g] * s;
 }
 
-// u = sum_k y_k v_k over the first m basis vectors (fixed order per entry)
+// u = sum_k y_k v_k over the first m basis vectors (fixed order per entry);
+// m is read from *mcount when given
 __global__ void k_gm_combine(int64_t n, int m, const double* __restrict__ V, const double* __restrict__ y,
-                             double* __restrict__ u)
+                             double* __restrict__ u, const int* mcount = nullptr)
 {
+    if (mcount) m = *mcount;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         double s = 0.0;
         for (int k = 0; k < m; ++k) s += y[k] * V[static_cast<int64_t>(k) * n + g];
         u[g] = s;
+    }
+}
+
+// Device-side state of a GMRES(m) cycle: the Givens rotations and the
+// rotated right-hand side g of the least-squares problem, beside the
+// Hessenberg matrix (column j contiguous, m + 1 entries).
+enum { GM_ACTIVE = 0, GM_JEND = 1, GM_BREAKDOWN = 2, GM_STEPS = 3, GM_NFLAGS = 4 };
+struct GmView {
+    double* H;          // (m+1) x m, column-major
+    double* cs;         // [m]
+    double* sn;         // [m]
+    double* g;          // [m+1]
+    double* y;          // [m]
+    int* flags;         // [GM_NFLAGS]
+    int m;
+};
+
+// Start of a cycle: g = (beta, 0, ...), beta = H[0] as left there by the
+// true-residual norm; the cycle may take `steps` Arnoldi steps.
+__global__ void k_gm_begin(GmView v, int steps)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    v.g[0] = v.H[0];
+    for (int i = 1; i <= v.m; ++i) v.g[i] = 0.0;
+    v.flags[GM_ACTIVE] = steps > 0 ? 1 : 0;
+    v.flags[GM_JEND] = 0;
+    v.flags[GM_BREAKDOWN] = 0;
+    v.flags[GM_STEPS] = 0;
+}
+
+// After Arnoldi step j (column j of H complete): the earlier rotations on
+// column j, the new rotation that zeroes H[j+1][j], g rotated.  The cycle
+// stops when |g[j+1]| <= tol, when H[j+1][j] was 0 (the Krylov space is
+// invariant) or after `steps` steps; the step count and "still active" are
+// recorded, and the latter copied to *host_flag (mapped host memory).
+__global__ void k_gm_givens(GmView v, int j, int steps, double tol, int* host_flag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!v.flags[GM_ACTIVE]) {
+        if (host_flag) __hip_atomic_store(host_flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return;
+    }
+    double* col = v.H + static_cast<int64_t>(j) * (v.m + 1);
+    const double hnext = col[j + 1];
+    for (int i = 0; i < j; ++i) {
+        const double a1 = col[i], a2 = col[i + 1];
+        col[i] = v.cs[i] * a1 + v.sn[i] * a2;
+        col[i + 1] = -v.sn[i] * a1 + v.cs[i] * a2;
+    }
+    const double a1 = col[j], a2 = col[j + 1];
+    const double rr = hypot(a1, a2);
+    if (rr == 0.0) {
+        v.cs[j] = 1.0;
+        v.sn[j] = 0.0;
+    } else {
+        v.cs[j] = a1 / rr;
+        v.sn[j] = a2 / rr;
+    }
+    col[j] = v.cs[j] * a1 + v.sn[j] * a2;
+    col[j + 1] = 0.0;
+    v.g[j + 1] = -v.sn[j] * v.g[j];
+    v.g[j] = v.cs[j] * v.g[j];
+    v.flags[GM_JEND] = j + 1;
+    v.flags[GM_STEPS] = j + 1;
+    const bool stop = fabs(v.g[j + 1]) <= tol || j + 1 >= steps || hnext == 0.0;
+    if (stop) v.flags[GM_ACTIVE] = 0;
+    if (host_flag) __hip_atomic_store(host_flag, stop ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// End of a cycle: y from the triangular system H[0:k, 0:k] y = g[0:k],
+// k = the cycle's step count; a zero diagonal entry records a breakdown
+// and leaves no update (step count set to 0).
+__global__ void k_gm_solve_y(GmView v)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int k = v.flags[GM_JEND];
+    const int ld = v.m + 1;
+    for (int i = k - 1; i >= 0; --i) {
+        double sum = v.g[i];
+        for (int q = i + 1; q < k; ++q) sum -= v.H[static_cast<int64_t>(q) * ld + i] * v.y[q];
+        const double d = v.H[static_cast<int64_t>(i) * ld + i];
+        if (d == 0.0) {
+            v.flags[GM_BREAKDOWN] = 1;
+            v.flags[GM_JEND] = 0;
+            return;
+        }
+        v.y[i] = sum / d;
     }
 }
 

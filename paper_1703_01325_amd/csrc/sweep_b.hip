@@ -59,7 +59,7 @@ bool tiled_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledAr
 template <int B, typename T, bool FUSE>
 bool helped_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
 {
-    if (a.group < 1 || a.group > kGroupMax) return false;
+    if (a.group < 1 || a.group > kHelpGroupMax) return false;
     const dim3 threads(128 * a.group);
     if constexpr (B >= 5) {
         if (kmax != 3) return false;

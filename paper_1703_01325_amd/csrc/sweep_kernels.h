@@ -669,7 +669,7 @@ __device__ __forceinline__ void tile_compute(const TiledArgs& a, int lo, int qc,
         // trip, then factor values and dependency values (LDS, or other
         // tiles' values polled together) in the next; products subtracted
         // in slot order, as for the first KMAX
-        constexpr int XB = B <= 2 ? 8 : (16 / B > 2 ? 16 / B : 2);
+        constexpr int XB = B == 1 ? 16 : B == 2 ? 8 : (16 / B > 2 ? 16 / B : 2);
         const T* __restrict__ vals = static_cast<const T*>(a.vals);
         const char* ob = reinterpret_cast<const char*>(a.out);
         for (int k0 = KMAX; k0 < s.w; k0 += XB) {
@@ -902,11 +902,13 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
 // every row a group reads from outside lies in a group with a smaller
 // ticket, so the persistent launch drains.
 // HELP: a.group helper wavefronts follow the a.group members (workgroup of
-// 2 * a.group wavefronts; a.group may then be 1, with a.ngroups the number
-// of tiles); LDS after the progress counts: kGroupMax delivered counts, then
-// the members' rings.
+// 2 * a.group wavefronts, a.group <= kHelpGroupMax; a.group may then be 1,
+// with a.ngroups the number of tiles); LDS after the progress counts:
+// kGroupMax delivered counts, then the members' rings.  At most four
+// wavefronts per workgroup keep each wavefront's full register budget (one
+// per SIMD), which the members' prefetch rings need.
 template <int B, typename T, bool FUSE, int KMAX, bool MULTI, bool HELP>
-__global__ __launch_bounds__(64 * kGroupMax * (HELP ? 2 : 1)) void k_sweep_grouped(TiledArgs a)
+__global__ __launch_bounds__(HELP ? 128 * kHelpGroupMax : 64 * kGroupMax) void k_sweep_grouped(TiledArgs a)
 {
     extern __shared__ double group_vals[];   // [group*tile_rows + 1][B], then kGroupMax progress counts
     __shared__ int s_ticket;

@@ -72,8 +72,11 @@ def write_traffic(fetch_db, write_db, cfetch_db, cwrite_db, substring, alg_bytes
     fetch = f_kib * 1024.0 * sf
     write = w_kib * 1024.0 * sw
     here = os.path.dirname(os.path.abspath(__file__))
-    with open(os.path.join(here, "csrc", "kernels.h"), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    hsh = hashlib.sha256()
+    for name in ("kernels.h", "sweep_kernels.h", "kernels_batch.h"):     # as bench.kernels_hash
+        with open(os.path.join(here, "csrc", name), "rb") as fh:
+            hsh.update(fh.read())
+    sha = hsh.hexdigest()[:16]
     rec = {"kernel": substring, "workload": workload, "dispatches": [nf, nw],
            "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
            "copy_scale_fetch": sf, "copy_scale_write": sw,
