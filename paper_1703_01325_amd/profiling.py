@@ -32,7 +32,10 @@ def kernel_table(db):
 def counter_avg(db, counter, selector):
     """Average of `counter` over the dispatches whose kernel name contains
     the selector; "name@even" / "name@odd" keep every other such dispatch
-    (two sweeps that share one kernel and strictly alternate)."""
+    (two sweeps that share one kernel and strictly alternate); "name@run"
+    keeps the dispatches that did work (a value of at least a tenth of the
+    largest), leaving out launches that a solver's device flag turned into
+    no-ops (the gated true-residual SpMV, the step queued after the exit)."""
     substring, _, parity = selector.partition("@")
     con = sqlite3.connect(db)
     rows = con.execute("select kernel_name, value from counters_collection where counter_name = ? "
@@ -43,6 +46,9 @@ def counter_avg(db, counter, selector):
         vals = vals[0::2]
     elif parity == "odd":
         vals = vals[1::2]
+    elif parity == "run" and vals:
+        top = max(vals)
+        vals = [v for v in vals if v >= 0.1 * top]
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
 
 
