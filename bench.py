@@ -209,8 +209,10 @@ def run_poisson_table(args, n=120, sizes=(1, 2, 4, 8), levels=(0, 1, 2, 3), rtol
 def run_batch(nsys=256, reps=5):
     """The uneven batch: nsys independent systems (sides U{8..40}, b from
     {2,3,4,6,8}, ILU(0)), preconditioned and solved together.  Setup (host
-    analysis, factorisation) is outside the timed solve; the apply + SpMV
-    pair over the whole batch is timed with events on the launch stream."""
+    analysis, factorisation, the device-timed choice of the members' tile
+    sizes) is outside the timed solve; the apply + SpMV pair over the whole
+    batch is timed with events on the launch stream, with the default tiles
+    and with the chosen ones."""
     import numpy as np
     import torch
 
@@ -229,6 +231,23 @@ def run_batch(nsys=256, reps=5):
     factor_s = time.perf_counter() - t0
     xs = torch.from_numpy(np.concatenate([m.xstar for m in members])).cuda()
     b = B.spmv(xs)
+    z = torch.empty_like(b)
+    y = torch.empty_like(b)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def pair_time():
+        B.apply(b, out=z)
+        B.spmv(z, out=y)
+        ev[0].record()
+        for _ in range(reps):
+            B.apply(b, out=z)
+            B.spmv(z, out=y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return 1e3 * ev[0].elapsed_time(ev[1]) / reps
+
+    default_pair_us = pair_time()
+    tune = B.autotune()                           # members' tile sizes, device-timed
     x, st, info = B.solve(b, rtol=1e-8)          # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,16 +257,7 @@ def run_batch(nsys=256, reps=5):
     bad = [i for i in info if i[0] != 0 or not (i[2] <= 1e-8)]
     if st != 0 or bad:
         raise RuntimeError(f"batch solve did not reach the 1e-8 true residual: status {st}, members {bad[:4]}")
-    z = torch.empty_like(b)
-    y = torch.empty_like(b)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record()
-    for _ in range(reps):
-        B.apply(b, out=z)
-        B.spmv(z, out=y)
-    ev[1].record()
-    torch.cuda.synchronize()
-    pair_us = 1e3 * ev[0].elapsed_time(ev[1]) / reps
+    pair_us = pair_time()
     pair_bytes = 0
     for s, m in enumerate(members):
         ab = algorithmic_bytes(B.member(s).info(), m.bs)
@@ -255,7 +265,9 @@ def run_batch(nsys=256, reps=5):
     out = {"systems": nsys, "unknowns": int(B.n), "analyze_s": analyze_s, "factor_s": factor_s,
            "solve_s": solve_s, "solves_per_s": nsys / solve_s, "status": int(st),
            "max_iters": max(i[1] for i in info), "max_relres": max(i[2] for i in info),
-           "apply_spmv_pair_us": pair_us, "apply_spmv_GBps": pair_bytes / pair_us / 1e3}
+           "apply_spmv_pair_us": pair_us, "apply_spmv_GBps": pair_bytes / pair_us / 1e3,
+           "tile_scale": tune["tile_scale"], "default_tiles_pair_us": default_pair_us,
+           "default_tiles_GBps": pair_bytes / default_pair_us / 1e3}
     B.close()
     return out
 

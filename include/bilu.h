@@ -412,6 +412,23 @@ bilu_status bilu_batch_spmv(bilu_batch* batch, const double* x, double* y, hipSt
 bilu_status bilu_batch_solve(bilu_batch* batch, const double* b, double* x, const bilu_solve_opts* opts,
                              bilu_rhs_info* info, hipStream_t stream);
 
+/* Device-timed choice of the members' row-tile sizes for the batch sweeps:
+ * every member's tiles are rebuilt with its default tile rows times a
+ * common scale (0.25, 0.5, 1, 2, 4; at least one chunk, at most 64 KiB of
+ * LDS per tile), the batch apply + SpMV pair is timed with HIP events on
+ * `stream` (three pairs after one untimed), and the fastest scale is kept.
+ * Results of apply, SpMV and solve do not depend on the choice.  Requires
+ * factors (bilu_batch_factor); allocates three batch vectors for the time of
+ * the call.  BILU_ERR_TIMEOUT if a timed sweep hit its spin limit. */
+typedef struct bilu_batch_tune_info {
+    double tile_scale;   /* chosen scale of the members' tile rows              */
+    double pair_us;      /* apply + SpMV over the batch with it, microseconds   */
+    double default_us;   /* the same with the tiles in force before the call    */
+    int candidates;      /* scales timed besides the one in force               */
+    int reserved;
+} bilu_batch_tune_info;
+bilu_status bilu_batch_autotune(bilu_batch* batch, hipStream_t stream, bilu_batch_tune_info* info);
+
 /* Member s as a single-system context (owned by the batch: do not destroy),
  * e.g. for bilu_get_factors. */
 bilu_status bilu_batch_member(bilu_batch* batch, int s, bilu_ctx** ctx);

@@ -32,7 +32,7 @@ EXPORTS = (
     "bilu_tune", "bilu_autotune", "bilu_check", "bilu_timing", "bilu_timing_read",
     "bilu_destroy", "bilu_status_string",
     "bilu_batch_create", "bilu_batch_offsets", "bilu_batch_factor", "bilu_batch_apply",
-    "bilu_batch_spmv", "bilu_batch_solve", "bilu_batch_member", "bilu_batch_destroy",
+    "bilu_batch_spmv", "bilu_batch_solve", "bilu_batch_autotune", "bilu_batch_member", "bilu_batch_destroy",
 )
 K_SWEEP_L, K_SWEEP_U, K_SWEEP_UT, K_SWEEP_LT, K_SPMV, K_FACTOR, K_SPLIT, K_SWEEP_U_SPMV, K_COUNT = range(9)
 K_NAMES = ("sweep_L", "sweep_U", "sweep_UT", "sweep_LT", "spmv", "factor", "split", "sweep_U_spmv")
@@ -65,6 +65,11 @@ class TuneResult(ct.Structure):
     _fields_ = [("sweep_mode", ct.c_int), ("tile_rows", ct.c_int), ("rhs_tile", ct.c_int),
                 ("candidates", ct.c_int), ("apply_us", ct.c_double), ("default_us", ct.c_double),
                 ("tile_group", ct.c_int)]
+
+
+class BatchTuneInfo(ct.Structure):
+    _fields_ = [("tile_scale", ct.c_double), ("pair_us", ct.c_double), ("default_us", ct.c_double),
+                ("candidates", ct.c_int), ("reserved", ct.c_int)]
 
 
 class SysDesc(ct.Structure):
@@ -113,6 +118,7 @@ def _load():
     L.bilu_batch_apply.argtypes = [VP, P, P, P]
     L.bilu_batch_spmv.argtypes = [VP, P, P, P]
     L.bilu_batch_solve.argtypes = [VP, P, P, ct.POINTER(SolveOpts), ct.POINTER(RhsInfo), P]
+    L.bilu_batch_autotune.argtypes = [VP, P, ct.POINTER(BatchTuneInfo)]
     L.bilu_batch_member.argtypes = [VP, I, ct.POINTER(VP)]
     L.bilu_batch_destroy.argtypes = [VP]
     L.bilu_batch_destroy.restype = None
@@ -324,6 +330,13 @@ def bilu_batch_solve(batch, nsys, b_ptr, x_ptr, rtol, maxit, stream):
     st = _check(lib.bilu_batch_solve(batch, ct.c_void_p(b_ptr), ct.c_void_p(x_ptr), ct.byref(opts), info,
                                      ct.c_void_p(stream)), "bilu_batch_solve", allow_positive=True)
     return st, [(i.status, i.iters, i.relres, i.restarts) for i in info]
+
+
+def bilu_batch_autotune(batch, stream):
+    info = BatchTuneInfo()
+    _check(lib.bilu_batch_autotune(batch, ct.c_void_p(stream), ct.byref(info)), "bilu_batch_autotune")
+    return {"tile_scale": info.tile_scale, "pair_us": info.pair_us, "default_us": info.default_us,
+            "candidates": info.candidates}
 
 
 def bilu_batch_member(batch, s):

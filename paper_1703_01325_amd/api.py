@@ -217,6 +217,10 @@ class BlockILUBatch:
         st, info = N.bilu_batch_solve(self._b, self.nsys, b.data_ptr(), x.data_ptr(), rtol, maxit, _stream())
         return x, st, info
 
+    def autotune(self):
+        """Device-timed choice of the members' tile sizes (results unchanged)."""
+        return N.bilu_batch_autotune(self._b, _stream())
+
     def member(self, s: int) -> BlockILU:
         """Member s as a BlockILU view (owned by the batch)."""
         nb, bs, Ap, Aj = self.systems[s]

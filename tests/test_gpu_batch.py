@@ -84,6 +84,29 @@ def test_batch_apply_repeatable(api, oracle_mod):
         assert torch.equal(B.apply(r), z1)
 
 
+def test_batch_autotune_keeps_results(api, oracle_mod):
+    """The batch autotune only re-tiles the members: applications, SpMVs
+    and solves give the same bits before and after, and the tuned pair is
+    no slower than the one in force when timed the same way."""
+    members = small_members()
+    B, Ax, O = build(api, oracle_mod, members, 1)
+    r = cuda(np.random.default_rng(4).standard_normal(B.n))
+    rhs = cuda(np.concatenate([oracle_mod.spmv(m.nb, m.bs, m.Ap, m.Aj, m.Ax, m.xstar) for m in members]))
+    z1, y1 = B.apply(r), B.spmv(r)
+    x1, st1, info1 = B.solve(rhs, rtol=1e-8)
+    t = B.autotune()
+    assert t["candidates"] >= 1 and t["tile_scale"] in (0.25, 0.5, 1.0, 2.0, 4.0)
+    assert t["pair_us"] <= t["default_us"]
+    for _ in range(2):
+        assert torch.equal(B.apply(r), z1) and torch.equal(B.spmv(r), y1)
+    x2, st2, info2 = B.solve(rhs, rtol=1e-8)
+    assert st1 == st2 == 0 and info1 == info2 and torch.equal(x1, x2)
+    zs = split(B, z1.cpu().numpy())
+    rs = split(B, r.cpu().numpy())
+    for s in range(len(members)):
+        assert rel(zs[s], O[s].apply(rs[s])) <= 1e-12, s
+
+
 def test_batch_solve(api, oracle_mod):
     members = small_members()
     B, Ax, O = build(api, oracle_mod, members, 0)
