@@ -206,6 +206,47 @@ def run_poisson_table(args, n=120, sizes=(1, 2, 4, 8), levels=(0, 1, 2, 3), rtol
                         f"GMRES(20), b = 1, x0 = 0, rtol {rtol:g}", "rows": rows}
 
 
+def run_point_ab(sysm, k, reps=10):
+    """One application through the block-row sweeps against the same
+    application through the point-granularity sweeps (the split factors
+    expanded to point rows, one point row per lane): both timed with events
+    on the launch stream, results compared bit for bit."""
+    import numpy as np
+    import torch
+
+    from paper_1703_01325_amd import api
+
+    M = api.BlockILU(sysm.nb, sysm.bs, sysm.Ap, sysm.Aj, k)
+    Ax = torch.from_numpy(sysm.Ax).cuda()
+    if M.factor(Ax) >= 0:
+        raise RuntimeError("singular pivot block")
+    r = torch.from_numpy(np.random.default_rng(1).standard_normal(sysm.n)).cuda()
+    z, zp = torch.empty_like(r), torch.empty_like(r)
+    t0 = time.perf_counter()
+    M.apply_point(r, out=zp)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return 1e3 * ev[0].elapsed_time(ev[1]) / reps
+
+    block_us = timed(lambda: M.apply(r, out=z))
+    point_us = timed(lambda: M.apply_point(r, out=zp))
+    same = bool(torch.equal(z, zp))
+    M.close()
+    if not same:
+        raise RuntimeError("point-granularity application differs from the block one")
+    return {"block_apply_us": block_us, "point_apply_us": point_us, "point_over_block": point_us / block_us,
+            "point_setup_s": setup_s, "identical": same}
+
+
 def run_batch(nsys=256, reps=5):
     """The uneven batch: nsys independent systems (sides U{8..40}, b from
     {2,3,4,6,8}, ILU(0)), preconditioned and solved together.  Setup (host
@@ -417,6 +458,8 @@ def main():
             variants[f"mid64_ilu1_nrhs{R}"] = variant_line(rr, R)
             rr["M"].close()
         variants["uneven_batch_256_ilu0"] = run_batch()
+        if args.workload == "layered":
+            variants["layered_ilu0_point_vs_block_apply"] = run_point_ab(sysm, 0)
         line["variants"] = variants
     if not args.no_table1:
         line["poisson_table1"] = run_poisson_table(args)

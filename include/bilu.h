@@ -202,6 +202,23 @@ bilu_status bilu_apply(bilu_ctx* ctx, const double* r, double* z, int nrhs,
                        hipStream_t stream);
 
 /*
+ * z = M^{-1} r through the point-granularity mechanism of Section 2.4 and
+ * Algorithm 6: the split factors are expanded to point matrices (unit-
+ * diagonal L and U', point row I*b + r holding row r of the blocks of block
+ * row I) and swept point row by point row, level by level, with D^{-1}
+ * applied by blocks between the two sweeps.  Point levels equal the block
+ * levels (every point of a block row has its block row's level), and each
+ * point row sums its products in the order the block sweeps use, so the
+ * result is the one bilu_apply gives.  One right-hand side, not transposed.
+ * The point context is analysed on the first call (host, pattern of
+ * nnz(P)*b entries about) and its values expanded from the factors after each
+ * factorisation (device, allocates the point matrices).  Factors must exist
+ * (bilu_factor_diag), else BILU_ERR_STATE; BILU_ERR_TIMEOUT if a sweep's
+ * bounded wait expired.
+ */
+bilu_status bilu_apply_point(bilu_ctx* ctx, const double* r, double* z, hipStream_t stream);
+
+/*
  * bilu_apply for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same kernels and the same result bits as bilu_apply, with the

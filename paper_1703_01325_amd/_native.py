@@ -28,7 +28,7 @@ WANT_TRANSPOSE = 1
 EXPORTS = (
     "bilu_analyze", "bilu_get_pattern", "bilu_get_levels", "bilu_get_info", "bilu_validate",
     "bilu_factor_numeric", "bilu_factor_diag", "bilu_get_factors", "bilu_get_factors_f32",
-    "bilu_apply", "bilu_apply_noalloc", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
+    "bilu_apply", "bilu_apply_noalloc", "bilu_apply_point", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
     "bilu_tune", "bilu_autotune", "bilu_check", "bilu_timing", "bilu_timing_read",
     "bilu_destroy", "bilu_status_string",
     "bilu_batch_create", "bilu_batch_offsets", "bilu_batch_factor", "bilu_batch_apply",
@@ -100,6 +100,7 @@ def _load():
     L.bilu_apply.argtypes = [VP, P, P, I, P]
     L.bilu_apply_transpose.argtypes = [VP, P, P, I, P]
     L.bilu_apply_noalloc.argtypes = [VP, P, P, I, P]
+    L.bilu_apply_point.argtypes = [VP, P, P, P]
     L.bilu_spmv.argtypes = [VP, P, P, P, I, I, P]
     L.bilu_solve.argtypes = [VP, P, P, P, I, ct.POINTER(SolveOpts), ct.POINTER(RhsInfo), I, P]
     L.bilu_grad_A.argtypes = [VP, P, P, P, P]
@@ -218,6 +219,11 @@ def bilu_get_factors_f32(ctx, F_ptr, Dinv_ptr, stream):
 def bilu_apply(ctx, r_ptr, z_ptr, nrhs, stream):
     _check(lib.bilu_apply(ctx, ct.c_void_p(r_ptr), ct.c_void_p(z_ptr), int(nrhs), ct.c_void_p(stream)),
            "bilu_apply")
+
+
+def bilu_apply_point(ctx, r_ptr, z_ptr, stream):
+    _check(lib.bilu_apply_point(ctx, ct.c_void_p(r_ptr), ct.c_void_p(z_ptr), ct.c_void_p(stream)),
+           "bilu_apply_point")
 
 
 def bilu_apply_noalloc(ctx, r_ptr, z_ptr, nrhs, stream):

@@ -98,6 +98,13 @@ class BlockILU:
         fn(self._ctx, r.data_ptr(), z.data_ptr(), self._vec_shape(r), _stream())
         return z
 
+    def apply_point(self, r: torch.Tensor, out: torch.Tensor | None = None):
+        """z = M^{-1} r through the point-granularity sweeps (one column)."""
+        _dev_f64(r, "r")
+        z = torch.empty_like(r) if out is None else out
+        N.bilu_apply_point(self._ctx, r.data_ptr(), z.data_ptr(), _stream())
+        return z
+
     def spmv(self, Ax: torch.Tensor, x: torch.Tensor, out=None, transpose=False):
         _dev_f64(Ax, "Ax")
         _dev_f64(x, "x")

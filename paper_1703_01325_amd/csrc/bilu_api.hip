@@ -98,6 +98,16 @@ struct bilu_ctx {
     int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
     bool fuse_spmv = false;     // solvers run U' sweep + SpMV as one launch
     int helper = 0;             // helper wavefronts: 0 automatic, 1 always, 2 never
+    // point-granularity view (bilu_apply_point): the split factors expanded
+    // to point rows and swept by a context of block size 1 whose values are
+    // set, not factored (values_only: no factorisation plan)
+    bool values_only = false;
+    bilu_ctx* point = nullptr;
+    int64_t* d_point_src = nullptr;   // per point entry: index into F, -1 the unit diagonal
+    double* d_point_y = nullptr;      // D^{-1} y between the two point sweeps
+    int64_t point_n = 0;              // point entries
+    unsigned long factor_gen = 0;     // bumped by every bilu_factor_diag
+    unsigned long point_gen = 0;      // factor_gen the point values were expanded from (0: none)
     unsigned int spin_limit = 1u << 24;
 
     int32_t *d_Ap = nullptr, *d_Aj = nullptr, *d_Arow = nullptr;
@@ -540,7 +550,7 @@ bilu_status ensure_device(bilu_ctx* c)
     CK(hipMemset(c->d_status, 0, sizeof(int)));
     CK(hipMemset(c->d_done, 0, sizeof(unsigned int)));
     CK(hipMemset(c->d_ticket, 0, sizeof(unsigned long long)));
-    if ((st = factor_plan(c))) return st;
+    if (!c->values_only && (st = factor_plan(c))) return st;
     c->dev_ready = true;
     return BILU_OK;
 }
@@ -1082,6 +1092,7 @@ bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
     timing_end(c, tslot, s);
     CK(hipGetLastError());
     c->split_done = true;
+    ++c->factor_gen;
     return BILU_OK;
 }
 
@@ -1170,6 +1181,109 @@ bilu_status bilu_apply_noalloc(bilu_ctx* c, const double* r, double* z, int nrhs
     hipLaunchKernelGGL(dev::k_merge_status, dim3(1), dim3(64), 0, s, sync.status, c->d_status);
     CK(hipGetLastError());
     return BILU_OK;
+}
+
+// Point rows of the split factors (block size b, pattern P): point row
+// I*b + r holds, in ascending column order, the unit diagonal for the
+// diagonal block (the diagonal blocks of L and U' are identities) and b
+// entries per off-diagonal block (I, J), element (r, c) at column J*b + c.
+static void expand_point_pattern(const Host& h, std::vector<int32_t>& Ap, std::vector<int32_t>& Aj,
+                                 std::vector<int64_t>& src)
+{
+    const int b = h.bs;
+    const int64_t bb = static_cast<int64_t>(b) * b;
+    const int64_t n = static_cast<int64_t>(h.nb) * b;
+    Ap.assign(static_cast<size_t>(n) + 1, 0);
+    for (int32_t I = 0; I < h.nb; ++I) {
+        const int32_t cnt = (h.Pp[I + 1] - h.Pp[I] - 1) * b + 1;
+        for (int r = 0; r < b; ++r) Ap[static_cast<size_t>(I) * b + r + 1] = cnt;
+    }
+    for (int64_t i = 0; i < n; ++i) Ap[i + 1] += Ap[i];
+    Aj.resize(static_cast<size_t>(Ap[n]));
+    src.resize(static_cast<size_t>(Ap[n]));
+    for (int32_t I = 0; I < h.nb; ++I)
+        for (int r = 0; r < b; ++r) {
+            int64_t q = Ap[static_cast<size_t>(I) * b + r];
+            for (int32_t e = h.Pp[I]; e < h.Pp[I + 1]; ++e) {
+                const int32_t J = h.Pj[e];
+                if (J == I) {
+                    Aj[q] = I * b + r;
+                    src[q++] = -1;
+                } else {
+                    for (int c = 0; c < b; ++c) {
+                        Aj[q] = J * b + c;
+                        src[q++] = static_cast<int64_t>(e) * bb + static_cast<int64_t>(c) * b + r;
+                    }
+                }
+            }
+        }
+}
+
+// The point view of the current factors: its context (analysed once), then
+// values expanded from F after every factorisation.
+static bilu_status ensure_point(bilu_ctx* c, hipStream_t s)
+{
+    bilu_status st;
+    const Host& h = c->h;
+    const int64_t n = static_cast<int64_t>(h.nb) * h.bs;
+    if (!c->point) {
+        if (n > INT32_MAX) return BILU_ERR_ARG;
+        std::vector<int32_t> Ap, Aj;
+        std::vector<int64_t> src;
+        try {
+            expand_point_pattern(h, Ap, Aj, src);
+        } catch (const std::bad_alloc&) {
+            return BILU_ERR_ALLOC;
+        }
+        bilu_ctx* p = nullptr;
+        if ((st = bilu_analyze(static_cast<int>(n), 1, Ap.data(), Aj.data(), 0, 0, &p))) return st;
+        p->values_only = true;
+        p->sweep_mode = c->sweep_mode;
+        p->spin_limit = c->spin_limit;
+        c->point = p;
+        c->point_gen = 0;
+        if ((st = ensure_device(p)) || (st = upload(c, &c->d_point_src, src)) ||
+            (st = dalloc(c, &c->d_point_y, static_cast<size_t>(n))))
+            return st;
+        c->point_n = static_cast<int64_t>(src.size());
+    }
+    if (c->point_gen != c->factor_gen) {
+        bilu_ctx* p = c->point;
+        if (!c->f_ready) {
+            if (!launch_split(c, s)) return BILU_ERR_ARG;
+            c->f_ready = true;
+        }
+        hipLaunchKernelGGL(dev::k_expand_point, dim3(grid_for(c->point_n)), dim3(256), 0, s, c->point_n,
+                           c->d_point_src, c->d_F, p->d_P);
+        hipLaunchKernelGGL(dev::k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, n, p->d_Dinv, 1.0);
+        CK(hipGetLastError());
+        p->factored = true;
+        if ((st = bilu_factor_diag(p, BILU_FACTORS_FP64, s))) return st;
+        c->point_gen = c->factor_gen;
+    }
+    return BILU_OK;
+}
+
+static bool launch_block_dinv(int bs, int64_t nb, const double* Dinv, const double* x, double* y, hipStream_t s)
+{
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_block_dinv<B>), dim3(grid_for(nb * B)), dim3(256), 0, s, nb, Dinv,
+                                         x, y))
+}
+
+bilu_status bilu_apply_point(bilu_ctx* c, const double* r, double* z, hipStream_t s)
+{
+    if (!c || !r || !z || r == z) return BILU_ERR_ARG;
+    if (!c->split_done) return BILU_ERR_STATE;
+    bilu_status st = ensure_point(c, s);
+    if (st) return st;
+    bilu_ctx* p = c->point;
+    if ((st = layout_form(p, sweep_form(p, 1), s)) || (st = ensure_y(p, 1, s))) return st;
+    // L sweep on the point rows (resets z), D^{-1} by blocks, U' sweep on
+    // the point rows with the unit D^{-1} of the point context (resets y)
+    if ((st = run_sweep(p, BILU_SWEEP_L, r, p->d_y, z, 1, s, nullptr))) return st;
+    if (!launch_block_dinv(c->h.bs, c->h.nb, c->d_Dinv, p->d_y, c->d_point_y, s)) return BILU_ERR_ARG;
+    CK(hipGetLastError());
+    return run_sweep(p, BILU_SWEEP_U, c->d_point_y, z, p->d_y, 1, s, nullptr);
 }
 
 bilu_status bilu_apply_transpose(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
@@ -1702,6 +1816,7 @@ bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x
 void bilu_destroy(bilu_ctx* c)
 {
     if (!c) return;
+    if (c->point) bilu_destroy(c->point);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->h_state) (void)hipHostFree(c->h_state);

@@ -296,6 +296,41 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Point-granularity view of the factors (the point-wise solver the paper
+// feeds with its block factors, Section 2.4 / Alg 6): every point entry of
+// the expanded unit-diagonal L and U' takes its value from element (r, c) of
+// a block of F (src = block * b*b + c*b + r), the unit diagonal 1 (src < 0).
+// ---------------------------------------------------------------------------
+__global__ void k_expand_point(int64_t n, const int64_t* __restrict__ src, const double* __restrict__ F,
+                               double* __restrict__ Ppt)
+{
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t k = src[e];
+        Ppt[e] = k >= 0 ? F[k] : 1.0;
+    }
+}
+
+// y = D^{-1} x with D^{-1} block diagonal (b x b blocks, column-major), one
+// thread per point row; the products summed over c in order, as in the
+// block sweep that fuses D^{-1}.
+template <int B>
+__global__ void k_block_dinv(int64_t nb, const double* __restrict__ Dinv, const double* __restrict__ x,
+                             double* __restrict__ y)
+{
+    constexpr int BB = B * B;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nb * B;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t I = i / B;
+        const int r = static_cast<int>(i - I * B);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc += Dinv[I * BB + c * B + r] * x[I * B + c];
+        y[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // U = D U' (Eq 5): F = L below the diagonal, U'_ij = D_i^{-1} U_ij above
 // it, the identity on the diagonal.
 // ---------------------------------------------------------------------------
