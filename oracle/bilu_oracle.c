@@ -795,8 +795,83 @@ done:
     return status;
 }
 
-/* method 0 = BiCGSTAB, 1 = GMRES(restart).  F32/Dinv32 non-NULL selects the
- * FP32-stored factors.  transpose = 1 solves A^T x = b with M^{-T}. */
+/*
+ * Right-preconditioned ORTHOMIN(k) (Vinsome's method, named in the paper's
+ * introduction as the reservoir simulators' Krylov solver), x0 = 0.  Each
+ * iteration takes the preconditioned residual z = M^{-1} r as a new search
+ * direction p with Ap = A z, makes Ap orthogonal to the A-images q_i of the
+ * last k kept directions, beta_i = -(A z, q_i) / (q_i, q_i) (every beta_i
+ * from the unmodified A z; the kept q_i are mutually orthogonal),
+ * p = z + sum_i beta_i p_i and q = A z + sum_i beta_i q_i (kept directions
+ * from the oldest to the newest), then minimises the residual along p:
+ * alpha = (r, q) / (q, q), x += alpha p, r -= alpha q.  Exit on the true
+ * residual as in BiCGSTAB; when the recurrence residual passes but the true
+ * one does not, r = b - A x and the kept directions are dropped.  k = 0
+ * is the minimal-residual iteration.  Returns 0, ORC_NOT_CONVERGED or
+ * ORC_BREAKDOWN ((q, q) = 0).
+ */
+static int orthomin(const orc_system *S, const double *bvec, double *x, double rtol, int k,
+                    int maxit, int *iters, double *relres)
+{
+    long long N = (long long)S->n * S->b;
+    size_t sz = (size_t)N * sizeof(double);
+    int K1 = k + 1;
+    double *P = malloc(sz * (size_t)K1), *Q = malloc(sz * (size_t)K1);
+    double *qq = calloc((size_t)K1, sizeof(double)), *beta = calloc((size_t)K1, sizeof(double));
+    double *r = malloc(sz), *w = malloc(sz);
+    int status = ORC_NOT_CONVERGED, it = 0, count = 0;
+    double bnorm = sqrt(dot(N, bvec, bvec)), rres = bnorm;
+    memset(x, 0, sz);
+    memcpy(r, bvec, sz);
+    last_restarts = 0;
+    if (bnorm == 0.0) { status = ORC_OK; rres = 0.0; goto done; }
+    for (it = 1; it <= maxit; it++) {
+        int s = (it - 1) % K1;
+        double *p = P + (size_t)s * N, *q = Q + (size_t)s * N;
+        op_M(S, r, p);
+        op_A(S, p, q);
+        /* kept directions: the count slots before s, oldest first */
+        for (int i = 0; i < count; i++) {
+            int si = ((s - count + i) % K1 + K1) % K1;
+            beta[i] = -dot(N, q, Q + (size_t)si * N) / qq[si];
+        }
+        for (int i = 0; i < count; i++) {
+            int si = ((s - count + i) % K1 + K1) % K1;
+            const double *pi = P + (size_t)si * N, *qi = Q + (size_t)si * N;
+            for (long long t = 0; t < N; t++) {
+                p[t] += beta[i] * pi[t];
+                q[t] += beta[i] * qi[t];
+            }
+        }
+        qq[s] = dot(N, q, q);
+        if (qq[s] == 0.0) { status = ORC_BREAKDOWN; break; }
+        double alpha = dot(N, r, q) / qq[s];
+        for (long long t = 0; t < N; t++) {
+            x[t] += alpha * p[t];
+            r[t] -= alpha * q[t];
+        }
+        count = count < k ? count + 1 : k;
+        double rnorm = sqrt(dot(N, r, r));
+        if (rnorm <= rtol * bnorm) {
+            rres = true_residual(S, bvec, x, w);
+            if (rres <= rtol * bnorm) { status = ORC_OK; break; }
+            memcpy(r, w, sz);
+            count = 0;
+            last_restarts++;
+        }
+    }
+    if (it > maxit) it = maxit;
+    if (status != ORC_OK) rres = true_residual(S, bvec, x, w);
+done:
+    *iters = it;
+    *relres = bnorm > 0.0 ? rres / bnorm : 0.0;
+    free(P); free(Q); free(qq); free(beta); free(r); free(w);
+    return status;
+}
+
+/* method 0 = BiCGSTAB, 1 = GMRES(restart), 2 = ORTHOMIN(k = restart).
+ * F32/Dinv32 non-NULL selects the FP32-stored factors.  transpose = 1 solves
+ * A^T x = b with M^{-T}. */
 int orc_solve(int n, int b, const int *Ap, const int *Aj, const double *Ax,
               const int *Pp, const int *Pj, const double *F, const double *Dinv,
               const float *F32, const float *Dinv32, const double *bvec, double *x,
@@ -808,6 +883,7 @@ int orc_solve(int n, int b, const int *Ap, const int *Aj, const double *Ax,
     S.M.n = n; S.M.b = b; S.M.Pp = Pp; S.M.Pj = Pj;
     S.M.F = F; S.M.Dinv = Dinv; S.M.F32 = F32; S.M.Dinv32 = Dinv32;
     if (method == 1) return gmres(&S, bvec, x, rtol, restart, maxit, iters, relres);
+    if (method == 2) return orthomin(&S, bvec, x, rtol, restart, maxit, iters, relres);
     return bicgstab(&S, bvec, x, rtol, maxit, iters, relres);
 }
 

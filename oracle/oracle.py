@@ -182,7 +182,8 @@ def spmv(nb, bs, Ap, Aj, Ax, x, transpose=False):
 
 def solve(nb, bs, Ap, Aj, Ax, Pp, Pj, F, Dinv, b, method=0, restart=30, rtol=1e-8,
           maxit=2000, transpose=False, F32=None, Dinv32=None):
-    """BiCGSTAB (method 0) or GMRES(restart) (method 1), right-preconditioned.
+    """BiCGSTAB (method 0), GMRES(restart) (method 1) or ORTHOMIN(k = restart)
+    (method 2), right-preconditioned.
 
     Returns (x, iters, relres, status)."""
     Ap, Aj, Pp, Pj = _i32(Ap), _i32(Aj), _i32(Pp), _i32(Pj)
