@@ -448,6 +448,9 @@ def main():
         variants[f"layered_ilu{args.k}_fp32"] = v
         r32["M"].close()
         if args.workload == "layered":
+            ro = run_gpu(args, sysm, args.k, "fp64", steps=3, warmup=1, method="orthomin", restart=10)
+            variants[f"layered_ilu{args.k}_orthomin10"] = variant_line(ro)
+            ro["M"].close()
             for prec in ("fp64", "fp32"):
                 r1 = run_gpu(args, sysm, 1, prec, steps=3, warmup=1)
                 variants[f"layered_ilu1_{prec}"] = variant_line(r1)

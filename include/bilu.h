@@ -75,7 +75,7 @@ typedef enum {
 } bilu_sweep;
 
 typedef enum { BILU_FACTORS_FP64 = 0, BILU_FACTORS_FP32 = 1 } bilu_precision;
-typedef enum { BILU_BICGSTAB = 0, BILU_GMRES = 1 } bilu_method;
+typedef enum { BILU_BICGSTAB = 0, BILU_GMRES = 1, BILU_ORTHOMIN = 2 } bilu_method;
 
 /* bilu_analyze flags */
 #define BILU_WANT_TRANSPOSE 1   /* also build U'^T / L^T sweeps and A^T SpMV */
@@ -247,11 +247,13 @@ bilu_status bilu_spmv(bilu_ctx* ctx, const double* Ax_dev, const double* x, doub
 
 /*
  * Solves A x = b (transpose = 0) or A^T x = b (transpose = 1) for nrhs
- * independent right-hand sides with right-preconditioned BiCGSTAB or
- * GMRES(m), x0 = 0, FP64 vectors and reductions on the GPU.  Exit test on
- * the true residual ||b - A x||_2 <= rtol ||b||_2.  info[nrhs] (host)
- * receives per-RHS results; the return value is the worst of them.
- * Synchronises `stream`.
+ * independent right-hand sides with right-preconditioned BiCGSTAB,
+ * GMRES(m) (opts->restart = m, one right-hand side) or ORTHOMIN(k), the
+ * reservoir simulators' method named in the paper's introduction
+ * (opts->restart = k kept directions, 0..16, one right-hand side), x0 = 0,
+ * FP64 vectors and reductions on the GPU.  Exit test on the true residual
+ * ||b - A x||_2 <= rtol ||b||_2.  info[nrhs] (host) receives per-RHS
+ * results; the return value is the worst of them.  Synchronises `stream`.
  */
 bilu_status bilu_solve(bilu_ctx* ctx, const double* Ax_dev, const double* b, double* x,
                        int nrhs, const bilu_solve_opts* opts, bilu_rhs_info* info,

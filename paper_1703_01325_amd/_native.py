@@ -21,7 +21,7 @@ ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_MISSING_DIAG, ERR_PATTERN, ERR_TIMEOUT, ERR_STA
 SINGULAR_PIVOT, NOT_CONVERGED, BREAKDOWN, NONFINITE = 1, 2, 3, 4
 SWEEP_L, SWEEP_U, SWEEP_UT, SWEEP_LT = 0, 1, 2, 3
 FACTORS_FP64, FACTORS_FP32 = 0, 1
-BICGSTAB, GMRES = 0, 1
+BICGSTAB, GMRES, ORTHOMIN = 0, 1, 2
 WANT_TRANSPOSE = 1
 
 # every symbol declared in include/bilu.h

@@ -119,7 +119,7 @@ class BlockILU:
         _dev_f64(Ax, "Ax")
         _dev_f64(b, "b")
         x = torch.empty_like(b) if out is None else out
-        m = N.GMRES if method == "gmres" else N.BICGSTAB
+        m = {"bicgstab": N.BICGSTAB, "gmres": N.GMRES, "orthomin": N.ORTHOMIN}[method]
         st, info = N.bilu_solve(self._ctx, Ax.data_ptr(), b.data_ptr(), x.data_ptr(), self._vec_shape(b),
                                 m, restart, rtol, maxit, int(transpose), _stream())
         return x, st, info

@@ -98,6 +98,7 @@ struct bilu_ctx {
     int rhs_tile = 0;           // columns per pass for several right-hand sides; 0: 8
     bool fuse_spmv = false;     // solvers run U' sweep + SpMV as one launch
     int helper = 0;             // helper wavefronts: 0 automatic, 1 always, 2 never
+    dev::OmState* d_om = nullptr; // ORTHOMIN(k) state
     // point-granularity view (bilu_apply_point): the split factors expanded
     // to point rows and swept by a context of block size 1 whose values are
     // set, not factored (values_only: no factorisation plan)
@@ -1798,6 +1799,91 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
     return static_cast<bilu_status>(status);
 }
 
+// Right-preconditioned ORTHOMIN(k), one right-hand side: each iteration
+// takes z = M^{-1} r as the new direction (ring slot (it-1) mod (k+1)) with
+// q = A z, makes q orthogonal to the A-images of the last k directions
+// (k_om_dots, k_om_beta, k_om_update), minimises the residual along it
+// (k_om_alpha, k_om_xr) and marks the iteration for the true-residual test
+// when the recurrence residual passes (k_om_end); the gated true-residual
+// SpMV and k_om_decide stop or restart.  The host queues iteration it and
+// waits only for iteration it - 1, as in BiCGSTAB.
+static bilu_status orthomin(bilu_ctx* c, const double* Ax, const double* b, double* x, const bilu_solve_opts* o,
+                            bilu_rhs_info* info, int tr, hipStream_t s)
+{
+    const int64_t n = static_cast<int64_t>(c->h.nb) * c->h.bs;
+    const int k = o->restart;
+    const int K1 = k + 1;
+    bilu_status st = ensure_krylov(c, 1, 2 * K1 + 2);
+    if (st) return st;
+    if ((st = ensure_step_host(c))) return st;
+    if (!c->d_om && (st = dalloc(c, &c->d_om, 1))) return st;
+    double* P = c->d_kv;
+    double* Q = P + static_cast<size_t>(K1) * n;
+    double* r = Q + static_cast<size_t>(K1) * n;
+    double* w = r + n;
+    double* part = c->d_part;
+    dev::OmState* S = c->d_om;
+    const int* g_active = &S->active;
+    const int* g_check = &S->check;
+    const int eg = grid_for(n);
+    const dim3 rb(dev::kRedBlocks), rt(dev::kThreads);
+
+    CK(hipMemcpyAsync(r, b, static_cast<size_t>(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(dev::k_fill_f64, dim3(eg), dim3(256), 0, s, n, x, 0.0);
+    hipLaunchKernelGGL(dev::k_dot, rb, rt, 0, s, n, 1, b, b, part, dev::SL_BB, nullptr);
+    hipLaunchKernelGGL(dev::k_om_init, dim3(1), dim3(64), 0, s, part, S, o->rtol);
+    hipLaunchKernelGGL(dev::k_om_decide, dim3(1), dim3(64), 0, s, part, S, 0, c->d_flags);
+    CK(hipGetLastError());
+    CK(hipEventRecord(c->step_ev[0], s));
+    int it = 0;
+    while (it < o->maxit) {
+        ++it;
+        const int sl = (it - 1) % K1;
+        double* p = P + static_cast<size_t>(sl) * n;
+        double* q = Q + static_cast<size_t>(sl) * n;
+        if ((st = do_apply(c, r, p, 1, tr != 0, s, g_active)) || (st = do_spmv(c, Ax, p, q, 1, tr, s, g_active)))
+            return st;
+        hipLaunchKernelGGL(dev::k_om_dots, rb, rt, 0, s, n, Q, sl, K1, S, part);
+        hipLaunchKernelGGL(dev::k_om_beta, dim3(1), dim3(64), 0, s, part, S, sl, K1);
+        hipLaunchKernelGGL(dev::k_om_update, rb, rt, 0, s, n, P, Q, r, sl, K1, S, part);
+        hipLaunchKernelGGL(dev::k_om_alpha, dim3(1), dim3(64), 0, s, part, S, sl);
+        hipLaunchKernelGGL(dev::k_om_xr, rb, rt, 0, s, n, x, r, P, Q, sl, S, part);
+        hipLaunchKernelGGL(dev::k_om_end, dim3(1), dim3(64), 0, s, part, S, k);
+        // true residual when the recurrence residual passes, then the verdict
+        if ((st = do_spmv(c, Ax, x, w, 1, tr, s, g_check, false))) return st;
+        hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE, g_check);
+        hipLaunchKernelGGL(dev::k_om_decide, dim3(1), dim3(64), 0, s, part, S, it, c->d_flags + (it & 1));
+        hipLaunchKernelGGL(dev::k_om_restart, dim3(eg), dim3(256), 0, s, n, w, r, S);
+        CK(hipGetLastError());
+        CK(hipEventRecord(c->step_ev[it & 1], s));
+        CK(hipEventSynchronize(c->step_ev[(it - 1) & 1]));
+        if (__hip_atomic_load(c->h_flags + ((it - 1) & 1), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == 0) break;
+    }
+    // final true residual
+    if ((st = do_spmv(c, Ax, x, w, 1, tr, s))) return st;
+    hipLaunchKernelGGL(dev::k_resid, rb, rt, 0, s, n, 1, b, w, part, dev::SL_TRUE, nullptr);
+    hipLaunchKernelGGL(dev::k_om_final, dim3(1), dim3(64), 0, s, part, S);
+    static_assert(sizeof(dev::OmState) <= sizeof(KState), "ORTHOMIN state readback fits the pinned state");
+    dev::OmState* hs = reinterpret_cast<dev::OmState*>(c->h_state);
+    CK(hipMemcpyAsync(hs, S, sizeof(dev::OmState), hipMemcpyDeviceToHost, s));
+    int sweep_err = 0;
+    CK(hipMemcpyAsync(&sweep_err, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    int stj = hs->status;
+    if (hs->active) stj = BILU_NOT_CONVERGED;
+    info[0].status = stj;
+    info[0].iters = hs->done_it >= 0 ? hs->done_it : it;
+    info[0].relres = hs->bnorm2 > 0 ? std::sqrt(hs->tnorm2 / hs->bnorm2) : 0.0;
+    info[0].restarts = hs->nrestart;
+    info[0].reserved = 0;
+    if (sweep_err) {
+        CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
+        CK(hipStreamSynchronize(s));
+        return BILU_ERR_TIMEOUT;
+    }
+    return static_cast<bilu_status>(stj);
+}
+
 bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x, int nrhs,
                        const bilu_solve_opts* o, bilu_rhs_info* info, int transpose, hipStream_t s)
 {
@@ -1809,6 +1895,10 @@ bilu_status bilu_solve(bilu_ctx* c, const double* Ax, const double* b, double* x
     if (o->method == BILU_GMRES) {
         if (nrhs != 1 || o->restart < 1 || o->restart > 1000) return BILU_ERR_ARG;
         return gmres(c, Ax, b, x, o, info, transpose, s);
+    }
+    if (o->method == BILU_ORTHOMIN) {
+        if (nrhs != 1 || o->restart < 0 || o->restart > dev::kOmMax) return BILU_ERR_ARG;
+        return orthomin(c, Ax, b, x, o, info, transpose, s);
     }
     return BILU_ERR_ARG;
 }

@@ -1114,5 +1114,207 @@ __global__ void k_axpy1(int64_t n, double* __restrict__ x, const double* __restr
         x[g] += z[g];
 }
 
+// ---------------------------------------------------------------------------
+// ORTHOMIN(k), right-preconditioned, one right-hand side, every decision on
+// the device.  The directions p and their A-images q sit in rings of k + 1
+// vectors; the direction of iteration it (1-based) is ring slot (it-1) mod
+// (k+1), and the `count` kept directions are the slots before it, oldest
+// first.  A restart from the true residual drops them (count = 0).
+// ---------------------------------------------------------------------------
+constexpr int kOmMax = 16;            // most directions kept
+
+struct OmState {
+    double qq[kOmMax + 1];            // (q_i, q_i) per ring slot
+    double beta[kOmMax];              // coefficients of the kept directions, oldest first
+    double alpha, bnorm2, tol2, rnorm2, tnorm2;
+    int count;                        // directions kept before the current one
+    int active, check, restart, status, done_it, nrestart, pad;
+};
+
+__device__ __forceinline__ int om_slot(int s, int count, int i, int K1)
+{
+    return ((s - count + i) % K1 + K1) % K1;
+}
+
+// setup: ||b||^2 from the partials, tolerance, flags (x = 0, r = b by the host)
+__global__ __launch_bounds__(64) void k_om_init(const double* part, OmState* st, double rtol)
+{
+    const double b2 = sum_partials(part, SL_BB, 0);
+    if (lane_id() != 0) return;
+    st->bnorm2 = b2;
+    st->tol2 = rtol * rtol * b2;
+    st->rnorm2 = b2;
+    st->tnorm2 = b2;
+    st->active = b2 > 0.0 ? 1 : 0;
+    st->status = b2 > 0.0 ? ST_NOT_CONV : ST_OK;
+    st->count = 0;
+    st->check = 0;
+    st->restart = 0;
+    st->done_it = st->active ? -1 : 0;
+    st->nrestart = 0;
+}
+
+// partials of (q_s, q_i) for the kept directions i (column i of slot SL_RHO)
+__global__ __launch_bounds__(kThreads) void k_om_dots(int64_t n, const double* __restrict__ Q, int s, int K1,
+                                                      const OmState* st, double* part)
+{
+    if (!st->active) return;
+    const int count = st->count;
+    const RedIdx ri = red_index(1);
+    const double* q = Q + static_cast<int64_t>(s) * n;
+    double acc[kOmMax];
+#pragma unroll
+    for (int i = 0; i < kOmMax; ++i) acc[i] = 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n; g += ri.stride) {
+            const double qv = q[g];
+#pragma unroll
+            for (int i = 0; i < kOmMax; ++i)
+                if (i < count) acc[i] += qv * Q[static_cast<int64_t>(om_slot(s, count, i, K1)) * n + g];
+        }
+    double* ps = slot_ptr(part, SL_RHO);
+    for (int i = 0; i < count; ++i) block_partial(acc[i], 1, ps + static_cast<int64_t>(i) * kRedBlocks);
+}
+
+// beta_i = -(q_s, q_i) / (q_i, q_i)
+__global__ __launch_bounds__(64) void k_om_beta(const double* part, OmState* st, int s, int K1)
+{
+    if (!st->active) return;
+    const int count = st->count;
+    for (int i = 0; i < count; ++i) {
+        const double d = sum_partials(part, SL_RHO, i);
+        if (lane_id() == 0) st->beta[i] = -d / st->qq[om_slot(s, count, i, K1)];
+    }
+}
+
+// p_s += sum_i beta_i p_i, q_s += sum_i beta_i q_i (oldest first), partials
+// of (q_s, q_s) and (r, q_s)
+__global__ __launch_bounds__(kThreads) void k_om_update(int64_t n, double* __restrict__ P, double* __restrict__ Q,
+                                                        const double* __restrict__ r, int s, int K1,
+                                                        const OmState* st, double* part)
+{
+    if (!st->active) return;
+    const int count = st->count;
+    const RedIdx ri = red_index(1);
+    double* p = P + static_cast<int64_t>(s) * n;
+    double* q = Q + static_cast<int64_t>(s) * n;
+    double qq = 0.0, rq = 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n; g += ri.stride) {
+            double pv = p[g], qv = q[g];
+            for (int i = 0; i < count; ++i) {
+                const int64_t o = static_cast<int64_t>(om_slot(s, count, i, K1)) * n + g;
+                const double bt = st->beta[i];
+                pv += bt * P[o];
+                qv += bt * Q[o];
+            }
+            p[g] = pv;
+            q[g] = qv;
+            qq += qv * qv;
+            rq += r[g] * qv;
+        }
+    block_partial(qq, 1, slot_ptr(part, SL_TT));
+    block_partial(rq, 1, slot_ptr(part, SL_TS));
+}
+
+// alpha = (r, q_s) / (q_s, q_s); a zero (q, q) is a breakdown
+__global__ __launch_bounds__(64) void k_om_alpha(const double* part, OmState* st, int s)
+{
+    if (!st->active) return;
+    const double qq = sum_partials(part, SL_TT, 0);
+    const double rq = sum_partials(part, SL_TS, 0);
+    if (lane_id() != 0) return;
+    st->qq[s] = qq;
+    if (!isfinite(qq) || !isfinite(rq)) {
+        st->status = ST_NONFINITE;
+        st->active = 0;
+    } else if (qq == 0.0) {
+        st->status = ST_BREAKDOWN;
+        st->active = 0;
+    } else {
+        st->alpha = rq / qq;
+    }
+}
+
+// x += alpha p_s, r -= alpha q_s, partial of (r, r)
+__global__ __launch_bounds__(kThreads) void k_om_xr(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ P, const double* __restrict__ Q,
+                                                    int s, const OmState* st, double* part)
+{
+    if (!st->active) return;
+    const RedIdx ri = red_index(1);
+    const double al = st->alpha;
+    const double* p = P + static_cast<int64_t>(s) * n;
+    const double* q = Q + static_cast<int64_t>(s) * n;
+    double rr = 0.0;
+    if (ri.live)
+        for (int64_t g = ri.start; g < n; g += ri.stride) {
+            x[g] += al * p[g];
+            const double rv = r[g] - al * q[g];
+            r[g] = rv;
+            rr += rv * rv;
+        }
+    block_partial(rr, 1, slot_ptr(part, SL_RR));
+}
+
+// End of an iteration: ||r||^2, one more kept direction (at most k), and
+// the mark for the true-residual test when the recurrence residual passes.
+__global__ __launch_bounds__(64) void k_om_end(const double* part, OmState* st, int k)
+{
+    if (!st->active) return;
+    const double r2 = sum_partials(part, SL_RR, 0);
+    if (lane_id() != 0) return;
+    st->rnorm2 = r2;
+    st->count = st->count < k ? st->count + 1 : k;
+    if (!isfinite(r2)) {
+        st->status = ST_NONFINITE;
+        st->active = 0;
+        return;
+    }
+    st->check = r2 <= st->tol2 ? 1 : 0;
+}
+
+// After iteration `it` (0: after the setup): a marked iteration stops if the
+// true residual meets the tolerance, else restarts from it (r = b - A x,
+// kept directions dropped).  Records the stopping iteration and copies
+// "still active" to *host_flag (mapped host memory).
+__global__ __launch_bounds__(64) void k_om_decide(const double* part, OmState* st, int it, int* host_flag)
+{
+    const bool checked = st->check && st->active;
+    const double t2 = checked ? sum_partials(part, SL_TRUE, 0) : 0.0;
+    if (lane_id() != 0) return;
+    st->restart = 0;
+    if (checked) {
+        st->tnorm2 = t2;
+        if (t2 <= st->tol2) {
+            st->active = 0;
+            st->status = ST_OK;
+        } else {
+            st->restart = 1;
+            st->count = 0;
+            st->nrestart += 1;
+        }
+    }
+    st->check = 0;
+    if (!st->active && st->done_it < 0) st->done_it = it;
+    if (host_flag) __hip_atomic_store(host_flag, st->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// r = w (the true residual) after a restart
+__global__ void k_om_restart(int64_t n, const double* __restrict__ w, double* __restrict__ r, const OmState* st)
+{
+    if (!st->restart) return;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        r[g] = w[g];
+}
+
+// ||b - A x||^2 of the final x into tnorm2 (whatever the flags)
+__global__ __launch_bounds__(64) void k_om_final(const double* part, OmState* st)
+{
+    const double t2 = sum_partials(part, SL_TRUE, 0);
+    if (lane_id() == 0) st->tnorm2 = t2;
+}
+
 }  // namespace dev
 }  // namespace bilu
