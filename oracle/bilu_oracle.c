@@ -27,6 +27,10 @@
 #define ORC_NOT_CONVERGED 2
 #define ORC_BREAKDOWN 3
 
+/* Largest block size: the large blocks of Section 3 (Table 2 uses b = 25)
+ * fit; the blocks live on the stack in the factorisation and the solves. */
+#define ORC_MAX_B 32
+
 /* ------------------------------------------------------------------------ */
 /* Pattern store in the spirit of imatcsr_t (Section 2.1, Fig. 3): row      */
 /* lengths plus one separately allocated column array per row, so a row can */
@@ -294,7 +298,7 @@ static void blk_mul_sub(int b, const double *A, const double *B, double *C)
  * Returns 0, or 1 if a pivot is zero or not finite. */
 static int blk_inv(int b, const double *A, double *Ainv)
 {
-    double W[8 * 16];          /* augmented [A | I], row-major, b <= 8 */
+    double W[ORC_MAX_B * 2 * ORC_MAX_B];   /* augmented [A | I], row-major */
     int w = 2 * b;
     for (int r = 0; r < b; r++)
         for (int c = 0; c < b; c++) {
@@ -353,7 +357,7 @@ int orc_factor(int n, int b, const int *Ap, const int *Aj, const double *Ax,
                const int *Pp, const int *Pj, double *LU, double *Dinv, int *bad_row)
 {
     const int bb = b * b;
-    if (b < 1 || b > 8) return ORC_ERR_PATTERN;
+    if (b < 1 || b > ORC_MAX_B) return ORC_ERR_PATTERN;
     /* Backfill: copy A's blocks into their positions in P, zeros elsewhere. */
     memset(LU, 0, (size_t)Pp[n] * bb * sizeof(double));
     for (int i = 0; i < n; i++)
@@ -362,7 +366,7 @@ int orc_factor(int n, int b, const int *Ap, const int *Aj, const double *Ax,
             if (pos < 0) return ORC_ERR_PATTERN;
             memcpy(LU + (size_t)pos * bb, Ax + (size_t)e * bb, bb * sizeof(double));
         }
-    double T[64];
+    double T[ORC_MAX_B * ORC_MAX_B];
     for (int i = 0; i < n; i++) {
         for (int e = Pp[i]; e < Pp[i + 1]; e++) {
             int p = Pj[e];
@@ -442,7 +446,7 @@ static void precond_apply(const orc_precond *M, const double *r, double *x)
 {
     const int n = M->n, b = M->b, bb = b * b;
     double *y = (double *)malloc((size_t)n * b * sizeof(double));
-    double acc[8];
+    double acc[ORC_MAX_B];
     for (int i = 0; i < n; i++) {
         for (int rr = 0; rr < b; rr++) acc[rr] = r[(size_t)i * b + rr];
         for (int e = M->Pp[i]; e < M->Pp[i + 1]; e++) {

@@ -334,7 +334,7 @@ def test_point_levels_equal_block_levels(oracle_mod):
 # ----------------------------------------------------------------------------
 # factorisation (Algorithms 4-5) and split (Eq 5)
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("bs", [1, 2, 3, 5])
+@pytest.mark.parametrize("bs", [1, 2, 3, 5, 25])
 @pytest.mark.parametrize("k", [0, 1, 3])
 def test_factor_reproduces_A_on_pattern(oracle_mod, bs, k):
     """IKJ incomplete LU: (L U)_ij = A'_ij for every (i, j) of the kept
@@ -356,7 +356,7 @@ def test_factor_reproduces_A_on_pattern(oracle_mod, bs, k):
     assert np.abs(D @ Up - Ud).max() <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("bs", [1, 2, 4])
+@pytest.mark.parametrize("bs", [1, 2, 4, 12])
 def test_factor_large_k_is_dense_block_lu(oracle_mod, bs):
     nb = 25
     Ap, Aj, Ax = random_system(nb, bs, 0.1, 3 + bs)
