@@ -120,7 +120,7 @@ def run_gpu(args, sysm, k, precision, R=1, steps=None, warmup=None, method="bicg
         if n_launch:
             per[key] = {"launches": int(n_launch), "avg_us": 1e3 * total_ms / n_launch,
                         "total_ms": total_ms}
-    pair_us = sum(per[kk]["avg_us"] for kk in ("sweep_L", "sweep_U", "spmv"))
+    pair_us = sum(per[kk]["avg_us"] for kk in ("sweep_L", "sweep_U", "spmv") if kk in per)
     pair_bytes = ab["sweep_L"] + ab["sweep_U"] + ab["spmv"]
     return {
         "M": M, "info": info, "analyze_s": analyze_s, "elapsed": elapsed, "steps": steps,
@@ -455,6 +455,13 @@ def main():
                 r1 = run_gpu(args, sysm, 1, prec, steps=3, warmup=1)
                 variants[f"layered_ilu1_{prec}"] = variant_line(r1)
                 r1["M"].close()
+        # large blocks (the b = 25 of the paper's Table 2) on a 7-point grid:
+        # block factorisation, point-granularity sweeps
+        big = synth.reservoir(24, 24, 24, 25, seed=7)
+        rb = run_gpu(args, big, 0, "fp64", steps=2, warmup=1)
+        variants["grid24_b25_ilu0"] = variant_line(rb)
+        rb["M"].close()
+        del big
         mid = synth.mid_64cube()
         for R in (1, 8, 32):
             rr = run_gpu(args, mid, 1, "fp64", R=R, steps=2, warmup=1)

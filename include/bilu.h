@@ -124,7 +124,12 @@ typedef struct {
 /*
  * Symbolic phase (Algorithm 5 steps 1-2: Algorithm 3 with Eq 1-2) and the
  * level sets of Eq 4.  Host-only: needs no GPU.
- *   nb, bs   block rows (>= 1) and block size (1..8)
+ *   nb, bs   block rows (>= 1) and block size (1..32).  Sizes 1..8 have
+ *            block-row sweep and SpMV kernels; 9..32 (the large blocks of
+ *            Section 3, Table 2) factor by blocks, sweep at point
+ *            granularity (bilu_apply_point) and take one right-hand side,
+ *            FP64 factors, no transposed solve, no batch, no autotune, no
+ *            bilu_apply_noalloc (BILU_ERR_ARG there)
  *   Ap, Aj   host block-CSR pattern of A (borrowed, copied)
  *   k        fill level (>= 0); entries with level <= k are kept
  *   flags    BILU_WANT_TRANSPOSE or 0

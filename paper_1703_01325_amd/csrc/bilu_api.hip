@@ -301,6 +301,12 @@ bool launch_fused(int bs, int kmax, int prec, int blocks, size_t lds, hipStream_
 bool launch_spmv(int bs, int rt, bool tr, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src,
                  const double* Ax, const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr)
 {
+    if (bs > kMaxKernelBs) {
+        if (R != 1) return false;
+        hipLaunchKernelGGL(dev::k_spmv_gen, dim3(grid_for(static_cast<int64_t>(nb) * bs)), dim3(256), 0, s, nb, bs,
+                           rp, cj, tr ? src : nullptr, Ax, x, y, gate);
+        return true;
+    }
     BILU_SWITCH_B(bs, if (!launch::spmv<B>(rt, tr, nb, rp, cj, src, Ax, x, y, R, s, gate)) return false)
 }
 
@@ -313,6 +319,12 @@ bool launch_factor(int bs, int64_t first, int nrows, int lds, bilu_ctx* c, hipSt
         BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows_lds<B>), dim3(nrows), dim3(64), lds, s, rec, nrows,
                                              c->d_Pj, c->d_upd_ptr, c->d_upd_f, c->d_upd_g, c->d_P, c->d_Dinv,
                                              c->d_bad))
+    }
+    if (bs > kMaxKernelBs) {
+        const size_t glds = (3 * static_cast<size_t>(bs) * bs + bs) * sizeof(double);
+        hipLaunchKernelGGL(dev::k_factor_rows_gen, dim3(nrows), dim3(256), glds, s, bs, rows, nrows, c->d_Pp,
+                           c->d_Pj, c->d_Pdiag, c->d_upd_ptr, c->d_upd_f, c->d_upd_g, c->d_P, c->d_Dinv, c->d_bad);
+        return true;
     }
     BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_factor_rows<B>), dim3(nrows), dim3(64), 0, s, rows, nrows,
                                          c->d_Pp, c->d_Pj, c->d_Pdiag, c->d_upd_ptr, c->d_upd_f, c->d_upd_g, c->d_P,
@@ -375,7 +387,7 @@ bilu_status factor_plan(bilu_ctx* c)
             q[4] = uptr[e0];
             q[5] = uptr[d] - uptr[e0];
         }
-        c->fac_lds[l] = m <= kCap ? static_cast<int32_t>(m) : 0;
+        c->fac_lds[l] = m <= kCap && h.bs <= kMaxKernelBs ? static_cast<int32_t>(m) : 0;
     }
     bilu_status st;
     if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)) ||
@@ -387,6 +399,12 @@ bilu_status factor_plan(bilu_ctx* c)
 bool launch_split(const bilu_ctx* c, hipStream_t s)
 {
     const int64_t nP = static_cast<int64_t>(c->h.Pj.size());
+    if (c->h.bs > kMaxKernelBs) {
+        const int bs = c->h.bs;
+        hipLaunchKernelGGL(dev::k_split_gen, dim3(grid_for(nP * bs * bs)), dim3(256), 0, s, nP, bs, c->d_Prow, c->d_Pj,
+                           c->d_P, c->d_Dinv, c->d_F);
+        return true;
+    }
     BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_split<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP,
                                               c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, c->d_F))
 }
@@ -828,12 +846,142 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
     return BILU_OK;
 }
 
+// Point rows of the split factors (block size b, pattern P): point row
+// I*b + r holds, in ascending column order, the unit diagonal for the
+// diagonal block (the diagonal blocks of L and U' are identities) and b
+// entries per off-diagonal block (I, J), element (r, c) at column J*b + c.
+static void expand_point_pattern(const Host& h, std::vector<int32_t>& Ap, std::vector<int32_t>& Aj,
+                                 std::vector<int64_t>& src)
+{
+    const int b = h.bs;
+    const int64_t bb = static_cast<int64_t>(b) * b;
+    const int64_t n = static_cast<int64_t>(h.nb) * b;
+    Ap.assign(static_cast<size_t>(n) + 1, 0);
+    for (int32_t I = 0; I < h.nb; ++I) {
+        const int32_t cnt = (h.Pp[I + 1] - h.Pp[I] - 1) * b + 1;
+        for (int r = 0; r < b; ++r) Ap[static_cast<size_t>(I) * b + r + 1] = cnt;
+    }
+    for (int64_t i = 0; i < n; ++i) Ap[i + 1] += Ap[i];
+    Aj.resize(static_cast<size_t>(Ap[n]));
+    src.resize(static_cast<size_t>(Ap[n]));
+    for (int32_t I = 0; I < h.nb; ++I)
+        for (int r = 0; r < b; ++r) {
+            int64_t q = Ap[static_cast<size_t>(I) * b + r];
+            for (int32_t e = h.Pp[I]; e < h.Pp[I + 1]; ++e) {
+                const int32_t J = h.Pj[e];
+                if (J == I) {
+                    Aj[q] = I * b + r;
+                    src[q++] = -1;
+                } else {
+                    for (int c = 0; c < b; ++c) {
+                        Aj[q] = J * b + c;
+                        src[q++] = static_cast<int64_t>(e) * bb + static_cast<int64_t>(c) * b + r;
+                    }
+                }
+            }
+        }
+}
+
+// The point view of the current factors: its context (analysed once), then
+// values expanded from F after every factorisation.
+static bilu_status ensure_point(bilu_ctx* c, hipStream_t s)
+{
+    bilu_status st;
+    const Host& h = c->h;
+    const int64_t n = static_cast<int64_t>(h.nb) * h.bs;
+    if (!c->point) {
+        if (n > INT32_MAX) return BILU_ERR_ARG;
+        std::vector<int32_t> Ap, Aj;
+        std::vector<int64_t> src;
+        try {
+            expand_point_pattern(h, Ap, Aj, src);
+        } catch (const std::bad_alloc&) {
+            return BILU_ERR_ALLOC;
+        }
+        bilu_ctx* p = nullptr;
+        if ((st = bilu_analyze(static_cast<int>(n), 1, Ap.data(), Aj.data(), 0, 0, &p))) return st;
+        p->values_only = true;
+        p->sweep_mode = c->sweep_mode;
+        p->spin_limit = c->spin_limit;
+        p->timing = c->timing;
+        c->point = p;
+        c->point_gen = 0;
+        if ((st = ensure_device(p)) || (st = upload(c, &c->d_point_src, src)) ||
+            (st = dalloc(c, &c->d_point_y, static_cast<size_t>(n))))
+            return st;
+        c->point_n = static_cast<int64_t>(src.size());
+    }
+    if (c->point_gen != c->factor_gen) {
+        bilu_ctx* p = c->point;
+        if (!c->f_ready) {
+            if (!launch_split(c, s)) return BILU_ERR_ARG;
+            c->f_ready = true;
+        }
+        hipLaunchKernelGGL(dev::k_expand_point, dim3(grid_for(c->point_n)), dim3(256), 0, s, c->point_n,
+                           c->d_point_src, c->d_F, p->d_P);
+        hipLaunchKernelGGL(dev::k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, n, p->d_Dinv, 1.0);
+        CK(hipGetLastError());
+        p->factored = true;
+        if ((st = bilu_factor_diag(p, BILU_FACTORS_FP64, s))) return st;
+        c->point_gen = c->factor_gen;
+    }
+    return BILU_OK;
+}
+
+static bool launch_block_dinv(int bs, int64_t nb, const double* Dinv, const double* x, double* y, hipStream_t s,
+                              const int* gate)
+{
+    if (bs > kMaxKernelBs) {
+        hipLaunchKernelGGL(dev::k_block_dinv_gen, dim3(grid_for(nb * bs)), dim3(256), 0, s, nb, bs, Dinv, x, y, gate);
+        return true;
+    }
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_block_dinv<B>), dim3(grid_for(nb * B)), dim3(256), 0, s, nb, Dinv,
+                                         x, y, gate))
+}
+
+// Reads and clears the expired-wait flag of the point view's sweeps (1 if
+// set); the caller's own flag is read where the caller reads it.
+static int point_sweep_error(bilu_ctx* c, hipStream_t s)
+{
+    if (!c->point || !c->point->dev_ready) return 0;
+    int v = 0;
+    if (hipMemcpyAsync(&v, c->point->d_status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return 1;
+    if (v) {
+        (void)hipMemsetAsync(c->point->d_status, 0, sizeof(int), s);
+        (void)hipStreamSynchronize(s);
+    }
+    return v ? 1 : 0;
+}
+
+// z = M^{-1} r at point granularity (one right-hand side): L sweep on the
+// point rows (resets z), D^{-1} by blocks, U' sweep on the point rows with
+// the unit D^{-1} of the point context (resets y); nothing runs when gate
+// is given and *gate == 0.
+static bilu_status do_apply_point(bilu_ctx* c, const double* r, double* z, hipStream_t s, const int* gate)
+{
+    bilu_status st = ensure_point(c, s);
+    if (st) return st;
+    bilu_ctx* p = c->point;
+    if ((st = layout_form(p, sweep_form(p, 1), s)) || (st = ensure_y(p, 1, s))) return st;
+    if ((st = run_sweep(p, BILU_SWEEP_L, r, p->d_y, z, 1, s, gate))) return st;
+    if (!launch_block_dinv(c->h.bs, c->h.nb, c->d_Dinv, p->d_y, c->d_point_y, s, gate)) return BILU_ERR_ARG;
+    CK(hipGetLastError());
+    return run_sweep(p, BILU_SWEEP_U, c->d_point_y, z, p->d_y, 1, s, gate);
+}
+
 // z = M^{-1} r: first sweep r -> y (resets z), second y -> z (resets y).
 bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transpose, hipStream_t s,
                      const int* gate = nullptr)
 {
     if (!c || !r || !z || R < 1 || R > dev::kMaxRhs || r == z) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
+    if (c->h.bs > kMaxKernelBs) {
+        // block sizes without block-row sweep kernels: point granularity
+        if (R != 1 || transpose) return BILU_ERR_ARG;
+        return do_apply_point(c, r, z, s, gate);
+    }
     const int first = transpose ? BILU_SWEEP_UT : BILU_SWEEP_L;
     const int second = transpose ? BILU_SWEEP_LT : BILU_SWEEP_U;
     if (!c->h.sweep[first].built || !c->h.sweep[second].built) return BILU_ERR_STATE;
@@ -1080,6 +1228,16 @@ bilu_status bilu_factor_diag(bilu_ctx* c, int precision, hipStream_t s)
 {
     if (!c || (precision != BILU_FACTORS_FP64 && precision != BILU_FACTORS_FP32)) return BILU_ERR_ARG;
     if (!c->factored) return BILU_ERR_STATE;
+    if (c->h.bs > kMaxKernelBs) {
+        // no block-row sweep layouts: the point view is formed from F when an
+        // application first needs it
+        if (precision != BILU_FACTORS_FP64) return BILU_ERR_ARG;
+        c->f_ready = false;
+        c->precision = precision;
+        c->split_done = true;
+        ++c->factor_gen;
+        return BILU_OK;
+    }
     const long tslot = timing_begin(c, BILU_K_SPLIT, s);
     c->f_ready = false;                       // F is formed when a caller asks for it
     c->precision = precision;
@@ -1149,7 +1307,7 @@ bilu_status bilu_apply(bilu_ctx* c, const double* r, double* z, int nrhs, hipStr
 
 bilu_status bilu_apply_noalloc(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
 {
-    if (!c || !r || !z || nrhs < 1 || nrhs > dev::kMaxRhs || r == z) return BILU_ERR_ARG;
+    if (!c || !r || !z || nrhs < 1 || nrhs > dev::kMaxRhs || r == z || c->h.bs > kMaxKernelBs) return BILU_ERR_ARG;
     const int64_t ny = static_cast<int64_t>(c->h.nb) * c->h.bs * nrhs;
     if (static_cast<size_t>(ny) * sizeof(double) > kScratchBytes - kScratchHeader) return BILU_ERR_ARG;
     if (!c->dev_ready || !c->split_done) return BILU_ERR_STATE;
@@ -1184,107 +1342,11 @@ bilu_status bilu_apply_noalloc(bilu_ctx* c, const double* r, double* z, int nrhs
     return BILU_OK;
 }
 
-// Point rows of the split factors (block size b, pattern P): point row
-// I*b + r holds, in ascending column order, the unit diagonal for the
-// diagonal block (the diagonal blocks of L and U' are identities) and b
-// entries per off-diagonal block (I, J), element (r, c) at column J*b + c.
-static void expand_point_pattern(const Host& h, std::vector<int32_t>& Ap, std::vector<int32_t>& Aj,
-                                 std::vector<int64_t>& src)
-{
-    const int b = h.bs;
-    const int64_t bb = static_cast<int64_t>(b) * b;
-    const int64_t n = static_cast<int64_t>(h.nb) * b;
-    Ap.assign(static_cast<size_t>(n) + 1, 0);
-    for (int32_t I = 0; I < h.nb; ++I) {
-        const int32_t cnt = (h.Pp[I + 1] - h.Pp[I] - 1) * b + 1;
-        for (int r = 0; r < b; ++r) Ap[static_cast<size_t>(I) * b + r + 1] = cnt;
-    }
-    for (int64_t i = 0; i < n; ++i) Ap[i + 1] += Ap[i];
-    Aj.resize(static_cast<size_t>(Ap[n]));
-    src.resize(static_cast<size_t>(Ap[n]));
-    for (int32_t I = 0; I < h.nb; ++I)
-        for (int r = 0; r < b; ++r) {
-            int64_t q = Ap[static_cast<size_t>(I) * b + r];
-            for (int32_t e = h.Pp[I]; e < h.Pp[I + 1]; ++e) {
-                const int32_t J = h.Pj[e];
-                if (J == I) {
-                    Aj[q] = I * b + r;
-                    src[q++] = -1;
-                } else {
-                    for (int c = 0; c < b; ++c) {
-                        Aj[q] = J * b + c;
-                        src[q++] = static_cast<int64_t>(e) * bb + static_cast<int64_t>(c) * b + r;
-                    }
-                }
-            }
-        }
-}
-
-// The point view of the current factors: its context (analysed once), then
-// values expanded from F after every factorisation.
-static bilu_status ensure_point(bilu_ctx* c, hipStream_t s)
-{
-    bilu_status st;
-    const Host& h = c->h;
-    const int64_t n = static_cast<int64_t>(h.nb) * h.bs;
-    if (!c->point) {
-        if (n > INT32_MAX) return BILU_ERR_ARG;
-        std::vector<int32_t> Ap, Aj;
-        std::vector<int64_t> src;
-        try {
-            expand_point_pattern(h, Ap, Aj, src);
-        } catch (const std::bad_alloc&) {
-            return BILU_ERR_ALLOC;
-        }
-        bilu_ctx* p = nullptr;
-        if ((st = bilu_analyze(static_cast<int>(n), 1, Ap.data(), Aj.data(), 0, 0, &p))) return st;
-        p->values_only = true;
-        p->sweep_mode = c->sweep_mode;
-        p->spin_limit = c->spin_limit;
-        c->point = p;
-        c->point_gen = 0;
-        if ((st = ensure_device(p)) || (st = upload(c, &c->d_point_src, src)) ||
-            (st = dalloc(c, &c->d_point_y, static_cast<size_t>(n))))
-            return st;
-        c->point_n = static_cast<int64_t>(src.size());
-    }
-    if (c->point_gen != c->factor_gen) {
-        bilu_ctx* p = c->point;
-        if (!c->f_ready) {
-            if (!launch_split(c, s)) return BILU_ERR_ARG;
-            c->f_ready = true;
-        }
-        hipLaunchKernelGGL(dev::k_expand_point, dim3(grid_for(c->point_n)), dim3(256), 0, s, c->point_n,
-                           c->d_point_src, c->d_F, p->d_P);
-        hipLaunchKernelGGL(dev::k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, n, p->d_Dinv, 1.0);
-        CK(hipGetLastError());
-        p->factored = true;
-        if ((st = bilu_factor_diag(p, BILU_FACTORS_FP64, s))) return st;
-        c->point_gen = c->factor_gen;
-    }
-    return BILU_OK;
-}
-
-static bool launch_block_dinv(int bs, int64_t nb, const double* Dinv, const double* x, double* y, hipStream_t s)
-{
-    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_block_dinv<B>), dim3(grid_for(nb * B)), dim3(256), 0, s, nb, Dinv,
-                                         x, y))
-}
-
 bilu_status bilu_apply_point(bilu_ctx* c, const double* r, double* z, hipStream_t s)
 {
     if (!c || !r || !z || r == z) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
-    bilu_status st = ensure_point(c, s);
-    if (st) return st;
-    bilu_ctx* p = c->point;
-    if ((st = layout_form(p, sweep_form(p, 1), s)) || (st = ensure_y(p, 1, s))) return st;
-    // L sweep on the point rows (resets z), D^{-1} by blocks, U' sweep on
-    // the point rows with the unit D^{-1} of the point context (resets y)
-    if ((st = run_sweep(p, BILU_SWEEP_L, r, p->d_y, z, 1, s, nullptr))) return st;
-    if (!launch_block_dinv(c->h.bs, c->h.nb, c->d_Dinv, p->d_y, c->d_point_y, s)) return BILU_ERR_ARG;
-    CK(hipGetLastError());
-    return run_sweep(p, BILU_SWEEP_U, c->d_point_y, z, p->d_y, 1, s, nullptr);
+    return do_apply_point(c, r, z, s, nullptr);
 }
 
 bilu_status bilu_apply_transpose(bilu_ctx* c, const double* r, double* z, int nrhs, hipStream_t s)
@@ -1404,7 +1466,7 @@ static bilu_status time_apply(bilu_ctx* c, const double* r, double* z, int R, hi
 
 bilu_status bilu_autotune(bilu_ctx* c, int nrhs, hipStream_t s, bilu_tune_result* out)
 {
-    if (!c || !out || nrhs < 1 || nrhs > dev::kMaxRhs) return BILU_ERR_ARG;
+    if (!c || !out || nrhs < 1 || nrhs > dev::kMaxRhs || c->h.bs > kMaxKernelBs) return BILU_ERR_ARG;
     if (!c->split_done) return BILU_ERR_STATE;
     std::memset(out, 0, sizeof(*out));
     // tile_rows / group: the layout requests (0: by schedule simulation)
@@ -1491,6 +1553,8 @@ bilu_status bilu_timing(bilu_ctx* c, int enable)
         c->ev_marks.clear();
     }
     c->timing = enable != 0;
+    // the point view's sweeps are timed with the caller's
+    if (c->point) bilu_timing(c->point, enable);
     return BILU_OK;
 }
 
@@ -1499,11 +1563,14 @@ bilu_status bilu_timing_read(bilu_ctx* c, hipStream_t s, bilu_kernel_time* out)
     if (!c || !out) return BILU_ERR_ARG;
     for (int k = 0; k < BILU_K_COUNT; ++k) out[k] = bilu_kernel_time{0, 0.0};
     CK(hipStreamSynchronize(s));
-    for (const auto& m : c->ev_marks) {
-        float ms = 0.f;
-        CK(hipEventElapsedTime(&ms, c->ev_pool[m.second], c->ev_pool[m.second + 1]));
-        out[m.first].launches += 1;
-        out[m.first].total_ms += ms;
+    for (const bilu_ctx* t : {static_cast<const bilu_ctx*>(c), static_cast<const bilu_ctx*>(c->point)}) {
+        if (!t) continue;
+        for (const auto& m : t->ev_marks) {
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, t->ev_pool[m.second], t->ev_pool[m.second + 1]));
+            out[m.first].launches += 1;
+            out[m.first].total_ms += ms;
+        }
     }
     return BILU_OK;
 }
@@ -1512,6 +1579,7 @@ bilu_status bilu_check(bilu_ctx* c, hipStream_t s)
 {
     if (!c) return BILU_ERR_ARG;
     if (!c->dev_ready) return BILU_OK;
+    if (point_sweep_error(c, s)) return BILU_ERR_TIMEOUT;
     int v = 0;
     CK(hipMemcpyAsync(&v, c->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
@@ -1653,6 +1721,7 @@ static bilu_status bicgstab(bilu_ctx* c, const double* Ax, const double* b, doub
         info[j].reserved = 0;
         if (stj > worst) worst = stj;
     }
+    if (point_sweep_error(c, s)) sweep_err = 1;
     if (sweep_err) {
         CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
         CK(hipStreamSynchronize(s));
@@ -1791,6 +1860,7 @@ static bilu_status gmres(bilu_ctx* c, const double* Ax, const double* b, double*
     info[0].relres = bnorm > 0.0 ? rres / bnorm : 0.0;
     info[0].restarts = cycles;
     info[0].reserved = 0;
+    if (point_sweep_error(c, s)) sweep_err = 1;
     if (sweep_err) {
         CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
         CK(hipStreamSynchronize(s));
@@ -1876,6 +1946,7 @@ static bilu_status orthomin(bilu_ctx* c, const double* Ax, const double* b, doub
     info[0].relres = hs->bnorm2 > 0 ? std::sqrt(hs->tnorm2 / hs->bnorm2) : 0.0;
     info[0].restarts = hs->nrestart;
     info[0].reserved = 0;
+    if (point_sweep_error(c, s)) sweep_err = 1;
     if (sweep_err) {
         CK(hipMemsetAsync(c->d_status, 0, sizeof(int), s));
         CK(hipStreamSynchronize(s));

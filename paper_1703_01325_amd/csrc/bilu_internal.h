@@ -12,7 +12,9 @@
 namespace bilu {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kMaxBs = 8;
+constexpr int kMaxBs = 32;          // block sizes the library accepts
+constexpr int kMaxKernelBs = 8;     // block sizes with block-row sweep and SpMV kernels;
+                                    // larger ones sweep at point granularity
 
 // Rows of a sweep grouped for the GPU: level by level (Eq 4), a level's rows
 // cut into chunks of `rpc` rows (one wavefront each), chunk c holding

@@ -316,8 +316,9 @@ __global__ void k_expand_point(int64_t n, const int64_t* __restrict__ src, const
 // block sweep that fuses D^{-1}.
 template <int B>
 __global__ void k_block_dinv(int64_t nb, const double* __restrict__ Dinv, const double* __restrict__ x,
-                             double* __restrict__ y)
+                             double* __restrict__ y, const int* gate)
 {
+    if (gated_off(gate)) return;
     constexpr int BB = B * B;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nb * B;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -326,6 +327,181 @@ __global__ void k_block_dinv(int64_t nb, const double* __restrict__ Dinv, const 
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < B; ++c) acc += Dinv[I * BB + c * B + r] * x[I * B + c];
+        y[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block sizes above the ones the templated kernels are built for (9..32):
+// the same operations with the block size a run-time value and a workgroup
+// of 256 threads per block row.  The sweeps of such systems run at point
+// granularity (bilu_apply_point), so only the factorisation, the split, the
+// block D^{-1} and the SpMV need these.
+// ---------------------------------------------------------------------------
+// Block ILU(0) on P (Algorithm 4) for the block rows of one L level, block
+// size bs: for each pivot entry (i, p) in order, A_ip <- A_ip D_p^{-1}
+// (staged in LDS), then the update pairs of the host-built lists,
+// A_ij <- A_ij - A_ip A_pj, over (pair, element) in parallel (distinct
+// targets); then D_i^{-1} by Gauss-Jordan with partial pivoting on
+// [A_ii | I].  LDS: bs*bs + 2*bs*bs + bs doubles.
+__global__ __launch_bounds__(256) void k_factor_rows_gen(int bs, const int32_t* __restrict__ rows, int nrows,
+                                                         const int32_t* __restrict__ Pp,
+                                                         const int32_t* __restrict__ Pj,
+                                                         const int32_t* __restrict__ Pdiag,
+                                                         const int32_t* __restrict__ upd_ptr,
+                                                         const int32_t* __restrict__ upd_f,
+                                                         const int32_t* __restrict__ upd_g, double* __restrict__ P,
+                                                         double* __restrict__ Dinv, int* bad_row)
+{
+    extern __shared__ double gsm[];
+    __shared__ int sPiv;
+    __shared__ int sBad;
+    if (static_cast<int>(blockIdx.x) >= nrows) return;
+    const int bb = bs * bs;
+    const int w2 = 2 * bs;
+    double* sT = gsm;
+    double* sW = gsm + bb;
+    double* sF = sW + 2 * bb;
+    const int i = rows[blockIdx.x];
+    const int e0 = Pp[i];
+    const int d = Pdiag[i];
+    const int t = threadIdx.x;
+    const int nt = blockDim.x;
+    if (t == 0) sBad = 0;
+    for (int e = e0; e < d; ++e) {
+        const int p = Pj[e];
+        const double* Aip = P + static_cast<int64_t>(e) * bb;
+        const double* Dp = Dinv + static_cast<int64_t>(p) * bb;
+        for (int el = t; el < bb; el += nt) {
+            const int c = el / bs, r = el - (el / bs) * bs;
+            double v = 0.0;
+            for (int u = 0; u < bs; ++u) v += Aip[u * bs + r] * Dp[c * bs + u];
+            sT[el] = v;
+        }
+        __syncthreads();
+        for (int el = t; el < bb; el += nt) P[static_cast<int64_t>(e) * bb + el] = sT[el];
+        const int q0 = upd_ptr[e];
+        const int64_t work = static_cast<int64_t>(upd_ptr[e + 1] - q0) * bb;
+        for (int64_t x = t; x < work; x += nt) {
+            const int q = q0 + static_cast<int>(x / bb);
+            const int el = static_cast<int>(x % bb);
+            const int c = el / bs, r = el - (el / bs) * bs;
+            const double* Apj = P + static_cast<int64_t>(upd_g[q]) * bb;
+            double acc = 0.0;
+            for (int u = 0; u < bs; ++u) acc += sT[u * bs + r] * Apj[c * bs + u];
+            P[static_cast<int64_t>(e0 + upd_f[q]) * bb + el] -= acc;
+        }
+        __syncthreads();
+    }
+    // Gauss-Jordan on [A_ii | I], row-major in LDS
+    for (int x = t; x < bs * w2; x += nt) {
+        const int r = x / w2, c = x - (x / w2) * w2;
+        sW[x] = c < bs ? P[static_cast<int64_t>(d) * bb + c * bs + r] : (c - bs == r ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int col = 0; col < bs; ++col) {
+        if (t == 0) {
+            int piv = col;
+            double best = fabs(sW[col * w2 + col]);
+            for (int rr = col + 1; rr < bs; ++rr) {
+                const double v = fabs(sW[rr * w2 + col]);
+                if (v > best) {
+                    best = v;
+                    piv = rr;
+                }
+            }
+            if (!(best > 0.0) || !isfinite(best)) sBad = 1;
+            sPiv = piv;
+        }
+        __syncthreads();
+        const int piv = sPiv;
+        if (piv != col)
+            for (int x = t; x < w2; x += nt) {
+                const double tmp = sW[col * w2 + x];
+                sW[col * w2 + x] = sW[piv * w2 + x];
+                sW[piv * w2 + x] = tmp;
+            }
+        __syncthreads();
+        const double dd = sW[col * w2 + col];
+        __syncthreads();
+        for (int x = t; x < w2; x += nt) sW[col * w2 + x] /= dd;
+        __syncthreads();
+        for (int rr = t; rr < bs; rr += nt) sF[rr] = sW[rr * w2 + col];
+        __syncthreads();
+        for (int x = t; x < bs * w2; x += nt) {
+            const int rr = x / w2, cc = x - (x / w2) * w2;
+            if (rr != col) sW[x] -= sF[rr] * sW[col * w2 + cc];
+        }
+        __syncthreads();
+    }
+    for (int el = t; el < bb; el += nt) {
+        const int c = el / bs, r = el - (el / bs) * bs;
+        Dinv[static_cast<int64_t>(i) * bb + el] = sW[r * w2 + bs + c];
+    }
+    if (t == 0 && sBad) atomicMin(bad_row, i);
+}
+
+// F from P and D^{-1} (as k_split), block size bs at run time
+__global__ void k_split_gen(int64_t nP, int bs, const int32_t* __restrict__ Prow, const int32_t* __restrict__ Pj,
+                            const double* __restrict__ P, const double* __restrict__ Dinv, double* __restrict__ F)
+{
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < nP * bb;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = g / bb;
+        const int el = static_cast<int>(g - e * bb);
+        const int c = el / bs, r = el - (el / bs) * bs;
+        const int i = Prow[e], j = Pj[e];
+        double v;
+        if (j < i) {
+            v = P[g];
+        } else if (j == i) {
+            v = r == c ? 1.0 : 0.0;
+        } else {
+            const double* Di = Dinv + static_cast<int64_t>(i) * bb;
+            const double* U = P + e * bb;
+            v = 0.0;
+            for (int u = 0; u < bs; ++u) v += Di[u * bs + r] * U[c * bs + u];
+        }
+        F[g] = v;
+    }
+}
+
+// y = D^{-1} x by blocks (as k_block_dinv), block size bs at run time
+__global__ void k_block_dinv_gen(int64_t nb, int bs, const double* __restrict__ Dinv, const double* __restrict__ x,
+                                 double* __restrict__ y, const int* gate)
+{
+    if (gated_off(gate)) return;
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nb * bs;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t I = i / bs;
+        const int r = static_cast<int>(i - I * bs);
+        double acc = 0.0;
+        for (int c = 0; c < bs; ++c) acc += Dinv[I * bb + c * bs + r] * x[I * bs + c];
+        y[i] = acc;
+    }
+}
+
+// y = A x (or A^T x through the transposed structure), one right-hand side,
+// one thread per point row, products summed as in spmv_rows (blocks in
+// order, components in order); block size bs at run time
+__global__ void k_spmv_gen(int nb, int bs, const int32_t* __restrict__ rp, const int32_t* __restrict__ cj,
+                           const int64_t* __restrict__ srcpos, const double* __restrict__ Ax,
+                           const double* __restrict__ x, double* __restrict__ y, const int* gate)
+{
+    if (gated_off(gate)) return;
+    const int64_t bb = static_cast<int64_t>(bs) * bs;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < static_cast<int64_t>(nb) * bs;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t I = i / bs;
+        const int r = static_cast<int>(i - I * bs);
+        double acc = 0.0;
+        for (int e = rp[I]; e < rp[I + 1]; ++e) {
+            const int64_t j = cj[e];
+            const double* A = Ax + (srcpos ? srcpos[e] : static_cast<int64_t>(e)) * bb;
+            for (int c = 0; c < bs; ++c) acc += (srcpos ? A[r * bs + c] : A[c * bs + r]) * x[j * bs + c];
+        }
         y[i] = acc;
     }
 }
