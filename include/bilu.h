@@ -79,6 +79,9 @@ typedef enum { BILU_BICGSTAB = 0, BILU_GMRES = 1, BILU_ORTHOMIN = 2 } bilu_metho
 
 /* bilu_analyze flags */
 #define BILU_WANT_TRANSPOSE 1   /* also build U'^T / L^T sweeps and A^T SpMV */
+#define BILU_DEVICE_SYMBOLIC 2  /* symbolic phase and level sets on the current GPU
+                                   (bilu_symbolic_device / bilu_levels_device), results
+                                   copied back; the same pattern and levels as the host */
 
 typedef struct bilu_ctx bilu_ctx;
 
@@ -132,10 +135,12 @@ typedef struct {
  *            bilu_apply_noalloc (BILU_ERR_ARG there)
  *   Ap, Aj   host block-CSR pattern of A (borrowed, copied)
  *   k        fill level (>= 0); entries with level <= k are kept
- *   flags    BILU_WANT_TRANSPOSE or 0
+ *   flags    BILU_WANT_TRANSPOSE and/or BILU_DEVICE_SYMBOLIC, or 0
  *   out      receives a new context (free with bilu_destroy)
  * Errors: BILU_ERR_ARG, BILU_ERR_PATTERN, BILU_ERR_MISSING_DIAG,
- * BILU_ERR_ALLOC.  Device memory is allocated on first factorisation.
+ * BILU_ERR_ALLOC (with BILU_DEVICE_SYMBOLIC also those of
+ * bilu_symbolic_device / bilu_levels_device).  Device memory is allocated on
+ * first factorisation.
  */
 bilu_status bilu_analyze(int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k,
                          int flags, bilu_ctx** out);
@@ -152,6 +157,52 @@ bilu_status bilu_get_levels(const bilu_ctx* ctx, int sweep, int* nlev,
                             const int32_t** level_ptr, const int32_t** level_rows);
 
 bilu_status bilu_get_info(const bilu_ctx* ctx, bilu_info* info);
+
+/*
+ * Symbolic phase on the GPU (Algorithm 3 with Eq 1-2): the ILU(k) pattern P
+ * and the level of fill of every kept entry, identical to bilu_analyze's
+ * (bilu_get_pattern).  Each row is searched independently: (i, j) is kept
+ * with level l when the shortest path from i to j in the graph of A whose
+ * inner vertices all lie below min(i, j) has l + 1 edges, which gives the
+ * levels of Eq 1-2's row-by-row recurrence.
+ *   nb       block rows (>= 1)
+ *   Ap, Aj   device block-CSR pattern of A (Ap[nb+1], Aj[Ap[nb]]), columns
+ *            strictly ascending per row, diagonal present (checked)
+ *   k        fill level, 0..250
+ *   Pp       device [nb+1]: receives the row pointers of P
+ *   Pj, lev  device [cap] each: receive the columns (ascending per row) and
+ *            levels of P; both NULL with cap = 0 to query the size
+ *   nnzb     host: receives the number of entries of P
+ *   stream   hipStream_t (NULL: the default stream); the call returns once
+ *            the results are complete
+ * Buffers are the caller's; the call allocates and frees device scratch.
+ * Errors: BILU_ERR_ARG (bad argument, or cap < *nnzb: Pp and *nnzb are
+ * still set), BILU_ERR_PATTERN, BILU_ERR_MISSING_DIAG, BILU_ERR_ALLOC (a
+ * row's search reaches more than 768 distinct block columns, or P exceeds
+ * 2^31 - 1 entries), BILU_ERR_HIP.
+ */
+bilu_status bilu_symbolic_device(int nb, const int32_t* Ap, const int32_t* Aj, int k, int32_t* Pp,
+                                 int32_t* Pj, int32_t* lev, int64_t cap, int64_t* nnzb, void* stream);
+
+/*
+ * Level sets of one sweep on the GPU (Eq 4, Algorithm 6): the level of a row
+ * is one more than the deepest row it reads, 0 for a row that reads none;
+ * identical to bilu_get_levels for the same pattern.
+ *   nb           block rows
+ *   Pp, Pj       device pattern of P (ascending columns, diagonal present)
+ *   sweep        bilu_sweep (L and U' read the rows of P below / above the
+ *                diagonal; U'^T and L^T the columns)
+ *   lvl          device [nb]: receives the level of every row
+ *   level_ptr    device [nb+1]: receives level_ptr[0..nlev]
+ *   level_rows   device [nb]: receives the rows ordered by level, ascending
+ *                inside a level
+ *   nlev         host: receives the number of levels
+ *   stream       as for bilu_symbolic_device; the call returns once done
+ * Errors: BILU_ERR_ARG, BILU_ERR_ALLOC, BILU_ERR_HIP, BILU_ERR_TIMEOUT (a
+ * bounded wait expired: the pattern is not one of P's forms).
+ */
+bilu_status bilu_levels_device(int nb, const int32_t* Pp, const int32_t* Pj, int sweep, int32_t* lvl,
+                               int32_t* level_ptr, int32_t* level_rows, int* nlev, void* stream);
 
 /* Host-only self-check of the sweep layouts: every row appears once per
  * sweep, every index is in range, every dependency sits in a strictly

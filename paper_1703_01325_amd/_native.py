@@ -23,10 +23,12 @@ SWEEP_L, SWEEP_U, SWEEP_UT, SWEEP_LT = 0, 1, 2, 3
 FACTORS_FP64, FACTORS_FP32 = 0, 1
 BICGSTAB, GMRES, ORTHOMIN = 0, 1, 2
 WANT_TRANSPOSE = 1
+DEVICE_SYMBOLIC = 2
 
 # every symbol declared in include/bilu.h
 EXPORTS = (
     "bilu_analyze", "bilu_get_pattern", "bilu_get_levels", "bilu_get_info", "bilu_validate",
+    "bilu_symbolic_device", "bilu_levels_device",
     "bilu_factor_numeric", "bilu_factor_diag", "bilu_get_factors", "bilu_get_factors_f32",
     "bilu_apply", "bilu_apply_noalloc", "bilu_apply_point", "bilu_apply_transpose", "bilu_spmv", "bilu_solve", "bilu_grad_A",
     "bilu_tune", "bilu_autotune", "bilu_check", "bilu_timing", "bilu_timing_read",
@@ -93,6 +95,8 @@ def _load():
     L.bilu_get_levels.argtypes = [VP, I, ct.POINTER(I), ct.POINTER(P), ct.POINTER(P)]
     L.bilu_get_info.argtypes = [VP, ct.POINTER(BiluInfo)]
     L.bilu_validate.argtypes = [VP]
+    L.bilu_symbolic_device.argtypes = [I, P, P, I, P, P, P, ct.c_int64, ct.POINTER(ct.c_int64), P]
+    L.bilu_levels_device.argtypes = [I, P, P, I, P, P, P, ct.POINTER(I), P]
     L.bilu_factor_numeric.argtypes = [VP, P, P, ct.POINTER(I)]
     L.bilu_factor_diag.argtypes = [VP, I, P]
     L.bilu_get_factors.argtypes = [VP, P, P, P]
@@ -183,6 +187,23 @@ def bilu_get_levels(ctx, sweep):
     lp = np.ctypeslib.as_array(ct.cast(ptr, ct.POINTER(ct.c_int32)), shape=(nlev.value + 1,)).copy()
     lr = np.ctypeslib.as_array(ct.cast(rows, ct.POINTER(ct.c_int32)), shape=(nb,)).copy()
     return lp, lr
+
+
+def bilu_symbolic_device(nb, Ap_ptr, Aj_ptr, k, Pp_ptr, Pj_ptr, lev_ptr, cap, stream):
+    """Device pointers in; returns the entry count of P (Pj_ptr = lev_ptr =
+    None with cap 0: size query, only Pp is written)."""
+    n = ct.c_int64()
+    _check(lib.bilu_symbolic_device(int(nb), Ap_ptr, Aj_ptr, int(k), Pp_ptr, Pj_ptr, lev_ptr, int(cap),
+                                    ct.byref(n), stream), "bilu_symbolic_device")
+    return n.value
+
+
+def bilu_levels_device(nb, Pp_ptr, Pj_ptr, sweep, lvl_ptr, level_ptr_ptr, level_rows_ptr, stream):
+    """Device pointers in; returns the level count."""
+    nlev = ct.c_int()
+    _check(lib.bilu_levels_device(int(nb), Pp_ptr, Pj_ptr, int(sweep), lvl_ptr, level_ptr_ptr, level_rows_ptr,
+                                  ct.byref(nlev), stream), "bilu_levels_device")
+    return nlev.value
 
 
 def bilu_get_info(ctx):

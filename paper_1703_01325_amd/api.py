@@ -22,20 +22,57 @@ def _dev_f64(t: torch.Tensor, name: str):
     return t
 
 
+def _dev_i32(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous int32 CUDA tensor")
+    return t
+
+
+def symbolic_device(Ap: torch.Tensor, Aj: torch.Tensor, k: int):
+    """Symbolic phase on the GPU (Algorithm 3, Eq 1-2): (Pp, Pj, lev) of the
+    ILU(k) pattern as int32 CUDA tensors, from A's block pattern on the GPU."""
+    _dev_i32(Ap, "Ap")
+    _dev_i32(Aj, "Aj")
+    nb = Ap.numel() - 1
+    Pp = torch.empty(nb + 1, dtype=torch.int32, device=Ap.device)
+    nnz = N.bilu_symbolic_device(nb, Ap.data_ptr(), Aj.data_ptr(), k, Pp.data_ptr(), None, None, 0, _stream())
+    Pj = torch.empty(max(nnz, 1), dtype=torch.int32, device=Ap.device)
+    lev = torch.empty(max(nnz, 1), dtype=torch.int32, device=Ap.device)
+    N.bilu_symbolic_device(nb, Ap.data_ptr(), Aj.data_ptr(), k, Pp.data_ptr(), Pj.data_ptr(), lev.data_ptr(),
+                           nnz, _stream())
+    return Pp, Pj[:nnz], lev[:nnz]
+
+
+def levels_device(Pp: torch.Tensor, Pj: torch.Tensor, sweep: int):
+    """Level sets of one sweep on the GPU (Eq 4): (lvl, level_ptr, level_rows)
+    as int32 CUDA tensors, level_ptr of length nlev + 1."""
+    _dev_i32(Pp, "Pp")
+    _dev_i32(Pj, "Pj")
+    nb = Pp.numel() - 1
+    lvl = torch.empty(nb, dtype=torch.int32, device=Pp.device)
+    ptr = torch.empty(nb + 1, dtype=torch.int32, device=Pp.device)
+    rows = torch.empty(nb, dtype=torch.int32, device=Pp.device)
+    nlev = N.bilu_levels_device(nb, Pp.data_ptr(), Pj.data_ptr(), sweep, lvl.data_ptr(), ptr.data_ptr(),
+                                rows.data_ptr(), _stream())
+    return lvl, ptr[:nlev + 1], rows
+
+
 class BlockILU:
     """Decoupled block ILU(k) of one block pattern (Algorithm 5, Eq 5).
 
     ``BlockILU(nb, bs, Ap, Aj, k)`` runs the symbolic phase and the level
-    sets on the host; ``factor(Ax)`` runs the numeric phase and the diagonal
-    split on the GPU; ``apply``/``spmv``/``solve`` run the hot path.
+    sets on the host (``device_symbolic=True``: on the GPU, the same
+    results); ``factor(Ax)`` runs the numeric phase and the diagonal split
+    on the GPU; ``apply``/``spmv``/``solve`` run the hot path.
     """
 
-    def __init__(self, nb, bs, Ap, Aj, k, transpose=False):
+    def __init__(self, nb, bs, Ap, Aj, k, transpose=False, device_symbolic=False):
         self.nb, self.bs, self.k = int(nb), int(bs), int(k)
         self.n = self.nb * self.bs
         self.Ap = np.ascontiguousarray(Ap, np.int32)
         self.Aj = np.ascontiguousarray(Aj, np.int32)
-        self._ctx = N.bilu_analyze(nb, bs, self.Ap, self.Aj, k, N.WANT_TRANSPOSE if transpose else 0)
+        flags = (N.WANT_TRANSPOSE if transpose else 0) | (N.DEVICE_SYMBOLIC if device_symbolic else 0)
+        self._ctx = N.bilu_analyze(nb, bs, self.Ap, self.Aj, k, flags)
         self.transpose = bool(transpose)
         self.precision = None
         self._owned = True

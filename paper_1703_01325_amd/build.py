@@ -2,8 +2,9 @@
 
 hipcc compiles the HIP translation units for the device (gfx950) and the
 host -- the ABI and the non-sweep kernels (bilu_api.hip), the sweep and
-SpMV kernels once per block size (sweep_b.hip with -DBILU_B=1..8) and the
-batch sweep (batch_sweep.hip) -- in parallel; g++ compiles the host-only
+SpMV kernels once per block size (sweep_b.hip with -DBILU_B=1..8), the
+batch sweep (batch_sweep.hip) and the device symbolic phase (symbolic.hip)
+-- in parallel; g++ compiles the host-only
 analysis.  Every HIP compile carries
 ``-Xclang -target-feature -Xclang -packed-fp32-ops`` (no packed FP32 ops).
 """
@@ -52,6 +53,7 @@ def build(verbose: bool = False) -> str:
     for b in range(1, 9):
         hip_job("sweep_b.hip", f"sweep_b{b}.o", f"-DBILU_B={b}")
     hip_job("batch_sweep.hip", "batch_sweep.o")
+    hip_job("symbolic.hip", "symbolic.o")
     objs.append(os.path.join(OUT_DIR, "analysis.o"))
     jobs.append(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "analysis.cpp"), "-o", objs[-1]])
     workers = max(1, min(len(jobs), int(os.environ.get("BILU_BUILD_JOBS", os.cpu_count() or 1))))

@@ -181,7 +181,13 @@ void build_sweep(const Host& h, int which, int rpc, HostSweep& s)
     s.which = which;
     s.rpc = rpc;
     s.transposed_blocks = (which == BILU_SWEEP_UT || which == BILU_SWEEP_LT);
-    s.nlev = sweep_levels(nb, h.Pp, h.Pj, which, lvl);
+    if (!h.dev_lvl[which].empty()) {
+        lvl = h.dev_lvl[which];
+        s.nlev = 0;
+        for (int32_t v : lvl) s.nlev = std::max(s.nlev, v + 1);
+    } else {
+        s.nlev = sweep_levels(nb, h.Pp, h.Pj, which, lvl);
+    }
     s.level_ptr.assign(static_cast<size_t>(s.nlev) + 1, 0);
     for (int32_t i = 0; i < nb; ++i) s.level_ptr[lvl[i] + 1]++;
     for (int l = 0; l < s.nlev; ++l) s.level_ptr[l + 1] += s.level_ptr[l];
@@ -1063,7 +1069,10 @@ int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, 
     for (int32_t i = 0; i < nb; ++i)
         for (int32_t e = Ap[i]; e < Ap[i + 1]; ++e) h.Arow[e] = i;
 
-    st = symbolic_iluk(nb, Ap, Aj, k, h.Pp, h.Pj, h.Plev);
+    if (flags & BILU_DEVICE_SYMBOLIC)
+        st = device_analysis(nb, Ap, Aj, k, (flags & BILU_WANT_TRANSPOSE) ? 4 : 2, h.Pp, h.Pj, h.Plev, h.dev_lvl);
+    else
+        st = symbolic_iluk(nb, Ap, Aj, k, h.Pp, h.Pj, h.Plev);
     if (st != BILU_OK) return st;
     const size_t nP = h.Pj.size();
     h.Pdiag.resize(static_cast<size_t>(nb));

@@ -186,6 +186,9 @@ struct Host {
     // A^T structure: row j lists the blocks (i, j) of A; ATsrc = their position in A
     std::vector<int32_t> ATp, ATj;
     std::vector<int64_t> ATsrc;
+    // levels of each sweep from the device symbolic phase (empty: computed
+    // on the host)
+    std::vector<int32_t> dev_lvl[4];
     HostSweep sweep[4];
     HostTiled tiled[4];
     HostTiled lines[4];     // line-sweep layouts (L and U' only; see build_line_layout)
@@ -199,6 +202,10 @@ int sweep_levels(int nb, const std::vector<int32_t>& Pp, const std::vector<int32
                  int which, std::vector<int32_t>& lvl);
 void build_sweep(const Host& h, int which, int rpc, HostSweep& out);
 int analyze_host(Host& h, int nb, int bs, const int32_t* Ap, const int32_t* Aj, int k, int flags);
+// The symbolic phase and the level sets of the first nsweeps sweeps run on
+// the current GPU (symbolic.hip), results copied back (BILU_DEVICE_SYMBOLIC).
+int device_analysis(int nb, const int32_t* Ap, const int32_t* Aj, int k, int nsweeps, std::vector<int32_t>& Pp,
+                    std::vector<int32_t>& Pj, std::vector<int32_t>& Plev, std::vector<int32_t> (&lvl)[4]);
 // Tiled layout of one sweep with tiles of tile_rows rows in groups of up to
 // `group` tiles (falls back to smaller groups, down to 1, where a grouping
 // would break the ticket order or the group's LDS exceeds lds_limit bytes).
