@@ -364,6 +364,12 @@ enum {
                                  of at most 2 tiles; larger groups run without);
                                  2: never.
                                  bilu_autotune times both                           */
+    BILU_TUNE_SPMV_STREAM = 10, /* A x with one right-hand side, b <= 3: 1 stages each
+                                 wavefront's run of A through LDS with nontemporal
+                                 whole-wavefront loads, the rows in contiguous
+                                 ranges per XCD (A fetched once, x kept in L2);
+                                 2: direct loads; 0 (default): staged from 2^19
+                                 block rows up.  Same bits either way              */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

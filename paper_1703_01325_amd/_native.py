@@ -280,6 +280,7 @@ TUNE_SWEEP_MODE, TUNE_TILE_ROWS, TUNE_BLOCKS, TUNE_RHS_TILE, TUNE_FUSE_SPMV, TUN
 TUNE_TILE_BLOCK = 7
 TUNE_LINE_SWEEP = 8
 TUNE_HELPER = 9
+TUNE_SPMV_STREAM = 10
 
 
 def bilu_tune(ctx, param, value):

@@ -91,7 +91,7 @@ class BlockILU:
         N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
 
     def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None,
-             tile_block=None, line_sweep=None, helper=None):
+             tile_block=None, line_sweep=None, helper=None, spmv_stream=None):
         """Launch knobs of the sweeps (results are bit-identical for all)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
                          (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
@@ -101,6 +101,8 @@ class BlockILU:
                           (0 if not line_sweep else line_sweep[0] + 256 * line_sweep[1])),
                          (N.TUNE_HELPER, None if helper is None else
                           (0 if helper == "auto" else 1 if helper else 2)),
+                         (N.TUNE_SPMV_STREAM, None if spmv_stream is None else
+                          (0 if spmv_stream == "auto" else 1 if spmv_stream else 2)),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

@@ -121,6 +121,7 @@ struct bilu_ctx {
     // pivots, first update pair, update pairs, 0, 0}
     int32_t* d_frec = nullptr;
     std::vector<int32_t> fac_lds;
+    int spmv_stream = 0;                  // BILU_TUNE_SPMV_STREAM
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
     int64_t* d_ATsrc = nullptr;
     double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
@@ -239,6 +240,18 @@ int spmv_tile(const bilu_ctx* c, int R)
     if (R == 1) return 1;
     return c->rhs_tile > 0 ? c->rhs_tile : 0;
 }
+
+// Whether A x with R columns stages A through LDS with nontemporal loads in
+// XCD-contiguous row ranges (BILU_TUNE_SPMV_STREAM; automatic: one column,
+// b <= 3, at least 2^19 block rows -- measured on MI355X: 60x220x85, b = 3,
+// 155-159 -> 145 us with 29% fewer fetched bytes; 64^3, b = 3, 32 -> 39 us,
+// where the lower occupancy of the staged kernel costs more than it saves).
+bool spmv_streams_a(const bilu_ctx* c, int R)
+{
+    if (R != 1 || c->h.bs > 3 || c->spmv_stream == 2) return false;
+    return c->spmv_stream == 1 || c->h.nb >= (1 << 19);
+}
+
 bool transposed_sweep(int w) { return w == BILU_SWEEP_UT || w == BILU_SWEEP_LT; }
 
 // Helper wavefronts for a tiled sweep of R columns.  Automatic: for single
@@ -299,7 +312,8 @@ bool launch_fused(int bs, int kmax, int prec, int blocks, size_t lds, hipStream_
 }
 
 bool launch_spmv(int bs, int rt, bool tr, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src,
-                 const double* Ax, const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr)
+                 const double* Ax, const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr,
+                 bool stream_a = false)
 {
     if (bs > kMaxKernelBs) {
         if (R != 1) return false;
@@ -307,7 +321,7 @@ bool launch_spmv(int bs, int rt, bool tr, int nb, const int32_t* rp, const int32
                            rp, cj, tr ? src : nullptr, Ax, x, y, gate);
         return true;
     }
-    BILU_SWITCH_B(bs, if (!launch::spmv<B>(rt, tr, nb, rp, cj, src, Ax, x, y, R, s, gate)) return false)
+    BILU_SWITCH_B(bs, if (!launch::spmv<B>(rt, tr, nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a)) return false)
 }
 
 // Rows [first, first + nrows) of the L level order.
@@ -1009,7 +1023,8 @@ bilu_status do_spmv(bilu_ctx* c, const double* Ax, const double* x, double* y, i
         if (!(h.flags & BILU_WANT_TRANSPOSE)) return BILU_ERR_STATE;
         ok = launch_spmv(h.bs, spmv_tile(c, R), true, h.nb, c->d_ATp, c->d_ATj, c->d_ATsrc, Ax, x, y, R, s, gate);
     } else {
-        ok = launch_spmv(h.bs, spmv_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s, gate);
+        ok = launch_spmv(h.bs, spmv_tile(c, R), false, h.nb, c->d_Ap, c->d_Aj, nullptr, Ax, x, y, R, s, gate,
+                         spmv_streams_a(c, R));
     }
     timing_end(c, tslot, s);
     if (!ok) return BILU_ERR_ARG;
@@ -1402,6 +1417,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
     case BILU_TUNE_HELPER:
         if (value < 0 || value > 2) return BILU_ERR_ARG;
         c->helper = value;
+        return BILU_OK;
+    case BILU_TUNE_SPMV_STREAM:
+        if (value < 0 || value > 2) return BILU_ERR_ARG;
+        c->spmv_stream = value;
         return BILU_OK;
     case BILU_TUNE_LINE_SWEEP: {
         const int ny = value & 255, nz = value >> 8;

@@ -42,10 +42,11 @@ bool lines(int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& 
 
 // y = A x (trans = false) or A^T x, rt columns per pass (1, 4 or 8), or
 // rt = 0: lanes over the R columns (2 <= R <= 32); nothing runs when gate
-// is given and *gate == 0.
+// is given and *gate == 0.  stream_a (one column, A x, b <= 3): A staged
+// through LDS with nontemporal loads, rows in contiguous ranges per XCD.
 template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
-          const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr);
+          const double* x, double* y, int R, hipStream_t s, const int* gate = nullptr, bool stream_a = false);
 
 // Batch sweep over the members' tiled layouts (every block size in one
 // kernel); fuse: the second sweep of an application (D^{-1} fused).

@@ -101,13 +101,16 @@ bool fused_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledAr
 
 template <int B, int RT, bool TR>
 void spmv_k(int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax, const double* x,
-            double* y, int R, hipStream_t s, const int* gate)
+            double* y, int R, hipStream_t s, const int* gate, bool stream_a)
 {
     constexpr int RPC = 64 / B;
     const int64_t waves = (static_cast<int64_t>(nb) + RPC - 1) / RPC;
-    const int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
-    hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), 0, s, nb, rp, cj, src, Ax, x,
-                       y, R, gate);
+    int blocks = static_cast<int>((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+    stream_a = stream_a && RT == 1 && !TR && dev::SpmvStage<B>::doubles > 0;
+    if (stream_a) blocks = (blocks + 7) / 8 * 8;
+    const size_t dyn = stream_a ? sizeof(double) * dev::kWavesPerBlock * dev::SpmvStage<B>::doubles : 0;
+    hipLaunchKernelGGL((dev::k_spmv<B, RT, TR>), dim3(blocks), dim3(dev::kThreads), dyn, s, nb, rp, cj, src, Ax, x,
+                       y, R, gate, stream_a ? 1 : 0);
 }
 
 template <int B, int CW, bool TR>
@@ -182,7 +185,7 @@ bool lines(int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& 
 
 template <int B>
 bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, const int64_t* src, const double* Ax,
-          const double* x, double* y, int R, hipStream_t s, const int* gate)
+          const double* x, double* y, int R, hipStream_t s, const int* gate, bool stream_a)
 {
     if (rt == 0) {
         // lanes over columns
@@ -195,9 +198,9 @@ bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, cons
         return true;
     }
     switch (rt) {
-    case 1: trans ? spmv_k<B, 1, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 1, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
-    case 4: trans ? spmv_k<B, 4, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 4, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
-    case 8: trans ? spmv_k<B, 8, true>(nb, rp, cj, src, Ax, x, y, R, s, gate) : spmv_k<B, 8, false>(nb, rp, cj, src, Ax, x, y, R, s, gate); return true;
+    case 1: trans ? spmv_k<B, 1, true>(nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a) : spmv_k<B, 1, false>(nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a); return true;
+    case 4: trans ? spmv_k<B, 4, true>(nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a) : spmv_k<B, 4, false>(nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a); return true;
+    case 8: trans ? spmv_k<B, 8, true>(nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a) : spmv_k<B, 8, false>(nb, rp, cj, src, Ax, x, y, R, s, gate, stream_a); return true;
     }
     return false;
 }
@@ -208,7 +211,7 @@ template bool helped<BILU_B>(int, int, bool, int, size_t, hipStream_t, const dev
 template bool fused<BILU_B>(int, int, int, size_t, hipStream_t, const dev::TiledArgs&, const dev::FusedSpmvArgs&);
 template bool lines<BILU_B>(int, bool, int, hipStream_t, const dev::LineArgs&);
 template bool spmv<BILU_B>(int, bool, int, const int32_t*, const int32_t*, const int64_t*, const double*,
-                           const double*, double*, int, hipStream_t, const int*);
+                           const double*, double*, int, hipStream_t, const int*, bool);
 
 }  // namespace launch
 }  // namespace bilu

@@ -1323,13 +1323,18 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __rest
                                                    const int64_t* __restrict__ srcpos,
                                                    const double* __restrict__ Ax,
                                                    const double* __restrict__ x,
-                                                   double* __restrict__ y, int R, const int* gate)
+                                                   double* __restrict__ y, int R, const int* gate, int stream_a)
 {
     constexpr int RPC = 64 / B;
     constexpr int BB = B * B;
     constexpr int STAGE = TRANS || RT == 1 ? 0 : SpmvStage<B>::doubles;
     if (gated_off(gate)) return;
-    const int64_t wave_global = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    // stream_a: workgroup b runs on XCD b % 8 (the grid is a multiple of 8),
+    // so each XCD takes a contiguous eighth of the rows and its L2 keeps the
+    // x entries its rows share
+    const int64_t lb = stream_a ? static_cast<int64_t>(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8
+                                : static_cast<int64_t>(blockIdx.x);
+    const int64_t wave_global = lb * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t row0 = wave_global * RPC;
     if constexpr (STAGE > 0) {
         // The wavefront's rows own one contiguous run of blocks: copied to
@@ -1356,6 +1361,38 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int nb, const int32_t* __rest
                 asm volatile("" ::: "memory");
                 spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, st, E0, x, y, R);
                 return;
+            }
+        }
+    }
+    if constexpr (!TRANS && RT == 1 && SpmvStage<B>::doubles > 0) {
+        if (stream_a) {
+            // One right-hand side on a large matrix: the wavefront's run of
+            // A is copied to LDS (dynamic) with whole-wavefront nontemporal
+            // loads, so every line of A is fetched once and does not evict
+            // x from L2, then read from there in the same order.
+            extern __shared__ double dyn_stage[];
+            constexpr int ST = SpmvStage<B>::doubles;
+            if (row0 < nb) {
+                const int64_t rend = row0 + RPC < nb ? row0 + RPC : nb;
+                const int32_t E0 = uniform_load(rp, row0);
+                const int64_t n = static_cast<int64_t>(uniform_load(rp, rend) - E0) * BB;
+                if (n <= ST) {
+                    constexpr int PER = (ST + 63) / 64;
+                    double* st = dyn_stage + (threadIdx.x >> 6) * ST;
+                    const double* src = Ax + static_cast<int64_t>(E0) * BB;
+                    const int lane = lane_id();
+                    double v[PER];
+#pragma unroll
+                    for (int k = 0; k < PER; ++k)
+                        v[k] = lane + 64 * k < n ? __builtin_nontemporal_load(src + lane + 64 * k) : 0.0;
+#pragma unroll
+                    for (int k = 0; k < PER; ++k)
+                        if (lane + 64 * k < n) st[lane + 64 * k] = v[k];
+                    __builtin_amdgcn_wave_barrier();
+                    asm volatile("" ::: "memory");
+                    spmv_rows<B, RT, TRANS>(row0, nb, rp, cj, srcpos, st, E0, x, y, R);
+                    return;
+                }
             }
         }
     }

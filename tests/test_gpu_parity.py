@@ -403,6 +403,27 @@ def test_spmv_short_and_long_rows(api, oracle_mod, bs):
         assert rel(yc[:, j], oracle_mod.spmv(nb, bs, Ap, Aj, Ax, X[:, j].copy())) <= 1e-13
 
 
+@pytest.mark.parametrize("bs", [1, 2, 3, 4])
+def test_spmv_streamed_a(api, oracle_mod, bs):
+    """One column with A staged through LDS (nontemporal whole-wavefront
+    loads, rows in contiguous ranges per XCD) gives the bits of the direct
+    kernel, on rows from 1 to about 40 blocks (long rows read A directly) and
+    a ragged last wavefront, and matches the oracle; block sizes above 3 have
+    no staged form and are unaffected."""
+    nb = 1000 + 37 * bs
+    Ap, Aj = synth.graded_block_pattern(nb, 0.002, 0.04, seed=81 + bs)
+    Ax = synth.random_block_values(Ap, Aj, bs, seed=82 + bs)
+    M = api.BlockILU(nb, bs, Ap, Aj, 0)
+    x = np.random.default_rng(83).standard_normal(nb * bs)
+    M.tune(spmv_stream=False)
+    y0 = M.spmv(cuda(Ax), cuda(x))
+    M.tune(spmv_stream=True)
+    y1 = M.spmv(cuda(Ax), cuda(x))
+    assert torch.equal(y0, y1)
+    assert rel(y1.cpu().numpy(), oracle_mod.spmv(nb, bs, Ap, Aj, Ax, x)) <= 1e-13
+    M.close()
+
+
 @pytest.mark.parametrize("bs", [1, 3, 8])
 @pytest.mark.parametrize("R", [2, 3, 5, 8, 16, 17, 32])
 def test_spmv_column_lanes(api, oracle_mod, bs, R):
