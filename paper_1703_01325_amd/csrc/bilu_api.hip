@@ -345,6 +345,13 @@ bool launch_factor(int bs, int64_t first, int nrows, int lds, bilu_ctx* c, hipSt
                                          c->d_Dinv, c->d_bad))
 }
 
+// Backfill with a compile-time block size (false: no kernel for bs).
+bool launch_backfill(int bs, int64_t nP, const int32_t* PtoA, const double* Ax, double* P, hipStream_t s)
+{
+    BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_backfill_b<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP,
+                                         PtoA, Ax, P))
+}
+
 // Update lists of Algorithm 4 for k_factor_rows_lds and k_factor_rows: for each pivot entry
 // e = (i, p) of P (in entry order), the pairs (f, g) of entries (i, j), f > e,
 // and (p, j), g > diagonal of p, with the same column (f as a block index in
@@ -421,6 +428,47 @@ bool launch_split(const bilu_ctx* c, hipStream_t s)
     }
     BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_split<B>), dim3(grid_for(nP * B * B)), dim3(256), 0, s, nP,
                                               c->d_Prow, c->d_Pj, c->d_P, c->d_Dinv, c->d_F))
+}
+
+// Sweep layouts with a compile-time block size (k_layout_b, k_layout_dinv_b;
+// dinv: the fused sweep's D^{-1} rows, or null).
+template <typename T>
+void layout_b_t(int bs, int64_t nslots, int64_t nrs, const int64_t* src, const int32_t* rows, const int32_t* Prow,
+                const double* P, const double* Dinv, int up, int tr, void* vals, void* dinv, hipStream_t s, bool& ok)
+{
+    ok = true;
+    switch (bs) {
+#define BILU_LAYOUT_CASE(BV)                                                                                         \
+    case BV:                                                                                                       \
+        hipLaunchKernelGGL((dev::k_layout_b<BV, T>), dim3(grid_for(nslots * BV * BV)), dim3(256), 0, s, nslots, src, \
+                           Prow, P, Dinv, up, tr, static_cast<T*>(vals));                                          \
+        if (dinv)                                                                                                  \
+            hipLaunchKernelGGL((dev::k_layout_dinv_b<BV, T>), dim3(grid_for(nrs * BV * BV)), dim3(256), 0, s, nrs,   \
+                               rows, Dinv, tr, static_cast<T*>(dinv));                                             \
+        return;
+        BILU_LAYOUT_CASE(1)
+        BILU_LAYOUT_CASE(2)
+        BILU_LAYOUT_CASE(3)
+        BILU_LAYOUT_CASE(4)
+        BILU_LAYOUT_CASE(5)
+        BILU_LAYOUT_CASE(6)
+        BILU_LAYOUT_CASE(7)
+        BILU_LAYOUT_CASE(8)
+#undef BILU_LAYOUT_CASE
+    }
+    ok = false;
+}
+
+bool launch_layout_b(int bs, bool fp32, int64_t nslots, int64_t nrs, const int64_t* src, const int32_t* rows,
+                     const int32_t* Prow, const double* P, const double* Dinv, int up, int tr, void* vals, void* dinv,
+                     hipStream_t s)
+{
+    bool ok = false;
+    if (fp32)
+        layout_b_t<float>(bs, nslots, nrs, src, rows, Prow, P, Dinv, up, tr, vals, dinv, s, ok);
+    else
+        layout_b_t<double>(bs, nslots, nrs, src, rows, Prow, P, Dinv, up, tr, vals, dinv, s, ok);
+    return ok;
 }
 
 void free_form(bilu_ctx* c, int form);
@@ -644,7 +692,11 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
         const int tr = transposed_sweep(w) ? 1 : 0;
         const int up = (w == BILU_SWEEP_U || w == BILU_SWEEP_UT) ? 1 : 0;
         const int64_t nrs = static_cast<int64_t>(nchunks) * rpc;
-        if (c->precision == BILU_FACTORS_FP32) {
+        if (rpc == kWave / h.bs && h.bs <= kMaxKernelBs && nslots % rpc == 0) {
+            if (!launch_layout_b(h.bs, c->precision == BILU_FACTORS_FP32, nslots, nrs, d.src, d.rows, c->d_Prow,
+                                 c->d_P, c->d_Dinv, up, tr, d.vals, d.dinv, s))
+                return BILU_ERR_ARG;
+        } else if (c->precision == BILU_FACTORS_FP32) {
             hipLaunchKernelGGL(dev::k_layout<float>, dim3(grid_for(nslots * bb)), dim3(256), 0, s, nslots, h.bs, rpc,
                                d.src, c->d_Prow, c->d_P, c->d_Dinv, up, tr, static_cast<float*>(d.vals));
             if (d.dinv)
@@ -1218,7 +1270,8 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     c->split_done = false;
     c->f_ready = false;
     const long tslot = timing_begin(c, BILU_K_FACTOR, s);
-    hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax, c->d_P);
+    if (!launch_backfill(h.bs, nP, c->d_PtoA, Ax, c->d_P, s))
+        hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax, c->d_P);
     hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(1), c->d_bad, INT_MAX);
     const HostSweep& L = h.sweep[BILU_SWEEP_L];
     for (int l = 0; l < L.nlev; ++l) {

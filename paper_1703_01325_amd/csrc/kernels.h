@@ -25,6 +25,23 @@ __global__ void k_backfill(int64_t nP, int bb, const int32_t* __restrict__ PtoA,
     }
 }
 
+// The same for a compile-time block size (the index arithmetic needs no
+// 64-bit division by a run-time value).
+template <int B>
+__global__ void k_backfill_b(int64_t nP, const int32_t* __restrict__ PtoA, const double* __restrict__ Ax,
+                             double* __restrict__ P)
+{
+    constexpr int BB = B * B;
+    const int64_t total = nP * BB;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t e = g / BB;
+        const int t = static_cast<int>(g - e * BB);
+        const int32_t a = PtoA[e];
+        P[g] = a >= 0 ? Ax[static_cast<int64_t>(a) * BB + t] : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Block ILU(0) on P (Algorithm 4) for the block rows of one level of the L
 // schedule: one 64-thread workgroup per block row, thread t = c*B + r owns
@@ -576,6 +593,66 @@ __global__ void k_layout(int64_t nslots, int B, int rpc, const int64_t* __restri
             }
         }
         vals[(s - q) * BB + static_cast<int64_t>(el) * rpc + q] = static_cast<T>(v);
+    }
+}
+
+// k_layout for a compile-time block size (rpc = 64/B), one thread per output
+// element in output order: the stores of a wavefront are contiguous and the
+// index arithmetic divides by constants.  Same values, same operations.
+template <int B, typename T>
+__global__ void k_layout_b(int64_t nslots, const int64_t* __restrict__ src, const int32_t* __restrict__ Prow,
+                           const double* __restrict__ P, const double* __restrict__ Dinv, int upper, int transposed,
+                           T* __restrict__ vals)
+{
+    constexpr int BB = B * B;
+    constexpr int RPC = 64 / B;
+    const int64_t total = nslots * BB;
+    for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < total;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t grp = o / (BB * RPC);
+        const int rem = static_cast<int>(o - grp * (BB * RPC));
+        const int el = rem / RPC;                       // el = c*B + r
+        const int q = rem - el * RPC;
+        const int c = el / B;
+        const int r = el - c * B;
+        const int64_t sp = src[grp * RPC + q];
+        double v = 0.0;
+        if (sp >= 0) {
+            const int fr = transposed ? c : r;
+            const int fc = transposed ? r : c;
+            if (!upper) {
+                v = P[sp * BB + fc * B + fr];
+            } else {
+                const double* Di = Dinv + static_cast<int64_t>(Prow[sp]) * BB;
+                const double* U = P + sp * BB;
+                for (int u = 0; u < B; ++u) v += Di[u * B + fr] * U[fc * B + u];
+            }
+        }
+        vals[o] = static_cast<T>(v);
+    }
+}
+
+template <int B, typename T>
+__global__ void k_layout_dinv_b(int64_t nrowslots, const int32_t* __restrict__ rows, const double* __restrict__ Dinv,
+                                int transposed, T* __restrict__ out)
+{
+    constexpr int BB = B * B;
+    constexpr int RPC = 64 / B;
+    const int64_t total = nrowslots * BB;
+    for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < total;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t grp = o / (BB * RPC);
+        const int rem = static_cast<int>(o - grp * (BB * RPC));
+        const int el = rem / RPC;
+        const int q = rem - el * RPC;
+        const int c = el / B;
+        const int r = el - c * B;
+        const int row = rows[grp * RPC + q];
+        double v = 0.0;
+        if (row >= 0)
+            v = transposed ? Dinv[static_cast<int64_t>(row) * BB + r * B + c]
+                           : Dinv[static_cast<int64_t>(row) * BB + c * B + r];
+        out[o] = static_cast<T>(v);
     }
 }
 
