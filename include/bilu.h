@@ -370,6 +370,13 @@ enum {
                                  ranges per XCD (A fetched once, x kept in L2);
                                  2: direct loads; 0 (default): staged from 2^19
                                  block rows up.  Same bits either way              */
+    BILU_TUNE_RHS_PAIRS = 11, /* mode 2, an even number R >= 2 of right-hand sides on
+                                 single tiles: two columns per wavefront (16-byte
+                                 vector accesses, each factor block loaded once for
+                                 both) where the doubled LDS fits, b <= 5 and at
+                                 most 18 dependency values per lane are kept.
+                                 0 (default): from 16 columns up; 1: never;
+                                 2: from 2 columns up.  Same bits                  */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

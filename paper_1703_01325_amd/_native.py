@@ -281,6 +281,7 @@ TUNE_TILE_BLOCK = 7
 TUNE_LINE_SWEEP = 8
 TUNE_HELPER = 9
 TUNE_SPMV_STREAM = 10
+TUNE_RHS_PAIRS = 11
 
 
 def bilu_tune(ctx, param, value):

@@ -122,6 +122,7 @@ struct bilu_ctx {
     int32_t* d_frec = nullptr;
     std::vector<int32_t> fac_lds;
     int spmv_stream = 0;                  // BILU_TUNE_SPMV_STREAM
+    int rhs_pairs = 0;                    // BILU_TUNE_RHS_PAIRS
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
     int64_t* d_ATsrc = nullptr;
     double *d_P = nullptr, *d_F = nullptr, *d_Dinv = nullptr;
@@ -268,6 +269,20 @@ bool use_helper(const bilu_ctx* c, const HostTiled& ht, int R)
     return ht.group == 1 && ht.kmax >= 6;
 }
 
+// Several right-hand sides on single tiles run two columns per wavefront
+// (k_sweep_tiled_pairs) where R is even, the doubled LDS fits and the
+// register ring of the pair walk fits without spilling (b <= 5 and at most
+// 18 dependency values per lane in registers: gfx950 ISA of the build);
+// automatically from 16 columns up (BILU_TUNE_RHS_PAIRS).  Measured on
+// MI355X, 64^3 ILU(1): 32 columns, L / U' sweeps 2900 / 2994 -> 2059 / 2095
+// us; 8 columns, 969 / 997 -> 1087 / 1086 us (half as many wavefronts on a
+// front that is already short of them).
+bool use_pairs(const bilu_ctx* c, const HostTiled& ht, int R, size_t lds)
+{
+    if (c->rhs_pairs == 1 || R < 2 || R % 2 != 0 || (c->rhs_pairs == 0 && R < 16)) return false;
+    return ht.group == 1 && c->h.bs <= 5 && ht.kmax * c->h.bs <= 18 && static_cast<int64_t>(2 * lds) <= c->lds_max;
+}
+
 // ----- templated launch helpers ---------------------------------------------
 #define BILU_SWITCH_B(bs, CALL)     \
     switch (bs) {                   \
@@ -293,6 +308,11 @@ bool launch_tiled(int bs, int kmax, int prec, bool fuse, bool multi, int blocks,
                   const TiledArgs& a)
 {
     BILU_SWITCH_B(bs, if (!launch::tiled<B>(kmax, prec, fuse, multi, blocks, lds, s, a)) return false)
+}
+
+bool launch_pairs(int bs, int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
+{
+    BILU_SWITCH_B(bs, if (!launch::pairs<B>(kmax, prec, fuse, blocks, lds, s, a)) return false)
 }
 
 bool launch_helped(int bs, int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const TiledArgs& a)
@@ -867,6 +887,11 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
             const int hblocks = persistent_blocks(c, a.ngroups, 1, std::max(1, 4 / ht.group));
             a.total_waves = static_cast<unsigned int>(hblocks);
             if (!launch_helped(c->h.bs, ht.kmax, c->precision, fuse != 0, hblocks, hlds, s, a)) return BILU_ERR_ARG;
+        } else if (use_pairs(c, ht, R, lds)) {
+            // two right-hand sides per wavefront: tickets tiles times column pairs
+            const int pblocks = persistent_blocks(c, ht.ntiles * (R / 2), 1, 8);
+            a.total_waves = static_cast<unsigned int>(pblocks);
+            if (!launch_pairs(c->h.bs, ht.kmax, c->precision, fuse != 0, pblocks, 2 * lds, s, a)) return BILU_ERR_ARG;
         } else if (!launch_tiled(c->h.bs, ht.kmax, c->precision, fuse != 0, R > 1, blocks, lds, s, a)) {
             return BILU_ERR_ARG;
         }
@@ -1470,6 +1495,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
     case BILU_TUNE_HELPER:
         if (value < 0 || value > 2) return BILU_ERR_ARG;
         c->helper = value;
+        return BILU_OK;
+    case BILU_TUNE_RHS_PAIRS:
+        if (value < 0 || value > 2) return BILU_ERR_ARG;
+        c->rhs_pairs = value;
         return BILU_OK;
     case BILU_TUNE_SPMV_STREAM:
         if (value < 0 || value > 2) return BILU_ERR_ARG;

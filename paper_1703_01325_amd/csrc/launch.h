@@ -37,6 +37,10 @@ bool fused(int kmax, int prec, int blocks, size_t lds, hipStream_t s, const dev:
            const dev::FusedSpmvArgs& m);
 
 // Line sweep (k_sweep_lines) of L (fuse = false) or U' (fuse = true).
+// Single tiles with two right-hand sides per wavefront (a.R even, a.group 1).
+template <int B>
+bool pairs(int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a);
+
 template <int B>
 bool lines(int prec, bool fuse, int blocks, hipStream_t s, const dev::LineArgs& a);
 

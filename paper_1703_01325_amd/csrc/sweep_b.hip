@@ -82,6 +82,33 @@ bool tiled_t(int kmax, bool fuse, bool multi, int blocks, size_t lds, hipStream_
     return multi ? tiled_k<B, T, false, true>(kmax, blocks, lds, s, a) : tiled_k<B, T, false, false>(kmax, blocks, lds, s, a);
 }
 
+// Single tiles, two right-hand sides per wavefront (a.R even).
+template <int B, typename T>
+bool pairs_k(int kmax, bool fuse, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (a.group > 1 || a.R < 2 || a.R % 2 != 0) return false;
+#define BILU_PAIRS(K)                                                                                         \
+    do {                                                                                                      \
+        if (fuse)                                                                                             \
+            hipLaunchKernelGGL((dev::k_sweep_tiled_pairs<B, T, true, K>), dim3(blocks), dim3(64), lds, s, a);  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((dev::k_sweep_tiled_pairs<B, T, false, K>), dim3(blocks), dim3(64), lds, s, a); \
+    } while (0)
+    if constexpr (B >= 5) {
+        if (kmax != 3) return false;
+        BILU_PAIRS(3);
+        return true;
+    } else {
+        switch (kmax) {
+        case 3: BILU_PAIRS(3); return true;
+        case 6: BILU_PAIRS(6); return true;
+        case 9: BILU_PAIRS(9); return true;
+        }
+        return false;
+    }
+#undef BILU_PAIRS
+}
+
 template <int B, typename T>
 bool fused_k(int kmax, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a, const dev::FusedSpmvArgs& m)
 {
@@ -154,6 +181,13 @@ bool tiled(int kmax, int prec, bool fuse, bool multi, int blocks, size_t lds, hi
 }
 
 template <int B>
+bool pairs(int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
+{
+    if (prec == BILU_FACTORS_FP32) return pairs_k<B, float>(kmax, fuse, blocks, lds, s, a);
+    return pairs_k<B, double>(kmax, fuse, blocks, lds, s, a);
+}
+
+template <int B>
 bool helped(int kmax, int prec, bool fuse, int blocks, size_t lds, hipStream_t s, const dev::TiledArgs& a)
 {
     if (prec == BILU_FACTORS_FP32)
@@ -207,6 +241,7 @@ bool spmv(int rt, bool trans, int nb, const int32_t* rp, const int32_t* cj, cons
 
 template bool sweep<BILU_B>(int, int, int, hipStream_t, const dev::SweepArgs&);
 template bool tiled<BILU_B>(int, int, bool, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
+template bool pairs<BILU_B>(int, int, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
 template bool helped<BILU_B>(int, int, bool, int, size_t, hipStream_t, const dev::TiledArgs&);
 template bool fused<BILU_B>(int, int, int, size_t, hipStream_t, const dev::TiledArgs&, const dev::FusedSpmvArgs&);
 template bool lines<BILU_B>(int, bool, int, hipStream_t, const dev::LineArgs&);

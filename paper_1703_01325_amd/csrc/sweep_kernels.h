@@ -895,6 +895,291 @@ __global__ __launch_bounds__(64) void k_sweep_tiled(TiledArgs a)
     finish_persistent(a.ticket, a.done, a.total_waves);
 }
 
+// ---------------------------------------------------------------------------
+// Two right-hand sides per wavefront (k_sweep_tiled_pairs, single tiles):
+// columns j0 and j0 + 1 (j0 even) of the (n x R) row-major vectors, R even,
+// lie next to each other, so every vector access of the one-column walk
+// (right-hand side, values of other tiles, the published row, its reset,
+// LDS) becomes one 16-byte access, while each factor block, dependency code
+// and D^{-1} value is loaded once for both columns.  Each column is formed
+// with the operations of the one-column sweep in the same order, so both
+// give the same bits.  LDS keeps both columns of a row: (tile rows + 1) *
+// B * 16 bytes, the dependency codes' LDS byte offsets doubled.
+// ---------------------------------------------------------------------------
+template <int B, typename T, int KMAX, bool FUSE>
+struct TileDataP {
+    int64_t off;
+    int w;
+    int row;
+    int code[KMAX];
+    T f[KMAX][B];
+    double2 x[KMAX][B];      // values read from other tiles (may show kNotReady)
+    double2 h[FUSE ? B : 1];
+    T d[FUSE ? B : 1];
+};
+
+__device__ __forceinline__ bool pair_not_ready(const double2& v) { return is_not_ready(v.x) || is_not_ready(v.y); }
+
+template <int B, typename T, int KMAX, bool FUSE>
+__device__ __forceinline__ void tile_data_p(const TiledArgs& a, int chunk, int qc, int r, const TileMeta<KMAX>& m,
+                                            TileDataP<B, T, KMAX, FUSE>& s, const ColMap<true>& cm)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    const int lane_off = r * RPC + qc;
+    s.off = m.off;
+    s.w = m.w;
+    s.row = m.row;
+    const T* vp = static_cast<const T*>(a.vals) + m.off * BB;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        s.code[k] = m.code[k];
+#pragma unroll
+        for (int c = 0; c < B; ++c) s.f[k][c] = vp[k * RPC * BB + c * B * RPC + lane_off];
+    }
+    const uint32_t rowc_b = static_cast<uint32_t>(m.row >= 0 ? m.row : 0) * (B * 8u);
+    const double2* rhs2 = reinterpret_cast<const double2*>(a.rhs);
+    if (FUSE) {
+        const T* dp = static_cast<const T*>(a.dinv) + static_cast<int64_t>(chunk) * RPC * BB;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            s.h[c] = load_at(rhs2, cm.at(rowc_b, c));
+            s.d[c] = dp[c * B * RPC + lane_off];
+        }
+    } else {
+        s.h[0] = load_at(rhs2, cm.at(rowc_b, r));
+    }
+    const double2* out2 = reinterpret_cast<const double2*>(a.out);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const uint32_t xb = s.code[k] >= 0 ? static_cast<uint32_t>(s.code[k]) : 0u;
+#pragma unroll
+        for (int c = 0; c < B; ++c) s.x[k][c] = load_at(out2, cm.at(xb, c));
+    }
+}
+
+// await_tile for column pairs: each column of a pair is polled on its own
+// (the two are published by two stores).
+template <int K, int B>
+__device__ __forceinline__ void await_tile_p(double2 (&v)[K * B], const int (&code)[K], const double* out,
+                                             const ColMap<true>& cm, unsigned int limit, int* status)
+{
+    bool pending = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & pair_not_ready(v[k * B + c]);
+    unsigned int spins = 0;
+    while (pending) {
+        if (++spins > limit) {
+            atomicOr(status, 1);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        pending = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < B; ++c)
+                if (code[k] >= 0 && pair_not_ready(v[k * B + c])) {
+                    const double* p = reinterpret_cast<const double*>(reinterpret_cast<const char*>(out) +
+                                                                      cm.at(static_cast<uint32_t>(code[k]), c));
+                    if (is_not_ready(v[k * B + c].x)) v[k * B + c].x = coherent_load(p);
+                    if (is_not_ready(v[k * B + c].y)) v[k * B + c].y = coherent_load(p + 1);
+                }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < B; ++c) pending |= (code[k] >= 0) & pair_not_ready(v[k * B + c]);
+    }
+}
+
+template <int B, typename T, int KMAX, bool FUSE>
+__device__ __forceinline__ void tile_compute_p(const TiledArgs& a, int lo, int qc, int r, bool active,
+                                               double2* tile_vals, const TileDataP<B, T, KMAX, FUSE>& s,
+                                               const ColMap<true>& cm, int wbase)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int BB = B * B;
+    // take delivery of the whole batch (see tile_compute)
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+#pragma unroll
+        for (int c = 0; c < B; ++c) asm volatile("" ::"v"(s.f[k][c]), "v"(s.x[k][c].x), "v"(s.x[k][c].y));
+    }
+#pragma unroll
+    for (int c = 0; c < (FUSE ? B : 1); ++c) asm volatile("" ::"v"(s.h[c].x), "v"(s.h[c].y), "v"(s.d[c]));
+    double2 xg[KMAX * B];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int c = 0; c < B; ++c) xg[k * B + c] = s.x[k][c];
+    await_tile_p<KMAX, B>(xg, s.code, a.out, cm, a.spin_limit, a.status);
+    if (!active || s.row < 0) return;
+    double acc0, acc1;
+    if (FUSE) {
+        acc0 = 0.0;
+        acc1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            acc0 += widen(s.d[c]) * s.h[c].x;
+            acc1 += widen(s.d[c]) * s.h[c].y;
+        }
+    } else {
+        acc0 = s.h[0].x;
+        acc1 = s.h[0].y;
+    }
+    const char* lds = reinterpret_cast<const char*>(tile_vals);
+    double2 lv[KMAX * B];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const uint32_t lb = s.code[k] < 0 ? 2u * (static_cast<uint32_t>(s.code[k]) & 0x7fffffffu) : 0u;
+#pragma unroll
+        for (int c = 0; c < B; ++c) lv[k * B + c] = *reinterpret_cast<const double2*>(lds + lb + c * 16u);
+    }
+#pragma unroll
+    for (int i = 0; i < KMAX * B; ++i) asm volatile("" : "+v"(lv[i].x), "+v"(lv[i].y));
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const bool local = s.code[k] < 0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const double f = widen(s.f[k][c]);
+            acc0 -= f * (local ? lv[k * B + c].x : xg[k * B + c].x);
+            acc1 -= f * (local ? lv[k * B + c].y : xg[k * B + c].y);
+        }
+    }
+    if (s.w > KMAX) {
+        // slots past the first KMAX, XB at a time, as in tile_compute
+        constexpr int XB = B == 1 ? 16 : B == 2 ? 8 : (16 / B > 2 ? 16 / B : 2);
+        const T* __restrict__ vals = static_cast<const T*>(a.vals);
+        const char* ob = reinterpret_cast<const char*>(a.out);
+        for (int k0 = KMAX; k0 < s.w; k0 += XB) {
+            int code[XB];
+#pragma unroll
+            for (int j = 0; j < XB; ++j)
+                code[j] = k0 + j < s.w ? a.deps[s.off + static_cast<int64_t>(k0 + j) * RPC + qc] : INT_MIN;
+            double2 xv[XB * B];
+            T fv[XB][B];
+#pragma unroll
+            for (int j = 0; j < XB; ++j) {
+                const int k = k0 + j < s.w ? k0 + j : k0;
+                const int64_t vbase = (s.off + static_cast<int64_t>(k) * RPC) * BB + r * RPC + qc;
+                const uint32_t lb = code[j] < 0 ? 2u * (static_cast<uint32_t>(code[j]) & 0x7fffffffu) : 0u;
+                const uint32_t gb = code[j] >= 0 ? static_cast<uint32_t>(code[j]) : 0u;
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    fv[j][c] = vals[vbase + c * B * RPC];
+                    const double2 lx = *reinterpret_cast<const double2*>(lds + lb + c * 16u);
+                    const double2 gx = *reinterpret_cast<const double2*>(ob + cm.at(gb, c));
+                    xv[j * B + c] = code[j] < 0 ? lx : gx;
+                }
+            }
+            await_tile_p<XB, B>(xv, code, a.out, cm, a.spin_limit, a.status);
+#pragma unroll
+            for (int j = 0; j < XB; ++j)
+                if (k0 + j < s.w)
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        acc0 -= widen(fv[j][c]) * xv[j * B + c].x;
+                        acc1 -= widen(fv[j][c]) * xv[j * B + c].y;
+                    }
+        }
+    }
+    const double v0 = publishable(acc0);
+    const double v1 = publishable(acc1);
+    const uint32_t ob = cm.at(static_cast<uint32_t>(s.row) * (B * 8u), r);
+    if (a.reset)
+        *reinterpret_cast<double2*>(reinterpret_cast<char*>(a.reset) + ob) = make_double2(not_ready(), not_ready());
+    double* dst = reinterpret_cast<double*>(reinterpret_cast<char*>(a.out) + ob);
+    coherent_store(dst, v0);
+    coherent_store(dst + 1, v1);
+    tile_vals[(wbase >= 0 ? wbase + qc : s.row - lo) * B + r] = make_double2(v0, v1);
+}
+
+// Ring depth of the column-pair walk (as TiledRing for single tiles, with
+// two values per vector element).
+template <int B, typename T, bool FUSE, int KMAX>
+struct TiledRingP {
+    static constexpr int w = sizeof(T) == 8 ? 2 : 1;
+    static constexpr int state = KMAX * B * (4 + w) + KMAX + (FUSE ? B * (4 + w) : 4) + 4 + KMAX + 3;
+    static constexpr int value = 3 * state + 40 <= 240 ? 3 : 2;
+};
+
+// One tile, one column pair (run_tile without groups or helpers).
+template <int B, typename T, bool FUSE, int KMAX>
+__device__ __forceinline__ void run_tile_p(const TiledArgs& a, int t, const ColMap<true>& cm, double2* tile_vals)
+{
+    constexpr int RPC = 64 / B;
+    constexpr int NR = TiledRingP<B, T, FUSE, KMAX>::value;
+    constexpr int LD = NR - 1;
+    constexpr int LM = 2 * LD;
+    const int lane = lane_id();
+    const int q = lane / B;
+    const int r = lane - q * B;
+    const bool lane_ok = q < RPC;
+    const int qc = lane_ok ? q : RPC - 1;
+    TileMeta<KMAX> mr[NR];
+    TileDataP<B, T, KMAX, FUSE> dr[NR];
+    const int lo = uniform_load(a.tile_lo, t);
+    const int c0 = uniform_load(a.tile_chunk_ptr, t);
+    const int nch = uniform_load(a.tile_chunk_ptr, t + 1) - c0;
+    if (nch <= 0) return;
+    const int clast = c0 + nch - 1;
+    auto chunk_at = [&](int i) { return min(c0 + i, clast); };
+    auto meta_at = [&](int i, TileMeta<KMAX>& m) {
+        const int ch = chunk_at(i);
+        const int sr = uniform_load(a.chunk_row, ch);
+        tile_meta<B, KMAX>(a, ch, sr, uniform_load(a.chunk_row, ch + 1) - sr, qc, m);
+    };
+#pragma unroll
+    for (int i = 0; i < NR; ++i) meta_at(i, mr[i]);
+#pragma unroll
+    for (int i = 0; i < LD; ++i) {
+        tile_data_p<B, T, KMAX, FUSE>(a, chunk_at(i), qc, r, mr[i % NR], dr[i % NR], cm);
+        if (NR + i < LM) meta_at(NR + i, mr[(NR + i) % NR]);
+    }
+    int pre_lo = uniform_load(a.chunk_row, chunk_at(LM));
+    int pre_hi = uniform_load(a.chunk_row, chunk_at(LM) + 1);
+    int wchunk = 0;
+    for (int i0 = 0; i0 < nch; i0 += NR) {
+#pragma unroll
+        for (int p = 0; p < NR; ++p) {
+            const int i = i0 + p;
+            tile_meta<B, KMAX>(a, chunk_at(i + LM), pre_lo, pre_hi - pre_lo, qc, mr[(p + LM) % NR]);
+            pre_lo = uniform_load(a.chunk_row, chunk_at(i + LM + 1));
+            pre_hi = uniform_load(a.chunk_row, chunk_at(i + LM + 1) + 1);
+            tile_data_p<B, T, KMAX, FUSE>(a, chunk_at(i + LD), qc, r, mr[(p + LD) % NR], dr[(p + LD) % NR], cm);
+            tile_compute_p<B, T, KMAX, FUSE>(a, lo, qc, r, lane_ok && i < nch, tile_vals, dr[p], cm,
+                                             a.ring > 0 ? wchunk * RPC : -1);
+            wchunk = wchunk + 1 == a.ring ? 0 : wchunk + 1;
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
+        }
+    }
+}
+
+// Tickets: tiles times column pairs, the pairs of a tile together (every
+// dependency of a ticket -- same columns, earlier tile -- has a smaller one).
+template <int B, typename T, bool FUSE, int KMAX>
+__global__ __launch_bounds__(64) void k_sweep_tiled_pairs(TiledArgs a)
+{
+    extern __shared__ double2 pair_vals[];                   // [tile rows + 1][B]
+    if (gated_off(a.gate)) return;
+    if (lane_id() < B) pair_vals[a.tile_rows * B + lane_id()] = make_double2(0.0, 0.0);
+    const int npairs = a.R / 2;
+    const int nticket = a.ntiles * npairs;
+    for (int tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket)); tk < nticket;
+         tk = __builtin_amdgcn_readfirstlane(grab_ticket(a.ticket))) {
+        const int t = tk / npairs;
+        ColMap<true> cm;
+        cm.R = static_cast<uint32_t>(a.R);
+        cm.j8 = static_cast<uint32_t>(tk - t * npairs) * 16u;
+        run_tile_p<B, T, FUSE, KMAX>(a, t, cm, pair_vals);
+    }
+    finish_persistent(a.ticket, a.done, a.total_waves);
+}
+
 // Tile groups: one workgroup of a.group wavefronts per ticket (a group, or
 // with MULTI a (group, column) pair); member m sweeps the group's m-th tile
 // into its part of the shared LDS and reads rows of earlier members there

@@ -153,6 +153,59 @@ def test_multi_rhs_columns(api, oracle_mod, R):
         assert rel(Y[:, j], oracle_mod.spmv(c.s.nb, c.s.bs, c.s.Ap, c.s.Aj, c.s.Ax, B[:, j])) <= 1e-12
 
 
+PAIR_CASES = [("res6x5x7_b3_k1", lambda: synth.reservoir(6, 5, 7, 3, seed=12), 1, "fp64"),
+              ("res6x5x7_b3_k1_fp32", lambda: synth.reservoir(6, 5, 7, 3, seed=12), 1, "fp32"),
+              ("res7x6x5_b2_k2", lambda: synth.reservoir(7, 6, 5, 2, seed=32), 2, "fp64"),
+              ("res13x3x11_b1_k3", lambda: synth.reservoir(13, 3, 11, 1, seed=45), 3, "fp64"),
+              ("res9x8x7_b5_k0", lambda: synth.reservoir(9, 8, 7, 5, seed=46), 0, "fp64")]
+
+
+@pytest.mark.parametrize("name,make,k,prec", PAIR_CASES, ids=[c[0] for c in PAIR_CASES])
+def test_rhs_pairs_identical(api, name, make, k, prec):
+    """Two right-hand sides per wavefront (single tiles, R even) give, for
+    every column, the bits of one column per wavefront and of a one-column
+    application, in both sweeps of M^{-1} and of M^{-T}."""
+    s = make()
+    M = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, k, transpose=True)
+    try:
+        M.tune(mode=2, tile_group=1)
+        assert M.factor(cuda(s.Ax), precision=prec) == -1
+        for R in (2, 8):
+            B = cuda(np.random.default_rng(100 + R).standard_normal((s.n, R)))
+            for tr in (False, True):
+                M.tune(rhs_pairs=True)
+                Zp = M.apply(B, transpose=tr)
+                M.tune(rhs_pairs=False)
+                Z1 = M.apply(B, transpose=tr)
+                assert torch.equal(Zp, Z1), (R, tr)
+                for j in (0, R - 1):
+                    zj = M.apply(B[:, j].contiguous(), transpose=tr)
+                    assert torch.equal(Zp[:, j], zj), (R, tr, j)
+    finally:
+        M.close()
+
+
+def test_rhs_pairs_mid64_ilu1(api, oracle_mod):
+    """The multi-right-hand-side workload of the benchmark (64^3, b = 3,
+    ILU(1)) with 8 columns: pairs against single columns, bit for bit, and
+    two columns against the oracle."""
+    s = synth.mid_64cube()
+    M = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, 1)
+    try:
+        assert M.factor(cuda(s.Ax)) == -1
+        B = synth.multi_rhs(s.n, 8, seed=41)
+        M.tune(rhs_pairs=True)
+        Zp = M.apply(cuda(B))
+        M.tune(rhs_pairs=False)
+        Z1 = M.apply(cuda(B))
+        assert torch.equal(Zp, Z1)
+        O = oracle_mod.OracleILU(s.nb, s.bs, s.Ap, s.Aj, 1).factor(s.Ax)
+        for j in (0, 7):
+            assert rel(Zp[:, j].cpu().numpy(), O.apply(B[:, j].copy())) <= 1e-12
+    finally:
+        M.close()
+
+
 @pytest.mark.parametrize("k", [0, 1])
 def test_solve_parity_small(api, oracle_mod, k):
     c = Case(oracle_mod, synth.small_10cube(), k)
