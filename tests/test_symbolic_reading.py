@@ -80,3 +80,16 @@ def test_fill_path_bound_is_strict(oracle_mod):
     # (2, 0) is fill of level 1 through the inner vertex 1 < min(2, 0)? No:
     # 1 > 0, so the entry must be absent
     assert 0 not in got[1][got[0][2]:got[0][3]].tolist()
+
+
+def test_device_symbolic_has_no_host_fallback():
+    """Without a GPU, asking bilu_analyze for the device symbolic phase fails
+    with an error instead of quietly running the host analysis."""
+    import torch
+    from paper_1703_01325_amd import _native as N
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    Ap, Aj = synth.stencil7_pattern(4, 4, 4)
+    with pytest.raises(N.BiluError) as e:
+        N.bilu_analyze(64, 3, Ap, Aj, 1, N.DEVICE_SYMBOLIC)
+    assert e.value.code in (N.ERR_ALLOC, N.ERR_HIP)
