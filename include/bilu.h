@@ -377,6 +377,11 @@ enum {
                                  most 18 dependency values per lane are kept.
                                  0 (default): from 16 columns up; 1: never;
                                  2: from 2 columns up.  Same bits                  */
+    BILU_TUNE_SPLIT_DINV = 12, /* one right-hand side, FP64 factors, mode 2: form
+                                 D^{-1} y by blocks ahead of the U' sweep and run that
+                                 sweep unfused (2), or fuse D^{-1} into it (1);
+                                 0 (default): split where U' rows keep six or more
+                                 dependency slots in registers.  Same bits           */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

@@ -282,6 +282,7 @@ TUNE_LINE_SWEEP = 8
 TUNE_HELPER = 9
 TUNE_SPMV_STREAM = 10
 TUNE_RHS_PAIRS = 11
+TUNE_SPLIT_DINV = 12
 
 
 def bilu_tune(ctx, param, value):

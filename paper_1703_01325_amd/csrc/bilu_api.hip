@@ -133,6 +133,9 @@ struct bilu_ctx {
 
     double* d_y = nullptr;      // intermediate of an application, kept at kNotReady
     size_t y_cap = 0;
+    double* d_y2 = nullptr;     // D^{-1} y when the U' sweep runs unfused
+    size_t y2_cap = 0;
+    int split_dinv = 0;         // BILU_TUNE_SPLIT_DINV
     int* d_bad = nullptr;
     int* d_status = nullptr;
     unsigned int* d_done = nullptr;
@@ -735,6 +738,33 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
     return BILU_OK;
 }
 
+// D^{-1} y by blocks ahead of an unfused U' sweep instead of inside it
+// (BILU_TUNE_SPLIT_DINV): one right-hand side, FP64 factors, tiled U'
+// layout; automatically where U' rows keep six or more dependency slots in
+// registers (ILU(k >= 1) on a 7-point grid), whose fused sweep spends the
+// most on the D^{-1} loads.  Same bits either way.
+bool use_split_dinv(const bilu_ctx* c, int R)
+{
+    if (c->split_dinv == 1 || R != 1 || c->precision != BILU_FACTORS_FP64) return false;
+    if (sweep_form(c, 1) != kFormTiled || use_lines(c, BILU_SWEEP_U, 1)) return false;
+    return c->split_dinv == 2 || c->h.tiled[BILU_SWEEP_U].kmax >= 6;
+}
+
+// Second intermediate of an application (D^{-1} y), one column.
+bilu_status ensure_y2(bilu_ctx* c, hipStream_t s)
+{
+    (void)s;
+    const size_t need = static_cast<size_t>(c->h.nb) * c->h.bs;
+    if (c->y2_cap >= need) return BILU_OK;
+    dfree(c, c->d_y2);
+    c->d_y2 = nullptr;
+    c->y2_cap = 0;
+    bilu_status st = dalloc(c, &c->d_y2, need);
+    if (st) return st;
+    c->y2_cap = need;
+    return BILU_OK;
+}
+
 bilu_status ensure_y(bilu_ctx* c, int R, hipStream_t s)
 {
     const size_t need = static_cast<size_t>(c->h.nb) * c->h.bs * R;
@@ -772,11 +802,23 @@ struct SweepSync {
 
 // sync: counters to use instead of the context's (may be null); timed:
 // recorded in bilu_timing's sweep classes.
+static bool launch_block_dinv(int bs, int64_t nb, const double* Dinv, const double* x, double* y, hipStream_t s,
+                              const int* gate);
+
+// scaled (U' sweep only, tiled form): D^{-1} rhs is formed into scaled by
+// blocks first (k_block_dinv, the fused sweep's products in its order) and
+// the sweep runs unfused on it; both count as the sweep's time.
 bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, double* reset, int R, hipStream_t s,
-                      const int* gate = nullptr, const SweepSync* sync = nullptr, bool timed = true)
+                      const int* gate = nullptr, const SweepSync* sync = nullptr, bool timed = true,
+                      double* scaled = nullptr)
 {
     const int form = sweep_form(c, R);
     const long tslot = timed ? timing_begin(c, BILU_K_SWEEP_L + which, s) : -1;
+    if (scaled) {
+        if (which != BILU_SWEEP_U || form != kFormTiled || R != 1 || use_lines(c, which, R)) return BILU_ERR_STATE;
+        if (!launch_block_dinv(c->h.bs, c->h.nb, c->d_Dinv, rhs, scaled, s, gate)) return BILU_ERR_ARG;
+        rhs = scaled;
+    }
     const SweepSync own{c->d_ticket, c->d_done, c->d_status};
     const SweepSync& sy = sync ? *sync : own;
     if (use_lines(c, which, R)) {
@@ -828,7 +870,7 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
         CK(hipGetLastError());
         return BILU_OK;
     }
-    const int fuse = fused_sweep(which) ? 1 : 0;
+    const int fuse = fused_sweep(which) && !scaled ? 1 : 0;
     if (form == kFormTiled) {
         const HostTiled& ht = c->h.tiled[which];
         const DevSweep& d = c->ds[kFormTiled][which];
@@ -1082,6 +1124,10 @@ bilu_status do_apply(bilu_ctx* c, const double* r, double* z, int R, bool transp
     if ((use_lines(c, first, R) || use_lines(c, second, R)) && (st = layout_form(c, kFormLines, s))) return st;
     if ((st = ensure_y(c, R, s))) return st;
     if ((st = run_sweep(c, first, r, c->d_y, z, R, s, gate))) return st;
+    if (!transpose && use_split_dinv(c, R)) {
+        if ((st = ensure_y2(c, s))) return st;
+        return run_sweep(c, second, c->d_y, z, c->d_y, R, s, gate, nullptr, true, c->d_y2);
+    }
     return run_sweep(c, second, c->d_y, z, c->d_y, R, s, gate);
 }
 
@@ -1495,6 +1541,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
     case BILU_TUNE_HELPER:
         if (value < 0 || value > 2) return BILU_ERR_ARG;
         c->helper = value;
+        return BILU_OK;
+    case BILU_TUNE_SPLIT_DINV:
+        if (value < 0 || value > 2) return BILU_ERR_ARG;
+        c->split_dinv = value;
         return BILU_OK;
     case BILU_TUNE_RHS_PAIRS:
         if (value < 0 || value > 2) return BILU_ERR_ARG;
