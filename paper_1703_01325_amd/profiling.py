@@ -35,18 +35,20 @@ def counter_avg(db, counter, selector):
     (two sweeps that share one kernel and strictly alternate); "name@run"
     keeps the dispatches that did work (a value of at least a tenth of the
     largest), leaving out launches that a solver's device flag turned into
-    no-ops (the gated true-residual SpMV, the step queued after the exit)."""
-    substring, _, parity = selector.partition("@")
+    no-ops (the gated true-residual SpMV, the step queued after the exit);
+    "name@even+run" / "name@odd+run" apply both, in that order."""
+    substring, _, flags = selector.partition("@")
+    parts = set(flags.split("+")) if flags else set()
     con = sqlite3.connect(db)
     rows = con.execute("select kernel_name, value from counters_collection where counter_name = ? "
                        "order by dispatch_id", (counter,)).fetchall()
     con.close()
     vals = [v for name, v in rows if substring in name]
-    if parity == "even":
+    if "even" in parts:
         vals = vals[0::2]
-    elif parity == "odd":
+    elif "odd" in parts:
         vals = vals[1::2]
-    elif parity == "run" and vals:
+    if "run" in parts and vals:
         top = max(vals)
         vals = [v for v in vals if v >= 0.1 * top]
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
