@@ -377,7 +377,7 @@ enum {
                                  most 18 dependency values per lane are kept.
                                  0 (default): from 16 columns up; 1: never;
                                  2: from 2 columns up.  Same bits                  */
-    BILU_TUNE_SPLIT_DINV = 12, /* one right-hand side, FP64 factors, mode 2: form
+    BILU_TUNE_SPLIT_DINV = 12, /* one right-hand side, mode 2: form
                                  D^{-1} y by blocks ahead of the U' sweep and run that
                                  sweep unfused (2), or fuse D^{-1} into it (1);
                                  0 (default): split where U' rows keep six or more

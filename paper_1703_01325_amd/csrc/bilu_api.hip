@@ -739,13 +739,14 @@ bilu_status layout_form(bilu_ctx* c, int form, hipStream_t s)
 }
 
 // D^{-1} y by blocks ahead of an unfused U' sweep instead of inside it
-// (BILU_TUNE_SPLIT_DINV): one right-hand side, FP64 factors, tiled U'
-// layout; automatically where U' rows keep six or more dependency slots in
+// (BILU_TUNE_SPLIT_DINV): one right-hand side, tiled U' layout;
+// automatically where U' rows keep six or more dependency slots in
 // registers (ILU(k >= 1) on a 7-point grid), whose fused sweep spends the
-// most on the D^{-1} loads.  Same bits either way.
+// most on the D^{-1} loads.  With FP32 factors the block pass multiplies
+// by the FP32-rounded D^{-1}, as the fused sweep does.  Same bits either way.
 bool use_split_dinv(const bilu_ctx* c, int R)
 {
-    if (c->split_dinv == 1 || R != 1 || c->precision != BILU_FACTORS_FP64) return false;
+    if (c->split_dinv == 1 || R != 1) return false;
     if (sweep_form(c, 1) != kFormTiled || use_lines(c, BILU_SWEEP_U, 1)) return false;
     return c->split_dinv == 2 || c->h.tiled[BILU_SWEEP_U].kmax >= 6;
 }
@@ -803,7 +804,7 @@ struct SweepSync {
 // sync: counters to use instead of the context's (may be null); timed:
 // recorded in bilu_timing's sweep classes.
 static bool launch_block_dinv(int bs, int64_t nb, const double* Dinv, const double* x, double* y, hipStream_t s,
-                              const int* gate);
+                              const int* gate, bool f32 = false);
 
 // scaled (U' sweep only, tiled form): D^{-1} rhs is formed into scaled by
 // blocks first (k_block_dinv, the fused sweep's products in its order) and
@@ -816,7 +817,9 @@ bilu_status run_sweep(bilu_ctx* c, int which, const double* rhs, double* out, do
     const long tslot = timed ? timing_begin(c, BILU_K_SWEEP_L + which, s) : -1;
     if (scaled) {
         if (which != BILU_SWEEP_U || form != kFormTiled || R != 1 || use_lines(c, which, R)) return BILU_ERR_STATE;
-        if (!launch_block_dinv(c->h.bs, c->h.nb, c->d_Dinv, rhs, scaled, s, gate)) return BILU_ERR_ARG;
+        if (!launch_block_dinv(c->h.bs, c->h.nb, c->d_Dinv, rhs, scaled, s, gate,
+                               c->precision == BILU_FACTORS_FP32))
+            return BILU_ERR_ARG;
         rhs = scaled;
     }
     const SweepSync own{c->d_ticket, c->d_done, c->d_status};
@@ -1062,11 +1065,16 @@ static bilu_status ensure_point(bilu_ctx* c, hipStream_t s)
 }
 
 static bool launch_block_dinv(int bs, int64_t nb, const double* Dinv, const double* x, double* y, hipStream_t s,
-                              const int* gate)
+                              const int* gate, bool f32)
 {
     if (bs > kMaxKernelBs) {
+        if (f32) return false;
         hipLaunchKernelGGL(dev::k_block_dinv_gen, dim3(grid_for(nb * bs)), dim3(256), 0, s, nb, bs, Dinv, x, y, gate);
         return true;
+    }
+    if (f32) {
+        BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_block_dinv<B, true>), dim3(grid_for(nb * B)), dim3(256), 0, s,
+                                             nb, Dinv, x, y, gate))
     }
     BILU_SWITCH_B(bs, hipLaunchKernelGGL((dev::k_block_dinv<B>), dim3(grid_for(nb * B)), dim3(256), 0, s, nb, Dinv,
                                          x, y, gate))

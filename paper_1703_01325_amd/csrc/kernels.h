@@ -330,8 +330,10 @@ __global__ void k_expand_point(int64_t n, const int64_t* __restrict__ src, const
 
 // y = D^{-1} x with D^{-1} block diagonal (b x b blocks, column-major), one
 // thread per point row; the products summed over c in order, as in the
-// block sweep that fuses D^{-1}.
-template <int B>
+// block sweep that fuses D^{-1}.  F32: D^{-1} taken as the FP32-stored
+// factors hold it (rounded to nearest even, widened back), as the fused
+// sweep of FP32 factors multiplies by it.
+template <int B, bool F32 = false>
 __global__ void k_block_dinv(int64_t nb, const double* __restrict__ Dinv, const double* __restrict__ x,
                              double* __restrict__ y, const int* gate)
 {
@@ -343,7 +345,10 @@ __global__ void k_block_dinv(int64_t nb, const double* __restrict__ Dinv, const 
         const int r = static_cast<int>(i - I * B);
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < B; ++c) acc += Dinv[I * BB + c * B + r] * x[I * B + c];
+        for (int c = 0; c < B; ++c) {
+            const double d = Dinv[I * BB + c * B + r];
+            acc += (F32 ? static_cast<double>(static_cast<float>(d)) : d) * x[I * B + c];
+        }
         y[i] = acc;
     }
 }
