@@ -126,7 +126,8 @@ typedef struct {
 
 /*
  * Symbolic phase (Algorithm 5 steps 1-2: Algorithm 3 with Eq 1-2) and the
- * level sets of Eq 4.  Host-only: needs no GPU.
+ * level sets of Eq 4, then the layouts of the sweeps.  On the host (needs no
+ * GPU) unless flags has BILU_DEVICE_SYMBOLIC.
  *   nb, bs   block rows (>= 1) and block size (1..32).  Sizes 1..8 have
  *            block-row sweep and SpMV kernels; 9..32 (the large blocks of
  *            Section 3, Table 2) factor by blocks, sweep at point
