@@ -283,6 +283,7 @@ TUNE_HELPER = 9
 TUNE_SPMV_STREAM = 10
 TUNE_RHS_PAIRS = 11
 TUNE_SPLIT_DINV = 12
+TUNE_FACTOR = 13
 
 
 def bilu_tune(ctx, param, value):

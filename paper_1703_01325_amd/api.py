@@ -91,7 +91,8 @@ class BlockILU:
         N.bilu_tune(self._ctx, N.TUNE_SWEEP_MODE, mode)
 
     def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None,
-             tile_block=None, line_sweep=None, helper=None, spmv_stream=None, rhs_pairs=None, split_dinv=None):
+             tile_block=None, line_sweep=None, helper=None, spmv_stream=None, rhs_pairs=None, split_dinv=None,
+             factor=None):
         """Launch knobs of the sweeps (results are bit-identical for all)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
                          (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
@@ -107,6 +108,7 @@ class BlockILU:
                           (0 if rhs_pairs == "auto" else 2 if rhs_pairs else 1)),
                          (N.TUNE_SPLIT_DINV, None if split_dinv is None else
                           (0 if split_dinv == "auto" else 2 if split_dinv else 1)),
+                         (N.TUNE_FACTOR, None if factor is None else {"waves": 0, "levels": 1}[factor]),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

@@ -121,6 +121,12 @@ struct bilu_ctx {
     // pivots, first update pair, update pairs, 0, 0}
     int32_t* d_frec = nullptr;
     std::vector<int32_t> fac_lds;
+    // the whole factorisation in one persistent launch (k_factor_waves):
+    // LDS bytes per wavefront (0: some row does not fit, one launch per
+    // level instead), ticket and expired-wait words
+    int fwave_lds = 0;
+    unsigned int* d_fticket = nullptr;
+    int factor_mode = 0;                  // BILU_TUNE_FACTOR
     int spmv_stream = 0;                  // BILU_TUNE_SPMV_STREAM
     int rhs_pairs = 0;                    // BILU_TUNE_RHS_PAIRS
     int32_t *d_ATp = nullptr, *d_ATj = nullptr;
@@ -433,11 +439,47 @@ bilu_status factor_plan(bilu_ctx* c)
         }
         c->fac_lds[l] = m <= kCap && h.bs <= kMaxKernelBs ? static_cast<int32_t>(m) : 0;
     }
+    int64_t mrow = 0;
+    bool all_fit = L.nlev > 0;
+    for (int l = 0; l < L.nlev; ++l) {
+        all_fit &= c->fac_lds[l] > 0;
+        mrow = std::max<int64_t>(mrow, c->fac_lds[l]);
+    }
+    mrow = (mrow + 7) / 8 * 8;
+    c->fwave_lds = all_fit && h.bs <= kMaxKernelBs && mrow * dev::kFacWaves <= 96 * 1024 ? static_cast<int>(mrow) : 0;
     bilu_status st;
     if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)) ||
-        (st = upload(c, &c->d_frec, rec)))
+        (st = upload(c, &c->d_frec, rec)) || (st = dalloc(c, &c->d_fticket, 2)))
         return st;
     return BILU_OK;
+}
+
+// The whole factorisation in one persistent launch (k_factor_waves); false
+// when there is no kernel for bs.
+bool launch_factor_waves(bilu_ctx* c, const double* Ax, hipStream_t s)
+{
+    dev::FactorWaveArgs a{};
+    a.rec = reinterpret_cast<const int4*>(c->d_frec);
+    a.Pj = c->d_Pj;
+    a.PtoA = c->d_PtoA;
+    a.Ax = Ax;
+    a.upd_ptr = c->d_upd_ptr;
+    a.upd_f = c->d_upd_f;
+    a.upd_g = c->d_upd_g;
+    a.P = c->d_P;
+    a.Dinv = c->d_Dinv;
+    a.bad_row = c->d_bad;
+    a.ticket = c->d_fticket;
+    a.status = reinterpret_cast<int*>(c->d_fticket + 1);
+    const HostSweep& L = c->h.sweep[BILU_SWEEP_L];
+    a.nrows = L.level_ptr[L.nlev];
+    a.lds_per_wave = c->fwave_lds;
+    a.spin_limit = c->spin_limit;
+    const int groups = (a.nrows + dev::kFacWaves - 1) / dev::kFacWaves;
+    const int blocks = std::max(1, std::min(groups, 2 * std::max(1, c->num_cu)));
+    const size_t lds = static_cast<size_t>(c->fwave_lds) * dev::kFacWaves;
+    BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B>), dim3(blocks), dim3(64 * dev::kFacWaves), lds,
+                                              s, a))
 }
 
 bool launch_split(const bilu_ctx* c, hipStream_t s)
@@ -1349,20 +1391,36 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     c->split_done = false;
     c->f_ready = false;
     const long tslot = timing_begin(c, BILU_K_FACTOR, s);
-    if (!launch_backfill(h.bs, nP, c->d_PtoA, Ax, c->d_P, s))
-        hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax, c->d_P);
     hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(1), c->d_bad, INT_MAX);
-    const HostSweep& L = h.sweep[BILU_SWEEP_L];
-    for (int l = 0; l < L.nlev; ++l) {
-        const int n = L.level_ptr[l + 1] - L.level_ptr[l];
-        const int lds = l < static_cast<int>(c->fac_lds.size()) ? c->fac_lds[l] : 0;
-        if (!launch_factor(h.bs, L.level_ptr[l], n, lds, c, s)) return BILU_ERR_ARG;
+    const bool waves = c->factor_mode == 0 && c->fwave_lds > 0 && !c->values_only;
+    if (waves) {
+        // P and D^{-1} start at kNotReady (rows read A directly); the ticket
+        // and the expired-wait word at zero
+        hipLaunchKernelGGL(dev::k_fill_not_ready, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP * bb, c->d_P);
+        hipLaunchKernelGGL(dev::k_fill_not_ready, dim3(grid_for(static_cast<int64_t>(h.nb) * bb)), dim3(256), 0, s,
+                           static_cast<int64_t>(h.nb) * bb, c->d_Dinv);
+        hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(2),
+                           reinterpret_cast<int32_t*>(c->d_fticket), 0);
+        if (!launch_factor_waves(c, Ax, s)) return BILU_ERR_ARG;
+    } else {
+        if (!launch_backfill(h.bs, nP, c->d_PtoA, Ax, c->d_P, s))
+            hipLaunchKernelGGL(dev::k_backfill, dim3(grid_for(nP * bb)), dim3(256), 0, s, nP, bb, c->d_PtoA, Ax,
+                               c->d_P);
+        const HostSweep& L = h.sweep[BILU_SWEEP_L];
+        for (int l = 0; l < L.nlev; ++l) {
+            const int n = L.level_ptr[l + 1] - L.level_ptr[l];
+            const int lds = l < static_cast<int>(c->fac_lds.size()) ? c->fac_lds[l] : 0;
+            if (!launch_factor(h.bs, L.level_ptr[l], n, lds, c, s)) return BILU_ERR_ARG;
+        }
     }
     timing_end(c, tslot, s);
     CK(hipGetLastError());
     int bad = INT_MAX;
+    int expired = 0;
     CK(hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (waves) CK(hipMemcpyAsync(&expired, c->d_fticket + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
+    if (expired) return BILU_ERR_TIMEOUT;
     c->factored = true;
     if (bad != INT_MAX) {
         if (bad_row) *bad_row = bad;
@@ -1549,6 +1607,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
     case BILU_TUNE_HELPER:
         if (value < 0 || value > 2) return BILU_ERR_ARG;
         c->helper = value;
+        return BILU_OK;
+    case BILU_TUNE_FACTOR:
+        if (value != 0 && value != 1) return BILU_ERR_ARG;
+        c->factor_mode = value;
         return BILU_OK;
     case BILU_TUNE_SPLIT_DINV:
         if (value < 0 || value > 2) return BILU_ERR_ARG;

@@ -313,6 +313,212 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Block ILU(0) on P (Algorithm 4), all levels in one persistent launch with
+// the arithmetic of k_factor_rows_lds: a workgroup of kFacWaves wavefronts
+// takes kFacWaves consecutive rows of the L level order from a ticket and
+// each wavefront factors one of them, in its own part of the LDS, with
+// wavefront-level ordering instead of workgroup barriers.  A row reads its
+// own blocks straight from A (PtoA: the backfill of Algorithm 5, zero at fill
+// positions) and its pivot rows' finished blocks -- D_p^{-1} and the A_pj of
+// its update pairs -- from P and Dinv, which start at kNotReady and receive
+// each value once, final, through a device-coherent store; the wavefront
+// polls those values (bounded) until none shows kNotReady.  Every pivot row
+// lies earlier in the level order: in an earlier ticket, held by a running
+// workgroup, or in a wavefront of the same workgroup, which progresses on
+// its own, so the launch drains.
+// ---------------------------------------------------------------------------
+constexpr int kFacWaves = 16;
+
+struct FactorWaveArgs {
+    const int4* rec;          // per position: {row, e0, nrow, dk}, {u0, npair, 0, 0}
+    const int32_t* Pj;
+    const int32_t* PtoA;
+    const double* Ax;
+    const int32_t* upd_ptr;
+    const int32_t* upd_f;
+    const int32_t* upd_g;
+    double* P;
+    double* Dinv;
+    int* bad_row;
+    unsigned int* ticket;     // zero at launch
+    int* status;
+    int nrows;
+    int lds_per_wave;         // bytes, a multiple of 8
+    unsigned int spin_limit;
+};
+
+#define BILU_WAVE_SYNC()                      \
+    do {                                      \
+        __builtin_amdgcn_wave_barrier();      \
+        asm volatile("" ::: "memory");        \
+    } while (0)
+
+template <int B>
+__global__ __launch_bounds__(64 * kFacWaves) void k_factor_waves(FactorWaveArgs a)
+{
+    constexpr int BB = B * B;
+    constexpr int W = 2 * B;
+    constexpr int kPairs = 64 / BB > 0 ? 64 / BB : 1;
+    extern __shared__ double fw[];
+    __shared__ double sWall[kFacWaves][B * W];
+    __shared__ int sPivAll[kFacWaves];
+    __shared__ int sBadAll[kFacWaves];
+    __shared__ unsigned int sTk;
+    const int wave = static_cast<int>(threadIdx.x) >> 6;
+    const int t = lane_id();
+    const int r = t % B;
+    const int c = t / B;
+    const int sub = t / BB;
+    const int el = t - sub * BB;
+    const int er = el % B;
+    const int ec = el / B;
+    double* sW = sWall[wave];
+    int& sPiv = sPivAll[wave];
+    int& sBad = sBadAll[wave];
+    double* mine = fw + static_cast<int64_t>(wave) * (a.lds_per_wave / 8);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) sTk = atomicAdd(a.ticket, 1u);
+        __syncthreads();
+        const int64_t x0 = static_cast<int64_t>(sTk) * kFacWaves;
+        if (x0 >= a.nrows) break;
+        const int64_t x = x0 + wave;
+        if (x < a.nrows) {
+            const int4 ra = a.rec[2 * x];
+            const int4 rb = a.rec[2 * x + 1];
+            const int i = ra.x, e0 = ra.y, nrow = ra.z, dk = ra.w, u0 = rb.x, npair = rb.y;
+            double* sRow = mine;
+            double* sD = sRow + nrow * BB;
+            double* sU = sD + dk * BB;
+            int* sQ = reinterpret_cast<int*>(sU + npair * BB);
+            int* sF = sQ + dk + 1;
+            int* sG = sF + npair;
+            int* sPv = sG + npair;
+            if (t == 0) sBad = 0;
+            for (int y = t; y < nrow * BB; y += 64) {
+                const int k = y / BB;
+                const int32_t src = a.PtoA[e0 + k];
+                sRow[y] = src >= 0 ? a.Ax[static_cast<int64_t>(src) * BB + (y - k * BB)] : 0.0;
+            }
+            for (int y = t; y <= dk; y += 64) sQ[y] = a.upd_ptr[e0 + y] - u0;
+            for (int y = t; y < npair; y += 64) {
+                sF[y] = a.upd_f[u0 + y];
+                sG[y] = a.upd_g[u0 + y];
+            }
+            for (int y = t; y < dk; y += 64) sPv[y] = a.Pj[e0 + y];
+            BILU_WAVE_SYNC();
+            // the pivot rows' finished blocks, polled together
+            bool first = true;
+            for (unsigned int spins = 0;;) {
+                bool pend = false;
+                for (int y = t; y < dk * BB; y += 64) {
+                    const int k = y / BB;
+                    double v = sD[y];
+                    if (first || is_not_ready(v)) {
+                        v = coherent_load(a.Dinv + static_cast<int64_t>(sPv[k]) * BB + (y - k * BB));
+                        sD[y] = v;
+                    }
+                    pend |= is_not_ready(v);
+                }
+                for (int y = t; y < npair * BB; y += 64) {
+                    const int qq = y / BB;
+                    double v = sU[y];
+                    if (first || is_not_ready(v)) {
+                        v = coherent_load(a.P + static_cast<int64_t>(sG[qq]) * BB + (y - qq * BB));
+                        sU[y] = v;
+                    }
+                    pend |= is_not_ready(v);
+                }
+                first = false;
+                BILU_WAVE_SYNC();
+                if (!__any(pend)) break;
+                if (++spins > a.spin_limit) {
+                    if (t == 0) atomicOr(a.status, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            // elimination (k_factor_rows_lds, wavefront-ordered)
+            for (int k = 0; k < dk; ++k) {
+                double tv = 0.0;
+                if (t < BB) {
+#pragma unroll
+                    for (int u = 0; u < B; ++u) tv += sRow[k * BB + u * B + r] * sD[k * BB + c * B + u];
+                }
+                BILU_WAVE_SYNC();
+                if (t < BB) sRow[k * BB + t] = tv;
+                BILU_WAVE_SYNC();
+                if (sub < kPairs)
+                    for (int qq = sQ[k] + sub; qq < sQ[k + 1]; qq += kPairs) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int u = 0; u < B; ++u) acc += sRow[k * BB + u * B + er] * sU[qq * BB + ec * B + u];
+                        sRow[sF[qq] * BB + el] -= acc;
+                    }
+                BILU_WAVE_SYNC();
+            }
+            if (t < BB) {
+                sW[r * W + c] = sRow[dk * BB + t];
+                sW[r * W + B + c] = (r == c) ? 1.0 : 0.0;
+            }
+            for (int y = t; y < nrow * BB; y += 64)
+                coherent_store(a.P + static_cast<int64_t>(e0) * BB + y, publishable(sRow[y]));
+            BILU_WAVE_SYNC();
+            for (int col = 0; col < B; ++col) {
+                if (t == 0) {
+                    int piv = col;
+                    double best = fabs(sW[col * W + col]);
+                    for (int rr = col + 1; rr < B; ++rr) {
+                        const double v = fabs(sW[rr * W + col]);
+                        if (v > best) {
+                            best = v;
+                            piv = rr;
+                        }
+                    }
+                    if (!(best > 0.0) || !isfinite(best)) sBad = 1;
+                    sPiv = piv;
+                }
+                BILU_WAVE_SYNC();
+                const int piv = sPiv;
+                if (piv != col && t < W) {
+                    const double tmp = sW[col * W + t];
+                    sW[col * W + t] = sW[piv * W + t];
+                    sW[piv * W + t] = tmp;
+                }
+                BILU_WAVE_SYNC();
+                const double dd = sW[col * W + col];
+                BILU_WAVE_SYNC();
+                if (t < W) sW[col * W + t] /= dd;
+                BILU_WAVE_SYNC();
+                double fct[2];
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int idx = t + 64 * s2;
+                    fct[s2] = idx < B * W ? sW[(idx / W) * W + col] : 0.0;
+                }
+                BILU_WAVE_SYNC();
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int idx = t + 64 * s2;
+                    if (idx < B * W) {
+                        const int rr = idx / W;
+                        const int cc = idx - rr * W;
+                        if (rr != col) sW[idx] -= fct[s2] * sW[col * W + cc];
+                    }
+                }
+                BILU_WAVE_SYNC();
+            }
+            if (t < BB)
+                coherent_store(a.Dinv + static_cast<int64_t>(i) * BB + t, publishable(sW[r * W + B + c]));
+            if (t == 0 && sBad) atomicMin(a.bad_row, i);
+            BILU_WAVE_SYNC();
+        }
+    }
+}
+
+#undef BILU_WAVE_SYNC
+
+// ---------------------------------------------------------------------------
 // Point-granularity view of the factors (the point-wise solver the paper
 // feeds with its block factors, Section 2.4 / Alg 6): every point entry of
 // the expanded unit-diagonal L and U' takes its value from element (r, c) of

@@ -101,6 +101,38 @@ def test_factor_long_rows(api, oracle_mod):
     M.check()
 
 
+FACTOR_CASES = SMALL + [("ragged_b1_k3", lambda: synth.reservoir(13, 3, 11, 1, seed=45), 3),
+                        ("layered60x220x85", lambda: synth.layered_60x220x85(), 0),
+                        ("layered60x220x85", lambda: synth.layered_60x220x85(), 1),
+                        ("mid64", lambda: synth.mid_64cube(), 2)]
+
+
+@pytest.mark.parametrize("name,make,k", FACTOR_CASES, ids=[f"{c[0]}_k{c[2]}" for c in FACTOR_CASES])
+def test_factor_waves_match_levels(api, name, make, k):
+    """The persistent factorisation (a wavefront per row, rows waiting for
+    their pivot rows' finished blocks) and one launch per L level run the
+    same arithmetic: the same bits, also after a refactorisation with other
+    values (P and D^{-1} restart at kNotReady each time)."""
+    s = make()
+    print(f"[factor] {name} k={k}", flush=True)
+    Ax = cuda(s.Ax)
+    Ax2 = cuda(s.Ax * (1.0 + 0.25 * np.cos(np.arange(s.Ax.size))))
+    A = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, k)
+    B = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, k)
+    try:
+        A.tune(factor="levels")
+        B.tune(factor="waves")
+        for vals in (Ax, Ax2):
+            assert A.factor(vals) == -1
+            assert B.factor(vals) == -1
+            FA, DA = A.factors()
+            FB, DB = B.factors()
+            assert torch.equal(FA, FB) and torch.equal(DA, DB)
+    finally:
+        A.close()
+        B.close()
+
+
 MODES = [(0, None), (1, None), (2, None), (2, 1), (2, 13), (2, 64)]
 
 
