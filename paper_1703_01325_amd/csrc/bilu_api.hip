@@ -125,6 +125,7 @@ struct bilu_ctx {
     // LDS bytes per wavefront (0: some row does not fit, one launch per
     // level instead), ticket and expired-wait words
     int fwave_lds = 0;
+    int fwave_n = 16;                     // wavefronts (rows) per workgroup and ticket
     unsigned int* d_fticket = nullptr;
     int factor_mode = 0;                  // BILU_TUNE_FACTOR
     int spmv_stream = 0;                  // BILU_TUNE_SPMV_STREAM
@@ -446,7 +447,9 @@ bilu_status factor_plan(bilu_ctx* c)
         mrow = std::max<int64_t>(mrow, c->fac_lds[l]);
     }
     mrow = (mrow + 7) / 8 * 8;
-    c->fwave_lds = all_fit && h.bs <= kMaxKernelBs && mrow * dev::kFacWaves <= 96 * 1024 ? static_cast<int>(mrow) : 0;
+    // as many wavefronts per workgroup (16, 8 or 4) as fit 96 KiB of LDS
+    c->fwave_n = mrow * 16 <= 96 * 1024 ? 16 : mrow * 8 <= 96 * 1024 ? 8 : 4;
+    c->fwave_lds = all_fit && h.bs <= kMaxKernelBs && mrow * c->fwave_n <= 96 * 1024 ? static_cast<int>(mrow) : 0;
     bilu_status st;
     if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)) ||
         (st = upload(c, &c->d_frec, rec)) || (st = dalloc(c, &c->d_fticket, 2)))
@@ -475,11 +478,17 @@ bool launch_factor_waves(bilu_ctx* c, const double* Ax, hipStream_t s)
     a.nrows = L.level_ptr[L.nlev];
     a.lds_per_wave = c->fwave_lds;
     a.spin_limit = c->spin_limit;
-    const int groups = (a.nrows + dev::kFacWaves - 1) / dev::kFacWaves;
-    const int blocks = std::max(1, std::min(groups, 2 * std::max(1, c->num_cu)));
-    const size_t lds = static_cast<size_t>(c->fwave_lds) * dev::kFacWaves;
-    BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B>), dim3(blocks), dim3(64 * dev::kFacWaves), lds,
-                                              s, a))
+    const int nw = c->fwave_n;
+    const int groups = (a.nrows + nw - 1) / nw;
+    const int blocks = std::max(1, std::min(groups, (32 / nw) * std::max(1, c->num_cu)));
+    const size_t lds = static_cast<size_t>(c->fwave_lds) * nw;
+    if (nw == 16) {
+        BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 16>), dim3(blocks), dim3(64 * 16), lds, s, a))
+    }
+    if (nw == 8) {
+        BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 8>), dim3(blocks), dim3(64 * 8), lds, s, a))
+    }
+    BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 4>), dim3(blocks), dim3(64 * 4), lds, s, a))
 }
 
 bool launch_split(const bilu_ctx* c, hipStream_t s)

@@ -314,8 +314,9 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
 
 // ---------------------------------------------------------------------------
 // Block ILU(0) on P (Algorithm 4), all levels in one persistent launch with
-// the arithmetic of k_factor_rows_lds: a workgroup of kFacWaves wavefronts
-// takes kFacWaves consecutive rows of the L level order from a ticket and
+// the arithmetic of k_factor_rows_lds: a workgroup of NWV wavefronts (16,
+// or 8 or 4 where rows need more LDS) takes NWV consecutive rows of the L
+// level order from a ticket and
 // each wavefront factors one of them, in its own part of the LDS, with
 // wavefront-level ordering instead of workgroup barriers.  A row reads its
 // own blocks straight from A (PtoA: the backfill of Algorithm 5, zero at fill
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
 // workgroup, or in a wavefront of the same workgroup, which progresses on
 // its own, so the launch drains.
 // ---------------------------------------------------------------------------
-constexpr int kFacWaves = 16;
+constexpr int kFacWaves = 16;     // wavefronts per workgroup, at most
 
 struct FactorWaveArgs {
     const int4* rec;          // per position: {row, e0, nrow, dk}, {u0, npair, 0, 0}
@@ -353,16 +354,16 @@ struct FactorWaveArgs {
         asm volatile("" ::: "memory");        \
     } while (0)
 
-template <int B>
-__global__ __launch_bounds__(64 * kFacWaves) void k_factor_waves(FactorWaveArgs a)
+template <int B, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_factor_waves(FactorWaveArgs a)
 {
     constexpr int BB = B * B;
     constexpr int W = 2 * B;
     constexpr int kPairs = 64 / BB > 0 ? 64 / BB : 1;
     extern __shared__ double fw[];
-    __shared__ double sWall[kFacWaves][B * W];
-    __shared__ int sPivAll[kFacWaves];
-    __shared__ int sBadAll[kFacWaves];
+    __shared__ double sWall[NWV][B * W];
+    __shared__ int sPivAll[NWV];
+    __shared__ int sBadAll[NWV];
     __shared__ unsigned int sTk;
     const int wave = static_cast<int>(threadIdx.x) >> 6;
     const int t = lane_id();
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(64 * kFacWaves) void k_factor_waves(FactorWaveArgs 
         __syncthreads();
         if (threadIdx.x == 0) sTk = atomicAdd(a.ticket, 1u);
         __syncthreads();
-        const int64_t x0 = static_cast<int64_t>(sTk) * kFacWaves;
+        const int64_t x0 = static_cast<int64_t>(sTk) * NWV;
         if (x0 >= a.nrows) break;
         const int64_t x = x0 + wave;
         if (x < a.nrows) {

@@ -102,6 +102,8 @@ def test_factor_long_rows(api, oracle_mod):
 
 
 FACTOR_CASES = SMALL + [("ragged_b1_k3", lambda: synth.reservoir(13, 3, 11, 1, seed=45), 3),
+                        ("res7x6x5_b4_k2", lambda: synth.reservoir(7, 6, 5, 4, seed=47), 2),
+                        ("res7x6x5_b8_k2", lambda: synth.reservoir(7, 6, 5, 8, seed=48), 2),
                         ("layered60x220x85", lambda: synth.layered_60x220x85(), 0),
                         ("layered60x220x85", lambda: synth.layered_60x220x85(), 1),
                         ("mid64", lambda: synth.mid_64cube(), 2)]
