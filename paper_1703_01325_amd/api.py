@@ -108,7 +108,7 @@ class BlockILU:
                           (0 if rhs_pairs == "auto" else 2 if rhs_pairs else 1)),
                          (N.TUNE_SPLIT_DINV, None if split_dinv is None else
                           (0 if split_dinv == "auto" else 2 if split_dinv else 1)),
-                         (N.TUNE_FACTOR, None if factor is None else {"waves": 0, "levels": 1}[factor]),
+                         (N.TUNE_FACTOR, None if factor is None else {"waves": 0, "levels": 1, "waves16": 2, "waves4": 3}[factor]),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

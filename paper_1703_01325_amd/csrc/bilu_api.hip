@@ -478,7 +478,11 @@ bool launch_factor_waves(bilu_ctx* c, const double* Ax, hipStream_t s)
     a.nrows = L.level_ptr[L.nlev];
     a.lds_per_wave = c->fwave_lds;
     a.spin_limit = c->spin_limit;
-    const int nw = c->fwave_n;
+    // wavefronts per workgroup: 8 where the LDS allows (measured on MI355X,
+    // 60x220x85: ILU(0) 2.40 ms with 16, 2.05 with 8, 3.54 with 4 -- four rows
+    // per ticket make the ticket counter the bottleneck; ILU(1) 4.60 / 4.38 /
+    // 4.73); BILU_TUNE_FACTOR 2: 16 where the LDS allows, 3: 4
+    const int nw = c->factor_mode == 2 ? c->fwave_n : c->factor_mode == 3 ? 4 : std::min(c->fwave_n, 8);
     const int groups = (a.nrows + nw - 1) / nw;
     const int blocks = std::max(1, std::min(groups, (32 / nw) * std::max(1, c->num_cu)));
     const size_t lds = static_cast<size_t>(c->fwave_lds) * nw;
@@ -1401,7 +1405,7 @@ bilu_status bilu_factor_numeric(bilu_ctx* c, const double* Ax, hipStream_t s, in
     c->f_ready = false;
     const long tslot = timing_begin(c, BILU_K_FACTOR, s);
     hipLaunchKernelGGL(dev::k_fill_i32, dim3(1), dim3(64), 0, s, int64_t(1), c->d_bad, INT_MAX);
-    const bool waves = c->factor_mode == 0 && c->fwave_lds > 0 && !c->values_only;
+    const bool waves = c->factor_mode != 1 && c->fwave_lds > 0 && !c->values_only;
     if (waves) {
         // P and D^{-1} start at kNotReady (rows read A directly); the ticket
         // and the expired-wait word at zero
@@ -1618,7 +1622,7 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         c->helper = value;
         return BILU_OK;
     case BILU_TUNE_FACTOR:
-        if (value != 0 && value != 1) return BILU_ERR_ARG;
+        if (value < 0 || value > 3) return BILU_ERR_ARG;
         c->factor_mode = value;
         return BILU_OK;
     case BILU_TUNE_SPLIT_DINV:

@@ -123,13 +123,14 @@ def test_factor_waves_match_levels(api, name, make, k):
     B = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, k)
     try:
         A.tune(factor="levels")
-        B.tune(factor="waves")
-        for vals in (Ax, Ax2):
-            assert A.factor(vals) == -1
-            assert B.factor(vals) == -1
-            FA, DA = A.factors()
-            FB, DB = B.factors()
-            assert torch.equal(FA, FB) and torch.equal(DA, DB)
+        for mode in ("waves", "waves16", "waves4"):
+            B.tune(factor=mode)
+            for vals in (Ax, Ax2):
+                assert A.factor(vals) == -1
+                assert B.factor(vals) == -1
+                FA, DA = A.factors()
+                FB, DB = B.factors()
+                assert torch.equal(FA, FB) and torch.equal(DA, DB), mode
     finally:
         A.close()
         B.close()
