@@ -380,11 +380,13 @@ enum {
                                  2: from 2 columns up.  Same bits                  */
     BILU_TUNE_FACTOR = 13,    /* numeric factorisation: 0 (default) one persistent
                                  launch, a wavefront per row (8 rows per workgroup,
-                                 4 where rows need more LDS), rows waiting for their
-                                 pivot rows' finished blocks instead of whole
-                                 levels, where every row fits the LDS; 1: one launch
-                                 per L level; 2 / 3: the persistent launch with 16
-                                 (where the LDS allows) / 4 rows per workgroup.
+                                 4, 2 or 1 where rows need more LDS), rows waiting
+                                 for their pivot rows' finished blocks instead of
+                                 whole levels, where each row's blocks, pivot
+                                 inverses, lists and one pivot's update blocks fit
+                                 96 KiB (block sizes 1-8); 1: one launch per L
+                                 level; 2 / 3: the persistent launch with 16 (where
+                                 the LDS allows) / at most 4 rows per workgroup.
                                  Same bits                                          */
     BILU_TUNE_SPLIT_DINV = 12, /* one right-hand side, mode 2: form
                                  D^{-1} y by blocks ahead of the U' sweep and run that

@@ -395,6 +395,7 @@ bilu_status factor_plan(bilu_ctx* c)
     const int64_t bb8 = static_cast<int64_t>(h.bs) * h.bs * 8;
     std::vector<int32_t> uptr(static_cast<size_t>(nP) + 1, 0), uf, ug;
     std::vector<int64_t> row_bytes(static_cast<size_t>(nb), 0);
+    int64_t row_min = 0;      // largest LDS a row needs with one pivot's pairs at a time
     for (int32_t i = 0; i < nb; ++i) {
         const int32_t e0 = h.Pp[i], e1 = h.Pp[i + 1], d = h.Pdiag[i];
         for (int32_t e = e0; e < e1; ++e) {
@@ -419,7 +420,11 @@ bilu_status factor_plan(bilu_ctx* c)
             uptr[e + 1] = static_cast<int32_t>(uf.size());
         }
         const int64_t nrow = e1 - e0, dk = d - e0, npair = uptr[d] - uptr[e0];
-        row_bytes[i] = (nrow + dk + npair) * bb8 + (2 * dk + 1 + 2 * npair) * 4;
+        const int64_t lists = ((2 * dk + 1 + 2 * npair) * 4 + 7) / 8 * 8;
+        row_bytes[i] = (nrow + dk + npair) * bb8 + lists;
+        int64_t maxpp = 0;
+        for (int32_t e = e0; e < d; ++e) maxpp = std::max<int64_t>(maxpp, uptr[e + 1] - uptr[e]);
+        row_min = std::max(row_min, (nrow + dk + maxpp) * bb8 + lists);
     }
     const HostSweep& L = h.sweep[BILU_SWEEP_L];
     c->fac_lds.assign(static_cast<size_t>(L.nlev), 0);
@@ -440,16 +445,18 @@ bilu_status factor_plan(bilu_ctx* c)
         }
         c->fac_lds[l] = m <= kCap && h.bs <= kMaxKernelBs ? static_cast<int32_t>(m) : 0;
     }
+    // the persistent factorisation: as many wavefronts per workgroup (16, 8,
+    // 4, 2 or 1) as fit 96 KiB of LDS with the largest row of the pattern; a
+    // row larger than 96 KiB stages the A_pj blocks of its pivots a run of
+    // pivots at a time, which takes one wavefront per workgroup and every
+    // row's blocks, pivot inverses, lists and one pivot's A_pj within 96 KiB
+    constexpr int64_t kWaveCap = 96 * 1024;
     int64_t mrow = 0;
-    bool all_fit = L.nlev > 0;
-    for (int l = 0; l < L.nlev; ++l) {
-        all_fit &= c->fac_lds[l] > 0;
-        mrow = std::max<int64_t>(mrow, c->fac_lds[l]);
-    }
-    mrow = (mrow + 7) / 8 * 8;
-    // as many wavefronts per workgroup (16, 8 or 4) as fit 96 KiB of LDS
-    c->fwave_n = mrow * 16 <= 96 * 1024 ? 16 : mrow * 8 <= 96 * 1024 ? 8 : 4;
-    c->fwave_lds = all_fit && h.bs <= kMaxKernelBs && mrow * c->fwave_n <= 96 * 1024 ? static_cast<int>(mrow) : 0;
+    for (int32_t i = 0; i < nb; ++i) mrow = std::max(mrow, row_bytes[i]);
+    mrow = std::min<int64_t>((mrow + 7) / 8 * 8, kWaveCap);
+    c->fwave_n = 16;
+    while (c->fwave_n > 1 && mrow * c->fwave_n > kWaveCap) c->fwave_n /= 2;
+    c->fwave_lds = L.nlev > 0 && h.bs <= kMaxKernelBs && row_min <= kWaveCap ? static_cast<int>(mrow) : 0;
     bilu_status st;
     if ((st = upload(c, &c->d_upd_ptr, uptr)) || (st = upload(c, &c->d_upd_f, uf)) || (st = upload(c, &c->d_upd_g, ug)) ||
         (st = upload(c, &c->d_frec, rec)) || (st = dalloc(c, &c->d_fticket, 2)))
@@ -481,8 +488,9 @@ bool launch_factor_waves(bilu_ctx* c, const double* Ax, hipStream_t s)
     // wavefronts per workgroup: 8 where the LDS allows (measured on MI355X,
     // 60x220x85: ILU(0) 2.40 ms with 16, 2.05 with 8, 3.54 with 4 -- four rows
     // per ticket make the ticket counter the bottleneck; ILU(1) 4.60 / 4.38 /
-    // 4.73); BILU_TUNE_FACTOR 2: 16 where the LDS allows, 3: 4
-    const int nw = c->factor_mode == 2 ? c->fwave_n : c->factor_mode == 3 ? 4 : std::min(c->fwave_n, 8);
+    // 4.73), fewer for larger rows; BILU_TUNE_FACTOR 2: 16 where the LDS
+    // allows, 3: at most 4
+    const int nw = c->factor_mode == 2 ? c->fwave_n : std::min(c->fwave_n, c->factor_mode == 3 ? 4 : 8);
     const int groups = (a.nrows + nw - 1) / nw;
     const int blocks = std::max(1, std::min(groups, (32 / nw) * std::max(1, c->num_cu)));
     const size_t lds = static_cast<size_t>(c->fwave_lds) * nw;
@@ -492,7 +500,13 @@ bool launch_factor_waves(bilu_ctx* c, const double* Ax, hipStream_t s)
     if (nw == 8) {
         BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 8>), dim3(blocks), dim3(64 * 8), lds, s, a))
     }
-    BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 4>), dim3(blocks), dim3(64 * 4), lds, s, a))
+    if (nw == 4) {
+        BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 4>), dim3(blocks), dim3(64 * 4), lds, s, a))
+    }
+    if (nw == 2) {
+        BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 2>), dim3(blocks), dim3(64 * 2), lds, s, a))
+    }
+    BILU_SWITCH_B(c->h.bs, hipLaunchKernelGGL((dev::k_factor_waves<B, 1>), dim3(blocks), dim3(64), lds, s, a))
 }
 
 bool launch_split(const bilu_ctx* c, hipStream_t s)

@@ -314,9 +314,9 @@ __global__ __launch_bounds__(64) void k_factor_rows_lds(const int4* __restrict__
 
 // ---------------------------------------------------------------------------
 // Block ILU(0) on P (Algorithm 4), all levels in one persistent launch with
-// the arithmetic of k_factor_rows_lds: a workgroup of NWV wavefronts (16,
-// or 8 or 4 where rows need more LDS) takes NWV consecutive rows of the L
-// level order from a ticket and
+// the arithmetic of k_factor_rows_lds: a workgroup of NWV wavefronts (16, 8,
+// 4, 2 or 1, as the LDS each row needs allows) takes NWV consecutive rows of
+// the L level order from a ticket and
 // each wavefront factors one of them, in its own part of the LDS, with
 // wavefront-level ordering instead of workgroup barriers.  A row reads its
 // own blocks straight from A (PtoA: the backfill of Algorithm 5, zero at fill
@@ -348,6 +348,27 @@ struct FactorWaveArgs {
     unsigned int spin_limit;
 };
 
+// dst[y] = load(y) for y = t, t + 64, ... < n (lane t of a wavefront), G
+// loads in flight per lane; true when some loaded value shows kNotReady.
+template <int G, typename Load>
+__device__ __forceinline__ bool gather(double* dst, int n, int t, Load load)
+{
+    bool pend = false;
+    for (int y0 = t; y0 < n; y0 += 64 * G) {
+        double v[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m)
+            if (y0 + 64 * m < n) v[m] = load(y0 + 64 * m);
+#pragma unroll
+        for (int m = 0; m < G; ++m)
+            if (y0 + 64 * m < n) {
+                dst[y0 + 64 * m] = v[m];
+                pend |= is_not_ready(v[m]);
+            }
+    }
+    return pend;
+}
+
 #define BILU_WAVE_SYNC()                      \
     do {                                      \
         __builtin_amdgcn_wave_barrier();      \
@@ -360,6 +381,11 @@ __global__ __launch_bounds__(64 * NWV) void k_factor_waves(FactorWaveArgs a)
     constexpr int BB = B * B;
     constexpr int W = 2 * B;
     constexpr int kPairs = 64 / BB > 0 ? 64 / BB : 1;
+    // loads in flight per lane while a row is staged: eight for b >= 4 (rows of
+    // many blocks; Poisson 120^3 b = 8, k = 3 214 -> 160 ms), one below, where
+    // the registers they take cost occupancy (60x220x85 b = 3, ILU(0): 2.45 ms
+    // with eight against 2.06)
+    constexpr int kG = B >= 4 ? 8 : 1;
     extern __shared__ double fw[];
     __shared__ double sWall[NWV][B * W];
     __shared__ int sPivAll[NWV];
@@ -391,16 +417,21 @@ __global__ __launch_bounds__(64 * NWV) void k_factor_waves(FactorWaveArgs a)
             double* sRow = mine;
             double* sD = sRow + nrow * BB;
             double* sU = sD + dk * BB;
-            int* sQ = reinterpret_cast<int*>(sU + npair * BB);
+            // A_pj blocks that fit beside the row, its pivot inverses and its
+            // lists: all of them, or (rows beyond the LDS per wavefront) the
+            // pairs of a run of pivots at a time, each pivot's at least
+            const int lists = ((2 * dk + 1 + 2 * npair) * 4 + 7) / 8 * 8;
+            const int cap = min(npair, (a.lds_per_wave - lists) / (8 * BB) - nrow - dk);
+            int* sQ = reinterpret_cast<int*>(sU + cap * BB);
             int* sF = sQ + dk + 1;
             int* sG = sF + npair;
             int* sPv = sG + npair;
             if (t == 0) sBad = 0;
-            for (int y = t; y < nrow * BB; y += 64) {
+            gather<kG>(sRow, nrow * BB, t, [&](int y) {
                 const int k = y / BB;
                 const int32_t src = a.PtoA[e0 + k];
-                sRow[y] = src >= 0 ? a.Ax[static_cast<int64_t>(src) * BB + (y - k * BB)] : 0.0;
-            }
+                return src >= 0 ? a.Ax[static_cast<int64_t>(src) * BB + (y - k * BB)] : 0.0;
+            });
             for (int y = t; y <= dk; y += 64) sQ[y] = a.upd_ptr[e0 + y] - u0;
             for (int y = t; y < npair; y += 64) {
                 sF[y] = a.upd_f[u0 + y];
@@ -408,55 +439,73 @@ __global__ __launch_bounds__(64 * NWV) void k_factor_waves(FactorWaveArgs a)
             }
             for (int y = t; y < dk; y += 64) sPv[y] = a.Pj[e0 + y];
             BILU_WAVE_SYNC();
-            // the pivot rows' finished blocks, polled together
-            bool first = true;
-            for (unsigned int spins = 0;;) {
-                bool pend = false;
-                for (int y = t; y < dk * BB; y += 64) {
+            for (int k0 = 0; k0 < dk;) {
+                // the run of pivots k0 .. k1 - 1 whose pairs fit
+                int k1 = k0 + 1;
+                while (k1 < dk && sQ[k1 + 1] - sQ[k0] <= cap) ++k1;
+                const int q0 = sQ[k0], nq = sQ[k1] - q0;
+                // the pivot rows' finished blocks, polled together (the pivot
+                // inverses with the first run)
+                const int nd = k0 == 0 ? dk * BB : 0;
+                // first pass: every value, eight loads in flight per lane; then
+                // only the values still missing
+                bool pend = gather<kG>(sD, nd, t, [&](int y) {
                     const int k = y / BB;
-                    double v = sD[y];
-                    if (first || is_not_ready(v)) {
-                        v = coherent_load(a.Dinv + static_cast<int64_t>(sPv[k]) * BB + (y - k * BB));
-                        sD[y] = v;
-                    }
-                    pend |= is_not_ready(v);
-                }
-                for (int y = t; y < npair * BB; y += 64) {
+                    return coherent_load(a.Dinv + static_cast<int64_t>(sPv[k]) * BB + (y - k * BB));
+                });
+                pend |= gather<kG>(sU, nq * BB, t, [&](int y) {
                     const int qq = y / BB;
-                    double v = sU[y];
-                    if (first || is_not_ready(v)) {
-                        v = coherent_load(a.P + static_cast<int64_t>(sG[qq]) * BB + (y - qq * BB));
-                        sU[y] = v;
+                    return coherent_load(a.P + static_cast<int64_t>(sG[q0 + qq]) * BB + (y - qq * BB));
+                });
+                BILU_WAVE_SYNC();
+                for (unsigned int spins = 0; __any(pend);) {
+                    if (++spins > a.spin_limit) {
+                        if (t == 0) atomicOr(a.status, 1);
+                        break;
                     }
-                    pend |= is_not_ready(v);
-                }
-                first = false;
-                BILU_WAVE_SYNC();
-                if (!__any(pend)) break;
-                if (++spins > a.spin_limit) {
-                    if (t == 0) atomicOr(a.status, 1);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            // elimination (k_factor_rows_lds, wavefront-ordered)
-            for (int k = 0; k < dk; ++k) {
-                double tv = 0.0;
-                if (t < BB) {
-#pragma unroll
-                    for (int u = 0; u < B; ++u) tv += sRow[k * BB + u * B + r] * sD[k * BB + c * B + u];
-                }
-                BILU_WAVE_SYNC();
-                if (t < BB) sRow[k * BB + t] = tv;
-                BILU_WAVE_SYNC();
-                if (sub < kPairs)
-                    for (int qq = sQ[k] + sub; qq < sQ[k + 1]; qq += kPairs) {
-                        double acc = 0.0;
-#pragma unroll
-                        for (int u = 0; u < B; ++u) acc += sRow[k * BB + u * B + er] * sU[qq * BB + ec * B + u];
-                        sRow[sF[qq] * BB + el] -= acc;
+                    __builtin_amdgcn_s_sleep(1);
+                    pend = false;
+                    for (int y = t; y < nd; y += 64) {
+                        const int k = y / BB;
+                        double v = sD[y];
+                        if (is_not_ready(v)) {
+                            v = coherent_load(a.Dinv + static_cast<int64_t>(sPv[k]) * BB + (y - k * BB));
+                            sD[y] = v;
+                        }
+                        pend |= is_not_ready(v);
                     }
-                BILU_WAVE_SYNC();
+                    for (int y = t; y < nq * BB; y += 64) {
+                        const int qq = y / BB;
+                        double v = sU[y];
+                        if (is_not_ready(v)) {
+                            v = coherent_load(a.P + static_cast<int64_t>(sG[q0 + qq]) * BB + (y - qq * BB));
+                            sU[y] = v;
+                        }
+                        pend |= is_not_ready(v);
+                    }
+                    BILU_WAVE_SYNC();
+                }
+                // elimination (k_factor_rows_lds, wavefront-ordered)
+                for (int k = k0; k < k1; ++k) {
+                    double tv = 0.0;
+                    if (t < BB) {
+#pragma unroll
+                        for (int u = 0; u < B; ++u) tv += sRow[k * BB + u * B + r] * sD[k * BB + c * B + u];
+                    }
+                    BILU_WAVE_SYNC();
+                    if (t < BB) sRow[k * BB + t] = tv;
+                    BILU_WAVE_SYNC();
+                    if (sub < kPairs)
+                        for (int qq = sQ[k] + sub; qq < sQ[k + 1]; qq += kPairs) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int u = 0; u < B; ++u)
+                                acc += sRow[k * BB + u * B + er] * sU[(qq - q0) * BB + ec * B + u];
+                            sRow[sF[qq] * BB + el] -= acc;
+                        }
+                    BILU_WAVE_SYNC();
+                }
+                k0 = k1;
             }
             if (t < BB) {
                 sW[r * W + c] = sRow[dk * BB + t];

@@ -106,7 +106,15 @@ FACTOR_CASES = SMALL + [("ragged_b1_k3", lambda: synth.reservoir(13, 3, 11, 1, s
                         ("res7x6x5_b8_k2", lambda: synth.reservoir(7, 6, 5, 8, seed=48), 2),
                         ("layered60x220x85", lambda: synth.layered_60x220x85(), 0),
                         ("layered60x220x85", lambda: synth.layered_60x220x85(), 1),
-                        ("mid64", lambda: synth.mid_64cube(), 2)]
+                        ("mid64", lambda: synth.mid_64cube(), 2),
+                        # rows of up to 31, 41 and 92 KiB: two, two and one
+                        # wavefront per workgroup of the persistent launch;
+                        # up to 119 KiB: the A_pj blocks staged a run of
+                        # pivots at a time
+                        ("poisson16x10x10_b4_k3", lambda: synth.poisson7(10, 4, nx=16), 3),
+                        ("poisson24x10x10_b8_k2", lambda: synth.poisson7(10, 8, nx=24), 2),
+                        ("poisson24x8x8_b8_k3", lambda: synth.poisson7(8, 8, nx=24), 3),
+                        ("poisson32x10x10_b8_k3", lambda: synth.poisson7(10, 8, nx=32), 3)]
 
 
 @pytest.mark.parametrize("name,make,k", FACTOR_CASES, ids=[f"{c[0]}_k{c[2]}" for c in FACTOR_CASES])
