@@ -93,7 +93,11 @@ class BlockILU:
     def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None,
              tile_block=None, line_sweep=None, helper=None, spmv_stream=None, rhs_pairs=None, split_dinv=None,
              factor=None):
-        """Launch knobs of the sweeps (results are bit-identical for all)."""
+        """Launch knobs of the sweeps and the factorisation (results are
+        bit-identical for all).  ``factor``: "waves" (one persistent launch,
+        8 rows per workgroup where the LDS allows), "levels" (one launch per
+        L level), "waves16" / "waves4" (16 where the LDS allows / at most 4
+        rows per workgroup)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
                          (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
                          (N.TUNE_TILE_BLOCK, None if tile_block is None else
