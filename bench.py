@@ -431,7 +431,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the single-system "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for {args.gpus}); the single-system "
               "preconditioner does not shard across GPUs without changing the method.", file=sys.stderr)
         sys.exit(2)
 
