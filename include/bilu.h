@@ -393,6 +393,10 @@ enum {
                                  sweep unfused (2), or fuse D^{-1} into it (1);
                                  0 (default): split where U' rows keep six or more
                                  dependency slots in registers.  Same bits           */
+    BILU_TUNE_SPIN_LIMIT = 14, /* polls a bounded wait of the persistent kernels
+                                 makes before it gives up (the call then returns
+                                 BILU_ERR_TIMEOUT, its results invalid); 0: the
+                                 default, 2^24.  For tests of that error path       */
     BILU_TUNE_TILE_GROUP = 6  /* mode 2: up to this many tiles (1..4) run as the
                                  wavefronts of one workgroup, handing rows to each
                                  other through its LDS instead of global memory; a

@@ -284,6 +284,7 @@ TUNE_SPMV_STREAM = 10
 TUNE_RHS_PAIRS = 11
 TUNE_SPLIT_DINV = 12
 TUNE_FACTOR = 13
+TUNE_SPIN_LIMIT = 14
 
 
 def bilu_tune(ctx, param, value):

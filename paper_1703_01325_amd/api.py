@@ -92,12 +92,13 @@ class BlockILU:
 
     def tune(self, mode=None, tile_rows=None, blocks=None, rhs_tile=None, fuse_spmv=None, tile_group=None,
              tile_block=None, line_sweep=None, helper=None, spmv_stream=None, rhs_pairs=None, split_dinv=None,
-             factor=None):
+             factor=None, spin_limit=None):
         """Launch knobs of the sweeps and the factorisation (results are
         bit-identical for all).  ``factor``: "waves" (one persistent launch,
         8 rows per workgroup where the LDS allows), "levels" (one launch per
         L level), "waves16" / "waves4" (16 where the LDS allows / at most 4
-        rows per workgroup)."""
+        rows per workgroup).  ``spin_limit``: polls of a bounded wait before
+        the call fails with a time-out (0: the default)."""
         for key, val in ((N.TUNE_SWEEP_MODE, mode), (N.TUNE_TILE_ROWS, tile_rows), (N.TUNE_BLOCKS, blocks),
                          (N.TUNE_RHS_TILE, rhs_tile), (N.TUNE_TILE_GROUP, tile_group),
                          (N.TUNE_TILE_BLOCK, None if tile_block is None else
@@ -113,6 +114,7 @@ class BlockILU:
                          (N.TUNE_SPLIT_DINV, None if split_dinv is None else
                           (0 if split_dinv == "auto" else 2 if split_dinv else 1)),
                          (N.TUNE_FACTOR, None if factor is None else {"waves": 0, "levels": 1, "waves16": 2, "waves4": 3}[factor]),
+                         (N.TUNE_SPIN_LIMIT, spin_limit),
                          (N.TUNE_FUSE_SPMV, None if fuse_spmv is None else int(bool(fuse_spmv)))):
             if val is not None:
                 N.bilu_tune(self._ctx, key, val)

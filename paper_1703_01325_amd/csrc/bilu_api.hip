@@ -1639,6 +1639,10 @@ bilu_status bilu_tune(bilu_ctx* c, int param, int value)
         if (value < 0 || value > 3) return BILU_ERR_ARG;
         c->factor_mode = value;
         return BILU_OK;
+    case BILU_TUNE_SPIN_LIMIT:
+        if (value < 0) return BILU_ERR_ARG;
+        c->spin_limit = value == 0 ? 1u << 24 : static_cast<unsigned int>(value);
+        return BILU_OK;
     case BILU_TUNE_SPLIT_DINV:
         if (value < 0 || value > 2) return BILU_ERR_ARG;
         c->split_dinv = value;

@@ -144,6 +144,37 @@ def test_factor_waves_match_levels(api, name, make, k):
         B.close()
 
 
+def test_factor_waves_timeout_reported(api):
+    """The persistent factorisation with its bounded waits cut to one poll
+    (forced from the host; every wavefront still finishes its rows and the
+    launch drains) reports the expired wait as BILU_ERR_TIMEOUT; with the
+    default limit back, the next factorisation gives the bits of one launch
+    per level."""
+    from paper_1703_01325_amd import _native as N
+    s = synth.layered_60x220x85()
+    print("[factor timeout] 60x220x85 k=0 spin_limit=1", flush=True)
+    Ax = cuda(s.Ax)
+    A = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, 0)
+    B = api.BlockILU(s.nb, s.bs, s.Ap, s.Aj, 0)
+    try:
+        B.tune(factor="waves", spin_limit=1)
+        with pytest.raises(N.BiluError) as err:
+            B.factor(Ax)
+        assert err.value.code == N.ERR_TIMEOUT
+        B.tune(spin_limit=0)
+        A.tune(factor="levels")
+        assert A.factor(Ax) == -1
+        assert B.factor(Ax) == -1
+        FA, DA = A.factors()
+        FB, DB = B.factors()
+        assert torch.equal(FA, FB) and torch.equal(DA, DB)
+        with pytest.raises(N.BiluError):
+            B.tune(spin_limit=-1)
+    finally:
+        A.close()
+        B.close()
+
+
 MODES = [(0, None), (1, None), (2, None), (2, 1), (2, 13), (2, 64)]
 
 
